@@ -1,0 +1,356 @@
+"""Pins of the oracle's step: closed forms, invariants and special cases that the
+paper's equations fix (Sec. 2.2-2.5, Sec. 4.2).
+
+Each test is chosen so that a plausible slip in the oracle fails it: a wrong
+sign of the spin term, a bulk coefficient of 1/3, an F1 instead of an F2/F3
+gradient, a wrong artificial-viscosity sign, Euler instead of midpoint RK2, a
+wrong extrapolation sign at the markers, or a body force of the wrong sign.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2507_05643_amd import scenes
+from paper_2507_05643_amd.scenes import Body, Scene
+
+RHO0, E, NU = 1700.0, 1.0e6, 0.3
+G = E / (2 * (1 + NU))
+K = E / (3 * (1 - 2 * NU))
+
+
+def _interior(n, lo=2):
+    idx = []
+    for k in range(lo, n - lo):
+        for j in range(lo, n - lo):
+            for i in range(lo, n - lo):
+                idx.append(i + n * j + n * n * k)
+    return np.array(idx)
+
+
+def _lattice_scene(n=10, **over):
+    sc = scenes.column(seed=0, n=n, jitter=0.0, walls=False)
+    sc.params.update(over)
+    return sc
+
+
+def _exact_lattice(n, dx=0.01):
+    """FP64 cell-centred lattice (x fastest), not rounded to FP32."""
+    i = np.arange(n ** 3)
+    return np.stack([i % n, (i // n) % n, i // (n * n)], axis=1) * dx + 0.5 * dx
+
+
+def _uniaxial_c(n=10):
+    """Lattice constant c of sum_j V_j (x_j - x_i) (x) grad_i W_ij = c I, measured
+    through the oracle's stress-rate path under uniaxial compression."""
+    sc = _lattice_scene(n)
+    rate = 0.1
+    x = _exact_lattice(n)
+    v = np.zeros_like(x)
+    v[:, 2] = -rate * x[:, 2]
+    o = Oracle(sc)
+    o.set_state(pos=x, vel=v)
+    r = o.eval_rhs()
+    ii = _interior(n)
+    return r, ii, rate, sc
+
+
+def test_uniaxial_compression_ratio_and_continuity():
+    r, ii, rate, sc = _uniaxial_c()
+    ds = r["ds"][ii]
+    # ds_zz = -c rate (K + 4G/3), ds_xx = ds_yy = -c rate (K - 2G/3)
+    ratio = ds[:, 0] / ds[:, 2]
+    assert np.allclose(ratio, NU / (1 - NU), rtol=1e-10, atol=0)
+    assert np.allclose(ds[:, 1], ds[:, 0], rtol=1e-12)
+    assert np.all(np.abs(ds[:, 3:]) < 1e-9 * np.abs(ds[:, 2]).max())
+    c = -ds[:, 2] / (rate * (K + 4 * G / 3))
+    assert np.allclose(c, c[0], rtol=1e-10)
+    assert 0.95 < c[0] < 1.0
+    # compression raises the density: drho/dt = rho c rate
+    drho = r["drho"][ii]
+    assert np.allclose(drho, RHO0 * c[0] * rate, rtol=1e-10)
+
+
+def test_rigid_rotation_gives_jaumann_spin_only():
+    n = 10
+    sc = _lattice_scene(n)
+    w = 2.0
+    x = _exact_lattice(n)
+    d = x - x.mean(axis=0)
+    vel = np.stack([-w * d[:, 1], w * d[:, 0], np.zeros(len(d))], axis=1)
+    s0 = np.array([1000.0, 2000.0, 3000.0, 150.0, -80.0, 60.0])
+    o = Oracle(sc)
+    o.set_state(pos=x, vel=vel, sigma=np.tile(s0, (sc.n_soil, 1)))
+    r = o.eval_rhs()
+    ii = _interior(n)
+    A = np.array([[0, -w, 0], [w, 0, 0], [0, 0, 0.0]])
+    S = np.array([[s0[0], s0[3], s0[4]], [s0[3], s0[1], s0[5]], [s0[4], s0[5], s0[2]]])
+    J = A @ S - S @ A                     # rate of R S R^T for R = exp(A t) at t = 0
+    Jv = np.array([J[0, 0], J[1, 1], J[2, 2], J[0, 1], J[0, 2], J[1, 2]])
+    c_rot = r["ds"][ii] @ Jv / (Jv @ Jv)
+    c_uni = None
+    ru, iu, rate, _ = _uniaxial_c(n)
+    c_uni = -ru["ds"][iu][0, 2] / (rate * (K + 4 * G / 3))
+    assert np.allclose(c_rot, c_uni, rtol=1e-9)          # positive: the spin sign is right
+    resid = r["ds"][ii] - np.outer(c_rot, Jv)
+    assert np.abs(resid).max() < 1e-9 * np.abs(Jv).max()
+    assert np.abs(r["drho"][ii]).max() < 1e-9            # volume preserving
+
+
+def test_uniform_velocity_gives_zero_rates_exactly():
+    sc = scenes.cluster(seed=2, n=6, vel_scale=0.0, sigma_scale=0.0)
+    sc.vel = np.tile(np.array([0.3, -0.2, 0.1], dtype=np.float32), (sc.n_soil, 1))
+    sc.sigma = np.tile(np.array([-500, -600, -700, 10, 20, 30], dtype=np.float32), (sc.n_soil, 1))
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    assert np.all(r["drho"] == 0.0)
+    assert np.all(r["ds"] == 0.0)
+
+
+@pytest.mark.parametrize("av_mode", [0, 1, 2])
+def test_momentum_conserved_isolated_cluster(av_mode):
+    sc = scenes.cluster(seed=7, n=6, vel_scale=0.05, sigma_scale=2.0e3)
+    sc.params.update(av_mode=av_mode, av_gamma=0.5, ps_freq=5, cohesion=5e3)
+    o = Oracle(sc, nbr_mode="cells")
+    m = o.mass
+    p0 = m * o.state()["vel"].sum(axis=0)
+    scale = m * np.abs(o.state()["vel"]).sum()
+    o.step(40)
+    st = o.state()
+    p1 = m * st["vel"].sum(axis=0)
+    assert np.abs(p1 - p0).max() <= 1e-12 * scale
+    assert np.abs(st["vel"] - sc.vel).max() > 1e-6   # something did happen
+
+
+def test_free_fall_is_exact_for_rk2():
+    sc = scenes.cluster(seed=1, n=4, vel_scale=0.0, sigma_scale=0.0, gravity=(0.0, 0.0, -9.81))
+    u0 = np.array([0.2, -0.1, 0.05])
+    sc.vel = np.tile(u0.astype(np.float32), (sc.n_soil, 1))
+    u0 = sc.vel[0].astype(np.float64)
+    o = Oracle(sc)
+    nstep = 30
+    o.step(nstep)
+    t = nstep * sc.params["dt"]
+    g = np.array([0.0, 0.0, -9.81])
+    st = o.state()
+    x_ref = sc.pos.astype(np.float64) + u0 * t + 0.5 * g * t * t
+    assert np.abs(st["pos"] - x_ref).max() < 1e-14
+    assert np.abs(st["vel"] - (u0 + g * t)).max() < 1e-13
+    # explicit Euler would be off by dt*g*t/2 in position
+    assert 0.5 * sc.params["dt"] * 9.81 * t > 1e3 * 1e-14
+
+
+@pytest.mark.parametrize("av_mode", [1, 2])
+def test_artificial_viscosity_dissipates(av_mode):
+    sc = scenes.cluster(seed=3, n=6, vel_scale=0.2, sigma_scale=0.0)
+    sc.params.update(av_mode=av_mode)
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    u = sc.vel.astype(np.float64)
+    power = float(np.sum(u * r["du"]))
+    assert power < 0.0
+
+
+def test_artificial_viscosity_head_on_pair_repels():
+    dx = 0.01
+    pos = np.array([[0.0, 0.0, 0.0], [1.5 * 1.2 * dx, 0.0, 0.0]], dtype=np.float32)
+    vel = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]], dtype=np.float32)
+    p = dict(scenes.DEFAULT_PARAMS, gravity=(0.0, 0.0, 0.0), av_mode=1, domain_lo=(-0.1,) * 3,
+             domain_hi=(0.1,) * 3)
+    sc = Scene("pair", p, pos, vel=vel)
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    assert r["du"][0, 0] < 0.0 and r["du"][1, 0] > 0.0     # decelerated towards each other
+    assert abs(r["du"][0, 0] + r["du"][1, 0]) < 1e-12 * abs(r["du"][0, 0])
+
+
+def _rm_params(**over):
+    p = dict(scenes.DEFAULT_PARAMS)
+    p.update(over)
+    return p
+
+
+def test_return_map_cases(orc):
+    p = _rm_params(mu_s=0.7, mu_2=0.7, cohesion=0.0)
+    zero = np.zeros(6)
+    # tension beyond the cut-off p* < -c/mu_s -> zero stress
+    out, br = orc.return_map(p, [100, 100, 100, 0, 0, 0], zero)
+    assert br == 1 and np.all(out == 0)
+    # admissible state is kept
+    s = np.array([-1000, -1000, -1000, 100, 0, 0.0])
+    out, br = orc.return_map(p, s, s)
+    assert br == 3 and np.array_equal(out, s)
+    # radial return: taubar = tau_max, p unchanged, deviator parallel
+    s = np.array([-1000, -1000, -1000, 2000, 0, 0.0])
+    out, br = orc.return_map(p, s, s)
+    assert br == 4
+    pp = -out[:3].sum() / 3
+    assert abs(pp - 1000) < 1e-9
+    dev = out.copy(); dev[:3] += pp
+    tb = math.sqrt(0.5 * (np.sum(dev[:3] ** 2) + 2 * np.sum(dev[3:] ** 2)))
+    assert abs(tb - 0.7 * 1000) < 1e-9
+    assert abs(out[3] / s[3] - 0.35) < 1e-15
+    # idempotent
+    out2, br2 = orc.return_map(p, out, s)
+    assert np.allclose(out2, out, rtol=1e-14, atol=1e-12)
+    # cohesion shifts the cut-off to p_cri = -c / mu_s
+    pc = _rm_params(mu_s=0.7, mu_2=0.7, cohesion=500.0)
+    out, br = orc.return_map(pc, [600, 600, 600, 0, 0, 0], zero)
+    assert br == 3
+    out, br = orc.return_map(pc, [720, 720, 720, 0, 0, 0], zero)
+    assert br == 1
+
+
+def test_k0_state_is_elastic(orc):
+    p = _rm_params(mu_s=0.7, mu_2=0.7, cohesion=0.0)
+    k0 = NU / (1 - NU)
+    s = np.array([-1000 * k0, -1000 * k0, -1000, 0, 0, 0])
+    out, br = orc.return_map(p, s, s)
+    assert br == 3
+    pp = -s[:3].sum() / 3
+    assert abs(pp - 1000 * (2 * k0 + 1) / 3) < 1e-9
+
+
+def test_mu_of_I(orc):
+    p = _rm_params(mu_s=0.7, mu_2=0.8, I0=0.08, grain_d=3e-3, rho0=1780.0)
+    P = 2000.0
+    gd = 0.08 / (3e-3 * math.sqrt(1780.0 / P))        # I = I0
+    assert abs(orc.mu_I(p, gd, P) - 0.75) < 1e-14
+    assert orc.mu_I(p, 0.0, P) == 0.7
+    assert orc.mu_I(p, -1.0, P) == 0.7
+    assert orc.mu_I(p, 1.0, -5.0) == 0.8
+    assert abs(orc.mu_I(p, 1e9, P) - 0.8) < 1e-6
+    assert orc.mu_I(p, gd / 2, P) < 0.75 < orc.mu_I(p, 2 * gd, P)
+
+
+def _periodic_column(nx=8, nz=12):
+    dx = 0.01
+    pos = scenes.lattice(nx, nx, nz, dx, jitter=0.0)
+    fl = []
+    for k in (-1, -2, -3):
+        for j in range(nx):
+            for i in range(nx):
+                fl.append(((i + 0.5) * dx, (j + 0.5) * dx, (k + 0.5) * dx))
+    floor = np.asarray(fl, dtype=np.float32)
+    p = dict(scenes.DEFAULT_PARAMS, dx=dx, h=1.2 * dx, domain_lo=(0.0, 0.0, -0.04),
+             domain_hi=(nx * dx, nx * dx, (nz + 4) * dx))
+    return Scene("periodic", p, pos, bodies=[Body(markers=floor)])
+
+
+def test_geostatic_column_is_in_discrete_equilibrium():
+    """Laterally periodic column with sigma_zz = -rho0 g d / c: interior particles
+    have zero acceleration. c is the lattice constant measured through the
+    stress-rate path, so this ties the momentum equation (F3 + gravity) to the
+    velocity-gradient estimate (F2)."""
+    ru, iu, rate, _ = _uniaxial_c()
+    c = -ru["ds"][iu][0, 2] / (rate * (K + 4 * G / 3))
+    nx, nz = 8, 12
+    sc = _periodic_column(nx, nz)
+    Htop = nz * 0.01
+    z = sc.pos[:, 2].astype(np.float64)
+    szz = -RHO0 * 9.81 * (Htop - z) / c
+    k0 = NU / (1 - NU)
+    sig = np.zeros((sc.n_soil, 6))
+    sig[:, 0] = sig[:, 1] = k0 * szz
+    sig[:, 2] = szz
+    sc.sigma = sig        # FP64 stress: this test checks the oracle's arithmetic
+    o = Oracle(sc, periodic=(1, 1, 0))
+    i = np.arange(sc.n_soil)
+    x = np.stack([i % nx, (i // nx) % nx, i // (nx * nx)], axis=1) * 0.01 + 0.005
+    szz = -RHO0 * 9.81 * (Htop - x[:, 2]) / c
+    sig[:, 0] = sig[:, 1] = k0 * szz
+    sig[:, 2] = szz
+    o.set_state(pos=x, sigma=sig)
+    r = o.eval_rhs()
+    kz = np.arange(sc.n_soil) // (nx * nx)
+    inner = (kz >= 2) & (kz <= nz - 3)
+    du = r["du"][: sc.n_soil]
+    assert np.abs(du[inner]).max() < 1e-8 * 9.81
+    # the bottom layers feel the floor markers and are not exactly balanced
+    assert np.abs(du[~inner]).max() > 1e-3
+
+
+def test_adami_no_slip_static_wall():
+    sc = scenes.column(seed=1, n=8)
+    u = np.array([0.1, 0.2, -0.05])
+    sc.vel = np.tile(u.astype(np.float32), (sc.n_soil, 1))
+    u = sc.vel[0].astype(np.float64)
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    mu = r["mu"][sc.n_soil:]
+    touched = np.any(r["ms"][sc.n_soil:] != 0, axis=1) | np.any(mu != 0, axis=1)
+    assert touched.sum() > 100
+    assert np.abs(mu[touched] + u).max() < 1e-15
+
+
+def test_adami_no_slip_moving_body():
+    sc = scenes.column(seed=1, n=8)
+    u = np.array([0.1, 0.2, -0.05])
+    sc.vel = np.tile(u.astype(np.float32), (sc.n_soil, 1))
+    u = sc.vel[0].astype(np.float64)
+    V = np.array([0.3, 0.0, 0.1])
+    sc.bodies[0].linvel = tuple(V)
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    mu = r["mu"][sc.n_soil:]
+    near = np.any(np.abs(mu - V) > 1e-12, axis=1)
+    assert near.sum() > 100
+    assert np.abs(mu[near] - (2 * V - u)).max() < 1e-14
+
+
+def test_hydrostatic_stress_extrapolation_is_exact():
+    sc = scenes.column(seed=4, n=8)
+    H = 0.2
+    z = sc.pos[:, 2].astype(np.float64)
+    ps = RHO0 * 9.81 * (H - z)
+    sig = np.zeros((sc.n_soil, 6))
+    sig[:, 0] = sig[:, 1] = sig[:, 2] = -ps
+    o = Oracle(sc)
+    o.set_state(sigma=sig)
+    r = o.eval_rhs()
+    x = o.positions()[sc.n_soil:]
+    ms = r["ms"][sc.n_soil:]
+    has = np.any(ms != 0, axis=1)
+    assert has.sum() > 100
+    ref = -RHO0 * 9.81 * (H - x[has, 2])
+    scale = RHO0 * 9.81 * H
+    assert np.abs(ms[has, 0] - ref).max() < 1e-12 * scale
+    assert np.abs(ms[has, 2] - ref).max() < 1e-12 * scale
+    assert np.abs(ms[has, 3:]).max() < 1e-12 * scale
+
+
+def test_body_force_is_reaction_of_fluid_force():
+    sc = scenes.plate_patch(seed=0, nx=12, ny=12, nz=6)
+    # put the plate into the soil so that it has fluid neighbours
+    pb = sc.bodies[1]
+    pb.pos = (pb.pos[0], pb.pos[1], 0.045)
+    rng = np.random.default_rng(0)
+    sc.vel = rng.normal(0, 0.05, size=(sc.n_soil, 3)).astype(np.float32)
+    sig = np.zeros((sc.n_soil, 6), dtype=np.float32)
+    sig[:, :3] = (-RHO0 * 9.81 * (0.06 - sc.pos[:, 2:3])).astype(np.float32)
+    sig[:, 3:] = rng.normal(0, 50.0, size=(sc.n_soil, 3)).astype(np.float32)
+    sc.sigma = sig
+    o = Oracle(sc)
+    r = o.eval_rhs()
+    m = o.mass
+    nb0 = sc.bodies[0].markers.shape[0]
+    for b, (lo, hi) in enumerate([(sc.n_soil, sc.n_soil + nb0), (sc.n_soil + nb0, o.n)]):
+        Fb = m * r["mas"][lo:hi].sum(axis=0)
+        Ff = m * o.fluid_acc_from_body(b)[: sc.n_soil].sum(axis=0)
+        assert np.abs(Fb).max() > 1e-3
+        assert np.abs(Fb + Ff).max() < 1e-11 * np.abs(Fb).max()
+
+
+def test_step_output_is_admissible():
+    sc = scenes.cluster(seed=5, n=5, vel_scale=0.5, sigma_scale=5.0e3)
+    sc.params.update(mu_s=0.5, mu_2=0.5, cohesion=100.0)
+    o = Oracle(sc)
+    o.step(3)
+    s = o.state()["sigma"]
+    p = -s[:, :3].sum(axis=1) / 3
+    dev = s.copy(); dev[:, :3] += p[:, None]
+    tb = np.sqrt(0.5 * (np.sum(dev[:, :3] ** 2, axis=1) + 2 * np.sum(dev[:, 3:] ** 2, axis=1)))
+    zero = np.all(s == 0, axis=1)
+    assert zero.sum() > 0 and (~zero).sum() > 0
+    assert np.all(tb[~zero] <= 0.5 * p[~zero] + 100.0 + 1e-9 * (1 + np.abs(p[~zero])))
