@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Throughput of the CRM step on one MI355X: particle-steps/s on the
+single-wheel soil bin (200 x 120 x 40 soil particles at dx = 5 mm, container,
+grousered wheel driven at slip 0.3 under a 100 N load).
+
+Every step is one co-simulation exchange as in the paper's FSI loop: the host
+(standing in for the multibody side) sets the wheel state, libcrm advances one
+step, and the host reads back the wheel force and integrates the wheel's free
+vertical degree of freedom.
+
+Prints one JSON line (see the keys below). With --gpus N > 1 it exits: this
+build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of the dominant kernel (soil RHS + stage-2 update + return
+# mapping), per neighbour pair and per soil particle:
+#   FP32 flops per pair: kernel gradient 12, V_j grad W 4, velocity difference
+#   and outer product 21, stress sum and contraction 24, artificial viscosity 19
+#   (only pairs with v.r < 0 in the unilateral form; not counted) -> 61.
+#   HBM bytes per particle: own y_mid 52 + own y_n 52 + y_{n+1} 52, its list
+#   (4 B per pair) and row/count/offset words 16.
+FLOPS_PER_PAIR = 61
+BYTES_PER_PARTICLE = 3 * 52 + 16
+BYTES_PER_PAIR = 4
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+class WheelDriver:
+    """Host stand-in for the multibody side: prescribed angular velocity and
+    forward speed v = (1 - s) w r_g, free vertical motion under the load."""
+
+    def __init__(self, scene):
+        m = scene.meta
+        self.omega = m["omega"]
+        self.v = (1.0 - m["slip"]) * m["omega"] * m["r_g"]
+        self.mass = m["mass"]
+        self.g = 9.81
+        self.bodies = scene.bodies
+        self.x = np.array(scene.bodies[1].pos, dtype=np.float64)
+        self.vz = 0.0
+        self.theta = 0.0
+
+    def state(self):
+        nb = len(self.bodies)
+        pos = np.array([b.pos for b in self.bodies], dtype=np.float64)
+        quat = np.tile([1.0, 0.0, 0.0, 0.0], (nb, 1))
+        lin = np.zeros((nb, 3))
+        ang = np.zeros((nb, 3))
+        pos[1] = self.x
+        quat[1] = [math.cos(0.5 * self.theta), 0.0, math.sin(0.5 * self.theta), 0.0]
+        lin[1] = [self.v, 0.0, self.vz]
+        ang[1] = [0.0, self.omega, 0.0]
+        return pos, quat, lin, ang
+
+    def advance(self, force, dt):
+        self.vz += dt * (force[2] / self.mass - self.g)
+        self.x += dt * np.array([self.v, 0.0, self.vz])
+        self.theta += dt * self.omega
+
+
+def cpu_baseline(scene, steps):
+    from oracle.oracle import Oracle
+    orc = Oracle(scene, nbr_mode="cells")
+    t0 = time.perf_counter()
+    orc.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=scene.n_total * steps / dt, unit="particle-steps/s", cores=Oracle.threads(),
+                kind="oracle",
+                sample=f"{steps} steps of the same wheel-bin workload ({scene.n_total} particles, all "
+                       f"processed), FP64 C oracle with cell-list search, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--ps-freq", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_05643_amd import crm, scenes
+
+    torch.cuda.set_device(0)
+    sc = scenes.wheel_bin(seed=0, ps_freq=args.ps_freq)
+    drv = WheelDriver(sc)
+    sim = crm.Simulation(sc, device=0)
+    dt = sc.params["dt"]
+
+    def one_step():
+        sim.set_bodies(*drv.state())
+        sim.step(1)
+        F, _ = sim.forces()
+        drv.advance(F[1], dt)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    sim.profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = sim.profile()
+    sim.profiling(False)
+    cnt = sim.counts()
+    F, T = sim.forces()
+    n_proc = cnt["n_proc"]
+    value = n_proc * args.steps / wall
+
+    st2 = prof["soil_stage2"]
+    ms2 = st2["ms"] / max(st2["launches"], 1)
+    pairs = prof["soil_pairs"]
+    rows = cnt["soil_rows"]
+    flops = FLOPS_PER_PAIR * pairs
+    bytes_ = BYTES_PER_PARTICLE * rows + BYTES_PER_PAIR * pairs
+    tflops = flops / (ms2 * 1e-3) / 1e12
+    gbs = bytes_ / (ms2 * 1e-3) / 1e9
+    roofline = dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(tflops / PEAK_FP32_TFLOPS, 4), traffic=None,
+                    kernel="k_fluid_stage2", launch_ms=round(ms2, 5), algorithmic_flops=flops,
+                    hbm_view=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                                  frac=round(gbs / PEAK_HBM_GBS, 4), algorithmic_bytes=bytes_))
+    breakdown = {k: round(v["ms"] / max(v["launches"], 1), 5) for k, v in prof.items() if isinstance(v, dict)}
+    print(json.dumps(dict(profile_ms_per_launch=breakdown, counts=cnt, wheel_force=F[1].tolist(),
+                          wheel_torque=T[1].tolist(), wheel_z=float(drv.x[2]))), file=sys.stderr, flush=True)
+    sim.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scenes.wheel_bin(seed=0, ps_freq=args.ps_freq), args.cpu_steps)
+
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single-wheel soil bin: 200x120x40 soil particles (dx 5 mm, seeded jitter) "
+                               "+ 3-layer container + grousered wheel r 0.25 m, slip 0.3, load 100 N; "
+                               "co-simulation exchange every step",
+                   "n_particles": cnt["n_total"], "n_processed": n_proc, "ps_freq": args.ps_freq,
+                   "dt": dt},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * crm.h -- C ABI of libcrm: the per-step particle update of the SPH
+ * "Continuous Representation Model" for granular media (arXiv 2507.05643,
+ * Chrono::CRM) on one AMD Instinct MI355X (gfx950).
+ *
+ * One call of crm_step advances the soil particles by explicit-midpoint RK2
+ * steps (Sec. 2.3) of the SPH-discretised continuity, momentum and Jaumann
+ * hypo-elastic stress-rate equations (Sec. 2.2), followed by the cohesive mu(I)
+ * return mapping (Sec. 2.4). Rigid bodies are represented by BCE markers whose
+ * velocity and stress are extrapolated from the soil (Sec. 2.5.1); the forces
+ * and torques the soil exerts on them are returned by crm_get_forces. The
+ * neighbour lists are built with the cell-linked list of Sec. 4.1 and kept for
+ * ps_freq steps (Alg. 2); with active domains (Sec. 4.2, Alg. 3) only the
+ * particles near moving bodies are processed.
+ *
+ * Conventions for every entry point:
+ *   - All pointers passed to the library are HOST pointers; their contents are
+ *     copied during the call and the caller keeps ownership.
+ *   - Device memory is owned by the library. It is obtained through the
+ *     caller's allocator callbacks when given (so that e.g. PyTorch's caching
+ *     allocator accounts for it), else with hipMalloc/hipFree.
+ *   - A context is bound to one HIP stream (the one given to crm_init) and to
+ *     the device current at crm_init; it is not thread-safe.
+ *   - Every call returns a crm_status and never throws. CRM_E_INVALID,
+ *     CRM_E_NOMEM and CRM_E_STATE leave the context unchanged. CRM_E_DEVICE and
+ *     CRM_E_NONFINITE poison the context: later calls return CRM_E_STATE.
+ *   - Kernels run asynchronously; a device error surfaces at the next call that
+ *     synchronises (crm_get_forces, crm_get_state, the debug exports, or a
+ *     rebuild step).
+ *   - Particle ids: the n_soil soil particles of crm_init are ids 0..n_soil-1;
+ *     the markers of body b follow in body order (ids n_soil + ...).
+ */
+#ifndef CRM_H
+#define CRM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CRM_ABI_VERSION 1u
+
+typedef enum {
+  CRM_OK = 0,
+  CRM_E_INVALID = -1,     /* bad argument or parameter */
+  CRM_E_NOMEM = -2,       /* an allocation failed */
+  CRM_E_DEVICE = -3,      /* a HIP call or kernel failed */
+  CRM_E_STATE = -4,       /* context poisoned or call out of order */
+  CRM_E_NONFINITE = -5,   /* a body force or torque is not finite */
+  CRM_E_UNSUPPORTED = -6  /* valid request this build does not handle */
+} crm_status;
+
+/* Artificial viscosity variants of Sec. 2.2 (eqs. artificial_viscosity_*). */
+enum { CRM_AV_OFF = 0, CRM_AV_BILATERAL = 1, CRM_AV_UNILATERAL = 2 };
+
+typedef struct crm_ctx crm_ctx;
+
+/* Allocator callbacks: return device memory of `bytes` bytes usable on
+ * `hip_stream` (or NULL on failure); free memory returned earlier. */
+typedef void* (*crm_alloc_fn)(size_t bytes, void* user, void* hip_stream);
+typedef void (*crm_free_fn)(void* ptr, void* user, void* hip_stream);
+
+/* Model and solver parameters (SI units). Paper passages:
+ *   dx (particle spacing d0), h (smoothing length), dt, gravity: Table 1, Sec. 3;
+ *   rho0, E, nu (G = E / (2(1+nu)), K = E / (3(1-2nu))): Sec. 2.1;
+ *   mu_s, mu_2, I0, grain_d (d), cohesion (c): Sec. 2.4 (eqs. pcrit, muI, yieldsurf);
+ *   av_mode, av_gamma (gamma_a), av_xi_over_h (xi / h): Sec. 2.2;
+ *   ps_freq: Sec. 4.1 (persistent neighbour lists);
+ *   active_domains, t_delay, grow_G (G), shrink_S (S), shrink_interval (S_I): Sec. 4.2.
+ * domain_lo/hi bound the cell grid (cell size 2h); particles outside are
+ * binned into the edge cells. bulk_coeff multiplies the bulk term K tr(D) I of
+ * the stress rate (1 = the continuum form of eq. stress_rate_hypoelastic). */
+typedef struct {
+  uint32_t abi_version;  /* must be CRM_ABI_VERSION */
+  uint32_t av_mode;
+  double dx, h, dt;
+  double gravity[3];
+  double rho0, E, nu, mu_s, mu_2, I0, grain_d, cohesion;
+  double av_gamma, av_xi_over_h;
+  double domain_lo[3], domain_hi[3];
+  uint32_t ps_freq;
+  uint32_t active_domains;
+  double t_delay;
+  double grow_G, shrink_S;
+  uint32_t shrink_interval;
+  uint32_t reserved;     /* must be 0 */
+  double bulk_coeff;
+} crm_params;
+
+/* A rigid body: BCE markers fixed in its frame (Sec. 2.5.1: layers at spacing
+ * d0, first layer on the collision surface) and an optional active box, an
+ * oriented box of half extents active_half centred at the body origin
+ * (Sec. 4.2 item 1; all zero = no box). */
+typedef struct {
+  int64_t n_markers;
+  const float* marker_local;  /* 3 * n_markers floats, body frame, copied */
+  double active_half[3];
+} crm_body_desc;
+
+/* Create a context. pos: 3*n_soil doubles (rounded to FP32 inside); vel: 3*n_soil
+ * floats or NULL (zero); sigma: 6*n_soil floats (xx, yy, zz, xy, xz, yz) or
+ * NULL (zero); rho: n_soil floats or NULL (rho0). Bodies start at the identity
+ * pose with zero velocity until crm_set_bodies is called. alloc/free may both
+ * be NULL (hipMalloc/hipFree). hip_stream may be NULL (the null stream).
+ * Errors: CRM_E_INVALID (parameters, sizes, NULL where required),
+ * CRM_E_NOMEM, CRM_E_DEVICE. On error *out is NULL. */
+crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos, const float* vel,
+                    const float* sigma, const float* rho, int32_t n_bodies,
+                    const crm_body_desc* bodies, crm_alloc_fn alloc, crm_free_fn free_fn,
+                    void* alloc_user, void* hip_stream, crm_ctx** out);
+
+/* Set the state of the bodies (the multibody side's position- and
+ * velocity-level state, Sec. 2.5); it stays frozen during crm_step. pos: 3*nb
+ * world positions of the body origins; quat: 4*nb unit quaternions (w, x, y, z);
+ * linvel, angvel: 3*nb (world frame; NULL = zero); linacc, angacc: 3*nb or NULL.
+ * Marker accelerations in the stress extrapolation are a + alpha x r +
+ * w x (w x r) when accelerations are given, else the centripetal part only.
+ * Errors: CRM_E_INVALID (nb differs from crm_init, NULL pos/quat, non-finite
+ * input), CRM_E_STATE. */
+crm_status crm_set_bodies(crm_ctx* ctx, int32_t nb, const double* pos, const double* quat,
+                          const double* linvel, const double* angvel, const double* linacc,
+                          const double* angacc);
+
+/* Advance n_steps steps (Alg. 3 per step: rebuild when step mod ps_freq == 0,
+ * then two RHS evaluations and the return mapping). Enqueued on the context's
+ * stream; returns once enqueued, except on rebuild steps, which wait for the
+ * particle and neighbour counts. Errors: CRM_E_INVALID (n_steps < 0),
+ * CRM_E_NOMEM, CRM_E_DEVICE, CRM_E_STATE. */
+crm_status crm_step(crm_ctx* ctx, int32_t n_steps);
+
+/* Force (N, world frame) and torque (N m, about the body origin) the soil
+ * exerts on each body, from the stage-2 evaluation of the last step
+ * (Sec. 2.5.1: sum of marker mass times marker acceleration). force, torque:
+ * 3*nb doubles. Synchronises the stream. Errors: CRM_E_INVALID, CRM_E_STATE
+ * (no step taken yet), CRM_E_NONFINITE, CRM_E_DEVICE. */
+crm_status crm_get_forces(crm_ctx* ctx, int32_t nb, double* force, double* torque);
+
+/* State of all n_total particles by id (soil, then markers: world positions,
+ * extrapolated velocity and stress of their last evaluation, rho0). Any
+ * pointer may be NULL. pos: 3n doubles; vel: 3n; sigma: 6n; rho: n floats.
+ * Synchronises. */
+crm_status crm_get_state(crm_ctx* ctx, double* pos, float* vel, float* sigma, float* rho);
+
+/* Overwrite the soil state (ids 0..n_soil-1); any pointer may be NULL. Takes
+ * effect from the next step; the next step rebuilds the neighbour lists. */
+crm_status crm_set_state(crm_ctx* ctx, const double* pos, const float* vel, const float* sigma,
+                         const float* rho);
+
+/* Sizes: out[0] n_total, out[1] n_soil, out[2] processed particles N_{a+e} of
+ * the last rebuild, out[3] active soil rows, out[4] processed marker rows,
+ * out[5] stored neighbour entries (valid, soil rows + marker rows), out[6]
+ * working-array capacity, out[7] steps taken, out[8] number of cells M,
+ * out[9] rebuilds done. out: 10 int64. */
+crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
+
+/* Export of the last rebuild for bit-exact checks (Sec. 4.1 steps 1-4):
+ * sorted_ids: N_{a+e} particle ids in cell-sorted order (ties by id);
+ * cell_start: M + 1 values, cell_start[c] = first sorted position of cell c
+ * (cellEnd[c] = cell_start[c + 1]); rows: ids of the particles that own a list
+ * (active soil, then processed markers), off: rows + 1 offsets, nbr: entries
+ * as particle ids (order within a row unspecified), cap: capacity of nbr.
+ * flags: n_total activity flags (0 inactive, 1 extended, 2 active).
+ * Any pointer may be NULL. Errors: CRM_E_INVALID if cap is too small,
+ * CRM_E_STATE before the first rebuild. Synchronises. */
+crm_status crm_debug_export(crm_ctx* ctx, int32_t* sorted_ids, uint32_t* cell_start, int32_t* rows,
+                            int64_t* off, int32_t* nbr, int64_t cap, uint8_t* flags);
+
+/* Kernel timing for measurement. enable = 1 starts recording HIP events around
+ * each kernel class of every following step on the context's stream (and
+ * clears earlier records); enable = 0 stops recording. */
+crm_status crm_set_profiling(crm_ctx* ctx, int32_t enable);
+
+/* Recorded timings, out: 16 doubles. For class k = 0..6, out[2k] = launches and
+ * out[2k + 1] = total milliseconds: 0 rebuild (all kernels of a rebuild step),
+ * 1 marker placement, 2 BCE extrapolation (stage 1), 3 soil RHS + stage-1
+ * update, 4 BCE + body forces (stage 2), 5 soil RHS + stage-2 update + return
+ * mapping, 6 body force reduction. out[14] = soil neighbour pairs and out[15] =
+ * marker neighbour pairs of the last rebuild. Synchronises. */
+crm_status crm_get_profile(crm_ctx* ctx, double* out);
+
+/* Capacity policy of Sec. 4.2 item 3 (host logic, no device access): grow to
+ * ceil(G * n) when n exceeds cap; at steps that are multiples of S_I, shrink
+ * to n when n / cap < S. Returns the new capacity. */
+int64_t crm_capacity_next(int64_t cap, int64_t n, int64_t step, double G, double S, int64_t S_I);
+
+/* Human-readable description of the last error of ctx (or of the last failed
+ * crm_init when ctx is NULL). Never NULL. */
+const char* crm_last_error(const crm_ctx* ctx);
+
+/* Release every resource of ctx (NULL is ignored). Synchronises. */
+void crm_destroy(crm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRM_H */

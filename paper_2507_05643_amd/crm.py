@@ -1,0 +1,332 @@
+"""Python binding of libcrm (include/crm.h): argument marshalling only.
+
+Every computation of the step runs in the HIP kernels of libcrm.so; this module
+converts numpy arrays to the C ABI and back. PyTorch provides the device memory
+(its caching allocator, through the allocator callbacks) and the stream.
+
+There is no fallback: if libcrm.so has not been built, importing the binding
+raises an ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime that libcrm.so binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrm.so")
+
+CRM_ABI_VERSION = 1
+STATUS = {0: "CRM_OK", -1: "CRM_E_INVALID", -2: "CRM_E_NOMEM", -3: "CRM_E_DEVICE",
+          -4: "CRM_E_STATE", -5: "CRM_E_NONFINITE", -6: "CRM_E_UNSUPPORTED"}
+
+
+class CrmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class crm_params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("av_mode", C.c_uint32),
+        ("dx", C.c_double), ("h", C.c_double), ("dt", C.c_double),
+        ("gravity", C.c_double * 3),
+        ("rho0", C.c_double), ("E", C.c_double), ("nu", C.c_double), ("mu_s", C.c_double),
+        ("mu_2", C.c_double), ("I0", C.c_double), ("grain_d", C.c_double), ("cohesion", C.c_double),
+        ("av_gamma", C.c_double), ("av_xi_over_h", C.c_double),
+        ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
+        ("ps_freq", C.c_uint32), ("active_domains", C.c_uint32),
+        ("t_delay", C.c_double),
+        ("grow_G", C.c_double), ("shrink_S", C.c_double),
+        ("shrink_interval", C.c_uint32), ("reserved", C.c_uint32),
+        ("bulk_coeff", C.c_double),
+    ]
+
+
+class crm_body_desc(C.Structure):
+    _fields_ = [("n_markers", C.c_int64), ("marker_local", C.POINTER(C.c_float)),
+                ("active_half", C.c_double * 3)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_2507_05643_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, fp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_float)
+    i32p, i64p, u32p, u8p = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint8)
+    L.crm_init.restype = C.c_int
+    L.crm_init.argtypes = [C.POINTER(crm_params), C.c_int64, dp, fp, fp, fp, C.c_int32,
+                           C.POINTER(crm_body_desc), ALLOC_FN, FREE_FN, vp, vp, C.POINTER(vp)]
+    L.crm_set_bodies.restype = C.c_int
+    L.crm_set_bodies.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp, dp]
+    L.crm_step.restype = C.c_int
+    L.crm_step.argtypes = [vp, C.c_int32]
+    L.crm_get_forces.restype = C.c_int
+    L.crm_get_forces.argtypes = [vp, C.c_int32, dp, dp]
+    L.crm_get_state.restype = C.c_int
+    L.crm_get_state.argtypes = [vp, dp, fp, fp, fp]
+    L.crm_set_state.restype = C.c_int
+    L.crm_set_state.argtypes = [vp, dp, fp, fp, fp]
+    L.crm_get_counts.restype = C.c_int
+    L.crm_get_counts.argtypes = [vp, i64p]
+    L.crm_debug_export.restype = C.c_int
+    L.crm_debug_export.argtypes = [vp, i32p, u32p, i32p, i64p, i32p, C.c_int64, u8p]
+    L.crm_set_profiling.restype = C.c_int
+    L.crm_set_profiling.argtypes = [vp, C.c_int32]
+    L.crm_get_profile.restype = C.c_int
+    L.crm_get_profile.argtypes = [vp, dp]
+    L.crm_capacity_next.restype = C.c_int64
+    L.crm_capacity_next.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_int64]
+    L.crm_last_error.restype = C.c_char_p
+    L.crm_last_error.argtypes = [vp]
+    L.crm_destroy.restype = None
+    L.crm_destroy.argtypes = [vp]
+    return L
+
+
+_lib = _load()
+
+EXPORTED = ("crm_init", "crm_set_bodies", "crm_step", "crm_get_forces", "crm_get_state",
+            "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_profiling",
+            "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy")
+
+PROFILE_CLASSES = ("rebuild", "place_markers", "bce_stage1", "soil_stage1", "bce_forces_stage2",
+                   "soil_stage2", "body_reduce")
+
+
+def lib():
+    return _lib
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def _check(ctx, st):
+    if st != 0:
+        raise CrmError(st, _lib.crm_last_error(ctx).decode())
+
+
+def make_params(p: dict) -> crm_params:
+    o = crm_params()
+    o.abi_version = CRM_ABI_VERSION
+    o.av_mode = int(p["av_mode"])
+    o.dx, o.h, o.dt = float(p["dx"]), float(p["h"]), float(p["dt"])
+    o.gravity[:] = [float(v) for v in p["gravity"]]
+    for k in ("rho0", "E", "nu", "mu_s", "mu_2", "I0", "grain_d", "cohesion", "av_gamma",
+              "av_xi_over_h", "t_delay", "grow_G", "shrink_S", "bulk_coeff"):
+        setattr(o, k, float(p[k]))
+    o.domain_lo[:] = [float(v) for v in p["domain_lo"]]
+    o.domain_hi[:] = [float(v) for v in p["domain_hi"]]
+    o.ps_freq = int(p["ps_freq"])
+    o.active_domains = int(p["active_domains"])
+    o.shrink_interval = int(p["shrink_interval"])
+    o.reserved = 0
+    return o
+
+
+class _TorchAllocator:
+    """Allocator callbacks backed by torch's caching allocator."""
+
+    def __init__(self, device: int):
+        self.device = device
+
+        def _alloc(nbytes, user, stream):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, user, stream):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+# ---- thin functions with the C names ----------------------------------------
+
+def crm_init(params: dict, pos, vel=None, sigma=None, rho=None, bodies=(), device=None, stream=None,
+             torch_allocator=True):
+    """Create a context. bodies: sequence of (marker_local (m,3) float32, active_half (3,))."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("libcrm needs a HIP device")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    torch.cuda.set_device(dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    P = make_params(params)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    vel = None if vel is None else np.ascontiguousarray(vel, dtype=np.float32).reshape(n, 3)
+    sigma = None if sigma is None else np.ascontiguousarray(sigma, dtype=np.float32).reshape(n, 6)
+    rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float32).reshape(n)
+    keep = []
+    descs = (crm_body_desc * max(len(bodies), 1))()
+    for b, (ml, half) in enumerate(bodies):
+        ml = np.ascontiguousarray(ml, dtype=np.float32).reshape(-1, 3)
+        keep.append(ml)
+        descs[b].n_markers = ml.shape[0]
+        descs[b].marker_local = ml.ctypes.data_as(C.POINTER(C.c_float))
+        descs[b].active_half[:] = [float(v) for v in half]
+    alloc = _TorchAllocator(dev) if torch_allocator else None
+    out = C.c_void_p()
+    st = _lib.crm_init(C.byref(P), n, _ptr(pos, C.c_double), _ptr(vel, C.c_float), _ptr(sigma, C.c_float),
+                       _ptr(rho, C.c_float), len(bodies), descs,
+                       alloc.alloc if alloc else ALLOC_FN(), alloc.free if alloc else FREE_FN(),
+                       None, C.c_void_p(stream), C.byref(out))
+    _check(None, st)
+    return out.value, alloc
+
+
+def crm_set_bodies(ctx, pos, quat, linvel=None, angvel=None, linacc=None, angacc=None):
+    arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+           for a in (pos, quat, linvel, angvel, linacc, angacc)]
+    nb = 0 if arr[0] is None else arr[0].reshape(-1, 3).shape[0]
+    _check(ctx, _lib.crm_set_bodies(ctx, nb, *[_ptr(a, C.c_double) for a in arr]))
+
+
+def crm_step(ctx, n_steps=1):
+    _check(ctx, _lib.crm_step(ctx, int(n_steps)))
+
+
+def crm_get_forces(ctx, nb):
+    F = np.zeros((max(nb, 1), 3))
+    T = np.zeros((max(nb, 1), 3))
+    _check(ctx, _lib.crm_get_forces(ctx, nb, _ptr(F, C.c_double), _ptr(T, C.c_double)))
+    return F[:nb], T[:nb]
+
+
+def crm_get_counts(ctx):
+    out = np.zeros(10, dtype=np.int64)
+    _check(ctx, _lib.crm_get_counts(ctx, _ptr(out, C.c_int64)))
+    keys = ("n_total", "n_soil", "n_proc", "soil_rows", "marker_rows", "entries", "capacity",
+            "steps", "cells", "rebuilds")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def crm_get_state(ctx, n_total):
+    pos = np.zeros((n_total, 3))
+    vel = np.zeros((n_total, 3), dtype=np.float32)
+    sig = np.zeros((n_total, 6), dtype=np.float32)
+    rho = np.zeros(n_total, dtype=np.float32)
+    _check(ctx, _lib.crm_get_state(ctx, _ptr(pos, C.c_double), _ptr(vel, C.c_float), _ptr(sig, C.c_float),
+                                   _ptr(rho, C.c_float)))
+    return dict(pos=pos, vel=vel, sigma=sig, rho=rho)
+
+
+def crm_set_state(ctx, pos=None, vel=None, sigma=None, rho=None):
+    a = [None if v is None else np.ascontiguousarray(v, dtype=t)
+         for v, t in ((pos, np.float64), (vel, np.float32), (sigma, np.float32), (rho, np.float32))]
+    _check(ctx, _lib.crm_set_state(ctx, _ptr(a[0], C.c_double), _ptr(a[1], C.c_float), _ptr(a[2], C.c_float),
+                                   _ptr(a[3], C.c_float)))
+
+
+def crm_debug_export(ctx):
+    c = crm_get_counts(ctx)
+    np_ = c["n_proc"]
+    rows_n = c["soil_rows"] + c["marker_rows"]
+    sid = np.zeros(max(np_, 1), dtype=np.int32)
+    cs = np.zeros(c["cells"] + 1, dtype=np.uint32)
+    rows = np.zeros(max(rows_n, 1), dtype=np.int32)
+    off = np.zeros(rows_n + 1, dtype=np.int64)
+    cap = max(c["entries"], 1)
+    nbr = np.zeros(cap, dtype=np.int32)
+    flags = np.zeros(c["n_total"], dtype=np.uint8)
+    _check(ctx, _lib.crm_debug_export(ctx, _ptr(sid, C.c_int32), _ptr(cs, C.c_uint32), _ptr(rows, C.c_int32),
+                                      _ptr(off, C.c_int64), _ptr(nbr, C.c_int32), cap, _ptr(flags, C.c_uint8)))
+    return dict(sorted_ids=sid[:np_], cell_start=cs, rows=rows[:rows_n], off=off, nbr=nbr[: off[-1]],
+                flags=flags)
+
+
+def crm_set_profiling(ctx, enable):
+    _check(ctx, _lib.crm_set_profiling(ctx, 1 if enable else 0))
+
+
+def crm_get_profile(ctx):
+    out = np.zeros(16)
+    _check(ctx, _lib.crm_get_profile(ctx, _ptr(out, C.c_double)))
+    res = {k: dict(launches=int(out[2 * i]), ms=float(out[2 * i + 1])) for i, k in enumerate(PROFILE_CLASSES)}
+    res["soil_pairs"] = int(out[14])
+    res["marker_pairs"] = int(out[15])
+    return res
+
+
+def crm_capacity_next(cap, n, step, G=1.2, S=0.75, S_I=50):
+    return int(_lib.crm_capacity_next(int(cap), int(n), int(step), float(G), float(S), int(S_I)))
+
+
+def crm_last_error(ctx=None):
+    return _lib.crm_last_error(ctx).decode()
+
+
+def crm_destroy(ctx):
+    _lib.crm_destroy(ctx)
+
+
+# ---- convenience wrapper over a scene ----------------------------------------
+
+class Simulation:
+    """A libcrm context built from a scene (see ``scenes``)."""
+
+    def __init__(self, scene, params=None, device=None, stream=None, torch_allocator=True):
+        p = dict(scene.params if params is None else params)
+        self.params = p
+        self.n_soil = scene.n_soil
+        self.nb = len(scene.bodies)
+        bodies = [(b.markers, b.active_half) for b in scene.bodies]
+        self.ctx, self._alloc = crm_init(p, scene.pos, scene.vel, scene.sigma, scene.rho, bodies,
+                                         device=device, stream=stream, torch_allocator=torch_allocator)
+        self.n_total = scene.n_total
+        if self.nb:
+            self.set_bodies(np.array([b.pos for b in scene.bodies]), np.array([b.quat for b in scene.bodies]),
+                            np.array([b.linvel for b in scene.bodies]), np.array([b.angvel for b in scene.bodies]))
+
+    def set_bodies(self, pos, quat, linvel=None, angvel=None, linacc=None, angacc=None):
+        crm_set_bodies(self.ctx, pos, quat, linvel, angvel, linacc, angacc)
+
+    def step(self, n=1):
+        crm_step(self.ctx, n)
+
+    def forces(self):
+        return crm_get_forces(self.ctx, self.nb)
+
+    def state(self):
+        return crm_get_state(self.ctx, self.n_total)
+
+    def set_state(self, pos=None, vel=None, sigma=None, rho=None):
+        crm_set_state(self.ctx, pos, vel, sigma, rho)
+
+    def counts(self):
+        return crm_get_counts(self.ctx)
+
+    def export(self):
+        return crm_debug_export(self.ctx)
+
+    def profiling(self, enable=True):
+        crm_set_profiling(self.ctx, enable)
+
+    def profile(self):
+        return crm_get_profile(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            crm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

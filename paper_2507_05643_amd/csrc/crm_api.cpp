@@ -1,0 +1,818 @@
+// Host side of the libcrm C ABI (include/crm.h): validation, device memory,
+// the rebuild pipeline of Alg. 3 (activity, compaction, capacity policy, cell
+// hashing, sort, neighbour lists) and the two-stage step of Sec. 2.3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "crm.h"
+#include "crm_internal.h"
+
+using crm::Body;
+using crm::Grid;
+using crm::Phys;
+using crm::Rec;
+
+namespace {
+
+std::string g_init_error = "no error";
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct crm_ctx {
+  crm_params prm{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  crm_alloc_fn alloc = nullptr;
+  crm_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  bool poisoned = false;
+  std::string err = "no error";
+
+  int64_t n_soil = 0, n_mark = 0, n_total = 0;
+  int32_t nb = 0;
+  Grid grid{};
+  Phys phys{};
+  int64_t M = 0;
+  bool ad_on = false;  // last rebuild used the activity flags
+
+  // master store (by particle id), four planes of float4
+  float4 *m_a = nullptr, *m_b = nullptr, *m_c = nullptr, *m_d = nullptr;
+  float4* local = nullptr;     // markers: (lx, ly, lz, body bits)
+  uint8_t* flags = nullptr;
+  int32_t* proc_ids = nullptr;
+  Body* d_bodies = nullptr;
+  std::vector<Body> h_bodies;
+  double* d_forces = nullptr;
+  uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
+
+  // cell grid
+  uint32_t* cell_cnt = nullptr;
+  uint32_t* cell_start = nullptr;
+  uint32_t* cell_tmp = nullptr;
+
+  // working set (capacity `cap`)
+  int64_t cap = 0;
+  Rec *A = nullptr, *B = nullptr;
+  float4* pos4 = nullptr;
+  int32_t* slot_id = nullptr;
+  uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
+  int32_t *frows = nullptr, *mrows = nullptr;
+  uint32_t *cnt_f = nullptr, *cnt_m = nullptr, *wlen_f = nullptr, *wlen_m = nullptr;
+  uint64_t *woff_f = nullptr, *woff_m = nullptr, *wtmp = nullptr;
+
+  // neighbour entries
+  uint32_t* nbr_f = nullptr;
+  int64_t nbr_f_cap = 0;
+  uint32_t* nbr_m = nullptr;
+  int64_t nbr_m_cap = 0;
+
+  double* partials = nullptr;
+  int64_t partials_cap = 0;
+  uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
+  uint64_t* h_counts = nullptr;   // pinned mirror
+
+  int64_t n_proc = 0, n_frows = 0, n_mrows = 0, ent_f = 0, ent_m = 0;
+  int64_t step = 0, rebuilds = 0;
+  bool working_valid = false;
+  bool force_rebuild = true;
+  bool stepped = false;
+
+  // profiling: event pairs per kernel class
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
+
+  std::vector<Buf> owned;
+};
+
+namespace {
+
+crm_status fail(crm_ctx* c, crm_status st, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (st == CRM_E_DEVICE || st == CRM_E_NONFINITE) c->poisoned = true;
+  } else {
+    g_init_error = msg;
+  }
+  return st;
+}
+
+void* dalloc(crm_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(bytes, c->user, (void*)c->stream);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->owned.push_back(Buf{p, bytes});
+  return p;
+}
+
+void dfree(crm_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->owned.size(); ++i) {
+    if (c->owned[i].p == p) {
+      c->owned.erase(c->owned.begin() + (long)i);
+      break;
+    }
+  }
+  if (c->free_fn)
+    c->free_fn(p, c->user, (void*)c->stream);
+  else
+    (void)hipFree(p);
+}
+
+template <typename T>
+bool alloc_n(crm_ctx* c, T*& p, int64_t n) {
+  p = (T*)dalloc(c, sizeof(T) * (size_t)(n > 0 ? n : 1));
+  return p != nullptr;
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+std::string check_params(const crm_params* p) {
+  if (!p) return "params is NULL";
+  if (p->abi_version != CRM_ABI_VERSION) return "abi_version mismatch";
+  if (p->reserved != 0) return "reserved must be 0";
+  auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+  if (!pos(p->dx)) return "dx must be > 0";
+  if (!pos(p->h)) return "h must be > 0";
+  if (!pos(p->dt)) return "dt must be > 0";
+  if (!finite3(p->gravity)) return "gravity must be finite";
+  if (!pos(p->rho0)) return "rho0 must be > 0";
+  if (!pos(p->E)) return "E must be > 0";
+  if (!(std::isfinite(p->nu) && p->nu >= 0.0 && p->nu < 0.5)) return "nu must be in [0, 0.5)";
+  if (!pos(p->mu_s)) return "mu_s must be > 0";
+  if (!(std::isfinite(p->mu_2) && p->mu_2 >= 0.0)) return "mu_2 must be >= 0";
+  if (!pos(p->I0)) return "I0 must be > 0";
+  if (!pos(p->grain_d)) return "grain_d must be > 0";
+  if (!(std::isfinite(p->cohesion) && p->cohesion >= 0.0)) return "cohesion must be >= 0";
+  if (p->av_mode > 2) return "av_mode must be 0, 1 or 2";
+  if (!(std::isfinite(p->av_gamma) && p->av_gamma >= 0.0)) return "av_gamma must be >= 0";
+  if (!pos(p->av_xi_over_h)) return "av_xi_over_h must be > 0";
+  for (int a = 0; a < 3; ++a)
+    if (!(std::isfinite(p->domain_lo[a]) && std::isfinite(p->domain_hi[a]) && p->domain_hi[a] > p->domain_lo[a]))
+      return "domain_hi must exceed domain_lo on every axis";
+  if (p->ps_freq < 1) return "ps_freq must be >= 1";
+  if (p->active_domains > 1) return "active_domains must be 0 or 1";
+  if (!std::isfinite(p->t_delay)) return "t_delay must be finite";
+  if (!(std::isfinite(p->grow_G) && p->grow_G >= 1.0)) return "grow_G must be >= 1";
+  if (!(std::isfinite(p->shrink_S) && p->shrink_S > 0.0 && p->shrink_S <= 1.0)) return "shrink_S must be in (0, 1]";
+  if (p->shrink_interval < 1) return "shrink_interval must be >= 1";
+  if (!std::isfinite(p->bulk_coeff)) return "bulk_coeff must be finite";
+  return "";
+}
+
+void quat_to_R(const double q[4], double R[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, CRM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+crm_status realloc_working(crm_ctx* c, int64_t cap) {
+  void* olds[] = {c->A, c->B, c->pos4, c->slot_id, c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows,
+                  c->cnt_f, c->cnt_m, c->wlen_f, c->wlen_m, c->woff_f, c->woff_m, c->wtmp};
+  for (void* p : olds) dfree(c, p);
+  c->A = c->B = nullptr;
+  c->pos4 = nullptr;
+  c->slot_id = c->frows = c->mrows = nullptr;
+  c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = c->wlen_f = c->wlen_m = nullptr;
+  c->woff_f = c->woff_m = c->wtmp = nullptr;
+  c->cap = 0;
+  const int64_t nw = (cap + crm::kWave - 1) / crm::kWave + 1;
+  bool ok = alloc_n(c, c->A, cap) && alloc_n(c, c->B, cap) && alloc_n(c, c->pos4, cap) &&
+            alloc_n(c, c->slot_id, cap) && alloc_n(c, c->skey, cap) && alloc_n(c, c->key, cap) &&
+            alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->frows, cap) &&
+            alloc_n(c, c->mrows, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
+            alloc_n(c, c->wlen_f, nw) && alloc_n(c, c->wlen_m, nw) && alloc_n(c, c->woff_f, nw + 1) &&
+            alloc_n(c, c->woff_m, nw + 1) && alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(nw));
+  if (!ok) return fail(c, CRM_E_NOMEM, "working-set allocation failed");
+  c->cap = cap;
+  c->working_valid = false;
+  return CRM_OK;
+}
+
+crm_status ensure_list(crm_ctx* c, uint32_t*& buf, int64_t& cap, int64_t need) {
+  if (need <= cap && buf) return CRM_OK;
+  dfree(c, buf);
+  buf = nullptr;
+  cap = 0;
+  int64_t n = (int64_t)std::ceil(c->prm.grow_G * (double)need) + crm::kWave;
+  if (!alloc_n(c, buf, n)) return fail(c, CRM_E_NOMEM, "neighbour-list allocation failed");
+  cap = n;
+  return CRM_OK;
+}
+
+crm_status read_counts(crm_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(uint64_t) * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CRM_OK;
+}
+
+// Alg. 3 lines for a rebuild step: activity (t > t_delay), count, capacity,
+// then PreprocessNeighborList + Algorithm 1 on the processed set.
+crm_status rebuild(crm_ctx* c) {
+  hipStream_t s = c->stream;
+  const crm_params& P = c->prm;
+  if (c->working_valid)
+    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->m_a, s));
+  const double t = (double)c->step * P.dt;
+  c->ad_on = P.active_domains && t > P.t_delay;
+  int64_t n_proc = c->n_total;
+  if (c->ad_on) {
+    HIPCHK(c, crm::activity_flags(c->m_a, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, s));
+    HIPCHK(c, crm::compact_flags(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
+    crm_status st = read_counts(c);
+    if (st != CRM_OK) return st;
+    n_proc = (int64_t)c->h_counts[0];
+  }
+  // capacity policy (Sec. 4.2 item 3)
+  int64_t ncap = crm_capacity_next(c->cap, n_proc, c->step, P.grow_G, P.shrink_S, P.shrink_interval);
+  if (ncap != c->cap || !c->A) {
+    crm_status st = realloc_working(c, ncap);
+    if (st != CRM_OK) return st;
+  }
+  c->n_proc = n_proc;
+  const int32_t* ids = c->ad_on ? c->proc_ids : nullptr;
+  const uint8_t* flg = c->ad_on ? c->flags : nullptr;
+  HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, c->M, s));
+  HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->grid, c->key, c->rank, c->cell_cnt, s));
+  HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
+  HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, c->tmp, s));
+  HIPCHK(c, crm::gather_sorted(c->tmp, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
+                               c->m_d, c->A, c->B, c->pos4, c->slot_id, c->skey, s));
+  HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
+  HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
+  const int64_t nw = (n_proc + crm::kWave - 1) / crm::kWave;
+  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->skey, c->cell_start, c->grid, c->cnt_f,
+                           c->wlen_f, s));
+  HIPCHK(c, crm::scan_u32_to_u64(c->wlen_f, c->woff_f, nw, c->wtmp, s));
+  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->skey, c->cell_start, c->grid, c->cnt_m,
+                           c->wlen_m, s));
+  HIPCHK(c, crm::scan_u32_to_u64(c->wlen_m, c->woff_m, nw, c->wtmp, s));
+  HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->woff_f + nw, c->woff_m + nw, s));
+  crm_status st = read_counts(c);
+  if (st != CRM_OK) return st;
+  c->n_frows = (int64_t)c->h_counts[1];
+  c->n_mrows = (int64_t)c->h_counts[2];
+  const int64_t ef = (int64_t)c->h_counts[3], em = (int64_t)c->h_counts[4];
+  st = ensure_list(c, c->nbr_f, c->nbr_f_cap, ef);
+  if (st != CRM_OK) return st;
+  st = ensure_list(c, c->nbr_m, c->nbr_m_cap, em);
+  if (st != CRM_OK) return st;
+  c->ent_f = ef;
+  c->ent_m = em;
+  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->skey, c->cell_start, c->grid, c->woff_f, c->nbr_f, s));
+  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->skey, c->cell_start, c->grid, c->woff_m, c->nbr_m, s));
+  const int64_t nbk = crm::bce_blocks(c->n_mrows);
+  if (nbk * c->nb > c->partials_cap) {
+    dfree(c, c->partials);
+    c->partials = nullptr;
+    c->partials_cap = 0;
+    int64_t n = (nbk + 1) * (c->nb > 0 ? c->nb : 1);
+    if (!alloc_n(c, c->partials, n * 6)) return fail(c, CRM_E_NOMEM, "partials allocation failed");
+    c->partials_cap = n;
+  }
+  c->working_valid = true;
+  c->force_rebuild = false;
+  c->rebuilds += 1;
+  return CRM_OK;
+}
+
+hipEvent_t prof_event(crm_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// Records a start event for kernel class k when profiling; returns it.
+hipEvent_t prof_begin(crm_ctx* c) {
+  if (!c->prof) return nullptr;
+  hipEvent_t e = prof_event(c);
+  if (e) (void)hipEventRecord(e, c->stream);
+  return e;
+}
+
+void prof_end(crm_ctx* c, int k, hipEvent_t start) {
+  if (!c->prof || !start) return;
+  hipEvent_t e = prof_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->stream);
+  c->prof_marks.push_back({k, {start, e}});
+}
+
+crm_status one_step(crm_ctx* c) {
+  hipStream_t s = c->stream;
+  if (c->force_rebuild || !c->working_valid || c->step % (int64_t)c->prm.ps_freq == 0) {
+    hipEvent_t e = prof_begin(c);
+    crm_status st = rebuild(c);
+    if (st != CRM_OK) return st;
+    prof_end(c, 0, e);
+  }
+  const Phys& P = c->phys;
+  hipEvent_t e = prof_begin(c);
+  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies, c->A,
+                                       c->B, s));
+  prof_end(c, 1, e);
+  // stage 1 at y_n
+  e = prof_begin(c);
+  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->cnt_m, c->woff_m, c->nbr_m, c->d_bodies, c->nb, P, nullptr, s));
+  prof_end(c, 2, e);
+  e = prof_begin(c);
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->cnt_f, c->woff_f, c->nbr_f, P, s));
+  prof_end(c, 3, e);
+  // stage 2 at y_mid, body forces from this evaluation
+  e = prof_begin(c);
+  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->cnt_m, c->woff_m, c->nbr_m, c->d_bodies, c->nb, P, c->partials,
+                     s));
+  prof_end(c, 4, e);
+  e = prof_begin(c);
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->cnt_f, c->woff_f, c->nbr_f, P, s));
+  prof_end(c, 5, e);
+  e = prof_begin(c);
+  HIPCHK(c, crm::body_reduce(c->partials, crm::bce_blocks(c->n_mrows), c->nb, c->d_forces, s));
+  prof_end(c, 6, e);
+  c->step += 1;
+  c->stepped = true;
+  return CRM_OK;
+}
+
+void release(crm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  std::vector<Buf> all = c->owned;
+  for (auto& b : all) dfree(c, b.p);
+  if (c->h_counts) (void)hipHostFree(c->h_counts);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+crm_status usable(crm_ctx* c) {
+  if (!c) return fail(nullptr, CRM_E_INVALID, "ctx is NULL");
+  if (c->poisoned) return fail(c, CRM_E_STATE, "context is poisoned by an earlier device error: " + c->err);
+  return CRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t crm_capacity_next(int64_t cap, int64_t n, int64_t step, double G, double S, int64_t S_I) {
+  if (n > cap) return (int64_t)std::ceil(G * (double)n);
+  if (S_I > 0 && step % S_I == 0 && cap > 0 && (double)n / (double)cap < S) return n;
+  return cap;
+}
+
+const char* crm_last_error(const crm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos, const float* vel,
+                    const float* sigma, const float* rho, int32_t n_bodies, const crm_body_desc* bodies,
+                    crm_alloc_fn alloc, crm_free_fn free_fn, void* alloc_user, void* hip_stream, crm_ctx** out) {
+  if (!out) return fail(nullptr, CRM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string msg = check_params(params);
+  if (!msg.empty()) return fail(nullptr, CRM_E_INVALID, msg);
+  if (n_soil < 0) return fail(nullptr, CRM_E_INVALID, "n_soil must be >= 0");
+  if (n_soil > 0 && !pos) return fail(nullptr, CRM_E_INVALID, "pos is NULL");
+  if (n_bodies < 0 || n_bodies > crm::kMaxBodies) return fail(nullptr, CRM_E_INVALID, "n_bodies out of range");
+  if (n_bodies > 0 && !bodies) return fail(nullptr, CRM_E_INVALID, "bodies is NULL");
+  if ((alloc == nullptr) != (free_fn == nullptr)) return fail(nullptr, CRM_E_INVALID, "alloc and free must both be set");
+  int64_t nm = 0;
+  for (int b = 0; b < n_bodies; ++b) {
+    if (bodies[b].n_markers < 0) return fail(nullptr, CRM_E_INVALID, "n_markers must be >= 0");
+    if (bodies[b].n_markers > 0 && !bodies[b].marker_local) return fail(nullptr, CRM_E_INVALID, "marker_local is NULL");
+    for (int a = 0; a < 3; ++a)
+      if (!(std::isfinite(bodies[b].active_half[a]) && bodies[b].active_half[a] >= 0.0))
+        return fail(nullptr, CRM_E_INVALID, "active_half must be finite and >= 0");
+    nm += bodies[b].n_markers;
+  }
+  const int64_t n_total = n_soil + nm;
+  if (n_total < 1) return fail(nullptr, CRM_E_INVALID, "no particles");
+  if (n_total > (int64_t)0x7fffffff - 1) return fail(nullptr, CRM_E_UNSUPPORTED, "more than 2^31 - 2 particles");
+  for (int64_t i = 0; i < 3 * n_soil; ++i)
+    if (!std::isfinite(pos[i])) return fail(nullptr, CRM_E_INVALID, "non-finite position");
+  Grid g{};
+  const double two_h = 2.0 * params->h;
+  g.inv = 1.0 / two_h;
+  g.R2 = two_h * two_h;
+  g.ext = two_h;
+  int64_t M = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = params->domain_lo[a];
+    double d = std::floor((params->domain_hi[a] - params->domain_lo[a]) * g.inv) + 1.0;
+    if (!(d >= 1.0 && d < 2.0e9)) return fail(nullptr, CRM_E_UNSUPPORTED, "cell grid too large");
+    g.dims[a] = (int32_t)d;
+    M *= (int64_t)d;
+  }
+  if (M > (int64_t)0xfffffffe) return fail(nullptr, CRM_E_UNSUPPORTED, "more than 2^32 - 2 cells");
+
+  crm_ctx* c = new crm_ctx();
+  c->prm = *params;
+  c->stream = (hipStream_t)hip_stream;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = alloc_user;
+  c->n_soil = n_soil;
+  c->n_mark = nm;
+  c->n_total = n_total;
+  c->nb = n_bodies;
+  c->grid = g;
+  c->M = M;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, CRM_E_DEVICE, "no HIP device");
+  }
+
+  // physical constants (Sec. 2.1, 2.2)
+  const crm_params& P = *params;
+  const double G = P.E / (2.0 * (1.0 + P.nu));
+  const double K = P.E / (3.0 * (1.0 - 2.0 * P.nu));
+  const double cs = std::sqrt(K / P.rho0);
+  const double m = P.rho0 * P.dx * P.dx * P.dx;
+  const double pi = 3.14159265358979323846;
+  Phys& ph = c->phys;
+  ph.inv_h = (float)(1.0 / P.h);
+  ph.kw = (float)(1.0 / (pi * P.h * P.h * P.h));
+  ph.kf = (float)(1.0 / (pi * P.h * P.h * P.h * P.h * P.h));
+  ph.dt = (float)P.dt;
+  ph.half_dt = (float)(0.5 * P.dt);
+  ph.gx = (float)P.gravity[0];
+  ph.gy = (float)P.gravity[1];
+  ph.gz = (float)P.gravity[2];
+  ph.m = (float)m;
+  ph.rho0 = (float)P.rho0;
+  ph.two_G = (float)(2.0 * G);
+  ph.iso = (float)(P.bulk_coeff * K - 2.0 * G / 3.0);
+  ph.av_coef = (float)(P.av_gamma * P.h * cs * m);
+  ph.xi2 = (float)((P.av_xi_over_h * P.h) * (P.av_xi_over_h * P.h));
+  ph.av_mode = (int32_t)P.av_mode;
+  ph.mu_s = (float)P.mu_s;
+  ph.mu_2 = (float)P.mu_2;
+  ph.I0 = (float)P.I0;
+  ph.grain_d = (float)P.grain_d;
+  ph.cohesion = (float)P.cohesion;
+  ph.p_cri = (float)(-P.cohesion / P.mu_s);
+  ph.inv_Gdt = (float)(1.0 / (G * P.dt));
+
+  // host staging of the master planes
+  std::vector<float4> ha((size_t)n_total), hb((size_t)n_total), hc((size_t)n_total), hd((size_t)n_total);
+  std::vector<float4> hl((size_t)(nm > 0 ? nm : 1));
+  for (int64_t i = 0; i < n_soil; ++i) {
+    float r0 = rho ? rho[i] : (float)P.rho0;
+    ha[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], r0);
+    float v[3] = {0.f, 0.f, 0.f}, sg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (vel)
+      for (int a = 0; a < 3; ++a) v[a] = vel[3 * i + a];
+    if (sigma)
+      for (int a = 0; a < 6; ++a) sg[a] = sigma[6 * i + a];
+    uint32_t aux = crm::kSoilActive;
+    float auxf;
+    std::memcpy(&auxf, &aux, 4);
+    hb[i] = make_float4(v[0], v[1], v[2], auxf);
+    hc[i] = make_float4(sg[0], sg[1], sg[2], sg[3]);
+    hd[i] = make_float4(sg[4], sg[5], 0.f, 0.f);
+  }
+  int64_t k = 0;
+  for (int b = 0; b < n_bodies; ++b) {
+    for (int64_t q = 0; q < bodies[b].n_markers; ++q, ++k) {
+      const float* l = bodies[b].marker_local + 3 * q;
+      uint32_t bb = (uint32_t)b;
+      float bf;
+      std::memcpy(&bf, &bb, 4);
+      hl[k] = make_float4(l[0], l[1], l[2], bf);
+      uint32_t aux = crm::kMarker | ((uint32_t)b << 2);
+      float auxf;
+      std::memcpy(&auxf, &aux, 4);
+      ha[n_soil + k] = make_float4(l[0], l[1], l[2], (float)P.rho0);
+      hb[n_soil + k] = make_float4(0.f, 0.f, 0.f, auxf);
+      hc[n_soil + k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      hd[n_soil + k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  c->h_bodies.resize((size_t)(n_bodies > 0 ? n_bodies : 1));
+  for (int b = 0; b < n_bodies; ++b) {
+    Body& B = c->h_bodies[b];
+    std::memset(&B, 0, sizeof(Body));
+    B.R[0] = B.R[4] = B.R[8] = 1.0;
+    for (int a = 0; a < 3; ++a) B.half[a] = bodies[b].active_half[a];
+    B.has_box = (B.half[0] > 0.0 || B.half[1] > 0.0 || B.half[2] > 0.0) ? 1 : 0;
+  }
+
+  const int64_t nbk = crm::compact_tmp_elems(n_total);
+  bool ok = alloc_n(c, c->m_a, n_total) && alloc_n(c, c->m_b, n_total) && alloc_n(c, c->m_c, n_total) &&
+            alloc_n(c, c->m_d, n_total) && alloc_n(c, c->local, nm) && alloc_n(c, c->flags, n_total) &&
+            alloc_n(c, c->proc_ids, n_total) && alloc_n(c, c->d_bodies, n_bodies > 0 ? n_bodies : 1) &&
+            alloc_n(c, c->d_forces, 6 * (n_bodies > 0 ? n_bodies : 1)) && alloc_n(c, c->ctmp, nbk) &&
+            alloc_n(c, c->cell_cnt, M) && alloc_n(c, c->cell_start, M + 1) &&
+            alloc_n(c, c->cell_tmp, (int64_t)crm::scan_tmp_elems(M)) && alloc_n(c, c->d_counts, 8);
+  if (!ok) {
+    release(c);
+    return fail(nullptr, CRM_E_NOMEM, "device allocation failed");
+  }
+  if (hipHostMalloc((void**)&c->h_counts, sizeof(uint64_t) * 8, hipHostMallocDefault) != hipSuccess) {
+    c->h_counts = nullptr;
+    release(c);
+    return fail(nullptr, CRM_E_NOMEM, "pinned allocation failed");
+  }
+  hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
+  const size_t f4 = sizeof(float4) * (size_t)n_total;
+  if (e == hipSuccess) e = hipMemcpyAsync(c->m_a, ha.data(), f4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->m_b, hb.data(), f4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->m_c, hc.data(), f4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->m_d, hd.data(), f4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && nm > 0)
+    e = hipMemcpyAsync(c->local, hl.data(), sizeof(float4) * (size_t)nm, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_bodies, c->h_bodies.data(), sizeof(Body) * c->h_bodies.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_forces, 0, sizeof(double) * 6 * (size_t)(n_bodies > 0 ? n_bodies : 1), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    std::string m2 = std::string("upload failed: ") + hipGetErrorString(e);
+    release(c);
+    return fail(nullptr, CRM_E_DEVICE, m2);
+  }
+  *out = c;
+  return CRM_OK;
+}
+
+crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const double* quat, const double* linvel,
+                          const double* angvel, const double* linacc, const double* angacc) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (nb != c->nb) return fail(c, CRM_E_INVALID, "nb differs from crm_init");
+  if (nb == 0) return CRM_OK;
+  if (!pos || !quat) return fail(c, CRM_E_INVALID, "pos and quat are required");
+  std::vector<Body> hb = c->h_bodies;
+  for (int b = 0; b < nb; ++b) {
+    Body& B = hb[b];
+    const double* arrs[] = {pos + 3 * b, linvel ? linvel + 3 * b : nullptr, angvel ? angvel + 3 * b : nullptr,
+                            linacc ? linacc + 3 * b : nullptr, angacc ? angacc + 3 * b : nullptr};
+    for (const double* a : arrs)
+      if (a && !finite3(a)) return fail(c, CRM_E_INVALID, "non-finite body state");
+    const double* q = quat + 4 * b;
+    if (!(std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]) && std::isfinite(q[3])))
+      return fail(c, CRM_E_INVALID, "non-finite quaternion");
+    for (int a = 0; a < 3; ++a) {
+      B.X[a] = pos[3 * b + a];
+      B.V[a] = linvel ? linvel[3 * b + a] : 0.0;
+      B.W[a] = angvel ? angvel[3 * b + a] : 0.0;
+      B.A[a] = linacc ? linacc[3 * b + a] : 0.0;
+      B.Al[a] = angacc ? angacc[3 * b + a] : 0.0;
+    }
+    quat_to_R(q, B.R);
+    B.has_acc = (linacc || angacc) ? 1 : 0;
+  }
+  hipError_t e = hipMemcpyAsync(c->d_bodies, hb.data(), sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
+  c->h_bodies = hb;
+  return CRM_OK;
+}
+
+crm_status crm_step(crm_ctx* c, int32_t n_steps) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (n_steps < 0) return fail(c, CRM_E_INVALID, "n_steps must be >= 0");
+  for (int32_t k = 0; k < n_steps; ++k) {
+    st = one_step(c);
+    if (st != CRM_OK) return st;
+  }
+  return CRM_OK;
+}
+
+crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (nb != c->nb) return fail(c, CRM_E_INVALID, "nb differs from crm_init");
+  if ((!force || !torque) && nb > 0) return fail(c, CRM_E_INVALID, "force and torque are required");
+  if (!c->stepped) return fail(c, CRM_E_STATE, "no step taken yet");
+  if (nb == 0) return CRM_OK;
+  std::vector<double> h((size_t)(6 * nb));
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_forces, sizeof(double) * 6 * (size_t)nb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < nb; ++b)
+    for (int a = 0; a < 3; ++a) {
+      force[3 * b + a] = h[6 * b + a];
+      torque[3 * b + a] = h[6 * b + 3 + a];
+    }
+  for (double v : h)
+    if (!std::isfinite(v)) return fail(c, CRM_E_NONFINITE, "non-finite body force or torque");
+  return CRM_OK;
+}
+
+crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, float* rho) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  hipStream_t s = c->stream;
+  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->m_a, s));
+  if (c->working_valid) {
+    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+    HIPCHK(c, crm::scatter_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  }
+  const size_t n = (size_t)c->n_total;
+  std::vector<float4> ha(n), hb(n), hc(n), hd(n);
+  HIPCHK(c, hipMemcpyAsync(ha.data(), c->m_a, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hb.data(), c->m_b, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hc.data(), c->m_c, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hd.data(), c->m_d, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i) {
+    if (pos) { pos[3 * i] = ha[i].x; pos[3 * i + 1] = ha[i].y; pos[3 * i + 2] = ha[i].z; }
+    if (rho) rho[i] = ha[i].w;
+    if (vel) { vel[3 * i] = hb[i].x; vel[3 * i + 1] = hb[i].y; vel[3 * i + 2] = hb[i].z; }
+    if (sigma) {
+      sigma[6 * i] = hc[i].x; sigma[6 * i + 1] = hc[i].y; sigma[6 * i + 2] = hc[i].z;
+      sigma[6 * i + 3] = hc[i].w; sigma[6 * i + 4] = hd[i].x; sigma[6 * i + 5] = hd[i].y;
+    }
+  }
+  return CRM_OK;
+}
+
+crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const float* sigma, const float* rho) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  const int64_t n = c->n_soil;
+  if (pos)
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(pos[i])) return fail(c, CRM_E_INVALID, "non-finite position");
+  hipStream_t s = c->stream;
+  if (c->working_valid)
+    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  std::vector<float4> ha((size_t)n), hb((size_t)n), hc((size_t)n), hd((size_t)n);
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(ha.data(), c->m_a, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hb.data(), c->m_b, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hc.data(), c->m_c, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hd.data(), c->m_d, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (pos) { ha[i].x = (float)pos[3 * i]; ha[i].y = (float)pos[3 * i + 1]; ha[i].z = (float)pos[3 * i + 2]; }
+    if (rho) ha[i].w = rho[i];
+    if (vel) { hb[i].x = vel[3 * i]; hb[i].y = vel[3 * i + 1]; hb[i].z = vel[3 * i + 2]; }
+    if (sigma) {
+      hc[i] = make_float4(sigma[6 * i], sigma[6 * i + 1], sigma[6 * i + 2], sigma[6 * i + 3]);
+      hd[i].x = sigma[6 * i + 4];
+      hd[i].y = sigma[6 * i + 5];
+    }
+  }
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->m_a, ha.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->m_b, hb.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->m_c, hc.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->m_d, hd.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  c->working_valid = false;
+  c->force_rebuild = true;
+  return CRM_OK;
+}
+
+crm_status crm_get_counts(crm_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(c, CRM_E_INVALID, "NULL argument");
+  out[0] = c->n_total;
+  out[1] = c->n_soil;
+  out[2] = c->n_proc;
+  out[3] = c->n_frows;
+  out[4] = c->n_mrows;
+  out[5] = c->ent_f + c->ent_m;
+  out[6] = c->cap;
+  out[7] = c->step;
+  out[8] = c->M;
+  out[9] = c->rebuilds;
+  return CRM_OK;
+}
+
+crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_start, int32_t* rows, int64_t* off,
+                            int32_t* nbr, int64_t cap, uint8_t* flags) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (c->rebuilds == 0 || !c->working_valid) return fail(c, CRM_E_STATE, "no valid rebuild to export");
+  hipStream_t s = c->stream;
+  const int64_t np = c->n_proc;
+  std::vector<int32_t> sid((size_t)np);
+  HIPCHK(c, hipMemcpyAsync(sid.data(), c->slot_id, sizeof(int32_t) * (size_t)np, hipMemcpyDeviceToHost, s));
+  if (cell_start)
+    HIPCHK(c, hipMemcpyAsync(cell_start, c->cell_start, sizeof(uint32_t) * (size_t)(c->M + 1), hipMemcpyDeviceToHost, s));
+  if (flags) {
+    if (c->ad_on)
+      HIPCHK(c, hipMemcpyAsync(flags, c->flags, (size_t)c->n_total, hipMemcpyDeviceToHost, s));
+    else
+      std::memset(flags, 2, (size_t)c->n_total);
+  }
+  const bool want_lists = rows || off || nbr;
+  const int64_t nw = (np + crm::kWave - 1) / crm::kWave;
+  std::vector<int32_t> fr, mr;
+  std::vector<uint32_t> cf, cm, ef, em;
+  std::vector<uint64_t> wf, wm;
+  if (want_lists) {
+    fr.resize((size_t)c->n_frows); mr.resize((size_t)c->n_mrows);
+    cf.resize((size_t)c->n_frows); cm.resize((size_t)c->n_mrows);
+    wf.resize((size_t)nw + 1); wm.resize((size_t)nw + 1);
+    ef.resize((size_t)c->ent_f); em.resize((size_t)c->ent_m);
+    auto cp = [&](void* d, const void* src, size_t bytes) {
+      return bytes ? hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+    };
+    HIPCHK(c, cp(fr.data(), c->frows, 4 * fr.size()));
+    HIPCHK(c, cp(mr.data(), c->mrows, 4 * mr.size()));
+    HIPCHK(c, cp(cf.data(), c->cnt_f, 4 * cf.size()));
+    HIPCHK(c, cp(cm.data(), c->cnt_m, 4 * cm.size()));
+    HIPCHK(c, cp(wf.data(), c->woff_f, 8 * wf.size()));
+    HIPCHK(c, cp(wm.data(), c->woff_m, 8 * wm.size()));
+    HIPCHK(c, cp(ef.data(), c->nbr_f, 4 * ef.size()));
+    HIPCHK(c, cp(em.data(), c->nbr_m, 4 * em.size()));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (sorted_ids) std::memcpy(sorted_ids, sid.data(), sizeof(int32_t) * (size_t)np);
+  if (want_lists) {
+    int64_t tot = 0;
+    for (uint32_t v : cf) tot += v;
+    for (uint32_t v : cm) tot += v;
+    if (nbr && tot > cap) return fail(c, CRM_E_INVALID, "cap too small for the neighbour entries");
+    int64_t row = 0, e = 0;
+    auto emit = [&](const std::vector<int32_t>& rr, const std::vector<uint32_t>& cc, const std::vector<uint64_t>& ww,
+                    const std::vector<uint32_t>& ee) {
+      for (size_t r = 0; r < rr.size(); ++r, ++row) {
+        if (rows) rows[row] = sid[(size_t)rr[r]];
+        if (off) off[row] = e;
+        const uint64_t base = ww[r / crm::kWave] + (r % crm::kWave);
+        for (uint32_t k = 0; k < cc[r]; ++k, ++e)
+          if (nbr) nbr[e] = sid[ee[base + (uint64_t)k * crm::kWave]];
+      }
+    };
+    emit(fr, cf, wf, ef);
+    emit(mr, cm, wm, em);
+    if (off) off[row] = e;
+  }
+  return CRM_OK;
+}
+
+crm_status crm_set_profiling(crm_ctx* c, int32_t enable) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (enable) {
+    c->prof_marks.clear();
+    c->ev_used = 0;
+  }
+  c->prof = enable != 0;
+  return CRM_OK;
+}
+
+crm_status crm_get_profile(crm_ctx* c, double* out) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (!out) return fail(c, CRM_E_INVALID, "out is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 16; ++k) out[k] = 0.0;
+  for (auto& m : c->prof_marks) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+    out[2 * m.first] += 1.0;
+    out[2 * m.first + 1] += (double)ms;
+  }
+  auto pairs = [&](const uint32_t* cnt, int64_t n, double& dst) -> crm_status {
+    std::vector<uint32_t> h((size_t)n);
+    if (n > 0) HIPCHK(c, hipMemcpy(h.data(), cnt, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost));
+    double t = 0.0;
+    for (uint32_t v : h) t += (double)v;
+    dst = t;
+    return CRM_OK;
+  };
+  if (c->working_valid) {
+    st = pairs(c->cnt_f, c->n_frows, out[14]);
+    if (st != CRM_OK) return st;
+    st = pairs(c->cnt_m, c->n_mrows, out[15]);
+    if (st != CRM_OK) return st;
+  }
+  return CRM_OK;
+}
+
+void crm_destroy(crm_ctx* c) { release(c); }
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations shared by the HIP kernels (crm_kernels.hip) and the
+// host side of the C ABI (crm_api.cpp). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace crm {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kWave = 64;        // gfx950 wavefront width
+constexpr int kMaxBodies = 64;   // bodies per context
+
+// Particle record of the working set: 64 bytes, one cache-line half, so that a
+// neighbour gather is four 16-byte loads from one contiguous segment.
+//   a = (x, y, z, rho)  b = (vx, vy, vz, aux)  c = (sxx, syy, szz, sxy)
+//   d = (sxz, syz, -, -)
+// aux (bit pattern of b.w) = kind | body << 2.
+struct alignas(16) Rec {
+  float4 a, b, c, d;
+};
+
+enum : uint32_t { kSoilActive = 0u, kSoilExtended = 1u, kMarker = 2u };
+
+// Rigid-body state on the device (FP64), frozen during a step.
+struct Body {
+  double X[3];    // origin, world
+  double R[9];    // rotation body -> world, row-major
+  double V[3];    // linear velocity
+  double W[3];    // angular velocity (world)
+  double A[3];    // linear acceleration
+  double Al[3];   // angular acceleration
+  double half[3]; // active box half extents (all zero: none)
+  int32_t has_acc;
+  int32_t has_box;
+};
+
+// Cell grid of the linked list (cell size 2h) and the FP64 neighbour radius.
+struct Grid {
+  double lo[3];
+  double inv;     // 1 / (2h), rounded once
+  double R2;      // (2h)^2
+  double ext;     // 2h, grow of the active boxes
+  int32_t dims[3];
+  int32_t pad;
+};
+
+// FP32 constants of the stage kernels.
+struct Phys {
+  float inv_h;
+  float kw;       // 1 / (pi h^3): W = kw * w(q)
+  float kf;       // 1 / (pi h^5): grad W = kf * f(q) * (x_i - x_j)
+  float dt, half_dt;
+  float gx, gy, gz;
+  float m;        // particle mass rho0 dx^3
+  float rho0;
+  float two_G;    // 2G
+  float iso;      // bulk_coeff K - 2G/3 (coefficient of tr(D) I)
+  float av_coef;  // gamma_a h c_s m
+  float xi2;      // (xi_over_h h)^2
+  int32_t av_mode;
+  float mu_s, mu_2, I0, grain_d, cohesion, p_cri, inv_Gdt;
+};
+
+// ---- launchers (all asynchronous on `s`) ----------------------------------
+
+// Exclusive scan of n values into out[0..n] (out[n] = total). tmp must hold
+// scan_tmp_elems(n) elements of TOut.
+size_t scan_tmp_elems(int64_t n);
+hipError_t scan_u32_to_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
+hipError_t scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, hipStream_t s);
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// dst[0] = *a, dst[1] = *b (device-side totals gathered for one read-back).
+hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStream_t s);
+
+// Marker world positions x = X + R l (FP64, rounded to FP32) into master plane 0.
+hipError_t place_markers_master(const float4* local, int64_t n_markers, int64_t n_soil,
+                                const Body* bodies, float4* m_a, hipStream_t s);
+
+// Activity flags of all particles (Sec. 4.2 item 2).
+hipError_t activity_flags(const float4* m_a, int64_t n, const Body* bodies, int32_t nb,
+                          Grid g, uint8_t* flags, hipStream_t s);
+
+// Order-preserving compaction of ids with flags != 0 (block counts, scan, write).
+size_t compact_tmp_elems(int64_t n);
+hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst,
+                         uint32_t* tmp, hipStream_t s);
+
+// Cell hash with per-cell arrival counts (counting sort, part 1).
+hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a, Grid g,
+                      uint32_t* key, uint32_t* rank, uint32_t* cell_cnt, hipStream_t s);
+// Place into cell order (part 2), then rank by id inside each cell and gather
+// the master state into the sorted working set (part 3).
+hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cell_start,
+                        int64_t n_proc, uint32_t* tmp, hipStream_t s);
+hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* proc_ids,
+                         const uint32_t* cell_start, int64_t n_proc, int64_t n_soil,
+                         const uint8_t* flags, const float4* m_a, const float4* m_b,
+                         const float4* m_c, const float4* m_d, Rec* A, Rec* B, float4* pos4,
+                         int32_t* slot_id, uint32_t* skey, hipStream_t s);
+
+// Row lists (slots owning a neighbour list): active soil rows and marker rows.
+hipError_t compact_kind(const float4* pos4, int64_t n_proc, uint32_t kind, int32_t* rows,
+                        uint64_t* count_dst, uint32_t* tmp, hipStream_t s);
+
+// Neighbour lists (Alg. 1) in wave-interleaved CSR: row r's k-th entry is at
+// woff[r / 64] + 64 k + r % 64. Count pass writes cnt[r] and wave_len[r / 64]
+// (64 * max count of the wave); fill pass writes the entries.
+hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev,
+                     const float4* pos4, const uint32_t* skey, const uint32_t* cell_start, Grid g,
+                     uint32_t* cnt, uint32_t* wave_len, hipStream_t s);
+hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const uint32_t* skey,
+                    const uint32_t* cell_start, Grid g, const uint64_t* woff, uint32_t* nbr,
+                    hipStream_t s);
+
+// Per step: marker positions of the processed markers into A and B.
+hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const int32_t* slot_id,
+                                 int64_t n_soil, const float4* local, const Body* bodies, Rec* A,
+                                 Rec* B, hipStream_t s);
+
+// BCE extrapolation at state S (Sec. 2.5.1); with partials != nullptr also the
+// marker accelerations and per-block body force/torque partial sums
+// (partials[block * nb + b][6], FP64).
+hipError_t bce(Rec* S, const int32_t* mrows, int64_t n_mrows, const uint32_t* cnt,
+               const uint64_t* woff, const uint32_t* nbr, const Body* bodies, int32_t nb, Phys P,
+               double* partials, hipStream_t s);
+int64_t bce_blocks(int64_t n_mrows);
+hipError_t body_reduce(const double* partials, int64_t nblocks, int32_t nb, double* forces,
+                       hipStream_t s);
+
+// Fluid RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
+// mapping (Sec. 2.4).
+hipError_t fluid_stage1(const Rec* A, Rec* B, const int32_t* frows, int64_t n_frows,
+                        const uint32_t* cnt, const uint64_t* woff, const uint32_t* nbr, Phys P,
+                        hipStream_t s);
+hipError_t fluid_stage2(const Rec* B, Rec* A, const int32_t* frows, int64_t n_frows,
+                        const uint32_t* cnt, const uint64_t* woff, const uint32_t* nbr, Phys P,
+                        hipStream_t s);
+
+// Scatter working records back to the master planes.
+hipError_t scatter_rows(const Rec* src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
+                        float4* m_a, float4* m_b, float4* m_c, float4* m_d, hipStream_t s);
+
+}  // namespace crm

@@ -1,0 +1,356 @@
+"""Parity of the HIP path (libcrm through its C ABI) with the FP64 oracle.
+
+Bit-exact: cell-sorted order, cellStart/cellEnd, neighbour lists, activity
+flags, untouched frozen particles. Floating point: normwise relative error per
+field (max |gpu - oracle| / max |oracle|) <= 1e-5 after one step and <= 1e-3
+after 100 steps; body forces to the same bars relative to the largest force
+component.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from oracle import oracle as O
+from paper_2507_05643_amd import scenes
+from tests.parity_util import csr_rows, fields_report, normwise, world_positions
+
+pytestmark = pytest.mark.gpu
+
+TOL_1 = 1e-5
+TOL_100 = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def crm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_05643_amd import crm as C
+    return C
+
+
+def _sim(crm, sc, **kw):
+    return crm.Simulation(sc, **kw)
+
+
+def test_sort_and_cells_bit_exact(crm):
+    for sc in (scenes.column(seed=0), scenes.plate_patch(seed=1, nx=20, ny=17, nz=9)):
+        say("case", sc.name, sc.n_total)
+        sim = _sim(crm, sc)
+        sim.step(1)
+        ex = sim.export()
+        x = world_positions(sc)
+        sid, skey, cs, ce = O.sort_cells(sc.params, x)
+        assert np.array_equal(ex["sorted_ids"], sid)
+        M = cs.size
+        assert ex["cell_start"].size == M + 1
+        assert np.array_equal(ex["cell_start"][:M].astype(np.int64), cs)
+        assert np.array_equal(ex["cell_start"][1:].astype(np.int64), ce)
+        sim.close()
+
+
+def test_neighbour_lists_bit_exact(crm):
+    for sc in (scenes.column(seed=2), scenes.wheel_bin(seed=0, nx=40, ny=24, nz=10)):
+        say("case", sc.name, sc.n_total)
+        sim = _sim(crm, sc)
+        sim.step(1)
+        ex = sim.export()
+        x = world_positions(sc)
+        off, nbr = O.neighbors(sc.params, x, mode="cells")
+        ref = csr_rows(off, nbr)
+        got = csr_rows(ex["off"], ex["nbr"], ex["rows"])
+        # every soil particle and every marker owns a list (no active domains)
+        assert sorted(got) == list(range(sc.n_total))
+        for i in range(sc.n_total):
+            assert np.array_equal(got[i], ref[i]), i
+        c = sim.counts()
+        assert c["entries"] == nbr.size
+        assert c["capacity"] == int(np.ceil(1.2 * sc.n_total))
+        sim.close()
+
+
+def _run_pair(crm, sc, steps, nbr_mode="cells"):
+    sim = _sim(crm, sc)
+    orc = Oracle(sc, nbr_mode=nbr_mode)
+    sim.step(steps)
+    orc.step(steps)
+    return sim, orc
+
+
+def test_one_step_parity_column(crm):
+    sc = scenes.column(seed=0)
+    sim, orc = _run_pair(crm, sc, 1)
+    g, r = sim.state(), orc.state()
+    rep = fields_report(g, r, sc.n_soil)
+    say("1 step column", rep)
+    for k, v in rep.items():
+        assert v <= TOL_1, (k, v)
+    # markers: stage-2 extrapolated velocity and stress
+    mk = slice(sc.n_soil, sc.n_total)
+    assert normwise(g["vel"][mk], r["vel"][mk]) <= TOL_1
+    assert normwise(g["sigma"][mk], r["sigma"][mk]) <= TOL_1
+    sim.close()
+
+
+def test_hundred_steps_parity_column(crm):
+    sc = scenes.column(seed=0)
+    sim, orc = _run_pair(crm, sc, 100)
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("100 steps column", rep)
+    for k, v in rep.items():
+        assert v <= TOL_100, (k, v)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    say("forces", F, Fr)
+    assert normwise(F, Fr) <= TOL_100
+    sim.close()
+
+
+def test_persistent_lists_parity(crm):
+    sc = scenes.column(seed=5, ps_freq=10)
+    sim, orc = _run_pair(crm, sc, 25)
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("ps_freq 10, 25 steps", rep)
+    for k, v in rep.items():
+        assert v <= TOL_100, (k, v)
+    assert sim.counts()["rebuilds"] == 3
+    sim.close()
+
+
+def test_plate_forces_parity(crm):
+    sc = scenes.plate_patch(seed=0, nx=20, ny=20, nz=8)
+    pl = sc.bodies[1]
+    pl.pos = (pl.pos[0], pl.pos[1], 0.07)          # start in contact with the soil
+    sim, orc = _run_pair(crm, sc, 1)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    say("plate 1 step", F, Fr)
+    assert np.abs(Fr).max() > 0
+    assert normwise(F, Fr) <= TOL_1
+    assert normwise(T, Tr) <= 10 * TOL_1
+    sim.step(19)
+    orc.step(19)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("plate 20 steps", rep, F, Fr)
+    for k, v in rep.items():
+        assert v <= TOL_100, (k, v)
+    assert normwise(F, Fr) <= TOL_100
+    sim.close()
+
+
+def test_wheel_small_parity(crm):
+    sc = scenes.wheel_bin(seed=3, nx=60, ny=36, nz=12, ps_freq=10)
+    wb = sc.bodies[1]
+    wb.pos = (wb.pos[0], wb.pos[1], wb.pos[2] - 0.012)  # grousers into the soil
+    sim, orc = _run_pair(crm, sc, 1)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("wheel 1 step", rep, F[1], Fr[1], T[1], Tr[1])
+    for k, v in rep.items():
+        assert v <= TOL_1, (k, v)
+    assert normwise(F, Fr) <= TOL_1
+    sim.step(29)
+    orc.step(29)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("wheel 30 steps", rep, F[1], Fr[1])
+    for k, v in rep.items():
+        assert v <= TOL_100, (k, v)
+    assert normwise(F[1], Fr[1]) <= TOL_100
+    assert normwise(T[1], Tr[1]) <= TOL_100
+    sim.close()
+
+
+def _strip():
+    return scenes.strip(seed=1, length=3.0, width=1.2, depth=0.2, dx=0.05, half=0.3, wheelbase=1.2,
+                        track=0.6, t_delay=-1.0, ps_freq=2)
+
+
+def test_active_domains_parity(crm):
+    sc = _strip()
+    sim, orc = _run_pair(crm, sc, 1)
+    ex = sim.export()
+    fl = orc.flags()
+    assert np.array_equal(ex["flags"], fl)
+    proc, off, nbr = orc.lists()
+    assert np.array_equal(np.sort(ex["sorted_ids"]), proc)
+    c = sim.counts()
+    assert c["n_proc"] == proc.size and c["capacity"] == int(np.ceil(1.2 * proc.size))
+    # lists of active soil and of processed markers
+    ref = csr_rows(off, nbr, proc)
+    got = csr_rows(ex["off"], ex["nbr"], ex["rows"])
+    owners = [i for i in proc if (i < sc.n_soil and fl[i] == 2) or i >= sc.n_soil]
+    assert sorted(got) == sorted(owners)
+    for i in owners:
+        assert np.array_equal(got[i], ref[i]), i
+    sim.step(4)
+    orc.step(4)
+    g, r = sim.state(), orc.state()
+    fl = orc.flags()[: sc.n_soil]
+    frozen = fl != 2
+    s0 = sc.pos.astype(np.float64)
+    assert np.array_equal(g["pos"][: sc.n_soil][frozen], s0[frozen])
+    assert np.all(g["vel"][: sc.n_soil][frozen] == 0)
+    act = ~frozen
+    for k in ("pos", "vel", "sigma", "rho"):
+        v = normwise(g[k][: sc.n_soil][act], r[k][: sc.n_soil][act])
+        say("AD field", k, v)
+        assert v <= TOL_100
+    sim.close()
+
+
+def test_covering_box_equals_plain_step(crm):
+    sc = scenes.column(seed=3, n=10, ps_freq=3)
+    sc.bodies.append(scenes.Body(markers=np.zeros((0, 3), dtype=np.float32), active_half=(10.0, 10.0, 10.0)))
+    p_ad = dict(sc.params, active_domains=1, t_delay=-1.0)
+    a = _sim(crm, sc, params=p_ad)
+    b = _sim(crm, sc)
+    a.step(7)
+    b.step(7)
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    Fa, _ = a.forces()
+    Fb, _ = b.forces()
+    assert np.array_equal(Fa, Fb)
+    a.close()
+    b.close()
+
+
+def test_momentum_conservation_gpu(crm):
+    sc = scenes.cluster(seed=7, n=8, vel_scale=0.05, sigma_scale=2.0e3)
+    sc.params.update(av_mode=1, av_gamma=0.5, ps_freq=5, cohesion=5e3)
+    sim = _sim(crm, sc)
+    m = sc.params["rho0"] * sc.params["dx"] ** 3
+    v0 = sim.state()["vel"].astype(np.float64)
+    p0 = m * v0.sum(axis=0)
+    scale = m * np.abs(v0).sum()
+    sim.step(40)
+    v1 = sim.state()["vel"].astype(np.float64)
+    drift = np.abs(m * v1.sum(axis=0) - p0).max()
+    say("momentum drift / scale", drift / scale)
+    assert drift <= 1e-6 * scale
+    sim.close()
+
+
+def test_free_fall_gpu(crm):
+    sc = scenes.cluster(seed=1, n=5, vel_scale=0.0, sigma_scale=0.0, gravity=(0.0, 0.0, -9.81))
+    u0 = np.array([0.2, -0.1, 0.05], dtype=np.float32)
+    sc.vel = np.tile(u0, (sc.n_soil, 1))
+    sim = _sim(crm, sc)
+    n = 40
+    sim.step(n)
+    t = n * sc.params["dt"]
+    g = np.array([0.0, 0.0, -9.81])
+    st = sim.state()
+    x_ref = sc.pos.astype(np.float64) + u0.astype(np.float64) * t + 0.5 * g * t * t
+    assert np.abs(st["pos"] - x_ref).max() < 4 * n * np.finfo(np.float32).eps * 0.1
+    assert np.abs(st["vel"] - (u0 + g * t)).max() < 1e-6
+    sim.close()
+
+
+def test_deterministic(crm):
+    sc = scenes.plate_patch(seed=4, nx=16, ny=16, nz=8)
+    runs = []
+    for _ in range(2):
+        sim = _sim(crm, sc)
+        sim.step(12)
+        runs.append((sim.state(), sim.forces()))
+        sim.close()
+    (s1, f1), (s2, f2) = runs
+    for k in s1:
+        assert np.array_equal(s1[k], s2[k])
+    assert np.array_equal(f1[0], f2[0]) and np.array_equal(f1[1], f2[1])
+
+
+def test_set_state_roundtrip_and_errors(crm):
+    sc = scenes.column(seed=1, n=6)
+    sim = _sim(crm, sc)
+    with pytest.raises(crm.CrmError) as e:
+        sim.forces()
+    assert e.value.status == -4                       # no step yet
+    rng = np.random.default_rng(0)
+    vel = rng.normal(0, 0.01, size=(sc.n_soil, 3)).astype(np.float32)
+    sim.set_state(vel=vel)
+    st = sim.state()
+    assert np.array_equal(st["vel"][: sc.n_soil], vel)
+    with pytest.raises(crm.CrmError) as e:
+        crm.crm_set_bodies(sim.ctx, np.zeros((3, 3)), np.tile([1.0, 0, 0, 0], (3, 1)))
+    assert e.value.status == -1
+    with pytest.raises(crm.CrmError):
+        crm.crm_step(sim.ctx, -1)
+    sim.step(2)
+    F, T = sim.forces()
+    assert np.all(np.isfinite(F))
+    sim.close()
+
+
+def test_edge_sizes(crm):
+    # a single soil particle, no bodies: free fall
+    sc = scenes.cluster(seed=0, n=1, vel_scale=0.0, sigma_scale=0.0, gravity=(0.0, 0.0, -9.81))
+    sim = _sim(crm, sc)
+    sim.step(3)
+    st = sim.state()
+    assert abs(st["vel"][0, 2] + 9.81 * 3 * sc.params["dt"]) < 1e-6
+    sim.close()
+    # markers only (no soil): forces are zero
+    sc = scenes.column(seed=0, n=4)
+    sc.pos = np.zeros((0, 3), dtype=np.float32)
+    sim = _sim(crm, sc)
+    sim.step(2)
+    F, T = sim.forces()
+    assert np.all(F == 0) and np.all(T == 0)
+    sim.close()
+    # ragged size: 7 x 5 x 3 soil block, not a multiple of 64
+    sc = scenes.column(seed=2, n=7)
+    sc.pos = sc.pos[: 7 * 5 * 3]
+    sim, orc = _run_pair(crm, sc, 3)
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    for k, v in rep.items():
+        assert v <= TOL_1 * 10, (k, v)
+    sim.close()
+
+
+@pytest.mark.skipif(os.environ.get("CRM_SKIP_FULL") == "1", reason="full-size case disabled")
+def test_full_size_wheel_bin_one_step(crm):
+    """The benchmark workload (960k soil particles + container + wheel) at full
+    size, in the benchmark's launch configuration: one step compared field by
+    field with the oracle, and a sample of neighbour lists compared bit-exactly."""
+    sc = scenes.wheel_bin(seed=0)
+    say("full wheel bin", sc.n_total)
+    sim = _sim(crm, sc)
+    sim.step(1)
+    ex = sim.export()
+    say("gpu step done")
+    orc = Oracle(sc, nbr_mode="cells")
+    orc.step(1)
+    say("oracle step done, threads", Oracle.threads())
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    say("full wheel 1 step", rep)
+    for k, v in rep.items():
+        assert v <= TOL_1, (k, v)
+    F, T = sim.forces()
+    Fr, Tr = orc.forces()
+    say("forces", F, Fr)
+    assert normwise(F, Fr) <= TOL_1
+    proc, off, nbr = orc.lists()
+    got_rows = ex["rows"]
+    rng = np.random.default_rng(0)
+    pick = rng.choice(got_rows.size, 4000, replace=False)
+    for r in pick:
+        i = int(got_rows[r])
+        a = np.sort(ex["nbr"][ex["off"][r]:ex["off"][r + 1]])
+        assert np.array_equal(a, nbr[off[i]:off[i + 1]]), i
+    sim.close()
