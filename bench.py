@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--ps-freq", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB once (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build",
@@ -147,6 +150,13 @@ def main():
     print(json.dumps(dict(profile_ms_per_launch=breakdown, counts=cnt, wheel_force=F[1].tolist(),
                           wheel_torque=T[1].tolist(), wheel_z=float(drv.x[2]))), file=sys.stderr, flush=True)
     sim.close()
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

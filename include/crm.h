@@ -150,7 +150,8 @@ crm_status crm_set_state(crm_ctx* ctx, const double* pos, const float* vel, cons
 
 /* Sizes: out[0] n_total, out[1] n_soil, out[2] processed particles N_{a+e} of
  * the last rebuild, out[3] active soil rows, out[4] processed marker rows,
- * out[5] stored neighbour entries (valid, soil rows + marker rows), out[6]
+ * out[5] stored neighbour slots (soil rows + marker rows, including the
+ * padding of each wave's block to its longest list), out[6]
  * working-array capacity, out[7] steps taken, out[8] number of cells M,
  * out[9] rebuilds done. out: 10 int64. */
 crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
