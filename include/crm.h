@@ -161,7 +161,10 @@ crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
  * cell_start: M + 1 values, cell_start[c] = first sorted position of cell c
  * (cellEnd[c] = cell_start[c + 1]); rows: ids of the particles that own a list
  * (active soil, then processed markers), off: rows + 1 offsets, nbr: entries
- * as particle ids (order within a row unspecified), cap: capacity of nbr.
+ * as particle ids (order within a row unspecified), cap: capacity of nbr. A
+ * soil row lists every particle within 2h (itself included); a marker row
+ * lists only the soil particles within 2h, the only ones its extrapolation
+ * and force sums use.
  * flags: n_total activity flags (0 inactive, 1 extended, 2 active).
  * Any pointer may be NULL. Errors: CRM_E_INVALID if cap is too small,
  * CRM_E_STATE before the first rebuild. Synchronises. */

@@ -266,11 +266,11 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
   const int64_t nw = (n_proc + crm::kWave - 1) / crm::kWave;
-  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->skey, c->cell_start, c->grid, c->cnt_f,
-                           c->wlen_f, s));
+  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->skey, c->cell_start, c->grid, false,
+                           c->cnt_f, c->wlen_f, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->wlen_f, c->woff_f, nw, c->wtmp, s));
-  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->skey, c->cell_start, c->grid, c->cnt_m,
-                           c->wlen_m, s));
+  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->skey, c->cell_start, c->grid, true,
+                           c->cnt_m, c->wlen_m, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->wlen_m, c->woff_m, nw, c->wtmp, s));
   HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->woff_f + nw, c->woff_m + nw, s));
   crm_status st = read_counts(c);
@@ -284,8 +284,10 @@ crm_status rebuild(crm_ctx* c) {
   if (st != CRM_OK) return st;
   c->ent_f = ef;
   c->ent_m = em;
-  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->skey, c->cell_start, c->grid, c->woff_f, c->nbr_f, s));
-  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->skey, c->cell_start, c->grid, c->woff_m, c->nbr_m, s));
+  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->skey, c->cell_start, c->grid, false, c->woff_f,
+                          c->nbr_f, s));
+  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->skey, c->cell_start, c->grid, true, c->woff_m,
+                          c->nbr_m, s));
   const int64_t nbk = crm::bce_blocks(c->n_mrows);
   if (nbk * c->nb > c->partials_cap) {
     dfree(c, c->partials);

@@ -108,13 +108,14 @@ hipError_t compact_kind(const float4* pos4, int64_t n_proc, uint32_t kind, int32
 
 // Neighbour lists (Alg. 1) in wave-interleaved CSR: row r's k-th entry is at
 // woff[r / 64] + 64 k + r % 64. Count pass writes cnt[r] and wave_len[r / 64]
-// (64 * max count of the wave); fill pass writes the entries.
+// (64 * max count of the wave); fill pass writes the entries. soil_only keeps
+// only soil neighbours (marker rows).
 hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev,
                      const float4* pos4, const uint32_t* skey, const uint32_t* cell_start, Grid g,
-                     uint32_t* cnt, uint32_t* wave_len, hipStream_t s);
+                     bool soil_only, uint32_t* cnt, uint32_t* wave_len, hipStream_t s);
 hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const uint32_t* skey,
-                    const uint32_t* cell_start, Grid g, const uint64_t* woff, uint32_t* nbr,
-                    hipStream_t s);
+                    const uint32_t* cell_start, Grid g, bool soil_only, const uint64_t* woff,
+                    uint32_t* nbr, hipStream_t s);
 
 // Per step: marker positions of the processed markers into A and B.
 hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const int32_t* slot_id,

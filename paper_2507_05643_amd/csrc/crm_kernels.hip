@@ -13,6 +13,19 @@ __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ inline int wave_id() { return threadIdx.x / kWave; }
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own L2.
+// Neighbouring particles are neighbours in the cell-sorted order, so give
+// every XCD one contiguous range of logical blocks: XCD x gets
+// [x q + min(x, r), ...) of length q + (x < r), with q, r = nblocks / 8, % 8.
+// This is a bijection of [0, nblocks).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb / kXcds, r = nb % kXcds;
+  const int64_t x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <typename T>
 __device__ inline T wave_incl_scan(T x) {
   const int lane = lane_id();
@@ -329,10 +342,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
 // cells x-1..x+1 of a (y, z) row are consecutive in the sorted order, so they
 // are scanned as one range [cellStart[c(x-1)], cellStart[c(x+1) + 1]).
 // Membership |x_i - x_j| < 2h is decided in FP64 on the FP32 positions.
-template <bool FILL>
+// With soil_only (marker rows) only soil candidates are kept: the BCE sums
+// of Sec. 2.5.1 run over soil particles, so marker-marker pairs are never used.
+template <bool FILL, typename Out>
 __device__ inline uint32_t scan_neighbours(float4 pi, uint32_t c, const float4* __restrict__ pos4,
-                                           const uint32_t* __restrict__ cs, const Grid& g,
-                                           uint32_t* __restrict__ out) {
+                                           const uint32_t* __restrict__ cs, const Grid& g, bool soil_only,
+                                           Out out) {
   const int X = g.dims[0], Y = g.dims[1], Z = g.dims[2];
   const int cx = (int)(c % (uint32_t)X);
   const uint32_t t = c / (uint32_t)X;
@@ -351,6 +366,7 @@ __device__ inline uint32_t scan_neighbours(float4 pi, uint32_t c, const float4* 
       const uint32_t b = cs[row + x0], e = cs[row + x1 + 1];
       for (uint32_t j = b; j < e; ++j) {
         float4 pj = pos4[j];
+        if (soil_only && (__float_as_uint(pj.w) & 3u) == kMarker) continue;
         if (dist2_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z) < g.R2) {
           if (FILL) out[(size_t)count * kWave] = j;
           ++count;
@@ -364,14 +380,14 @@ __device__ inline uint32_t scan_neighbours(float4 pi, uint32_t c, const float4* 
 __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict__ rows, int64_t rows_cap,
                                                       const uint64_t* __restrict__ n_rows_dev,
                                                       const float4* __restrict__ pos4, const uint32_t* __restrict__ skey,
-                                                      const uint32_t* __restrict__ cs, Grid g,
+                                                      const uint32_t* __restrict__ cs, Grid g, int soil_only,
                                                       uint32_t* __restrict__ cnt, uint32_t* __restrict__ wave_len) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = xcd_block() * kBlock + threadIdx.x;
   const int64_t nr = (int64_t)*n_rows_dev;
   uint32_t count = 0;
   if (r < nr) {
     const int32_t s = rows[r];
-    count = scan_neighbours<false>(pos4[s], skey[s], pos4, cs, g, nullptr);
+    count = scan_neighbours<false>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, (uint32_t*)nullptr);
   }
   if (r < rows_cap) cnt[r] = count;
   uint32_t mx = count;
@@ -383,15 +399,39 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict_
   if (lane_id() == 0 && r < rows_cap) wave_len[r / kWave] = mx * (uint32_t)kWave;
 }
 
+// Each wave gathers its entries in LDS and writes them out as whole 256-byte
+// rows (lanes finish their candidate loops at different times, so direct
+// stores would reach L2 as partial lines); a wave whose longest list exceeds
+// the LDS slots writes directly.
+constexpr int kFillSlots = 72;
+
 __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__ rows, int64_t n_rows,
                                                      const float4* __restrict__ pos4, const uint32_t* __restrict__ skey,
-                                                     const uint32_t* __restrict__ cs, Grid g,
+                                                     const uint32_t* __restrict__ cs, Grid g, int soil_only,
                                                      const uint64_t* __restrict__ woff, uint32_t* __restrict__ nbr) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= n_rows) return;
-  const int32_t s = rows[r];
-  uint32_t* out = nbr + woff[r / kWave] + (r % kWave);
-  scan_neighbours<true>(pos4[s], skey[s], pos4, cs, g, out);
+  __shared__ uint32_t buf[kBlock / kWave][kFillSlots * kWave];
+  const int64_t r = xcd_block() * kBlock + threadIdx.x;
+  const int64_t w = r / kWave;
+  const int lane = lane_id();
+  const bool wave_live = w * kWave < n_rows;
+  uint64_t base = 0;
+  uint32_t wmax = 0;
+  if (wave_live) {
+    base = woff[w];
+    wmax = (uint32_t)((woff[w + 1] - base) / kWave);
+  }
+  const bool use_lds = wmax <= (uint32_t)kFillSlots;
+  uint32_t* lbuf = &buf[wave_id()][lane];
+  if (r < n_rows) {
+    const int32_t s = rows[r];
+    if (use_lds)
+      scan_neighbours<true>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, lbuf);
+    else
+      scan_neighbours<true>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, nbr + base + lane);
+  }
+  __syncthreads();
+  if (wave_live && use_lds)
+    for (uint32_t k = 0; k < wmax; ++k) nbr[base + (uint64_t)k * kWave + lane] = lbuf[k * kWave];
 }
 
 // ------------------------------------------------------- SPH kernel (FP32) ---
@@ -447,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32
                                                 const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ woff,
                                                 const uint32_t* __restrict__ nbr, const Body* __restrict__ bodies,
                                                 int32_t nb, Phys P, double* __restrict__ partials) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = xcd_block() * kBlock + threadIdx.x;
   const bool valid = r < n;
   int body = -1;
   double fr[6] = {0, 0, 0, 0, 0, 0};
@@ -556,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32
     for (int b = 0; b < nb; ++b) {
       const int any = __syncthreads_or(body == b);
       if (!any) {
-        if (t < 6) partials[((int64_t)blockIdx.x * nb + b) * 6 + t] = 0.0;
+        if (t < 6) partials[(xcd_block() * nb + b) * 6 + t] = 0.0;
         continue;
       }
       for (int a = 0; a < 6; ++a) red[a][t] = (body == b) ? fr[a] : 0.0;
@@ -566,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32
           for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + o];
         __syncthreads();
       }
-      if (t < 6) partials[((int64_t)blockIdx.x * nb + b) * 6 + t] = red[t][0];
+      if (t < 6) partials[(xcd_block() * nb + b) * 6 + t] = red[t][0];
       __syncthreads();
     }
   }
@@ -705,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(const Rec* __restrict__
                                                          const uint32_t* __restrict__ cnt,
                                                          const uint64_t* __restrict__ woff,
                                                          const uint32_t* __restrict__ nbr, Phys P) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = xcd_block() * kBlock + threadIdx.x;
   if (r >= n) return;
   const int32_t s = rows[r];
   const Rec me = A[s];
@@ -725,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(const Rec* __restrict__
                                                          const uint32_t* __restrict__ cnt,
                                                          const uint64_t* __restrict__ woff,
                                                          const uint32_t* __restrict__ nbr, Phys P) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = xcd_block() * kBlock + threadIdx.x;
   if (r >= n) return;
   const int32_t s = rows[r];
   const Rec mid = B[s];
@@ -841,17 +881,18 @@ hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t
 }
 
 hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
-                     const uint32_t* skey, const uint32_t* cs, Grid g, uint32_t* cnt, uint32_t* wave_len,
-                     hipStream_t s) {
+                     const uint32_t* skey, const uint32_t* cs, Grid g, bool soil_only, uint32_t* cnt,
+                     uint32_t* wave_len, hipStream_t s) {
   if (rows_cap <= 0) return hipSuccess;
-  k_nbr_count<<<nblk(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, skey, cs, g, cnt, wave_len);
+  k_nbr_count<<<nblk(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, skey, cs, g, soil_only ? 1 : 0,
+                                                cnt, wave_len);
   return hipGetLastError();
 }
 
 hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const uint32_t* skey,
-                    const uint32_t* cs, Grid g, const uint64_t* woff, uint32_t* nbr, hipStream_t s) {
+                    const uint32_t* cs, Grid g, bool soil_only, const uint64_t* woff, uint32_t* nbr, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  k_nbr_fill<<<nblk(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, skey, cs, g, woff, nbr);
+  k_nbr_fill<<<nblk(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, skey, cs, g, soil_only ? 1 : 0, woff, nbr);
   return hipGetLastError();
 }
 
