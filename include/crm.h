@@ -55,6 +55,13 @@ typedef enum {
 /* Artificial viscosity variants of Sec. 2.2 (eqs. artificial_viscosity_*). */
 enum { CRM_AV_OFF = 0, CRM_AV_BILATERAL = 1, CRM_AV_UNILATERAL = 2 };
 
+/* Stored form of particle positions. CRM_POS_FP32: FP32 absolute coordinates.
+ * CRM_POS_CELL_OFFSET: the integer cell (cell size 2h, from domain_lo) and an
+ * FP32 offset inside it, so that motion stays resolved far from the origin
+ * (km-scale terrain, Sec. 5); offsets are advanced in FP64 and renormalised into
+ * their cell every stage. Requires fewer than 32768 cells along y and z. */
+enum { CRM_POS_FP32 = 0, CRM_POS_CELL_OFFSET = 1 };
+
 typedef struct crm_ctx crm_ctx;
 
 /* Allocator callbacks: return device memory of `bytes` bytes usable on
@@ -85,7 +92,7 @@ typedef struct {
   double t_delay;
   double grow_G, shrink_S;
   uint32_t shrink_interval;
-  uint32_t reserved;     /* must be 0 */
+  uint32_t pos_mode;     /* CRM_POS_FP32 or CRM_POS_CELL_OFFSET */
   double bulk_coeff;
 } crm_params;
 

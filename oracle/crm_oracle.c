@@ -54,6 +54,8 @@ typedef struct orc_params {
   int32_t shrink_interval;
   int32_t nbr_mode;       /* 0 brute force, 1 cell list */
   double bulk_coeff;      /* factor on the bulk term K tr(D) I (1 = continuum form) */
+  int32_t pos_mode;       /* stored position form of the kernel: 0 FP32 absolute,
+                             1 cell index + FP32 offset */
 } orc_params;
 
 /* ------------------------------------------------------------------ kernel */
@@ -95,14 +97,49 @@ static void sep(const orc_params* P, const double* xi, const double* xj, double 
 }
 
 /* ------------------------------------------------------- neighbour search */
-/* Neighbour predicate: |x_i - x_j| < 2h evaluated in FP64 on FP32-rounded
- * positions, as ((dx^2 + dy^2) + dz^2) < (2h)^2. The self pair is included
- * (Algorithm 1 scans the particle's own cell). */
+/* Integer decisions (cell of a particle, neighbour membership, activity) are
+ * taken on the position as the kernel stores it, so both sides decide the
+ * same way. pos_mode 0: FP32 absolute coordinates. pos_mode 1: integer cell
+ * coordinate c = floor((x - lo) / (2h)) and FP32 offset o = x - lo - c 2h (the
+ * physics of the oracle stays FP64 in both modes). */
+typedef struct { int64_t c[3]; double o[3]; } rep_t;
+
+static void to_rep(const orc_params* P, const double* x, rep_t* r) {
+  const double S = 2.0 * P->h, inv = 1.0 / S;
+  for (int a = 0; a < 3; ++a) {
+    if (P->pos_mode == 1) {
+      double t = x[a] - P->lo[a];
+      double c = floor(t * inv);
+      r->c[a] = (int64_t)c;
+      r->o[a] = (double)(float)(t - c * S);
+    } else {
+      r->c[a] = 0;
+      r->o[a] = (double)(float)x[a];
+    }
+  }
+}
+
+/* Absolute FP64 position of a stored representation. */
+static void rep_abs(const orc_params* P, const rep_t* r, double* x) {
+  const double S = 2.0 * P->h;
+  for (int a = 0; a < 3; ++a)
+    x[a] = (P->pos_mode == 1) ? (P->lo[a] + (double)r->c[a] * S) + r->o[a] : r->o[a];
+}
+
+/* Neighbour predicate: |x_i - x_j| < 2h in FP64 on the stored positions, as
+ * ((dx^2 + dy^2) + dz^2) < (2h)^2 with dx = (c_i - c_j) 2h + (o_i - o_j). The
+ * self pair is included (Algorithm 1 scans the particle's own cell). */
 static int is_nbr(const orc_params* P, const double* xi, const double* xj) {
+  rep_t a, b;
+  to_rep(P, xi, &a);
+  to_rep(P, xj, &b);
+  const double S = 2.0 * P->h;
   double d[3];
-  double a[3], b[3];
-  for (int k = 0; k < 3; ++k) { a[k] = (double)(float)xi[k]; b[k] = (double)(float)xj[k]; }
-  sep(P, a, b, d);
+  for (int k = 0; k < 3; ++k) d[k] = (double)(a.c[k] - b.c[k]) * S + (a.o[k] - b.o[k]);
+  if (P->pos_mode == 0) {
+    double aa[3] = {a.o[0], a.o[1], a.o[2]}, bb[3] = {b.o[0], b.o[1], b.o[2]};
+    sep(P, aa, bb, d);
+  }
   double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
   double R = 2.0 * P->h;
   return r2 < R * R;
@@ -142,17 +179,30 @@ static int64_t cell_coord(double x, double lo, double inv, int64_t dim) {
   return (int64_t)t;
 }
 
-/* Step 1 of Sec. 4.1: c = z * (Y * X) + y * X + x, from FP32-rounded positions. */
+/* Cell of a stored position, clamped to the grid: floor((x - lo) / (2h)) of the
+ * FP32 absolute position, or the stored cell index. */
+static void cell_of(const orc_params* P, const double* x, const int64_t dims[3], double inv, int64_t out[3]) {
+  rep_t r;
+  to_rep(P, x, &r);
+  for (int a = 0; a < 3; ++a) {
+    if (P->pos_mode == 1) {
+      int64_t c = r.c[a];
+      out[a] = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
+    } else {
+      out[a] = cell_coord(r.o[a], P->lo[a], inv, dims[a]);
+    }
+  }
+}
+
+/* Step 1 of Sec. 4.1: c = z * (Y * X) + y * X + x. */
 void orc_cell_keys(const orc_params* P, int64_t n_set, const int32_t* ids, const double* x,
                    int64_t* keys) {
   int64_t dims[3]; double inv;
   orc_grid_dims(P, dims, &inv);
   for (int64_t a = 0; a < n_set; ++a) {
-    const double* p = x + 3 * (int64_t)ids[a];
-    int64_t cx = cell_coord((double)(float)p[0], P->lo[0], inv, dims[0]);
-    int64_t cy = cell_coord((double)(float)p[1], P->lo[1], inv, dims[1]);
-    int64_t cz = cell_coord((double)(float)p[2], P->lo[2], inv, dims[2]);
-    keys[a] = cz * (dims[1] * dims[0]) + cy * dims[0] + cx;
+    int64_t c[3];
+    cell_of(P, x + 3 * (int64_t)ids[a], dims, inv, c);
+    keys[a] = c[2] * (dims[1] * dims[0]) + c[1] * dims[0] + c[0];
   }
 }
 
@@ -224,7 +274,7 @@ int64_t orc_neighbors_cells(const orc_params* P, int64_t n_set, const int32_t* i
     for (int64_t a = 0; a < n_set; ++a) {
       const double* xi = x + 3 * (int64_t)ids[a];
       int64_t c[3];
-      for (int k = 0; k < 3; ++k) c[k] = cell_coord((double)(float)xi[k], P->lo[k], inv, dims[k]);
+      cell_of(P, xi, dims, inv, c);
       int64_t count = 0;
       for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -479,10 +529,12 @@ static int rebuild(orc_ctx* c) {
   const orc_params* P = &c->P;
   int64_t n = c->n;
   if (P->active_domains && c->t > P->t_delay) {
-    /* activity is evaluated on FP32-rounded positions, as the neighbour test */
+    /* activity is evaluated on the stored positions, as the neighbour test */
     for (int64_t i = 0; i < n; ++i) {
-      double xf[3] = {(double)(float)c->x[3 * i], (double)(float)c->x[3 * i + 1],
-                      (double)(float)c->x[3 * i + 2]};
+      rep_t r;
+      double xf[3];
+      to_rep(P, c->x + 3 * i, &r);
+      rep_abs(P, &r, xf);
       c->flag[i] = (uint8_t)orc_flag_of(P, c->nb, c->B, xf);
     }
   } else {

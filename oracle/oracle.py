@@ -42,6 +42,7 @@ class OrcParams(C.Structure):
         ("shrink_interval", C.c_int32),
         ("nbr_mode", C.c_int32),
         ("bulk_coeff", C.c_double),
+        ("pos_mode", C.c_int32),
     ]
 
 
@@ -60,6 +61,7 @@ def make_params(p: dict, nbr_mode: int = 0, periodic=(0, 0, 0)) -> OrcParams:
     o.active_domains = int(p["active_domains"])
     o.shrink_interval = int(p["shrink_interval"])
     o.nbr_mode = int(nbr_mode)
+    o.pos_mode = int(p.get("pos_mode", 0))
     return o
 
 

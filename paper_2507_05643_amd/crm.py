@@ -16,7 +16,8 @@ import numpy as np
 import torch  # loads the HIP runtime that libcrm.so binds to
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcrm.so")
+# CRM_LIB_PATH selects another build of the same library (e.g. for A/B timing).
+LIB_PATH = os.environ.get("CRM_LIB_PATH") or os.path.join(HERE, "libcrm.so")
 
 CRM_ABI_VERSION = 1
 STATUS = {0: "CRM_OK", -1: "CRM_E_INVALID", -2: "CRM_E_NOMEM", -3: "CRM_E_DEVICE",
@@ -41,7 +42,7 @@ class crm_params(C.Structure):
         ("ps_freq", C.c_uint32), ("active_domains", C.c_uint32),
         ("t_delay", C.c_double),
         ("grow_G", C.c_double), ("shrink_S", C.c_double),
-        ("shrink_interval", C.c_uint32), ("reserved", C.c_uint32),
+        ("shrink_interval", C.c_uint32), ("pos_mode", C.c_uint32),
         ("bulk_coeff", C.c_double),
     ]
 
@@ -129,7 +130,7 @@ def make_params(p: dict) -> crm_params:
     o.ps_freq = int(p["ps_freq"])
     o.active_domains = int(p["active_domains"])
     o.shrink_interval = int(p["shrink_interval"])
-    o.reserved = 0
+    o.pos_mode = int(p.get("pos_mode", 0))
     return o
 
 

@@ -15,7 +15,8 @@
 using crm::Body;
 using crm::Grid;
 using crm::Phys;
-using crm::Rec;
+using crm::CPlanes;
+using crm::Planes;
 
 namespace {
 
@@ -62,13 +63,15 @@ struct crm_ctx {
 
   // working set (capacity `cap`)
   int64_t cap = 0;
-  Rec *A = nullptr, *B = nullptr;
+  Planes A{}, B{};
   float4* pos4 = nullptr;
+  int4* cpos = nullptr;          // cells of the sorted slots (cell-offset positions)
   int32_t* slot_id = nullptr;
   uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
   int32_t *frows = nullptr, *mrows = nullptr;
-  uint32_t *cnt_f = nullptr, *cnt_m = nullptr, *wlen_f = nullptr, *wlen_m = nullptr;
-  uint64_t *woff_f = nullptr, *woff_m = nullptr, *wtmp = nullptr;
+  uint32_t *cnt_f = nullptr, *cnt_m = nullptr;
+  uint64_t *off_f = nullptr, *off_m = nullptr, *wtmp = nullptr;
+  uint32_t *stash_f = nullptr, *stash_m = nullptr;  // count-pass scratch of the lists
 
   // neighbour entries
   uint32_t* nbr_f = nullptr;
@@ -146,7 +149,7 @@ bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]
 std::string check_params(const crm_params* p) {
   if (!p) return "params is NULL";
   if (p->abi_version != CRM_ABI_VERSION) return "abi_version mismatch";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->pos_mode > 1) return "pos_mode must be CRM_POS_FP32 or CRM_POS_CELL_OFFSET";
   auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
   if (!pos(p->dx)) return "dx must be > 0";
   if (!pos(p->h)) return "h must be > 0";
@@ -176,6 +179,48 @@ std::string check_params(const crm_params* p) {
   return "";
 }
 
+// FP64 coordinate <-> cell index + FP32 offset (cell-offset positions).
+void to_cell(double x, double lo, double inv, double S, int32_t& c, float& o) {
+#pragma clang fp contract(off)
+  const double t = x - lo;
+  const double cc = std::floor(t * inv);
+  c = (int32_t)cc;
+  o = (float)(t - cc * S);
+}
+
+double from_cell(int32_t c, float o, double lo, double S) {
+#pragma clang fp contract(off)
+  return (lo + (double)c * S) + (double)o;
+}
+
+// Stored position (a.xyz, d.zw) of a host FP64 position.
+void host_store_pos(const crm_ctx* c, const double* x, float4& a, float4& d) {
+  if (c->grid.cell) {
+    int32_t q[3];
+    float o[3];
+    for (int k = 0; k < 3; ++k) to_cell(x[k], c->grid.lo[k], c->grid.inv, c->grid.S, q[k], o[k]);
+    a.x = o[0]; a.y = o[1]; a.z = o[2];
+    uint32_t cx = (uint32_t)q[0], yz = crm::pack_yz(q[1], q[2]);
+    std::memcpy(&d.z, &cx, 4);
+    std::memcpy(&d.w, &yz, 4);
+  } else {
+    a.x = (float)x[0]; a.y = (float)x[1]; a.z = (float)x[2];
+  }
+}
+
+void host_abs_pos(const crm_ctx* c, const float4& a, const float4& d, double* x) {
+  if (c->grid.cell) {
+    uint32_t cx, yz;
+    std::memcpy(&cx, &d.z, 4);
+    std::memcpy(&yz, &d.w, 4);
+    x[0] = from_cell((int32_t)cx, a.x, c->grid.lo[0], c->grid.S);
+    x[1] = from_cell(crm::unpack_y(yz), a.y, c->grid.lo[1], c->grid.S);
+    x[2] = from_cell(crm::unpack_z(yz), a.z, c->grid.lo[2], c->grid.S);
+  } else {
+    x[0] = a.x; x[1] = a.y; x[2] = a.z;
+  }
+}
+
 void quat_to_R(const double q[4], double R[9]) {
   const double w = q[0], x = q[1], y = q[2], z = q[3];
   R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
@@ -191,22 +236,30 @@ void quat_to_R(const double q[4], double R[9]) {
   } while (0)
 
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
-  void* olds[] = {c->A, c->B, c->pos4, c->slot_id, c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows,
-                  c->cnt_f, c->cnt_m, c->wlen_f, c->wlen_m, c->woff_f, c->woff_m, c->wtmp};
+  void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id,
+                  c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->cnt_f, c->cnt_m, c->off_f,
+                  c->off_m, c->wtmp, c->stash_f, c->stash_m};
   for (void* p : olds) dfree(c, p);
-  c->A = c->B = nullptr;
+  c->A = Planes{};
+  c->B = Planes{};
   c->pos4 = nullptr;
+  c->cpos = nullptr;
   c->slot_id = c->frows = c->mrows = nullptr;
-  c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = c->wlen_f = c->wlen_m = nullptr;
-  c->woff_f = c->woff_m = c->wtmp = nullptr;
+  c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = nullptr;
+  c->off_f = c->off_m = c->wtmp = nullptr;
+  c->stash_f = c->stash_m = nullptr;
   c->cap = 0;
-  const int64_t nw = (cap + crm::kWave - 1) / crm::kWave + 1;
-  bool ok = alloc_n(c, c->A, cap) && alloc_n(c, c->B, cap) && alloc_n(c, c->pos4, cap) &&
+  bool ok = alloc_n(c, c->A.a, cap) && alloc_n(c, c->A.b, cap) && alloc_n(c, c->A.c, cap) &&
+            alloc_n(c, c->A.d, cap) && alloc_n(c, c->B.a, cap) && alloc_n(c, c->B.b, cap) &&
+            alloc_n(c, c->B.c, cap) && alloc_n(c, c->B.d, cap) && alloc_n(c, c->pos4, cap) &&
+            alloc_n(c, c->cpos, c->grid.cell ? cap : 1) &&
             alloc_n(c, c->slot_id, cap) && alloc_n(c, c->skey, cap) && alloc_n(c, c->key, cap) &&
             alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->frows, cap) &&
             alloc_n(c, c->mrows, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
-            alloc_n(c, c->wlen_f, nw) && alloc_n(c, c->wlen_m, nw) && alloc_n(c, c->woff_f, nw + 1) &&
-            alloc_n(c, c->woff_m, nw + 1) && alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(nw));
+            alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
+            alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
+            alloc_n(c, c->stash_f, (int64_t)crm::stash_elems(cap)) &&
+            alloc_n(c, c->stash_m, (int64_t)crm::stash_elems(cap));
   if (!ok) return fail(c, CRM_E_NOMEM, "working-set allocation failed");
   c->cap = cap;
   c->working_valid = false;
@@ -237,12 +290,12 @@ crm_status rebuild(crm_ctx* c) {
   const crm_params& P = c->prm;
   if (c->working_valid)
     HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
-  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->m_a, s));
+  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d, s));
   const double t = (double)c->step * P.dt;
   c->ad_on = P.active_domains && t > P.t_delay;
   int64_t n_proc = c->n_total;
   if (c->ad_on) {
-    HIPCHK(c, crm::activity_flags(c->m_a, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, s));
+    HIPCHK(c, crm::activity_flags(c->m_a, c->m_d, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, s));
     HIPCHK(c, crm::compact_flags(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
     crm_status st = read_counts(c);
     if (st != CRM_OK) return st;
@@ -250,7 +303,7 @@ crm_status rebuild(crm_ctx* c) {
   }
   // capacity policy (Sec. 4.2 item 3)
   int64_t ncap = crm_capacity_next(c->cap, n_proc, c->step, P.grow_G, P.shrink_S, P.shrink_interval);
-  if (ncap != c->cap || !c->A) {
+  if (ncap != c->cap || !c->A.a) {
     crm_status st = realloc_working(c, ncap);
     if (st != CRM_OK) return st;
   }
@@ -258,21 +311,20 @@ crm_status rebuild(crm_ctx* c) {
   const int32_t* ids = c->ad_on ? c->proc_ids : nullptr;
   const uint8_t* flg = c->ad_on ? c->flags : nullptr;
   HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, c->M, s));
-  HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->grid, c->key, c->rank, c->cell_cnt, s));
+  HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->m_d, c->grid, c->key, c->rank, c->cell_cnt, s));
   HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
   HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, c->tmp, s));
   HIPCHK(c, crm::gather_sorted(c->tmp, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
-                               c->m_d, c->A, c->B, c->pos4, c->slot_id, c->skey, s));
+                               c->m_d, c->A, c->B, c->pos4, c->cpos, c->slot_id, c->skey, c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
-  const int64_t nw = (n_proc + crm::kWave - 1) / crm::kWave;
-  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->skey, c->cell_start, c->grid, false,
-                           c->cnt_f, c->wlen_f, s));
-  HIPCHK(c, crm::scan_u32_to_u64(c->wlen_f, c->woff_f, nw, c->wtmp, s));
-  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->skey, c->cell_start, c->grid, true,
-                           c->cnt_m, c->wlen_m, s));
-  HIPCHK(c, crm::scan_u32_to_u64(c->wlen_m, c->woff_m, nw, c->wtmp, s));
-  HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->woff_f + nw, c->woff_m + nw, s));
+  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
+                           false, c->cnt_f, c->stash_f, s));
+  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_f, c->off_f, n_proc, c->wtmp, s));
+  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
+                           true, c->cnt_m, c->stash_m, s));
+  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_m, c->off_m, n_proc, c->wtmp, s));
+  HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->off_f + n_proc, c->off_m + n_proc, s));
   crm_status st = read_counts(c);
   if (st != CRM_OK) return st;
   c->n_frows = (int64_t)c->h_counts[1];
@@ -284,10 +336,10 @@ crm_status rebuild(crm_ctx* c) {
   if (st != CRM_OK) return st;
   c->ent_f = ef;
   c->ent_m = em;
-  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->skey, c->cell_start, c->grid, false, c->woff_f,
-                          c->nbr_f, s));
-  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->skey, c->cell_start, c->grid, true, c->woff_m,
-                          c->nbr_m, s));
+  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, false,
+                          c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
+  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
+                          c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
   const int64_t nbk = crm::bce_blocks(c->n_mrows);
   if (nbk * c->nb > c->partials_cap) {
     dfree(c, c->partials);
@@ -338,23 +390,22 @@ crm_status one_step(crm_ctx* c) {
   }
   const Phys& P = c->phys;
   hipEvent_t e = prof_begin(c);
-  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies, c->A,
-                                       c->B, s));
+  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies,
+                                       c->grid, c->A, c->B, s));
   prof_end(c, 1, e);
   // stage 1 at y_n
   e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->cnt_m, c->woff_m, c->nbr_m, c->d_bodies, c->nb, P, nullptr, s));
+  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->nb, P, nullptr, s));
   prof_end(c, 2, e);
   e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->cnt_f, c->woff_f, c->nbr_f, P, s));
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
   prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->cnt_m, c->woff_m, c->nbr_m, c->d_bodies, c->nb, P, c->partials,
-                     s));
+  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->nb, P, c->partials, s));
   prof_end(c, 4, e);
   e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->cnt_f, c->woff_f, c->nbr_f, P, s));
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
   prof_end(c, 5, e);
   e = prof_begin(c);
   HIPCHK(c, crm::body_reduce(c->partials, crm::bce_blocks(c->n_mrows), c->nb, c->d_forces, s));
@@ -423,6 +474,8 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   g.inv = 1.0 / two_h;
   g.R2 = two_h * two_h;
   g.ext = two_h;
+  g.S = two_h;
+  g.cell = params->pos_mode == CRM_POS_CELL_OFFSET ? 1 : 0;
   int64_t M = 1;
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = params->domain_lo[a];
@@ -432,6 +485,9 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     M *= (int64_t)d;
   }
   if (M > (int64_t)0xfffffffe) return fail(nullptr, CRM_E_UNSUPPORTED, "more than 2^32 - 2 cells");
+  if (g.cell && (g.dims[1] > 32767 || g.dims[2] > 32767))
+    return fail(nullptr, CRM_E_UNSUPPORTED, "cell-offset positions need fewer than 32768 cells along y and z");
+  if (n_total > ((int64_t)1 << 28)) return fail(nullptr, CRM_E_UNSUPPORTED, "more than 2^28 particles");
 
   crm_ctx* c = new crm_ctx();
   c->prm = *params;
@@ -480,13 +536,18 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   ph.cohesion = (float)P.cohesion;
   ph.p_cri = (float)(-P.cohesion / P.mu_s);
   ph.inv_Gdt = (float)(1.0 / (G * P.dt));
+  ph.cell = g.cell;
+  ph.Sf = (float)g.S;
+  ph.S = g.S;
+  ph.invS = g.inv;
+  for (int q = 0; q < 3; ++q) ph.lo[q] = g.lo[q];
 
   // host staging of the master planes
   std::vector<float4> ha((size_t)n_total), hb((size_t)n_total), hc((size_t)n_total), hd((size_t)n_total);
   std::vector<float4> hl((size_t)(nm > 0 ? nm : 1));
   for (int64_t i = 0; i < n_soil; ++i) {
     float r0 = rho ? rho[i] : (float)P.rho0;
-    ha[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], r0);
+    ha[i] = make_float4(0.f, 0.f, 0.f, r0);
     float v[3] = {0.f, 0.f, 0.f}, sg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (vel)
       for (int a = 0; a < 3; ++a) v[a] = vel[3 * i + a];
@@ -498,6 +559,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     hb[i] = make_float4(v[0], v[1], v[2], auxf);
     hc[i] = make_float4(sg[0], sg[1], sg[2], sg[3]);
     hd[i] = make_float4(sg[4], sg[5], 0.f, 0.f);
+    host_store_pos(c, pos + 3 * i, ha[i], hd[i]);
   }
   int64_t k = 0;
   for (int b = 0; b < n_bodies; ++b) {
@@ -631,7 +693,7 @@ crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, floa
   crm_status st = usable(c);
   if (st != CRM_OK) return st;
   hipStream_t s = c->stream;
-  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->m_a, s));
+  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d, s));
   if (c->working_valid) {
     HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
     HIPCHK(c, crm::scatter_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
@@ -644,7 +706,7 @@ crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, floa
   HIPCHK(c, hipMemcpyAsync(hd.data(), c->m_d, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   for (size_t i = 0; i < n; ++i) {
-    if (pos) { pos[3 * i] = ha[i].x; pos[3 * i + 1] = ha[i].y; pos[3 * i + 2] = ha[i].z; }
+    if (pos) host_abs_pos(c, ha[i], hd[i], pos + 3 * i);
     if (rho) rho[i] = ha[i].w;
     if (vel) { vel[3 * i] = hb[i].x; vel[3 * i + 1] = hb[i].y; vel[3 * i + 2] = hb[i].z; }
     if (sigma) {
@@ -674,7 +736,7 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
     HIPCHK(c, hipStreamSynchronize(s));
   }
   for (int64_t i = 0; i < n; ++i) {
-    if (pos) { ha[i].x = (float)pos[3 * i]; ha[i].y = (float)pos[3 * i + 1]; ha[i].z = (float)pos[3 * i + 2]; }
+    if (pos) host_store_pos(c, pos + 3 * i, ha[i], hd[i]);
     if (rho) ha[i].w = rho[i];
     if (vel) { hb[i].x = vel[3 * i]; hb[i].y = vel[3 * i + 1]; hb[i].z = vel[3 * i + 2]; }
     if (sigma) {
@@ -728,47 +790,40 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
       std::memset(flags, 2, (size_t)c->n_total);
   }
   const bool want_lists = rows || off || nbr;
-  const int64_t nw = (np + crm::kWave - 1) / crm::kWave;
   std::vector<int32_t> fr, mr;
-  std::vector<uint32_t> cf, cm, ef, em;
-  std::vector<uint64_t> wf, wm;
+  std::vector<uint64_t> of, om;
+  std::vector<uint32_t> ef, em;
   if (want_lists) {
     fr.resize((size_t)c->n_frows); mr.resize((size_t)c->n_mrows);
-    cf.resize((size_t)c->n_frows); cm.resize((size_t)c->n_mrows);
-    wf.resize((size_t)nw + 1); wm.resize((size_t)nw + 1);
+    of.resize((size_t)c->n_frows + 1); om.resize((size_t)c->n_mrows + 1);
     ef.resize((size_t)c->ent_f); em.resize((size_t)c->ent_m);
     auto cp = [&](void* d, const void* src, size_t bytes) {
       return bytes ? hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
     };
     HIPCHK(c, cp(fr.data(), c->frows, 4 * fr.size()));
     HIPCHK(c, cp(mr.data(), c->mrows, 4 * mr.size()));
-    HIPCHK(c, cp(cf.data(), c->cnt_f, 4 * cf.size()));
-    HIPCHK(c, cp(cm.data(), c->cnt_m, 4 * cm.size()));
-    HIPCHK(c, cp(wf.data(), c->woff_f, 8 * wf.size()));
-    HIPCHK(c, cp(wm.data(), c->woff_m, 8 * wm.size()));
+    HIPCHK(c, cp(of.data(), c->off_f, 8 * of.size()));
+    HIPCHK(c, cp(om.data(), c->off_m, 8 * om.size()));
     HIPCHK(c, cp(ef.data(), c->nbr_f, 4 * ef.size()));
     HIPCHK(c, cp(em.data(), c->nbr_m, 4 * em.size()));
   }
   HIPCHK(c, hipStreamSynchronize(s));
   if (sorted_ids) std::memcpy(sorted_ids, sid.data(), sizeof(int32_t) * (size_t)np);
   if (want_lists) {
-    int64_t tot = 0;
-    for (uint32_t v : cf) tot += v;
-    for (uint32_t v : cm) tot += v;
+    const int64_t tot = (int64_t)(of.back() + om.back());
     if (nbr && tot > cap) return fail(c, CRM_E_INVALID, "cap too small for the neighbour entries");
     int64_t row = 0, e = 0;
-    auto emit = [&](const std::vector<int32_t>& rr, const std::vector<uint32_t>& cc, const std::vector<uint64_t>& ww,
+    auto emit = [&](const std::vector<int32_t>& rr, const std::vector<uint64_t>& oo,
                     const std::vector<uint32_t>& ee) {
       for (size_t r = 0; r < rr.size(); ++r, ++row) {
         if (rows) rows[row] = sid[(size_t)rr[r]];
         if (off) off[row] = e;
-        const uint64_t base = ww[r / crm::kWave] + (r % crm::kWave);
-        for (uint32_t k = 0; k < cc[r]; ++k, ++e)
-          if (nbr) nbr[e] = sid[ee[base + (uint64_t)k * crm::kWave]];
+        for (uint64_t k = oo[r]; k < oo[r + 1]; ++k, ++e)
+          if (nbr) nbr[e] = sid[ee[k]];
       }
     };
-    emit(fr, cf, wf, ef);
-    emit(mr, cm, wm, em);
+    emit(fr, of, ef);
+    emit(mr, om, em);
     if (off) off[row] = e;
   }
   return CRM_OK;

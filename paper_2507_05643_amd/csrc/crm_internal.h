@@ -13,13 +13,25 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kWave = 64;        // gfx950 wavefront width
 constexpr int kMaxBodies = 64;   // bodies per context
 
-// Particle record of the working set: 64 bytes, one cache-line half, so that a
-// neighbour gather is four 16-byte loads from one contiguous segment.
+// Particle state as four float4 planes (structure of arrays of 16-byte
+// vectors), indexed by cell-sorted slot in the working set:
 //   a = (x, y, z, rho)  b = (vx, vy, vz, aux)  c = (sxx, syy, szz, sxy)
 //   d = (sxz, syz, -, -)
-// aux (bit pattern of b.w) = kind | body << 2.
-struct alignas(16) Rec {
-  float4 a, b, c, d;
+// aux (bit pattern of b.w) = kind | body << 2. A lane group reading the
+// records of consecutive slots touches consecutive 16-byte vectors of a plane.
+struct Planes {
+  float4* a;
+  float4* b;
+  float4* c;
+  float4* d;
+};
+struct CPlanes {
+  const float4* a;
+  const float4* b;
+  const float4* c;
+  const float4* d;
+  CPlanes() = default;
+  __host__ __device__ CPlanes(const Planes& p) : a(p.a), b(p.b), c(p.c), d(p.d) {}
 };
 
 enum : uint32_t { kSoilActive = 0u, kSoilExtended = 1u, kMarker = 2u };
@@ -43,9 +55,18 @@ struct Grid {
   double inv;     // 1 / (2h), rounded once
   double R2;      // (2h)^2
   double ext;     // 2h, grow of the active boxes
+  double S;       // cell size 2h
   int32_t dims[3];
-  int32_t pad;
+  int32_t cell;   // positions stored as cell index + FP32 offset
 };
+
+// Cell-offset positions: cx is kept in d.z, cy and cz as two 16-bit signed
+// halves of d.w (bit patterns of the floats), the offsets in a.xyz.
+__host__ __device__ inline uint32_t pack_yz(int32_t cy, int32_t cz) {
+  return (uint32_t)(uint16_t)(int16_t)cy | ((uint32_t)(uint16_t)(int16_t)cz << 16);
+}
+__host__ __device__ inline int32_t unpack_y(uint32_t w) { return (int32_t)(int16_t)(uint16_t)(w & 0xffffu); }
+__host__ __device__ inline int32_t unpack_z(uint32_t w) { return (int32_t)(int16_t)(uint16_t)(w >> 16); }
 
 // FP32 constants of the stage kernels.
 struct Phys {
@@ -62,6 +83,10 @@ struct Phys {
   float xi2;      // (xi_over_h h)^2
   int32_t av_mode;
   float mu_s, mu_2, I0, grain_d, cohesion, p_cri, inv_Gdt;
+  int32_t cell;   // positions stored as cell index + FP32 offset
+  float Sf;       // cell size 2h in FP32 (cell-offset positions)
+  double S, invS; // cell size and its inverse in FP64
+  double lo[3];   // grid origin
 };
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
@@ -78,11 +103,11 @@ hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStr
 
 // Marker world positions x = X + R l (FP64, rounded to FP32) into master plane 0.
 hipError_t place_markers_master(const float4* local, int64_t n_markers, int64_t n_soil,
-                                const Body* bodies, float4* m_a, hipStream_t s);
+                                const Body* bodies, Grid g, float4* m_a, float4* m_d, hipStream_t s);
 
 // Activity flags of all particles (Sec. 4.2 item 2).
-hipError_t activity_flags(const float4* m_a, int64_t n, const Body* bodies, int32_t nb,
-                          Grid g, uint8_t* flags, hipStream_t s);
+hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies,
+                          int32_t nb, Grid g, uint8_t* flags, hipStream_t s);
 
 // Order-preserving compaction of ids with flags != 0 (block counts, scan, write).
 size_t compact_tmp_elems(int64_t n);
@@ -90,8 +115,8 @@ hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint
                          uint32_t* tmp, hipStream_t s);
 
 // Cell hash with per-cell arrival counts (counting sort, part 1).
-hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a, Grid g,
-                      uint32_t* key, uint32_t* rank, uint32_t* cell_cnt, hipStream_t s);
+hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a, const float4* m_d,
+                      Grid g, uint32_t* key, uint32_t* rank, uint32_t* cell_cnt, hipStream_t s);
 // Place into cell order (part 2), then rank by id inside each cell and gather
 // the master state into the sorted working set (part 3).
 hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cell_start,
@@ -99,50 +124,52 @@ hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_
 hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* proc_ids,
                          const uint32_t* cell_start, int64_t n_proc, int64_t n_soil,
                          const uint8_t* flags, const float4* m_a, const float4* m_b,
-                         const float4* m_c, const float4* m_d, Rec* A, Rec* B, float4* pos4,
-                         int32_t* slot_id, uint32_t* skey, hipStream_t s);
+                         const float4* m_c, const float4* m_d, Planes A, Planes B, float4* pos4,
+                         int4* cpos, int32_t* slot_id, uint32_t* skey, bool cell, hipStream_t s);
 
 // Row lists (slots owning a neighbour list): active soil rows and marker rows.
 hipError_t compact_kind(const float4* pos4, int64_t n_proc, uint32_t kind, int32_t* rows,
                         uint64_t* count_dst, uint32_t* tmp, hipStream_t s);
 
-// Neighbour lists (Alg. 1) in wave-interleaved CSR: row r's k-th entry is at
-// woff[r / 64] + 64 k + r % 64. Count pass writes cnt[r] and wave_len[r / 64]
-// (64 * max count of the wave); fill pass writes the entries. soil_only keeps
-// only soil neighbours (marker rows).
+// Neighbour lists (Alg. 1) in CSR: counts per row, offsets by an exclusive
+// scan of the counts (u64, rows + 1), then the fill. A group of 8 lanes serves
+// one row. soil_only keeps only soil neighbours (marker rows). The count pass
+// runs over rows_cap rows with the live row count read on the device, writes
+// cnt[r] = 0 beyond it, and keeps each row's first entries in `stash`
+// (stash_elems(rows_cap) words), from which the fill pass copies.
+size_t stash_elems(int64_t rows_cap);
 hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev,
-                     const float4* pos4, const uint32_t* skey, const uint32_t* cell_start, Grid g,
-                     bool soil_only, uint32_t* cnt, uint32_t* wave_len, hipStream_t s);
-hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const uint32_t* skey,
-                    const uint32_t* cell_start, Grid g, bool soil_only, const uint64_t* woff,
-                    uint32_t* nbr, hipStream_t s);
+                     const float4* pos4, const int4* cpos, const uint32_t* skey,
+                     const uint32_t* cell_start, Grid g, bool soil_only, uint32_t* cnt, uint32_t* stash,
+                     hipStream_t s);
+hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos,
+                    const uint32_t* skey, const uint32_t* cell_start, Grid g, bool soil_only,
+                    const uint32_t* cnt, const uint32_t* stash, const uint64_t* off, uint32_t* nbr,
+                    hipStream_t s);
 
 // Per step: marker positions of the processed markers into A and B.
 hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const int32_t* slot_id,
-                                 int64_t n_soil, const float4* local, const Body* bodies, Rec* A,
-                                 Rec* B, hipStream_t s);
+                                 int64_t n_soil, const float4* local, const Body* bodies, Grid g,
+                                 Planes A, Planes B, hipStream_t s);
 
 // BCE extrapolation at state S (Sec. 2.5.1); with partials != nullptr also the
 // marker accelerations and per-block body force/torque partial sums
-// (partials[block * nb + b][6], FP64).
-hipError_t bce(Rec* S, const int32_t* mrows, int64_t n_mrows, const uint32_t* cnt,
-               const uint64_t* woff, const uint32_t* nbr, const Body* bodies, int32_t nb, Phys P,
-               double* partials, hipStream_t s);
+// (partials[block * nb + b][6], FP64, bce_blocks(n_mrows) blocks).
+hipError_t bce(Planes S, const int32_t* mrows, int64_t n_mrows, const uint64_t* off, const uint32_t* nbr,
+               const Body* bodies, int32_t nb, Phys P, double* partials, hipStream_t s);
 int64_t bce_blocks(int64_t n_mrows);
 hipError_t body_reduce(const double* partials, int64_t nblocks, int32_t nb, double* forces,
                        hipStream_t s);
 
-// Fluid RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
+// Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
 // mapping (Sec. 2.4).
-hipError_t fluid_stage1(const Rec* A, Rec* B, const int32_t* frows, int64_t n_frows,
-                        const uint32_t* cnt, const uint64_t* woff, const uint32_t* nbr, Phys P,
-                        hipStream_t s);
-hipError_t fluid_stage2(const Rec* B, Rec* A, const int32_t* frows, int64_t n_frows,
-                        const uint32_t* cnt, const uint64_t* woff, const uint32_t* nbr, Phys P,
-                        hipStream_t s);
+hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
+                        const uint32_t* nbr, Phys P, hipStream_t s);
+hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_frows, const uint64_t* off,
+                        const uint32_t* nbr, Phys P, hipStream_t s);
 
 // Scatter working records back to the master planes.
-hipError_t scatter_rows(const Rec* src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
+hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
                         float4* m_a, float4* m_b, float4* m_c, float4* m_d, hipStream_t s);
 
 }  // namespace crm

@@ -16,15 +16,18 @@ __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 // The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own L2.
 // Neighbouring particles are neighbours in the cell-sorted order, so give
 // every XCD one contiguous range of logical blocks: XCD x gets
-// [x q + min(x, r), ...) of length q + (x < r), with q, r = nblocks / 8, % 8.
-// This is a bijection of [0, nblocks).
+// [x q + min(x, r), ...) of length q + (x < r), with q, r = nb / 8, % 8.
+// This is a bijection of [0, nb); blocks from nb on keep their index (used
+// when only the first nb blocks of a grid carry live rows).
 constexpr int kXcds = 8;
-__device__ inline int64_t xcd_block() {
-  const int64_t nb = gridDim.x, b = blockIdx.x;
+__device__ inline int64_t xcd_block_n(int64_t nb) {
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return b;
   const int64_t q = nb / kXcds, r = nb % kXcds;
   const int64_t x = b % kXcds, k = b / kXcds;
   return x * q + (x < r ? x : r) + k;
 }
+__device__ inline int64_t xcd_block() { return xcd_block_n(gridDim.x); }
 
 template <typename T>
 __device__ inline T wave_incl_scan(T x) {
@@ -231,33 +234,80 @@ __device__ inline void body_point(const Body& b, float lx, float ly, float lz, d
     out[a] = b.X[a] + ((b.R[3 * a] * l0 + b.R[3 * a + 1] * l1) + b.R[3 * a + 2] * l2);
 }
 
+// FP64 position -> cell index + FP32 offset: c = floor((x - lo) / S), o = x - lo - c S.
+__device__ inline void to_cell(double x, double lo, double inv, double S, int32_t& c, float& o) {
+#pragma clang fp contract(off)
+  const double t = x - lo;
+  const double cc = floor(t * inv);
+  c = (int32_t)cc;
+  o = (float)(t - cc * S);
+}
+
+// Absolute FP64 coordinate of a cell-offset position: (lo + c S) + o.
+__device__ inline double from_cell(int32_t c, float o, double lo, double S) {
+#pragma clang fp contract(off)
+  return (lo + (double)c * S) + (double)o;
+}
+
+// Stored position (a = offsets or coordinates, d.zw = cells) -> FP64 absolute.
+__device__ inline void abs_pos(float4 a, float4 d, const Grid& g, double x[3]) {
+  if (g.cell) {
+    const uint32_t w = __float_as_uint(d.w);
+    x[0] = from_cell((int32_t)__float_as_uint(d.z), a.x, g.lo[0], g.S);
+    x[1] = from_cell(unpack_y(w), a.y, g.lo[1], g.S);
+    x[2] = from_cell(unpack_z(w), a.z, g.lo[2], g.S);
+  } else {
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+  }
+}
+
+// FP64 world position -> stored position (a.xyz and, for cells, d.zw).
+__device__ inline void store_pos(const double x[3], const Grid& g, float4& a, float4& d) {
+  if (g.cell) {
+    int32_t c[3];
+    float o[3];
+    for (int q = 0; q < 3; ++q) to_cell(x[q], g.lo[q], g.inv, g.S, c[q], o[q]);
+    a.x = o[0];
+    a.y = o[1];
+    a.z = o[2];
+    d.z = __uint_as_float((uint32_t)c[0]);
+    d.w = __uint_as_float(pack_yz(c[1], c[2]));
+  } else {
+    a.x = (float)x[0];
+    a.y = (float)x[1];
+    a.z = (float)x[2];
+  }
+}
+
 // ---------------------------------------------------- markers and flags ---
 __global__ __launch_bounds__(kBlock) void k_place_markers_master(const float4* __restrict__ local, int64_t nm,
                                                                  int64_t n_soil, const Body* __restrict__ bodies,
-                                                                 float4* __restrict__ m_a) {
+                                                                 Grid g, float4* __restrict__ m_a,
+                                                                 float4* __restrict__ m_d) {
   int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= nm) return;
   float4 l = local[k];
   const Body& b = bodies[__float_as_uint(l.w)];
   double x[3];
   body_point(b, l.x, l.y, l.z, x);
-  float4 o = m_a[n_soil + k];
-  o.x = (float)x[0];
-  o.y = (float)x[1];
-  o.z = (float)x[2];
-  m_a[n_soil + k] = o;
+  float4 a = m_a[n_soil + k], d = m_d[n_soil + k];
+  store_pos(x, g, a, d);
+  m_a[n_soil + k] = a;
+  if (g.cell) m_d[n_soil + k] = d;
 }
 
 // Sec. 4.2 item 2: Active inside an oriented box (|R^T (x - X)| <= half per
 // local axis), Extended-Active inside the box grown by 2h, else Inactive.
-__global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, int64_t n,
-                                                     const Body* __restrict__ bodies, int32_t nb, Grid g,
+__global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
+                                                     int64_t n, const Body* __restrict__ bodies, int32_t nb, Grid g,
                                                      uint8_t* __restrict__ flags) {
 #pragma clang fp contract(off)
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  float4 p = m_a[i];
-  double xw[3] = {(double)p.x, (double)p.y, (double)p.z};
+  double xw[3];
+  abs_pos(m_a[i], g.cell ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f), g, xw);
   uint8_t best = 0;
   for (int b = 0; b < nb; ++b) {
     const Body& B = bodies[b];
@@ -277,20 +327,33 @@ __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ 
   flags[i] = best;
 }
 
+
 // ------------------------------------------------------ hashing and sort ---
 // Sec. 4.1 step 1: c = z * (Y * X) + y * X + x with cell size 2h. The arrival
 // rank of each particle in its cell comes from an atomic counter (counting sort).
+__device__ inline int32_t clamp_cell(int32_t c, int32_t dim) { return c < 0 ? 0 : (c > dim - 1 ? dim - 1 : c); }
+
 __global__ __launch_bounds__(kBlock) void k_hash_count(const int32_t* __restrict__ ids, int64_t n,
-                                                       const float4* __restrict__ m_a, Grid g,
+                                                       const float4* __restrict__ m_a,
+                                                       const float4* __restrict__ m_d, Grid g,
                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
                                                        uint32_t* __restrict__ cnt) {
   int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   int64_t id = ids ? ids[k] : k;
-  float4 p = m_a[id];
-  int32_t cx = cell_coord((double)p.x, g.lo[0], g.inv, g.dims[0]);
-  int32_t cy = cell_coord((double)p.y, g.lo[1], g.inv, g.dims[1]);
-  int32_t cz = cell_coord((double)p.z, g.lo[2], g.inv, g.dims[2]);
+  int32_t cx, cy, cz;
+  if (g.cell) {   // the stored cell, clamped to the grid
+    const float4 d = m_d[id];
+    const uint32_t w = __float_as_uint(d.w);
+    cx = clamp_cell((int32_t)__float_as_uint(d.z), g.dims[0]);
+    cy = clamp_cell(unpack_y(w), g.dims[1]);
+    cz = clamp_cell(unpack_z(w), g.dims[2]);
+  } else {
+    const float4 p = m_a[id];
+    cx = cell_coord((double)p.x, g.lo[0], g.inv, g.dims[0]);
+    cy = cell_coord((double)p.y, g.lo[1], g.inv, g.dims[1]);
+    cz = cell_coord((double)p.z, g.lo[2], g.inv, g.dims[2]);
+  }
   uint32_t c = ((uint32_t)cz * (uint32_t)g.dims[1] + (uint32_t)cy) * (uint32_t)g.dims[0] + (uint32_t)cx;
   key[k] = c;
   rank[k] = atomicAdd(&cnt[c], 1u);
@@ -306,13 +369,13 @@ __global__ __launch_bounds__(kBlock) void k_place(const uint32_t* __restrict__ k
 
 // Sec. 4.1 step 2 (sort by cell, ties by particle id): the atomic arrival order
 // inside a cell is replaced by the id order (a cell holds ~10-20 particles), and
-// the master state is gathered into the cell-sorted working records.
+// the master state is gathered into the cell-sorted working planes.
 __global__ __launch_bounds__(kBlock) void k_gather_sorted(
     const uint32_t* __restrict__ tmp, const uint32_t* __restrict__ key, const int32_t* __restrict__ ids,
     const uint32_t* __restrict__ cs, int64_t n, int64_t n_soil, const uint8_t* __restrict__ flags,
     const float4* __restrict__ m_a, const float4* __restrict__ m_b, const float4* __restrict__ m_c,
-    const float4* __restrict__ m_d, Rec* __restrict__ A, Rec* __restrict__ B, float4* __restrict__ pos4,
-    int32_t* __restrict__ slot_id, uint32_t* __restrict__ skey) {
+    const float4* __restrict__ m_d, Planes A, Planes B, float4* __restrict__ pos4, int4* __restrict__ cpos,
+    int cell, int32_t* __restrict__ slot_id, uint32_t* __restrict__ skey) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
   uint32_t k = tmp[p];
@@ -324,214 +387,391 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   int64_t id = ids ? ids[k] : (int64_t)k;
   slot_id[f] = (int32_t)id;
   skey[f] = c;
-  Rec rec;
-  rec.a = m_a[id];
-  rec.b = m_b[id];
-  rec.c = m_c[id];
-  rec.d = m_d[id];
-  uint32_t aux = __float_as_uint(rec.b.w) & ~3u;
+  float4 a = m_a[id], b = m_b[id], cc = m_c[id], d = m_d[id];
+  uint32_t aux = __float_as_uint(b.w) & ~3u;
   uint32_t kind = (id < n_soil) ? ((flags == nullptr || flags[id] == 2) ? kSoilActive : kSoilExtended) : kMarker;
-  rec.b.w = __uint_as_float(aux | kind);
-  A[f] = rec;
-  B[f] = rec;
-  pos4[f] = make_float4(rec.a.x, rec.a.y, rec.a.z, rec.b.w);
+  b.w = __uint_as_float(aux | kind);
+  A.a[f] = a; A.b[f] = b; A.c[f] = cc; A.d[f] = d;
+  B.a[f] = a; B.b[f] = b; B.c[f] = cc; B.d[f] = d;
+  pos4[f] = make_float4(a.x, a.y, a.z, b.w);
+  if (cell) {
+    const uint32_t w = __float_as_uint(d.w);
+    cpos[f] = make_int4((int32_t)__float_as_uint(d.z), unpack_y(w), unpack_z(w), 0);
+  }
+}
+
+// --------------------------------------------------------- lane groups ---
+// A row (a soil particle or a marker) is served by a group of kGroup
+// consecutive lanes: the group walks the row's candidates or neighbours kGroup
+// at a time, so that the lanes of a group touch consecutive slots of the
+// cell-sorted planes, and then sums its partial results across the group.
+constexpr int kGroup = 8;
+static_assert(kWave % kGroup == 0, "group must divide the wave");
+
+__device__ inline int group_lane() { return threadIdx.x & (kGroup - 1); }
+
+// Sum over the kGroup lanes of a group; every lane gets the total. DPP lane
+// permutations: swap neighbours, swap pairs, mirror the two quads of 8 lanes,
+// mirror the two halves of 16 lanes.
+template <int Ctrl>
+__device__ inline float dpp_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+__device__ inline float group_sum(float v) {
+  static_assert(kGroup == 2 || kGroup == 4 || kGroup == 8 || kGroup == 16, "group of 2, 4, 8 or 16 lanes");
+  v += dpp_perm<0xB1>(v);                          // quad [1,0,3,2]
+  if (kGroup >= 4) v += dpp_perm<0x4E>(v);         // quad [2,3,0,1]
+  if (kGroup >= 8) v += dpp_perm<0x141>(v);        // half-row mirror
+  if (kGroup >= 16) v += dpp_perm<0x140>(v);       // row mirror
+  return v;
+}
+
+// Bits of this lane's group in a wave ballot.
+__device__ inline uint32_t group_bits(uint64_t ballot) {
+  return (uint32_t)(ballot >> (lane_id() & ~(kGroup - 1))) & ((1u << kGroup) - 1u);
 }
 
 // ------------------------------------------------------- neighbour lists ---
 // Algorithm 1: for each row particle, the 27 cells around its own; the three
 // cells x-1..x+1 of a (y, z) row are consecutive in the sorted order, so they
-// are scanned as one range [cellStart[c(x-1)], cellStart[c(x+1) + 1]).
-// Membership |x_i - x_j| < 2h is decided in FP64 on the FP32 positions.
-// With soil_only (marker rows) only soil candidates are kept: the BCE sums
-// of Sec. 2.5.1 run over soil particles, so marker-marker pairs are never used.
-template <bool FILL, typename Out>
-__device__ inline uint32_t scan_neighbours(float4 pi, uint32_t c, const float4* __restrict__ pos4,
-                                           const uint32_t* __restrict__ cs, const Grid& g, bool soil_only,
-                                           Out out) {
+// are scanned as one range [cellStart[c(x-1)], cellStart[c(x+1) + 1]). The group
+// tests kGroup consecutive candidates at a time; membership |x_i - x_j| < 2h is
+// decided in FP64 on the FP32 positions. Entries come out in slot order. With
+// soil_only (marker rows) only soil candidates are kept: the BCE sums of
+// Sec. 2.5.1 run over soil particles, so marker-marker pairs are never used.
+__device__ inline double dist2_cell(float4 pi, int4 ci, float4 pj, int4 cj, double S) {
+#pragma clang fp contract(off)
+  const double dx = (double)(ci.x - cj.x) * S + ((double)pi.x - (double)pj.x);
+  const double dy = (double)(ci.y - cj.y) * S + ((double)pi.y - (double)pj.y);
+  const double dz = (double)(ci.z - cj.z) * S + ((double)pi.z - (double)pj.z);
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+template <bool FILL>
+__device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const float4* __restrict__ pos4,
+                                      const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
+                                      const Grid& g, bool soil_only, uint32_t* __restrict__ out, uint32_t limit) {
   const int X = g.dims[0], Y = g.dims[1], Z = g.dims[2];
-  const int cx = (int)(c % (uint32_t)X);
-  const uint32_t t = c / (uint32_t)X;
-  const int cy = (int)(t % (uint32_t)Y);
-  const int cz = (int)(t / (uint32_t)Y);
+  const int gl = group_lane();
+  int cx = 0, cy = 0, cz = 0;
+  if (live) {
+    cx = (int)(c % (uint32_t)X);
+    const uint32_t t = c / (uint32_t)X;
+    cy = (int)(t % (uint32_t)Y);
+    cz = (int)(t / (uint32_t)Y);
+  }
   const int x0 = cx > 0 ? cx - 1 : 0;
   const int x1 = cx < X - 1 ? cx + 1 : X - 1;
   uint32_t count = 0;
   for (int dz = -1; dz <= 1; ++dz) {
-    const int z = cz + dz;
-    if (z < 0 || z >= Z) continue;
     for (int dy = -1; dy <= 1; ++dy) {
-      const int y = cy + dy;
-      if (y < 0 || y >= Y) continue;
-      const uint32_t row = ((uint32_t)z * (uint32_t)Y + (uint32_t)y) * (uint32_t)X;
-      const uint32_t b = cs[row + x0], e = cs[row + x1 + 1];
-      for (uint32_t j = b; j < e; ++j) {
-        float4 pj = pos4[j];
-        if (soil_only && (__float_as_uint(pj.w) & 3u) == kMarker) continue;
-        if (dist2_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z) < g.R2) {
-          if (FILL) out[(size_t)count * kWave] = j;
-          ++count;
+      const int z = cz + dz, y = cy + dy;
+      uint32_t b = 0, e = 0;
+      if (live && z >= 0 && z < Z && y >= 0 && y < Y) {
+        const uint32_t row = ((uint32_t)z * (uint32_t)Y + (uint32_t)y) * (uint32_t)X;
+        b = cs[row + x0];
+        e = cs[row + x1 + 1];
+      }
+      for (uint32_t j0 = b; j0 < e; j0 += kGroup) {
+        const uint32_t j = j0 + gl;
+        bool hit = false;
+        if (j < e) {
+          const float4 pj = pos4[j];
+          if (!(soil_only && (__float_as_uint(pj.w) & 3u) == kMarker))
+            hit = (g.cell ? dist2_cell(pi, ci, pj, cpos[j], g.S) : dist2_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z)) <
+                  g.R2;
         }
+        const uint32_t m = group_bits(__ballot(hit));
+        if (FILL && hit) {
+          const uint32_t at = count + __popc(m & ((1u << gl) - 1u));
+          if (at < limit) out[at] = j;
+        }
+        count += __popc(m);
       }
     }
   }
   return count;
 }
 
+// Count pass: counts every row's neighbours and keeps the first kStash of them
+// in a fixed-stride scratch, so that the fill pass is a copy (rows with more
+// are scanned again there). The grid covers rows_cap rows; the live row count
+// is read on the device and only the blocks that carry live rows are spread
+// over the XCDs.
+constexpr uint32_t kStash = 80;
+
 __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict__ rows, int64_t rows_cap,
                                                       const uint64_t* __restrict__ n_rows_dev,
-                                                      const float4* __restrict__ pos4, const uint32_t* __restrict__ skey,
+                                                      const float4* __restrict__ pos4, const int4* __restrict__ cpos,
+                                                      const uint32_t* __restrict__ skey,
                                                       const uint32_t* __restrict__ cs, Grid g, int soil_only,
-                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ wave_len) {
-  const int64_t r = xcd_block() * kBlock + threadIdx.x;
+                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ stash) {
   const int64_t nr = (int64_t)*n_rows_dev;
-  uint32_t count = 0;
-  if (r < nr) {
+  const int64_t nb_live = (nr * kGroup + kBlock - 1) / kBlock;
+  const int64_t r = (xcd_block_n(nb_live) * kBlock + threadIdx.x) / kGroup;
+  const bool live = r < nr;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  int4 ci = make_int4(0, 0, 0, 0);
+  uint32_t c = 0;
+  uint32_t* out = stash;
+  if (live) {
     const int32_t s = rows[r];
-    count = scan_neighbours<false>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, (uint32_t*)nullptr);
+    pi = pos4[s];
+    if (g.cell) ci = cpos[s];
+    c = skey[s];
+    out = stash + (uint64_t)r * kStash;
   }
-  if (r < rows_cap) cnt[r] = count;
-  uint32_t mx = count;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    uint32_t y = __shfl_xor(mx, o, kWave);
-    mx = y > mx ? y : mx;
-  }
-  if (lane_id() == 0 && r < rows_cap) wave_len[r / kWave] = mx * (uint32_t)kWave;
+  const uint32_t count = group_scan<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, out, kStash);
+  if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
-// Each wave gathers its entries in LDS and writes them out as whole 256-byte
-// rows (lanes finish their candidate loops at different times, so direct
-// stores would reach L2 as partial lines); a wave whose longest list exceeds
-// the LDS slots writes directly.
-constexpr int kFillSlots = 72;
-
 __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__ rows, int64_t n_rows,
-                                                     const float4* __restrict__ pos4, const uint32_t* __restrict__ skey,
+                                                     const float4* __restrict__ pos4, const int4* __restrict__ cpos,
+                                                     const uint32_t* __restrict__ skey,
                                                      const uint32_t* __restrict__ cs, Grid g, int soil_only,
-                                                     const uint64_t* __restrict__ woff, uint32_t* __restrict__ nbr) {
-  __shared__ uint32_t buf[kBlock / kWave][kFillSlots * kWave];
-  const int64_t r = xcd_block() * kBlock + threadIdx.x;
-  const int64_t w = r / kWave;
-  const int lane = lane_id();
-  const bool wave_live = w * kWave < n_rows;
-  uint64_t base = 0;
-  uint32_t wmax = 0;
-  if (wave_live) {
-    base = woff[w];
-    wmax = (uint32_t)((woff[w + 1] - base) / kWave);
+                                                     const uint32_t* __restrict__ cnt,
+                                                     const uint32_t* __restrict__ stash,
+                                                     const uint64_t* __restrict__ off, uint32_t* __restrict__ nbr) {
+  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+  const bool live = r < n_rows;
+  const uint32_t count = live ? cnt[r] : 0u;
+  const bool rescan = count > kStash;                 // uniform within the group
+  if (live && !rescan) {
+    const uint64_t base = off[r];
+    const uint32_t* src = stash + (uint64_t)r * kStash;
+    for (uint32_t k = group_lane(); k < count; k += kGroup) nbr[base + k] = src[k];
   }
-  const bool use_lds = wmax <= (uint32_t)kFillSlots;
-  uint32_t* lbuf = &buf[wave_id()][lane];
-  if (r < n_rows) {
+  if (rescan) {
     const int32_t s = rows[r];
-    if (use_lds)
-      scan_neighbours<true>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, lbuf);
-    else
-      scan_neighbours<true>(pos4[s], skey[s], pos4, cs, g, soil_only != 0, nbr + base + lane);
+    const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
+    group_scan<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, soil_only != 0, nbr + off[r], 0xffffffffu);
   }
-  __syncthreads();
-  if (wave_live && use_lds)
-    for (uint32_t k = 0; k < wmax; ++k) nbr[base + (uint64_t)k * kWave + lane] = lbuf[k * kWave];
 }
 
 // ------------------------------------------------------- SPH kernel (FP32) ---
 // Cubic spline with support 2h (Sec. 4.1): W = kw w(q) and
-// grad_i W_ij = kf f(q) (x_i - x_j), f = W'(r) / (r h^-5 pi^-1 ...) folded so that
-// the self pair (r = 0) gives a zero gradient without a division by r.
+// grad_i W_ij = kf f(q) (x_i - x_j) with f = h^5 pi W'(r) / r, so that the self
+// pair (r = 0) gives a zero gradient without a division by r.
 __device__ inline float kernel_f(float q, float kf) {
-  if (q < 1.0f) return kf * (2.25f * q - 3.0f);
-  if (q < 2.0f) {
-    float t = 2.0f - q;
-    return -0.75f * kf * t * t * __builtin_amdgcn_rcpf(q);
-  }
-  return 0.0f;
+  const float t = fmaxf(2.0f - q, 0.0f);
+  const float outer = -0.75f * kf * t * t * __builtin_amdgcn_rcpf(q);   // 1 <= q < 2 (0 beyond)
+  const float inner = kf * (2.25f * q - 3.0f);                          // q < 1
+  return q < 1.0f ? inner : outer;
 }
 
 __device__ inline float kernel_w(float q, float kw) {
-  if (q < 1.0f) return kw * (1.0f + q * q * (0.75f * q - 1.5f));
-  if (q < 2.0f) {
-    float t = 2.0f - q;
-    return 0.25f * kw * t * t * t;
-  }
-  return 0.0f;
+  const float t = fmaxf(2.0f - q, 0.0f);
+  const float outer = 0.25f * kw * t * t * t;
+  const float inner = kw * (1.0f + q * q * (0.75f * q - 1.5f));
+  return q < 1.0f ? inner : outer;
 }
 
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// A neighbour's record, loaded from the four planes with a 32-bit byte offset
+// from each plane's base (slots < 2^28).
+struct Nbr {
+  float4 a, b, c, d;
+};
+
+__device__ inline const float4& at(const float4* base, uint32_t j) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(base) + (j << 4));
+}
+
+__device__ inline Nbr load_nbr(const CPlanes& S, uint32_t j) {
+  Nbr n;
+  n.a = at(S.a, j);
+  n.b = at(S.b, j);
+  n.c = at(S.c, j);
+  n.d = at(S.d, j);
+  return n;
+}
+
+// Walks entries k0 + lane, k0 + lane + kGroup, ... < k1 of a CSR row and calls
+// f(record, slot) for each. The gathers are software-pipelined: the index two
+// entries ahead and the record one entry ahead are in flight while f runs.
+template <class Fn>
+__device__ inline void walk_row(const CPlanes& S, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
+                                Fn&& f) {
+  uint64_t k = k0 + group_lane();
+  if (k >= k1) return;
+  const uint64_t last = k;                       // a valid entry, read when past the end
+  uint32_t j = nbr[k];
+  uint64_t kn = k + kGroup;
+  uint32_t jn = nbr[kn < k1 ? kn : last];
+  Nbr cur = load_nbr(S, j);
+  for (;;) {
+    const bool more = kn < k1;
+    const uint64_t knn = kn + kGroup;
+    const uint32_t jnn = nbr[knn < k1 ? knn : last];
+    const Nbr nxt = load_nbr(S, jn);
+    f(cur, j);
+    if (!more) break;
+    cur = nxt;
+    j = jn;
+    jn = jnn;
+    kn = knn;
+  }
+}
+
+// Own position of a row for pair separations: coordinates (FP32 absolute) or
+// offsets plus integer cell (cell-offset positions).
+struct Own {
+  float x, y, z;
+  int32_t cx, cy, cz;
+};
+
+template <bool CELL>
+__device__ inline Own own_pos(float4 a, float4 d) {
+  Own p{a.x, a.y, a.z, 0, 0, 0};
+  if (CELL) {
+    const uint32_t w = __float_as_uint(d.w);
+    p.cx = (int32_t)__float_as_uint(d.z);
+    p.cy = unpack_y(w);
+    p.cz = unpack_z(w);
+  }
+  return p;
+}
+
+// x_i - x_j in FP32: the coordinate difference, plus the cell difference times
+// the cell size for cell-offset positions.
+template <bool CELL>
+__device__ inline void pair_sep(const Own& p, const Nbr& o, float Sf, float& dx, float& dy, float& dz) {
+  dx = p.x - o.a.x;
+  dy = p.y - o.a.y;
+  dz = p.z - o.a.z;
+  if (CELL) {
+    const uint32_t w = __float_as_uint(o.d.w);
+    dx += (float)(p.cx - (int32_t)__float_as_uint(o.d.z)) * Sf;
+    dy += (float)(p.cy - unpack_y(w)) * Sf;
+    dz += (float)(p.cz - unpack_z(w)) * Sf;
+  }
+}
+
+// x + h u for one stored position: FP32 for absolute coordinates; for
+// cell-offset positions the offset is advanced in FP64 and folded back into
+// [0, S) by moving whole cells.
+template <bool CELL>
+__device__ inline void advance_pos(float4& a, float4& d, float h, float ux, float uy, float uz, const Phys& P) {
+  if (!CELL) {
+    a.x += h * ux;
+    a.y += h * uy;
+    a.z += h * uz;
+    return;
+  }
+  const uint32_t w = __float_as_uint(d.w);
+  int32_t c[3] = {(int32_t)__float_as_uint(d.z), unpack_y(w), unpack_z(w)};
+  const float o[3] = {a.x, a.y, a.z}, u[3] = {ux, uy, uz};
+  float on[3];
+  for (int q = 0; q < 3; ++q) {
+    double v = (double)o[q] + (double)h * (double)u[q];
+    const double kk = floor(v * P.invS);
+    v -= kk * P.S;
+    c[q] += (int32_t)kk;
+    on[q] = (float)v;
+  }
+  a.x = on[0];
+  a.y = on[1];
+  a.z = on[2];
+  d.z = __uint_as_float((uint32_t)c[0]);
+  d.w = __uint_as_float(pack_yz(c[1], c[2]));
+}
 
 // ------------------------------------------------------------ markers ---
 __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t* __restrict__ mrows, int64_t n,
                                                                   const int32_t* __restrict__ slot_id, int64_t n_soil,
                                                                   const float4* __restrict__ local,
-                                                                  const Body* __restrict__ bodies,
-                                                                  Rec* __restrict__ A, Rec* __restrict__ B) {
+                                                                  const Body* __restrict__ bodies, Grid g,
+                                                                  Planes A, Planes B) {
   int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
   int32_t s = mrows[r];
   float4 l = local[slot_id[s] - n_soil];
   double x[3];
   body_point(bodies[__float_as_uint(l.w)], l.x, l.y, l.z, x);
-  float4 a = A[s].a;
-  a.x = (float)x[0];
-  a.y = (float)x[1];
-  a.z = (float)x[2];
-  A[s].a = a;
-  B[s].a = a;
+  float4 a = A.a[s], d = A.d[s];
+  store_pos(x, g, a, d);
+  A.a[s] = a;
+  B.a[s] = a;
+  if (g.cell) {
+    A.d[s] = d;
+    B.d[s] = d;
+  }
 }
 
 // Sec. 2.5.1: Adami velocity u~ = sum u_f W / sum W, no-slip u_s = 2 u_body - u~;
 // stress s_s = [sum s_f W - ((g - a_s) . sum rho_f (x_s - x_f) W) I] / sum W.
 // With `partials`, the marker acceleration from the momentum equation over the
-// fluid neighbours (no body force) and the per-block body force and torque.
-template <bool FORCE>
-__global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32_t* __restrict__ mrows, int64_t n,
-                                                const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ woff,
-                                                const uint32_t* __restrict__ nbr, const Body* __restrict__ bodies,
-                                                int32_t nb, Phys P, double* __restrict__ partials) {
-  const int64_t r = xcd_block() * kBlock + threadIdx.x;
-  const bool valid = r < n;
+// soil neighbours (no body force) and the per-block body force and torque.
+template <bool FORCE, bool CELL>
+__global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows, int64_t n,
+                                                const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbr,
+                                                const Body* __restrict__ bodies, int32_t nb, Phys P,
+                                                double* __restrict__ partials) {
+  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+  const int gl = group_lane();
+  const bool live = r < n;
   int body = -1;
-  double fr[6] = {0, 0, 0, 0, 0, 0};
-  if (valid) {
-    const int32_t s = mrows[r];
-    Rec me = S[s];
-    body = (int)(__float_as_uint(me.b.w) >> 2);
-    const Body& B = bodies[body];
-    const float xs = me.a.x, ys = me.a.y, zs = me.a.z;
+  int32_t s = 0;
+  float4 ma = make_float4(0.f, 0.f, 0.f, 0.f), mb = ma, md = ma;
+  uint64_t k0 = 0, k1 = 0;
+  if (live) {
+    s = mrows[r];
+    ma = S.a[s];
+    mb = S.b[s];
+    if (CELL) md = S.d[s];
+    body = (int)(__float_as_uint(mb.w) >> 2);
+    k0 = off[r];
+    k1 = off[r + 1];
+  }
+  const Own me = own_pos<CELL>(ma, md);
+  float sw = 0.f, su0 = 0.f, su1 = 0.f, su2 = 0.f;
+  float ss0 = 0.f, ss1 = 0.f, ss2 = 0.f, ss3 = 0.f, ss4 = 0.f, ss5 = 0.f;
+  float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f;
+  walk_row(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+    float dx, dy, dz;
+    pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
+    const float q = fsqrt(dx * dx + dy * dy + dz * dz) * P.inv_h;
+    const float w = kernel_w(q, P.kw);
+    sw += w;
+    su0 += o.b.x * w; su1 += o.b.y * w; su2 += o.b.z * w;
+    ss0 += o.c.x * w; ss1 += o.c.y * w; ss2 += o.c.z * w;
+    ss3 += o.c.w * w; ss4 += o.d.x * w; ss5 += o.d.y * w;
+    const float rw = o.a.w * w;
+    sr0 += rw * dx; sr1 += rw * dy; sr2 += rw * dz;
+  });
+  sw = group_sum(sw);
+  su0 = group_sum(su0); su1 = group_sum(su1); su2 = group_sum(su2);
+  ss0 = group_sum(ss0); ss1 = group_sum(ss1); ss2 = group_sum(ss2);
+  ss3 = group_sum(ss3); ss4 = group_sum(ss4); ss5 = group_sum(ss5);
+  sr0 = group_sum(sr0); sr1 = group_sum(sr1); sr2 = group_sum(sr2);
+  double rv[3] = {0.0, 0.0, 0.0};
+  float us[3] = {0.f, 0.f, 0.f}, sg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (live) {
+    const Body& Bd = bodies[body];
     // body velocity and acceleration at the marker (FP64 lever arm)
-    double rv[3] = {(double)xs - B.X[0], (double)ys - B.X[1], (double)zs - B.X[2]};
-    double wr[3] = {B.W[1] * rv[2] - B.W[2] * rv[1], B.W[2] * rv[0] - B.W[0] * rv[2],
-                    B.W[0] * rv[1] - B.W[1] * rv[0]};
-    double wwr[3] = {B.W[1] * wr[2] - B.W[2] * wr[1], B.W[2] * wr[0] - B.W[0] * wr[2],
-                     B.W[0] * wr[1] - B.W[1] * wr[0]};
+    if (CELL) {
+      rv[0] = from_cell(me.cx, me.x, P.lo[0], P.S) - Bd.X[0];
+      rv[1] = from_cell(me.cy, me.y, P.lo[1], P.S) - Bd.X[1];
+      rv[2] = from_cell(me.cz, me.z, P.lo[2], P.S) - Bd.X[2];
+    } else {
+      rv[0] = (double)me.x - Bd.X[0];
+      rv[1] = (double)me.y - Bd.X[1];
+      rv[2] = (double)me.z - Bd.X[2];
+    }
+    double wr[3] = {Bd.W[1] * rv[2] - Bd.W[2] * rv[1], Bd.W[2] * rv[0] - Bd.W[0] * rv[2],
+                    Bd.W[0] * rv[1] - Bd.W[1] * rv[0]};
+    double wwr[3] = {Bd.W[1] * wr[2] - Bd.W[2] * wr[1], Bd.W[2] * wr[0] - Bd.W[0] * wr[2],
+                     Bd.W[0] * wr[1] - Bd.W[1] * wr[0]};
     float ub[3], as[3];
-    for (int a = 0; a < 3; ++a) ub[a] = (float)(B.V[a] + wr[a]);
-    if (B.has_acc) {
-      double ar[3] = {B.Al[1] * rv[2] - B.Al[2] * rv[1], B.Al[2] * rv[0] - B.Al[0] * rv[2],
-                      B.Al[0] * rv[1] - B.Al[1] * rv[0]};
-      for (int a = 0; a < 3; ++a) as[a] = (float)(B.A[a] + ar[a] + wwr[a]);
+    for (int a = 0; a < 3; ++a) ub[a] = (float)(Bd.V[a] + wr[a]);
+    if (Bd.has_acc) {
+      double ar[3] = {Bd.Al[1] * rv[2] - Bd.Al[2] * rv[1], Bd.Al[2] * rv[0] - Bd.Al[0] * rv[2],
+                      Bd.Al[0] * rv[1] - Bd.Al[1] * rv[0]};
+      for (int a = 0; a < 3; ++a) as[a] = (float)(Bd.A[a] + ar[a] + wwr[a]);
     } else {
       for (int a = 0; a < 3; ++a) as[a] = (float)wwr[a];
     }
-    const uint32_t c = cnt[r];
-    const uint32_t* lp = nbr + woff[r / kWave] + (r % kWave);
-    float sw = 0.f, su0 = 0.f, su1 = 0.f, su2 = 0.f;
-    float ss0 = 0.f, ss1 = 0.f, ss2 = 0.f, ss3 = 0.f, ss4 = 0.f, ss5 = 0.f;
-    float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f;
-    for (uint32_t k = 0; k < c; ++k) {
-      const uint32_t j = lp[(size_t)k * kWave];
-      const Rec o = S[j];
-      if ((__float_as_uint(o.b.w) & 3u) == kMarker) continue;
-      const float dx = xs - o.a.x, dy = ys - o.a.y, dz = zs - o.a.z;
-      const float q = fsqrt(dx * dx + dy * dy + dz * dz) * P.inv_h;
-      const float w = kernel_w(q, P.kw);
-      sw += w;
-      su0 += o.b.x * w; su1 += o.b.y * w; su2 += o.b.z * w;
-      ss0 += o.c.x * w; ss1 += o.c.y * w; ss2 += o.c.z * w;
-      ss3 += o.c.w * w; ss4 += o.d.x * w; ss5 += o.d.y * w;
-      const float rw = o.a.w * w;
-      sr0 += rw * dx; sr1 += rw * dy; sr2 += rw * dz;
-    }
-    float us[3], sg[6];
     if (sw > 0.f) {
       const float iw = 1.0f / sw;
       const float gd = ((P.gx - as[0]) * sr0 + (P.gy - as[1]) * sr1) + (P.gz - as[2]) * sr2;
@@ -542,43 +782,44 @@ __global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32
       sg[3] = ss3 * iw; sg[4] = ss4 * iw; sg[5] = ss5 * iw;
     } else {
       us[0] = ub[0]; us[1] = ub[1]; us[2] = ub[2];
-      for (int a = 0; a < 6; ++a) sg[a] = 0.f;
     }
-    me.b.x = us[0]; me.b.y = us[1]; me.b.z = us[2];
-    me.c = make_float4(sg[0], sg[1], sg[2], sg[3]);
-    me.d.x = sg[4]; me.d.y = sg[5];
-    S[s].b = me.b;
-    S[s].c = me.c;
-    S[s].d = me.d;
-    if (FORCE) {
-      // Momentum equation at the marker (F3) with artificial viscosity,
-      // fluid neighbours only: a_s = (1/rho_s) sum V_f (s_s + s_f) gradW + Pi.
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-      const float rhos = me.a.w;
-      for (uint32_t k = 0; k < c; ++k) {
-        const uint32_t j = lp[(size_t)k * kWave];
-        const Rec o = S[j];
-        if ((__float_as_uint(o.b.w) & 3u) == kMarker) continue;
-        const float dx = xs - o.a.x, dy = ys - o.a.y, dz = zs - o.a.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float q = fsqrt(r2) * P.inv_h;
-        const float F = kernel_f(q, P.kf);
-        const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;
-        const float wx = VF * dx, wy = VF * dy, wz = VF * dz;
-        const float sxx = sg[0] + o.c.x, syy = sg[1] + o.c.y, szz = sg[2] + o.c.z;
-        const float sxy = sg[3] + o.c.w, sxz = sg[4] + o.d.x, syz = sg[5] + o.d.y;
-        a0 += sxx * wx + sxy * wy + sxz * wz;
-        a1 += sxy * wx + syy * wy + syz * wz;
-        a2 += sxz * wx + syz * wy + szz * wz;
-        if (P.av_mode != 0) {
-          const float vr = (us[0] - o.b.x) * dx + (us[1] - o.b.y) * dy + (us[2] - o.b.z) * dz;
-          if (P.av_mode == 1 || vr < 0.f) {
-            const float cf = P.av_coef * vr * F *
-                             __builtin_amdgcn_rcpf(0.5f * (rhos + o.a.w) * (r2 + P.xi2));
-            v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
-          }
-        }
-      }
+    if (gl == 1) S.b[s] = make_float4(us[0], us[1], us[2], mb.w);
+    if (gl == 2) S.c[s] = make_float4(sg[0], sg[1], sg[2], sg[3]);
+    if (gl == 3) {
+      float4 d = S.d[s];
+      d.x = sg[4];
+      d.y = sg[5];
+      S.d[s] = d;
+    }
+  }
+  if (FORCE) {
+    // Momentum equation at the marker (F3) with artificial viscosity, soil
+    // neighbours only: a_s = (1/rho_s) sum V_f (s_s + s_f) gradW + Pi.
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    const float rhos = live ? ma.w : 1.0f;
+    walk_row(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+      float dx, dy, dz;
+      pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float q = fsqrt(r2) * P.inv_h;
+      const float F = kernel_f(q, P.kf);
+      const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;
+      const float wx = VF * dx, wy = VF * dy, wz = VF * dz;
+      const float sxx = sg[0] + o.c.x, syy = sg[1] + o.c.y, szz = sg[2] + o.c.z;
+      const float sxy = sg[3] + o.c.w, sxz = sg[4] + o.d.x, syz = sg[5] + o.d.y;
+      a0 += sxx * wx + sxy * wy + sxz * wz;
+      a1 += sxy * wx + syy * wy + syz * wz;
+      a2 += sxz * wx + syz * wy + szz * wz;
+      const float vr = (us[0] - o.b.x) * dx + (us[1] - o.b.y) * dy + (us[2] - o.b.z) * dz;
+      const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
+      const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhos + o.a.w) * (r2 + P.xi2)) : 0.f;
+      v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
+    });
+    a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
+    v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
+    double fr[6] = {0, 0, 0, 0, 0, 0};
+    const bool owner = live && gl == 0;
+    if (owner) {
       const float ir = 1.0f / rhos;
       const double f0 = (double)P.m * (double)(a0 * ir + v0);
       const double f1 = (double)P.m * (double)(a1 * ir + v1);
@@ -588,25 +829,25 @@ __global__ __launch_bounds__(kBlock) void k_bce(Rec* __restrict__ S, const int32
       fr[4] = rv[2] * f0 - rv[0] * f2;
       fr[5] = rv[0] * f1 - rv[1] * f0;
     }
-  }
-  if (FORCE) {
+    const int ob_ = owner ? body : -1;
     // Deterministic per-block sums per body (fixed tree order, no float atomics).
     __shared__ double red[6][kBlock];
     const int t = threadIdx.x;
+    const int64_t blk = xcd_block();
     for (int b = 0; b < nb; ++b) {
-      const int any = __syncthreads_or(body == b);
+      const int any = __syncthreads_or(ob_ == b);
       if (!any) {
-        if (t < 6) partials[(xcd_block() * nb + b) * 6 + t] = 0.0;
+        if (t < 6) partials[(blk * nb + b) * 6 + t] = 0.0;
         continue;
       }
-      for (int a = 0; a < 6; ++a) red[a][t] = (body == b) ? fr[a] : 0.0;
+      for (int a = 0; a < 6; ++a) red[a][t] = (ob_ == b) ? fr[a] : 0.0;
       __syncthreads();
       for (int o = kBlock / 2; o > 0; o >>= 1) {
         if (t < o)
           for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + o];
         __syncthreads();
       }
-      if (t < 6) partials[(xcd_block() * nb + b) * 6 + t] = red[t][0];
+      if (t < 6) partials[(blk * nb + b) * 6 + t] = red[t][0];
       __syncthreads();
     }
   }
@@ -631,8 +872,8 @@ __global__ __launch_bounds__(kBlock) void k_body_reduce(const double* __restrict
 
 // ------------------------------------------------------------- fluid ---
 struct Rates {
-  float dx, dy, dz;           // position rate = own velocity
-  float ax, ay, az;           // acceleration
+  float dx, dy, dz;              // position rate = own velocity
+  float ax, ay, az;              // acceleration
   float s0, s1, s2, s3, s4, s5;  // stress rate
   float drho;
 };
@@ -641,22 +882,24 @@ struct Rates {
 // a = (1/rho_i) sum_j V_j (s_i + s_j) . gradW + g + Pi_a (F3, artificial viscosity
 // with the sign that repels approaching pairs); ds/dt = Om s - s Om + 2G D +
 // (bulk K - 2G/3) tr D I with D, Om the symmetric and skew parts of L.
-__device__ inline Rates fluid_rhs(const Rec& me, const Rec* __restrict__ S, uint32_t c,
-                                  const uint32_t* __restrict__ lp, const Phys& P) {
-  const float xi = me.a.x, yi = me.a.y, zi = me.a.z, rhoi = me.a.w;
-  const float ux = me.b.x, uy = me.b.y, uz = me.b.z;
-  const float s0 = me.c.x, s1 = me.c.y, s2 = me.c.z, s3 = me.c.w, s4 = me.d.x, s5 = me.d.y;
+// The group's lanes take the row's neighbours k = lane, lane + kGroup, ...
+template <bool CELL>
+__device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, CPlanes S, uint64_t k0,
+                                  uint64_t k1, const uint32_t* __restrict__ nbr, const Phys& P) {
+  const Own me = own_pos<CELL>(ma, md);
+  const float rhoi = ma.w;
+  const float ux = mb.x, uy = mb.y, uz = mb.z;
+  const float s0 = mc.x, s1 = mc.y, s2 = mc.z, s3 = mc.w, s4 = md.x, s5 = md.y;
   float L00 = 0.f, L01 = 0.f, L02 = 0.f, L10 = 0.f, L11 = 0.f, L12 = 0.f, L20 = 0.f, L21 = 0.f, L22 = 0.f;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-  for (uint32_t k = 0; k < c; ++k) {
-    const uint32_t j = lp[(size_t)k * kWave];
-    const Rec o = S[j];
-    const float dx = xi - o.a.x, dy = yi - o.a.y, dz = zi - o.a.z;
+  walk_row(S, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+    float dx, dy, dz;
+    pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float q = fsqrt(r2) * P.inv_h;
     const float F = kernel_f(q, P.kf);
     const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;   // V_j * (gradW / r_ij)
-    const float wx = VF * dx, wy = VF * dy, wz = VF * dz;      // V_j grad_i W_ij
+    const float wx = VF * dx, wy = VF * dy, wz = VF * dz;       // V_j grad_i W_ij
     const float dux = o.b.x - ux, duy = o.b.y - uy, duz = o.b.z - uz;
     L00 += dux * wx; L01 += dux * wy; L02 += dux * wz;
     L10 += duy * wx; L11 += duy * wy; L12 += duy * wz;
@@ -666,14 +909,16 @@ __device__ inline Rates fluid_rhs(const Rec& me, const Rec* __restrict__ S, uint
     a0 += sxx * wx + sxy * wy + sxz * wz;
     a1 += sxy * wx + syy * wy + syz * wz;
     a2 += sxz * wx + syz * wy + szz * wz;
-    if (P.av_mode != 0) {
-      const float vr = -(dux * dx + duy * dy + duz * dz);      // v_ij . r_ij
-      if (P.av_mode == 1 || vr < 0.f) {
-        const float cf = P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhoi + o.a.w) * (r2 + P.xi2));
-        v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
-      }
-    }
-  }
+    const float vr = -(dux * dx + duy * dy + duz * dz);         // v_ij . r_ij
+    const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
+    const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhoi + o.a.w) * (r2 + P.xi2)) : 0.f;
+    v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
+  });
+  L00 = group_sum(L00); L01 = group_sum(L01); L02 = group_sum(L02);
+  L10 = group_sum(L10); L11 = group_sum(L11); L12 = group_sum(L12);
+  L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
+  a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
+  v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
   Rates R;
   const float ir = 1.0f / rhoi;
   R.dx = ux; R.dy = uy; R.dz = uz;
@@ -740,66 +985,101 @@ __device__ inline void return_map(float st[6], const float sn[6], const Phys& P)
 }
 
 // Stage 1 of the explicit midpoint rule (Sec. 2.3): B = A + dt/2 f(A).
-__global__ __launch_bounds__(kBlock) void k_fluid_stage1(const Rec* __restrict__ A, Rec* __restrict__ B,
-                                                         const int32_t* __restrict__ rows, int64_t n,
-                                                         const uint32_t* __restrict__ cnt,
-                                                         const uint64_t* __restrict__ woff,
+// Lanes 0-3 of the group write the four planes of the row's record.
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
+                                                         int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P) {
-  const int64_t r = xcd_block() * kBlock + threadIdx.x;
-  if (r >= n) return;
-  const int32_t s = rows[r];
-  const Rec me = A[s];
-  const Rates R = fluid_rhs(me, A, cnt[r], nbr + woff[r / kWave] + (r % kWave), P);
+  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+  const int gl = group_lane();
+  const bool live = r < n;
+  int32_t s = 0;
+  uint64_t k0 = 0, k1 = 0;
+  float4 ma = make_float4(0.f, 0.f, 0.f, 1.f), mb = make_float4(0.f, 0.f, 0.f, 0.f), mc = mb, md = mb;
+  if (live) {
+    s = rows[r];
+    ma = A.a[s]; mb = A.b[s]; mc = A.c[s]; md = A.d[s];
+    k0 = off[r];
+    k1 = off[r + 1];
+  }
+  const Rates R = fluid_rhs<CELL>(ma, mb, mc, md, A, k0, k1, nbr, P);
+  if (!live) return;
   const float h = P.half_dt;
-  Rec o;
-  o.a = make_float4(me.a.x + h * R.dx, me.a.y + h * R.dy, me.a.z + h * R.dz, me.a.w + h * R.drho);
-  o.b = make_float4(me.b.x + h * R.ax, me.b.y + h * R.ay, me.b.z + h * R.az, me.b.w);
-  o.c = make_float4(me.c.x + h * R.s0, me.c.y + h * R.s1, me.c.z + h * R.s2, me.c.w + h * R.s3);
-  o.d = make_float4(me.d.x + h * R.s4, me.d.y + h * R.s5, me.d.z, me.d.w);
-  B[s] = o;
+  float4 na = ma, nd = md;
+  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
+  na.w = ma.w + h * R.drho;
+  nd.x = md.x + h * R.s4;
+  nd.y = md.y + h * R.s5;
+  if (gl == 0) B.a[s] = na;
+  else if (gl == 1) B.b[s] = make_float4(mb.x + h * R.ax, mb.y + h * R.ay, mb.z + h * R.az, mb.w);
+  else if (gl == 2) B.c[s] = make_float4(mc.x + h * R.s0, mc.y + h * R.s1, mc.z + h * R.s2, mc.w + h * R.s3);
+  else if (gl == 3) B.d[s] = nd;
 }
 
 // Stage 2: A = A + dt f(B), then the return mapping on the stress.
-__global__ __launch_bounds__(kBlock) void k_fluid_stage2(const Rec* __restrict__ B, Rec* __restrict__ A,
-                                                         const int32_t* __restrict__ rows, int64_t n,
-                                                         const uint32_t* __restrict__ cnt,
-                                                         const uint64_t* __restrict__ woff,
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
+                                                         int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P) {
-  const int64_t r = xcd_block() * kBlock + threadIdx.x;
-  if (r >= n) return;
-  const int32_t s = rows[r];
-  const Rec mid = B[s];
-  const Rates R = fluid_rhs(mid, B, cnt[r], nbr + woff[r / kWave] + (r % kWave), P);
-  const Rec y = A[s];
+  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+  const int gl = group_lane();
+  const bool live = r < n;
+  int32_t s = 0;
+  uint64_t k0 = 0, k1 = 0;
+  float4 ma = make_float4(0.f, 0.f, 0.f, 1.f), mb = make_float4(0.f, 0.f, 0.f, 0.f), mc = mb, md = mb;
+  if (live) {
+    s = rows[r];
+    ma = B.a[s]; mb = B.b[s]; mc = B.c[s]; md = B.d[s];
+    k0 = off[r];
+    k1 = off[r + 1];
+  }
+  const Rates R = fluid_rhs<CELL>(ma, mb, mc, md, B, k0, k1, nbr, P);
+  if (!live) return;
   const float h = P.dt;
-  float sn[6] = {y.c.x, y.c.y, y.c.z, y.c.w, y.d.x, y.d.y};
-  float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
-                 sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-  return_map(st, sn, P);
-  Rec o;
-  o.a = make_float4(y.a.x + h * R.dx, y.a.y + h * R.dy, y.a.z + h * R.dz, y.a.w + h * R.drho);
-  o.b = make_float4(y.b.x + h * R.ax, y.b.y + h * R.ay, y.b.z + h * R.az, y.b.w);
-  o.c = make_float4(st[0], st[1], st[2], st[3]);
-  o.d = make_float4(st[4], st[5], y.d.z, y.d.w);
-  A[s] = o;
+  if (gl == 0 || gl == 3) {
+    float4 ya = A.a[s], yd = A.d[s];
+    advance_pos<CELL>(ya, yd, h, R.dx, R.dy, R.dz, P);
+    if (gl == 0) {
+      ya.w += h * R.drho;
+      A.a[s] = ya;
+    } else {
+      const float4 yc = A.c[s];
+      const float4 yd0 = A.d[s];
+      float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd0.x, yd0.y};
+      float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
+                     sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
+      return_map(st, sn, P);
+      A.d[s] = make_float4(st[4], st[5], yd.z, yd.w);
+    }
+  } else if (gl == 1) {
+    const float4 yb = A.b[s];
+    A.b[s] = make_float4(yb.x + h * R.ax, yb.y + h * R.ay, yb.z + h * R.az, yb.w);
+  } else if (gl == 2) {
+    const float4 yc = A.c[s], yd = A.d[s];
+    float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
+    float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
+                   sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
+    return_map(st, sn, P);
+    A.c[s] = make_float4(st[0], st[1], st[2], st[3]);
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const Rec* __restrict__ src, const int32_t* __restrict__ rows,
-                                                    int64_t n, const int32_t* __restrict__ slot_id,
+__global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* __restrict__ rows, int64_t n,
+                                                    const int32_t* __restrict__ slot_id,
                                                     float4* __restrict__ m_a, float4* __restrict__ m_b,
                                                     float4* __restrict__ m_c, float4* __restrict__ m_d) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
   const int32_t s = rows[r];
   const int32_t id = slot_id[s];
-  const Rec v = src[s];
-  m_a[id] = v.a;
-  m_b[id] = v.b;
-  m_c[id] = v.c;
-  m_d[id] = v.d;
+  m_a[id] = src.a[s];
+  m_b[id] = src.b[s];
+  m_c[id] = src.c[s];
+  m_d[id] = src.d[s];
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned nblk_groups(int64_t rows) { return nblk(rows * kGroup); }
 
 }  // namespace
 
@@ -827,17 +1107,17 @@ hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStr
   return hipGetLastError();
 }
 
-hipError_t place_markers_master(const float4* local, int64_t nm, int64_t n_soil, const Body* bodies,
-                                float4* m_a, hipStream_t s) {
+hipError_t place_markers_master(const float4* local, int64_t nm, int64_t n_soil, const Body* bodies, Grid g,
+                                float4* m_a, float4* m_d, hipStream_t s) {
   if (nm <= 0) return hipSuccess;
-  k_place_markers_master<<<nblk(nm), kBlock, 0, s>>>(local, nm, n_soil, bodies, m_a);
+  k_place_markers_master<<<nblk(nm), kBlock, 0, s>>>(local, nm, n_soil, bodies, g, m_a, m_d);
   return hipGetLastError();
 }
 
-hipError_t activity_flags(const float4* m_a, int64_t n, const Body* bodies, int32_t nb, Grid g,
+hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
                           uint8_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_activity<<<nblk(n), kBlock, 0, s>>>(m_a, n, bodies, nb, g, flags);
+  k_activity<<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
   return hipGetLastError();
 }
 
@@ -856,10 +1136,10 @@ hipError_t compact_kind(const float4* pos4, int64_t n, uint32_t kind, int32_t* r
   return compact_impl(PredKind{pos4, kind}, n, rows, count_dst, tmp, s);
 }
 
-hipError_t hash_count(const int32_t* ids, int64_t n, const float4* m_a, Grid g, uint32_t* key,
+hipError_t hash_count(const int32_t* ids, int64_t n, const float4* m_a, const float4* m_d, Grid g, uint32_t* key,
                       uint32_t* rank, uint32_t* cnt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_hash_count<<<nblk(n), kBlock, 0, s>>>(ids, n, m_a, g, key, rank, cnt);
+  k_hash_count<<<nblk(n), kBlock, 0, s>>>(ids, n, m_a, m_d, g, key, rank, cnt);
   return hipGetLastError();
 }
 
@@ -872,46 +1152,58 @@ hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_
 
 hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* ids, const uint32_t* cs,
                          int64_t n, int64_t n_soil, const uint8_t* flags, const float4* m_a,
-                         const float4* m_b, const float4* m_c, const float4* m_d, Rec* A, Rec* B,
-                         float4* pos4, int32_t* slot_id, uint32_t* skey, hipStream_t s) {
+                         const float4* m_b, const float4* m_c, const float4* m_d, Planes A, Planes B,
+                         float4* pos4, int4* cpos, int32_t* slot_id, uint32_t* skey, bool cell, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_gather_sorted<<<nblk(n), kBlock, 0, s>>>(tmp, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d, A, B,
-                                             pos4, slot_id, skey);
+                                             pos4, cpos, cell ? 1 : 0, slot_id, skey);
   return hipGetLastError();
 }
+
+size_t stash_elems(int64_t rows_cap) { return (size_t)rows_cap * kStash; }
 
 hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
-                     const uint32_t* skey, const uint32_t* cs, Grid g, bool soil_only, uint32_t* cnt,
-                     uint32_t* wave_len, hipStream_t s) {
+                     const int4* cpos, const uint32_t* skey, const uint32_t* cs, Grid g, bool soil_only,
+                     uint32_t* cnt, uint32_t* stash, hipStream_t s) {
   if (rows_cap <= 0) return hipSuccess;
-  k_nbr_count<<<nblk(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, skey, cs, g, soil_only ? 1 : 0,
-                                                cnt, wave_len);
+  k_nbr_count<<<nblk_groups(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs, g,
+                                                       soil_only ? 1 : 0, cnt, stash);
   return hipGetLastError();
 }
 
-hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const uint32_t* skey,
-                    const uint32_t* cs, Grid g, bool soil_only, const uint64_t* woff, uint32_t* nbr, hipStream_t s) {
+hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos, const uint32_t* skey,
+                    const uint32_t* cs, Grid g, bool soil_only, const uint32_t* cnt, const uint32_t* stash,
+                    const uint64_t* off, uint32_t* nbr, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  k_nbr_fill<<<nblk(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, skey, cs, g, soil_only ? 1 : 0, woff, nbr);
+  k_nbr_fill<<<nblk_groups(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, cpos, skey, cs, g, soil_only ? 1 : 0, cnt,
+                                                    stash, off, nbr);
   return hipGetLastError();
 }
 
 hipError_t place_markers_working(const int32_t* mrows, int64_t n, const int32_t* slot_id, int64_t n_soil,
-                                 const float4* local, const Body* bodies, Rec* A, Rec* B, hipStream_t s) {
+                                 const float4* local, const Body* bodies, Grid g, Planes A, Planes B, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_place_markers_working<<<nblk(n), kBlock, 0, s>>>(mrows, n, slot_id, n_soil, local, bodies, A, B);
+  k_place_markers_working<<<nblk(n), kBlock, 0, s>>>(mrows, n, slot_id, n_soil, local, bodies, g, A, B);
   return hipGetLastError();
 }
 
-int64_t bce_blocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
+int64_t bce_blocks(int64_t n) { return nblk_groups(n); }
 
-hipError_t bce(Rec* S, const int32_t* mrows, int64_t n, const uint32_t* cnt, const uint64_t* woff,
-               const uint32_t* nbr, const Body* bodies, int32_t nb, Phys P, double* partials, hipStream_t s) {
+hipError_t bce(Planes S, const int32_t* mrows, int64_t n, const uint64_t* off, const uint32_t* nbr,
+               const Body* bodies, int32_t nb, Phys P, double* partials, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (partials)
-    k_bce<true><<<nblk(n), kBlock, 0, s>>>(S, mrows, n, cnt, woff, nbr, bodies, nb, P, partials);
-  else
-    k_bce<false><<<nblk(n), kBlock, 0, s>>>(S, mrows, n, cnt, woff, nbr, bodies, nb, P, nullptr);
+  const unsigned gsz = nblk_groups(n);
+  if (P.cell) {
+    if (partials)
+      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, partials);
+    else
+      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, nullptr);
+  } else {
+    if (partials)
+      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, partials);
+    else
+      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -921,21 +1213,27 @@ hipError_t body_reduce(const double* partials, int64_t nblocks, int32_t nb, doub
   return hipGetLastError();
 }
 
-hipError_t fluid_stage1(const Rec* A, Rec* B, const int32_t* rows, int64_t n, const uint32_t* cnt,
-                        const uint64_t* woff, const uint32_t* nbr, Phys P, hipStream_t s) {
+hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off,
+                        const uint32_t* nbr, Phys P, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_fluid_stage1<<<nblk(n), kBlock, 0, s>>>(A, B, rows, n, cnt, woff, nbr, P);
+  if (P.cell)
+    k_fluid_stage1<true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P);
+  else
+    k_fluid_stage1<false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P);
   return hipGetLastError();
 }
 
-hipError_t fluid_stage2(const Rec* B, Rec* A, const int32_t* rows, int64_t n, const uint32_t* cnt,
-                        const uint64_t* woff, const uint32_t* nbr, Phys P, hipStream_t s) {
+hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off,
+                        const uint32_t* nbr, Phys P, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_fluid_stage2<<<nblk(n), kBlock, 0, s>>>(B, A, rows, n, cnt, woff, nbr, P);
+  if (P.cell)
+    k_fluid_stage2<true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P);
+  else
+    k_fluid_stage2<false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P);
   return hipGetLastError();
 }
 
-hipError_t scatter_rows(const Rec* src, const int32_t* rows, int64_t n, const int32_t* slot_id, float4* m_a,
+hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n, const int32_t* slot_id, float4* m_a,
                         float4* m_b, float4* m_c, float4* m_d, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_scatter<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_a, m_b, m_c, m_d);

@@ -42,7 +42,7 @@ DEFAULT_PARAMS = dict(
     domain_lo=(0.0, 0.0, 0.0), domain_hi=(1.0, 1.0, 1.0),
     active_domains=0, t_delay=0.0,
     grow_G=1.2, shrink_S=0.75, shrink_interval=50,
-    bulk_coeff=1.0,
+    bulk_coeff=1.0, pos_mode=0,
 )
 
 
@@ -86,15 +86,22 @@ def _f32(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
 
 
-def lattice(nx, ny, nz, dx, origin=(0.0, 0.0, 0.0), jitter=0.05, seed=0):
-    """Cell-centred cubic lattice, x fastest, with uniform jitter of +-jitter*dx per axis."""
+def lattice(nx, ny, nz, dx, origin=(0.0, 0.0, 0.0), jitter=0.05, seed=0, fp64=False):
+    """Cell-centred cubic lattice, x fastest, with uniform jitter of +-jitter*dx per axis.
+
+    The lattice is built relative to `origin` and rounded to FP32 there; with
+    fp64 the origin is added afterwards in FP64 (positions far from the
+    coordinate origin, for cell-offset positions), else the result is FP32."""
     ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
     p = np.stack([ix.ravel(order="F"), iy.ravel(order="F"), iz.ravel(order="F")], axis=1)
-    p = (p.astype(np.float64) + 0.5) * dx + np.asarray(origin, dtype=np.float64)
+    p = (p.astype(np.float64) + 0.5) * dx
     if jitter:
         rng = np.random.default_rng(seed)
         p = p + rng.uniform(-jitter * dx, jitter * dx, size=p.shape)
-    return _f32(p)
+    p = _f32(p).astype(np.float64)
+    if fp64:
+        return np.ascontiguousarray(p + np.asarray(origin, dtype=np.float64))
+    return _f32(p + np.asarray(origin, dtype=np.float64))
 
 
 def box_container(nx, ny, nz_wall, dx, layers=3):
@@ -172,16 +179,20 @@ def _params(**over):
     return p
 
 
-def column(seed=0, n=16, jitter=0.05, ps_freq=1, dx=0.01, walls=True):
-    """Granular column: n^3 soil particles in a 3-layer marker box (column settling)."""
+def column(seed=0, n=16, jitter=0.05, ps_freq=1, dx=0.01, walls=True, origin=None, pos_mode=0):
+    """Granular column: n^3 soil particles in a 3-layer marker box (column settling).
+
+    With `origin` the whole column (soil, container and domain) is translated
+    there, positions staying FP64 (far-from-origin terrain)."""
     h = 1.2 * dx
-    pos = lattice(n, n, n, dx, jitter=jitter, seed=seed)
+    o = np.zeros(3) if origin is None else np.asarray(origin, dtype=np.float64)
+    pos = lattice(n, n, n, dx, jitter=jitter, seed=seed, origin=o, fp64=origin is not None)
     bodies = []
     if walls:
-        bodies.append(Body(markers=box_container(n, n, n, dx), name="container"))
-    lo = (-4 * dx, -4 * dx, -4 * dx)
-    hi = ((n + 4) * dx, (n + 4) * dx, (n + 4) * dx)
-    params = _params(dx=dx, h=h, ps_freq=ps_freq, domain_lo=lo, domain_hi=hi)
+        bodies.append(Body(markers=box_container(n, n, n, dx), pos=tuple(o), name="container"))
+    lo = tuple(o + np.array([-4 * dx, -4 * dx, -4 * dx]))
+    hi = tuple(o + np.array([(n + 4) * dx, (n + 4) * dx, (n + 4) * dx]))
+    params = _params(dx=dx, h=h, ps_freq=ps_freq, domain_lo=lo, domain_hi=hi, pos_mode=pos_mode)
     return Scene("column", params, pos, bodies=bodies,
                  meta=dict(n_lattice=(n, n, n), seed=seed))
 

@@ -15,7 +15,7 @@ def normwise(a, b):
 def world_positions(scene):
     """Soil positions and marker positions at the scenes' initial poses (identity
     rotations only), in FP64, in particle-id order."""
-    parts = [scene.pos.astype(np.float64)]
+    parts = [np.asarray(scene.pos, dtype=np.float64)]
     for b in scene.bodies:
         assert np.allclose(b.quat, (1.0, 0.0, 0.0, 0.0))
         parts.append(np.asarray(b.pos, dtype=np.float64) + b.markers.astype(np.float64))

@@ -1,0 +1,119 @@
+"""Cell-index + FP32-offset positions (pos_mode 1) against the FP64 oracle.
+
+Far from the coordinate origin (a column placed at x = 9,999 m, where the FP32
+spacing is 0.98 mm, larger than the motion of a step) the cell-offset form
+keeps the motion: displacements, velocities, stresses and densities match the
+oracle to the same bars as the plain form near the origin, while the plain
+FP32 form loses the displacements there. Integer decisions (cells, neighbour
+lists) are bit-exact, taken on the stored representation on both sides.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.oracle import Oracle
+from paper_2507_05643_amd import scenes
+from tests.parity_util import csr_rows, normwise, world_positions
+
+pytestmark = pytest.mark.gpu
+FAR = (9999.0, 0.0, 0.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def crm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_05643_amd import crm as C
+    return C
+
+
+def _local_report(g, r, origin, n):
+    """Normwise errors with positions taken relative to the column's origin, the
+    same normalisation as for a column placed at the coordinate origin."""
+    o = np.asarray(origin, dtype=np.float64)
+    return dict(pos=normwise(g["pos"][:n] - o, r["pos"][:n] - o),
+                vel=normwise(g["vel"][:n], r["vel"][:n]),
+                sigma=normwise(g["sigma"][:n], r["sigma"][:n]),
+                rho=normwise(g["rho"][:n], r["rho"][:n]))
+
+
+@pytest.mark.parametrize("origin", [None, FAR])
+def test_cell_offset_lists_bit_exact(crm, origin):
+    sc = scenes.column(seed=2, origin=origin, pos_mode=1)
+    sim = crm.Simulation(sc)
+    sim.step(1)
+    ex = sim.export()
+    x = world_positions(sc)
+    sid, skey, cs, ce = O.sort_cells(sc.params, x)
+    assert np.array_equal(ex["sorted_ids"], sid)
+    assert np.array_equal(ex["cell_start"][:-1].astype(np.int64), cs)
+    off, nbr = O.neighbors(sc.params, x, mode="cells")
+    ref = csr_rows(off, nbr)
+    got = csr_rows(ex["off"], ex["nbr"], ex["rows"])
+    for i in range(sc.n_total):
+        want = ref[i] if i < sc.n_soil else ref[i][ref[i] < sc.n_soil]
+        assert np.array_equal(got[i], want), i
+    sim.close()
+
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-5), (100, 1e-3)])
+def test_cell_offset_parity_far_from_origin(crm, steps, tol):
+    sc = scenes.column(seed=0, origin=FAR, pos_mode=1)
+    sim = crm.Simulation(sc)
+    orc = Oracle(sc, nbr_mode="cells")
+    sim.step(steps)
+    orc.step(steps)
+    rep = _local_report(sim.state(), orc.state(), FAR, sc.n_soil)
+    say("cell-offset at 9999 m", steps, rep)
+    for k, v in rep.items():
+        assert v <= tol, (k, v)
+    F, _ = sim.forces()
+    Fr, _ = orc.forces()
+    assert normwise(F, Fr) <= tol
+    sim.close()
+
+
+def test_cell_offset_equals_plain_near_origin(crm):
+    """Near the origin both forms resolve the motion and agree to FP32 rounding."""
+    a = scenes.column(seed=1, pos_mode=1)
+    b = scenes.column(seed=1, pos_mode=0)
+    sa, sb = crm.Simulation(a), crm.Simulation(b)
+    sa.step(50)
+    sb.step(50)
+    ga, gb = sa.state(), sb.state()
+    x0 = world_positions(a)
+    n = a.n_soil
+    assert normwise(ga["pos"][:n] - x0[:n], gb["pos"][:n] - x0[:n]) < 1e-4
+    assert normwise(ga["sigma"][:n], gb["sigma"][:n]) < 1e-4
+    sa.close()
+    sb.close()
+
+
+def test_plain_fp32_loses_motion_far_from_origin(crm):
+    """The reason for the cell-offset form: at 9,999 m the FP32 spacing (0.98 mm)
+    exceeds the per-step motion, so plain FP32 positions stop moving, while the
+    cell-offset form tracks the oracle's displacements."""
+    errs = {}
+    for mode in (0, 1):
+        sc = scenes.column(seed=0, origin=FAR, pos_mode=mode)
+        x0 = world_positions(sc)
+        sim = crm.Simulation(sc)
+        orc = Oracle(sc, nbr_mode="cells")
+        sim.step(40)
+        orc.step(40)
+        g, r = sim.state(), orc.state()
+        n = sc.n_soil
+        disp_ref = r["pos"][:n] - x0[:n]
+        assert np.abs(disp_ref[:, 2]).max() > 1e-7
+        errs[mode] = normwise(g["pos"][:n] - x0[:n], disp_ref)
+        sim.close()
+    say("displacement error after 40 steps at 9999 m: plain", errs[0], "cell-offset", errs[1])
+    assert errs[0] > 0.5
+    assert errs[1] < 1e-2
