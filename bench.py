@@ -72,6 +72,148 @@ class WheelDriver:
         self.theta += dt * self.omega
 
 
+class BinDrivers:
+    """One WheelDriver-like wheel per bin of a batched scene (bodies 2b, 2b + 1)."""
+
+    def __init__(self, scene):
+        self.bins = scene.meta["bins"]
+        self.bodies = scene.bodies
+        nb = len(self.bins)
+        self.x = np.array([scene.bodies[2 * k + 1].pos for k in range(nb)], dtype=np.float64)
+        self.v = np.array([(1.0 - b["slip"]) * b["omega"] * b["r_g"] for b in self.bins])
+        self.omega = np.array([b["omega"] for b in self.bins])
+        self.mass = np.array([b["mass"] for b in self.bins])
+        self.vz = np.zeros(nb)
+        self.theta = np.zeros(nb)
+
+    def state(self, ks=None):
+        ks = range(len(self.bins)) if ks is None else ks
+        pos, quat, lin, ang = [], [], [], []
+        for k in ks:
+            c = self.bodies[2 * k]
+            pos += [c.pos, self.x[k]]
+            quat += [(1.0, 0.0, 0.0, 0.0), (math.cos(0.5 * self.theta[k]), 0.0, math.sin(0.5 * self.theta[k]), 0.0)]
+            lin += [(0.0, 0.0, 0.0), (self.v[k], 0.0, self.vz[k])]
+            ang += [(0.0, 0.0, 0.0), (0.0, self.omega[k], 0.0)]
+        return (np.array(pos, dtype=np.float64), np.array(quat), np.array(lin), np.array(ang))
+
+    def advance(self, fz, dt, ks=None):
+        ks = np.arange(len(self.bins)) if ks is None else np.asarray(ks)
+        self.vz[ks] += dt * (fz / self.mass[ks] - 9.81)
+        self.x[ks, 0] += dt * self.v[ks]
+        self.x[ks, 2] += dt * self.vz[ks]
+        self.theta[ks] += dt * self.omega[ks]
+
+
+def run_batch(args):
+    """Batched bins: one context for all bins (kernels replayed as a graph) vs
+    one context per bin, stepped one after the other on the same stream."""
+    import torch
+    from paper_2507_05643_amd import crm, scenes
+    sc = scenes.batch_bins(seed=0, ps_freq=args.ps_freq)
+    dt = sc.params["dt"]
+    nbins = len(sc.meta["bins"])
+
+    def timed(step_fn, n_warm, n_steps):
+        for _ in range(n_warm):
+            step_fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            step_fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    drv = BinDrivers(sc)
+    sim = crm.Simulation(sc, device=0)
+    sim.set_materials(sc.meta["materials"], sc.meta["material"])
+    sim.graph(True)
+
+    def step_batched():
+        sim.set_bodies(*drv.state())
+        sim.step(1)
+        F, _ = sim.forces()
+        drv.advance(F[1::2, 2], dt)
+
+    wall = timed(step_batched, args.warmup, args.steps)
+    n_proc = sim.counts()["n_proc"]
+    sim.close()
+    value = n_proc * args.steps / wall
+
+    # one context per bin
+    drv2 = BinDrivers(sc)
+    sims = []
+    for k in range(nbins):
+        one = scenes.batch_bins(seed=0, ps_freq=args.ps_freq, only=[k])
+        s1 = crm.Simulation(one, device=0)
+        s1.set_materials(one.meta["materials"], one.meta["material"])
+        s1.graph(True)
+        sims.append(s1)
+
+    def step_separate():
+        for k, s1 in enumerate(sims):
+            s1.set_bodies(*drv2.state([k]))
+            s1.step(1)
+        fz = np.array([s1.forces()[0][1, 2] for s1 in sims])
+        drv2.advance(fz, dt)
+
+    n_sep = max(1, args.steps // 4)
+    wall2 = timed(step_separate, max(1, args.warmup // 4), n_sep)
+    for s1 in sims:
+        s1.close()
+    value2 = n_proc * n_sep / wall2
+    return dict(value=value, wall=wall, n_proc=n_proc, separate=value2, n_bins=nbins,
+                config={"workload": f"{nbins} independent single-wheel bins, sizes log-uniform 8k-250k soil "
+                                    "particles (seed 0), per-bin friction 0.5-0.9, slip 0-0.6, load 50-200 N, "
+                                    "one context, step kernels replayed as a hipGraph",
+                        "n_particles": int(sc.n_total), "n_processed": int(n_proc), "ps_freq": args.ps_freq,
+                        "dt": dt, "separate_contexts_particle_steps_per_s": value2,
+                        "batched_over_separate": value / value2})
+
+
+def run_strip(args):
+    """Long strip with four wheels carrying active boxes, positions plain FP32
+    or cell index + FP32 offset; the vehicle sits at x = args.strip_x."""
+    import torch
+    from paper_2507_05643_amd import crm, scenes
+    sc = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x, ps_freq=args.ps_freq,
+                      t_delay=-1.0)
+    sc.params["pos_mode"] = args.pos_mode
+    dt = sc.params["dt"]
+    sim = crm.Simulation(sc, device=0)
+    sim.graph(True)
+    pos0 = np.array([b.pos for b in sc.bodies], dtype=np.float64)
+    quat = np.tile([1.0, 0.0, 0.0, 0.0], (len(sc.bodies), 1))
+    lin = np.array([b.linvel for b in sc.bodies])
+    ang = np.array([b.angvel for b in sc.bodies])
+    state = {"k": 0}
+
+    def one_step():
+        p = pos0.copy()
+        p[1:, 0] += lin[1:, 0] * dt * state["k"]
+        sim.set_bodies(p, quat, lin, ang)
+        sim.step(1)
+        sim.forces()
+        state["k"] += 1
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = sim.counts()
+    sim.close()
+    value = cnt["n_proc"] * args.steps / wall
+    return dict(value=value, wall=wall, n_proc=cnt["n_proc"],
+                config={"workload": f"strip {args.strip_length:g} m x 4 m x 0.3 m at dx 0.05 m, 4 wheels at "
+                                    f"x = {args.strip_x:g} m with 2 m active boxes, pos_mode {args.pos_mode}",
+                        "n_particles": cnt["n_total"], "n_processed": cnt["n_proc"], "ps_freq": args.ps_freq,
+                        "dt": dt})
+
+
 def cpu_baseline(scene, steps):
     from oracle.oracle import Oracle
     orc = Oracle(scene, nbr_mode="cells")
@@ -92,6 +234,10 @@ def main():
     ap.add_argument("--ps-freq", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("wheel", "batch", "strip"), default="wheel")
+    ap.add_argument("--pos-mode", type=int, default=0)
+    ap.add_argument("--strip-length", type=float, default=10000.0)
+    ap.add_argument("--strip-x", type=float, default=5000.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB once (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
@@ -105,6 +251,14 @@ def main():
     from paper_2507_05643_amd import crm, scenes
 
     torch.cuda.set_device(0)
+    if args.workload != "wheel":
+        res = run_batch(args) if args.workload == "batch" else run_strip(args)
+        out = {"metric": "particle-steps/s", "value": res["value"], "unit": "particle-steps/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["wall"] / args.steps * 1e3,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic", "config": res["config"], "roofline": None, "cpu_baseline": None}
+        print(json.dumps(out), flush=True)
+        return
     sc = scenes.wheel_bin(seed=0, ps_freq=args.ps_freq)
     drv = WheelDriver(sc)
     sim = crm.Simulation(sc, device=0)

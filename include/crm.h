@@ -130,6 +130,15 @@ crm_status crm_set_bodies(crm_ctx* ctx, int32_t nb, const double* pos, const dou
                           const double* linvel, const double* angvel, const double* linacc,
                           const double* angacc);
 
+/* Materials of the return mapping (Sec. 2.4): for material m, friction
+ * mu_s[m], mu_2[m] and cohesion[m] (the other constants stay those of the
+ * parameters); material[i] (< n_mat) for each soil particle i. Until called, all
+ * soil has one material with the parameters' values. Allowed only before the
+ * first step. n_mat <= 256. Errors: CRM_E_INVALID (sizes, ids, values as in
+ * crm_init), CRM_E_STATE (after the first step), CRM_E_DEVICE. */
+crm_status crm_set_materials(crm_ctx* ctx, int32_t n_mat, const double* mu_s, const double* mu_2,
+                             const double* cohesion, const uint16_t* material);
+
 /* Advance n_steps steps (Alg. 3 per step: rebuild when step mod ps_freq == 0,
  * then two RHS evaluations and the return mapping). Enqueued on the context's
  * stream; returns once enqueued, except on rebuild steps, which wait for the
@@ -177,6 +186,12 @@ crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
  * CRM_E_STATE before the first rebuild. Synchronises. */
 crm_status crm_debug_export(crm_ctx* ctx, int32_t* sorted_ids, uint32_t* cell_start, int32_t* rows,
                             int64_t* off, int32_t* nbr, int64_t cap, uint8_t* flags);
+
+/* enable = 1: run the kernels of each step after its rebuild as one hipGraph,
+ * captured on a private stream whenever the working set's buffers or row
+ * counts change and launched on the context's stream; results are identical
+ * to direct launches. Not used while profiling. enable = 0: direct launches. */
+crm_status crm_set_graph(crm_ctx* ctx, int32_t enable);
 
 /* Kernel timing for measurement. enable = 1 starts recording HIP events around
  * each kernel class of every following step on the context's stream (and

@@ -393,6 +393,9 @@ typedef struct orc_ctx {
   int64_t cap;                  /* capacity of the working arrays (policy only) */
   double* F; double* T;         /* per body, 3 each */
   double* as;                   /* 3n marker accelerations of the last stage 2 */
+  int32_t* mat;                 /* material of each soil particle (0 = the parameters) */
+  int32_t n_mat;
+  double* mat_tab;              /* per material: mu_s, mu_2, cohesion */
 } orc_ctx;
 
 void orc_destroy(orc_ctx* c);
@@ -432,6 +435,10 @@ orc_ctx* orc_create(const orc_params* P, int64_t n_soil, const double* pos, cons
   c->F = (double*)calloc(3 * (size_t)(nb > 0 ? nb : 1), sizeof(double));
   c->T = (double*)calloc(3 * (size_t)(nb > 0 ? nb : 1), sizeof(double));
   c->as = (double*)calloc(1, n3);
+  c->mat = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  c->n_mat = 1;
+  c->mat_tab = (double*)malloc(3 * sizeof(double));
+  c->mat_tab[0] = P->mu_s; c->mat_tab[1] = P->mu_2; c->mat_tab[2] = P->cohesion;
   for (int64_t i = 0; i < n_soil; ++i) {
     for (int k = 0; k < 3; ++k) {
       c->x[3 * i + k] = pos[3 * i + k];
@@ -460,8 +467,18 @@ void orc_destroy(orc_ctx* c) {
   free(c->xm); free(c->um); free(c->sm); free(c->rhom);
   free(c->dx_); free(c->du); free(c->ds); free(c->drho);
   free(c->flag); free(c->proc); free(c->slot); free(c->off); free(c->nbr);
-  free(c->F); free(c->T); free(c->as);
+  free(c->F); free(c->T); free(c->as); free(c->mat); free(c->mat_tab);
   free(c);
+}
+
+/* Materials: per material (mu_s, mu_2, cohesion) of the return mapping
+ * (Sec. 2.4), and the material of each soil particle. */
+void orc_set_materials(orc_ctx* c, int32_t n_mat, const double* tab, const int32_t* mat) {
+  free(c->mat_tab);
+  c->n_mat = n_mat;
+  c->mat_tab = (double*)malloc(3 * sizeof(double) * (size_t)n_mat);
+  memcpy(c->mat_tab, tab, 3 * sizeof(double) * (size_t)n_mat);
+  for (int64_t i = 0; i < c->n_soil; ++i) c->mat[i] = mat[i];
 }
 
 void orc_set_bodies(orc_ctx* c, int32_t nb, const double* X, const double* q, const double* V,
@@ -763,7 +780,10 @@ static int one_step(orc_ctx* c) {
     }
     double sn[6], sstar[6];
     for (int k = 0; k < 6; ++k) { sn[k] = c->s[6 * i + k]; sstar[k] = sn[k] + P->dt * c->ds[6 * i + k]; }
-    orc_return_map(P, sstar, sn, c->s + 6 * i);
+    orc_params Pm = *P;             /* the return mapping with the particle's material */
+    const double* mt = c->mat_tab + 3 * c->mat[i];
+    Pm.mu_s = mt[0]; Pm.mu_2 = mt[1]; Pm.cohesion = mt[2];
+    orc_return_map(&Pm, sstar, sn, c->s + 6 * i);
     c->rho[i] += P->dt * c->drho[i];
   }
   /* marker values of the midpoint are what the step last computed */

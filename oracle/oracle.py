@@ -101,6 +101,8 @@ def lib():
         L.orc_create.argtypes = [pp, C.c_int64, dp, dp, dp, dp, C.c_int32, i64p, dp, dp]
         L.orc_destroy.restype = None
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_materials.restype = None
+        L.orc_set_materials.argtypes = [C.c_void_p, C.c_int32, dp, i32p]
         L.orc_set_bodies.restype = None
         L.orc_set_bodies.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, dp, dp, dp]
         L.orc_step.restype = C.c_int
@@ -251,6 +253,12 @@ class Oracle:
         dp = C.c_double
         a = [_d(v) for v in (pos, quat, linvel, angvel, linacc, angacc)]
         lib().orc_set_bodies(self.ctx, self.nb, *[_p(v, dp) for v in a])
+
+    def set_materials(self, table, material):
+        """table: (n_mat, 3) rows (mu_s, mu_2, cohesion); material: id per soil particle."""
+        tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 3)
+        mat = np.ascontiguousarray(material, dtype=np.int32)
+        lib().orc_set_materials(self.ctx, tab.shape[0], _p(tab, C.c_double), _p(mat, C.c_int32))
 
     def step(self, n=1):
         r = lib().orc_step(self.ctx, int(n))

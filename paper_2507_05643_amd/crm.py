@@ -68,6 +68,8 @@ def _load():
                            C.POINTER(crm_body_desc), ALLOC_FN, FREE_FN, vp, vp, C.POINTER(vp)]
     L.crm_set_bodies.restype = C.c_int
     L.crm_set_bodies.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp, dp]
+    L.crm_set_materials.restype = C.c_int
+    L.crm_set_materials.argtypes = [vp, C.c_int32, dp, dp, dp, C.POINTER(C.c_uint16)]
     L.crm_step.restype = C.c_int
     L.crm_step.argtypes = [vp, C.c_int32]
     L.crm_get_forces.restype = C.c_int
@@ -80,6 +82,8 @@ def _load():
     L.crm_get_counts.argtypes = [vp, i64p]
     L.crm_debug_export.restype = C.c_int
     L.crm_debug_export.argtypes = [vp, i32p, u32p, i32p, i64p, i32p, C.c_int64, u8p]
+    L.crm_set_graph.restype = C.c_int
+    L.crm_set_graph.argtypes = [vp, C.c_int32]
     L.crm_set_profiling.restype = C.c_int
     L.crm_set_profiling.argtypes = [vp, C.c_int32]
     L.crm_get_profile.restype = C.c_int
@@ -95,8 +99,8 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("crm_init", "crm_set_bodies", "crm_step", "crm_get_forces", "crm_get_state",
-            "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_profiling",
+EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_get_forces", "crm_get_state",
+            "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy")
 
 PROFILE_CLASSES = ("rebuild", "place_markers", "bce_stage1", "soil_stage1", "bce_forces_stage2",
@@ -198,6 +202,15 @@ def crm_set_bodies(ctx, pos, quat, linvel=None, angvel=None, linacc=None, angacc
     _check(ctx, _lib.crm_set_bodies(ctx, nb, *[_ptr(a, C.c_double) for a in arr]))
 
 
+def crm_set_materials(ctx, table, material):
+    """table: (n_mat, 3) rows (mu_s, mu_2, cohesion); material: uint16 id per soil particle."""
+    tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 3)
+    cols = [np.ascontiguousarray(tab[:, k]) for k in range(3)]
+    mat = np.ascontiguousarray(material, dtype=np.uint16)
+    _check(ctx, _lib.crm_set_materials(ctx, tab.shape[0], *[_ptr(v, C.c_double) for v in cols],
+                                       _ptr(mat, C.c_uint16)))
+
+
 def crm_step(ctx, n_steps=1):
     _check(ctx, _lib.crm_step(ctx, int(n_steps)))
 
@@ -251,6 +264,10 @@ def crm_debug_export(ctx):
                 flags=flags)
 
 
+def crm_set_graph(ctx, enable):
+    _check(ctx, _lib.crm_set_graph(ctx, 1 if enable else 0))
+
+
 def crm_set_profiling(ctx, enable):
     _check(ctx, _lib.crm_set_profiling(ctx, 1 if enable else 0))
 
@@ -297,6 +314,9 @@ class Simulation:
     def set_bodies(self, pos, quat, linvel=None, angvel=None, linacc=None, angacc=None):
         crm_set_bodies(self.ctx, pos, quat, linvel, angvel, linacc, angacc)
 
+    def set_materials(self, table, material):
+        crm_set_materials(self.ctx, table, material)
+
     def step(self, n=1):
         crm_step(self.ctx, n)
 
@@ -314,6 +334,9 @@ class Simulation:
 
     def export(self):
         return crm_debug_export(self.ctx)
+
+    def graph(self, enable=True):
+        crm_set_graph(self.ctx, enable)
 
     def profiling(self, enable=True):
         crm_set_profiling(self.ctx, enable)

@@ -52,6 +52,7 @@ struct crm_ctx {
   uint8_t* flags = nullptr;
   int32_t* proc_ids = nullptr;
   Body* d_bodies = nullptr;
+  float4* d_mat = nullptr;     // material table
   std::vector<Body> h_bodies;
   double* d_forces = nullptr;
   uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
@@ -79,8 +80,8 @@ struct crm_ctx {
   uint32_t* nbr_m = nullptr;
   int64_t nbr_m_cap = 0;
 
-  double* partials = nullptr;
-  int64_t partials_cap = 0;
+  double* contrib = nullptr;     // per marker id: force and torque on its body (6 FP64)
+  int64_t* d_bstart = nullptr;   // first marker id (relative) of each body, nb + 1
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
   uint64_t* h_counts = nullptr;   // pinned mirror
 
@@ -89,6 +90,13 @@ struct crm_ctx {
   bool working_valid = false;
   bool force_rebuild = true;
   bool stepped = false;
+
+  // replay of the per-step kernels as one hipGraph
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> graph_key;
 
   // profiling: event pairs per kernel class
   bool prof = false;
@@ -340,15 +348,8 @@ crm_status rebuild(crm_ctx* c) {
                           c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
-  const int64_t nbk = crm::bce_blocks(c->n_mrows);
-  if (nbk * c->nb > c->partials_cap) {
-    dfree(c, c->partials);
-    c->partials = nullptr;
-    c->partials_cap = 0;
-    int64_t n = (nbk + 1) * (c->nb > 0 ? c->nb : 1);
-    if (!alloc_n(c, c->partials, n * 6)) return fail(c, CRM_E_NOMEM, "partials allocation failed");
-    c->partials_cap = n;
-  }
+  // markers outside the processed set contribute nothing until the next rebuild
+  HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mark, s));
   c->working_valid = true;
   c->force_rebuild = false;
   c->rebuilds += 1;
@@ -380,36 +381,80 @@ void prof_end(crm_ctx* c, int k, hipEvent_t start) {
   c->prof_marks.push_back({k, {start, e}});
 }
 
+// The kernels of one step after the (optional) rebuild, on stream s.
+crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof) {
+  const Phys& P = c->phys;
+  hipEvent_t e = prof ? prof_begin(c) : nullptr;
+  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies,
+                                       c->grid, c->A, c->B, s));
+  if (prof) prof_end(c, 1, e);
+  // stage 1 at y_n
+  if (prof) e = prof_begin(c);
+  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P, nullptr,
+                     s));
+  if (prof) prof_end(c, 2, e);
+  if (prof) e = prof_begin(c);
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
+  if (prof) prof_end(c, 3, e);
+  // stage 2 at y_mid, body forces from this evaluation
+  if (prof) e = prof_begin(c);
+  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P,
+                     c->contrib, s));
+  if (prof) prof_end(c, 4, e);
+  if (prof) e = prof_begin(c);
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
+  if (prof) prof_end(c, 5, e);
+  if (prof) e = prof_begin(c);
+  HIPCHK(c, crm::body_reduce(c->contrib, c->d_bstart, c->nb, c->d_forces, s));
+  if (prof) prof_end(c, 6, e);
+  return CRM_OK;
+}
+
+void drop_graph(crm_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_key.clear();
+}
+
+// Everything the captured kernels bake in: buffers and row counts.
+std::vector<const void*> graph_key(const crm_ctx* c) {
+  return {c->A.a, c->B.a, c->frows, c->mrows, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->slot_id,
+          c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows};
+}
+
+crm_status step_graph(crm_ctx* c) {
+  std::vector<const void*> key = graph_key(c);
+  if (!c->gexec || key != c->graph_key) {
+    drop_graph(c);
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    crm_status st = launch_step(c, c->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != CRM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ee != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->graph_key = key;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  return CRM_OK;
+}
+
 crm_status one_step(crm_ctx* c) {
-  hipStream_t s = c->stream;
   if (c->force_rebuild || !c->working_valid || c->step % (int64_t)c->prm.ps_freq == 0) {
     hipEvent_t e = prof_begin(c);
     crm_status st = rebuild(c);
     if (st != CRM_OK) return st;
     prof_end(c, 0, e);
   }
-  const Phys& P = c->phys;
-  hipEvent_t e = prof_begin(c);
-  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies,
-                                       c->grid, c->A, c->B, s));
-  prof_end(c, 1, e);
-  // stage 1 at y_n
-  e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->nb, P, nullptr, s));
-  prof_end(c, 2, e);
-  e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
-  prof_end(c, 3, e);
-  // stage 2 at y_mid, body forces from this evaluation
-  e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->nb, P, c->partials, s));
-  prof_end(c, 4, e);
-  e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
-  prof_end(c, 5, e);
-  e = prof_begin(c);
-  HIPCHK(c, crm::body_reduce(c->partials, crm::bce_blocks(c->n_mrows), c->nb, c->d_forces, s));
-  prof_end(c, 6, e);
+  crm_status st = (c->use_graph && !c->prof) ? step_graph(c) : launch_step(c, c->stream, c->prof);
+  if (st != CRM_OK) return st;
   c->step += 1;
   c->stepped = true;
   return CRM_OK;
@@ -422,6 +467,8 @@ void release(crm_ctx* c) {
   for (auto& b : all) dfree(c, b.p);
   if (c->h_counts) (void)hipHostFree(c->h_counts);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -593,7 +640,9 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
             alloc_n(c, c->proc_ids, n_total) && alloc_n(c, c->d_bodies, n_bodies > 0 ? n_bodies : 1) &&
             alloc_n(c, c->d_forces, 6 * (n_bodies > 0 ? n_bodies : 1)) && alloc_n(c, c->ctmp, nbk) &&
             alloc_n(c, c->cell_cnt, M) && alloc_n(c, c->cell_start, M + 1) &&
-            alloc_n(c, c->cell_tmp, (int64_t)crm::scan_tmp_elems(M)) && alloc_n(c, c->d_counts, 8);
+            alloc_n(c, c->cell_tmp, (int64_t)crm::scan_tmp_elems(M)) && alloc_n(c, c->d_counts, 8) &&
+            alloc_n(c, c->d_mat, crm::kMaxMaterials) && alloc_n(c, c->contrib, 6 * nm) &&
+            alloc_n(c, c->d_bstart, n_bodies + 1);
   if (!ok) {
     release(c);
     return fail(nullptr, CRM_E_NOMEM, "device allocation failed");
@@ -615,6 +664,14 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_bodies, c->h_bodies.data(), sizeof(Body) * c->h_bodies.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->d_forces, 0, sizeof(double) * 6 * (size_t)(n_bodies > 0 ? n_bodies : 1), s);
+  std::vector<int64_t> bstart((size_t)n_bodies + 1, 0);
+  for (int b = 0; b < n_bodies; ++b) bstart[b + 1] = bstart[b] + bodies[b].n_markers;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_bstart, bstart.data(), sizeof(int64_t) * bstart.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && nm > 0) e = hipMemsetAsync(c->contrib, 0, sizeof(double) * 6 * (size_t)nm, s);
+  const float4 mat0 = make_float4((float)P.mu_s, (float)P.mu_2, (float)P.cohesion, (float)(-P.cohesion / P.mu_s));
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_mat, &mat0, sizeof(float4), hipMemcpyHostToDevice, s);
+  c->phys.mat = c->d_mat;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     std::string m2 = std::string("upload failed: ") + hipGetErrorString(e);
@@ -655,6 +712,41 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
   hipError_t e = hipMemcpyAsync(c->d_bodies, hb.data(), sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
   c->h_bodies = hb;
+  return CRM_OK;
+}
+
+crm_status crm_set_materials(crm_ctx* c, int32_t n_mat, const double* mu_s, const double* mu_2,
+                             const double* cohesion, const uint16_t* material) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (c->stepped || c->rebuilds > 0) return fail(c, CRM_E_STATE, "materials must be set before the first step");
+  if (n_mat < 1 || n_mat > crm::kMaxMaterials) return fail(c, CRM_E_INVALID, "n_mat out of range");
+  if (!mu_s || !mu_2 || !cohesion || (c->n_soil > 0 && !material)) return fail(c, CRM_E_INVALID, "NULL argument");
+  std::vector<float4> tab((size_t)n_mat);
+  for (int m = 0; m < n_mat; ++m) {
+    if (!(std::isfinite(mu_s[m]) && mu_s[m] > 0.0)) return fail(c, CRM_E_INVALID, "mu_s must be > 0");
+    if (!(std::isfinite(mu_2[m]) && mu_2[m] >= 0.0)) return fail(c, CRM_E_INVALID, "mu_2 must be >= 0");
+    if (!(std::isfinite(cohesion[m]) && cohesion[m] >= 0.0)) return fail(c, CRM_E_INVALID, "cohesion must be >= 0");
+    tab[m] = make_float4((float)mu_s[m], (float)mu_2[m], (float)cohesion[m], (float)(-cohesion[m] / mu_s[m]));
+  }
+  for (int64_t i = 0; i < c->n_soil; ++i)
+    if (material[i] >= n_mat) return fail(c, CRM_E_INVALID, "material id out of range");
+  hipStream_t s = c->stream;
+  const size_t n = (size_t)c->n_soil;
+  std::vector<float4> hb(n);
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(hb.data(), c->m_b, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  for (size_t i = 0; i < n; ++i) {
+    uint32_t aux;
+    std::memcpy(&aux, &hb[i].w, 4);
+    aux = (aux & 3u) | ((uint32_t)material[i] << 2);
+    std::memcpy(&hb[i].w, &aux, 4);
+  }
+  if (n > 0) HIPCHK(c, hipMemcpyAsync(c->m_b, hb.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_mat, tab.data(), sizeof(float4) * (size_t)n_mat, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
   return CRM_OK;
 }
 
@@ -826,6 +918,14 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
     emit(mr, om, em);
     if (off) off[row] = e;
   }
+  return CRM_OK;
+}
+
+crm_status crm_set_graph(crm_ctx* c, int32_t enable) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
   return CRM_OK;
 }
 

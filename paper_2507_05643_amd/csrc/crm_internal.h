@@ -11,13 +11,15 @@ namespace crm {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kWave = 64;        // gfx950 wavefront width
-constexpr int kMaxBodies = 64;   // bodies per context
+constexpr int kMaxBodies = 1024; // bodies per context
+constexpr int kMaxMaterials = 256;
 
 // Particle state as four float4 planes (structure of arrays of 16-byte
 // vectors), indexed by cell-sorted slot in the working set:
 //   a = (x, y, z, rho)  b = (vx, vy, vz, aux)  c = (sxx, syy, szz, sxy)
 //   d = (sxz, syz, -, -)
-// aux (bit pattern of b.w) = kind | body << 2. A lane group reading the
+// aux (bit pattern of b.w) = kind | body << 2 for markers, kind | material << 2
+// for soil. A lane group reading the
 // records of consecutive slots touches consecutive 16-byte vectors of a plane.
 struct Planes {
   float4* a;
@@ -87,6 +89,7 @@ struct Phys {
   float Sf;       // cell size 2h in FP32 (cell-offset positions)
   double S, invS; // cell size and its inverse in FP64
   double lo[3];   // grid origin
+  const float4* mat;  // per material: (mu_s, mu_2, cohesion, -cohesion / mu_s)
 };
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
@@ -152,13 +155,14 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const in
                                  int64_t n_soil, const float4* local, const Body* bodies, Grid g,
                                  Planes A, Planes B, hipStream_t s);
 
-// BCE extrapolation at state S (Sec. 2.5.1); with partials != nullptr also the
-// marker accelerations and per-block body force/torque partial sums
-// (partials[block * nb + b][6], FP64, bce_blocks(n_mrows) blocks).
+// BCE extrapolation at state S (Sec. 2.5.1); with contrib != nullptr also the
+// marker accelerations and each processed marker's force and torque on its
+// body (FP64, 6 per marker, indexed by marker id = particle id - n_soil).
 hipError_t bce(Planes S, const int32_t* mrows, int64_t n_mrows, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, int32_t nb, Phys P, double* partials, hipStream_t s);
-int64_t bce_blocks(int64_t n_mrows);
-hipError_t body_reduce(const double* partials, int64_t nblocks, int32_t nb, double* forces,
+               const Body* bodies, const int32_t* slot_id, int64_t n_soil, Phys P, double* contrib,
+               hipStream_t s);
+// forces[b] = sum of contrib over body b's marker ids [bstart[b], bstart[b + 1]).
+hipError_t body_reduce(const double* contrib, const int64_t* bstart, int32_t nb, double* forces,
                        hipStream_t s);
 
 // Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return

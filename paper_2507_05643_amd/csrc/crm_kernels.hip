@@ -701,13 +701,13 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
 
 // Sec. 2.5.1: Adami velocity u~ = sum u_f W / sum W, no-slip u_s = 2 u_body - u~;
 // stress s_s = [sum s_f W - ((g - a_s) . sum rho_f (x_s - x_f) W) I] / sum W.
-// With `partials`, the marker acceleration from the momentum equation over the
-// soil neighbours (no body force) and the per-block body force and torque.
+// With `contrib`, the marker acceleration from the momentum equation over the
+// soil neighbours (no body force) and the marker's force and torque on its body.
 template <bool FORCE, bool CELL>
 __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows, int64_t n,
                                                 const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbr,
-                                                const Body* __restrict__ bodies, int32_t nb, Phys P,
-                                                double* __restrict__ partials) {
+                                                const Body* __restrict__ bodies, const int32_t* __restrict__ slot_id,
+                                                int64_t n_soil, Phys P, double* __restrict__ contrib) {
   const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
   const bool live = r < n;
@@ -817,49 +817,35 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
     });
     a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
     v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
-    double fr[6] = {0, 0, 0, 0, 0, 0};
-    const bool owner = live && gl == 0;
-    if (owner) {
+    if (live && gl == 0) {
+      // force and torque of this marker on its body, by marker id
       const float ir = 1.0f / rhos;
       const double f0 = (double)P.m * (double)(a0 * ir + v0);
       const double f1 = (double)P.m * (double)(a1 * ir + v1);
       const double f2 = (double)P.m * (double)(a2 * ir + v2);
-      fr[0] = f0; fr[1] = f1; fr[2] = f2;
-      fr[3] = rv[1] * f2 - rv[2] * f1;
-      fr[4] = rv[2] * f0 - rv[0] * f2;
-      fr[5] = rv[0] * f1 - rv[1] * f0;
-    }
-    const int ob_ = owner ? body : -1;
-    // Deterministic per-block sums per body (fixed tree order, no float atomics).
-    __shared__ double red[6][kBlock];
-    const int t = threadIdx.x;
-    const int64_t blk = xcd_block();
-    for (int b = 0; b < nb; ++b) {
-      const int any = __syncthreads_or(ob_ == b);
-      if (!any) {
-        if (t < 6) partials[(blk * nb + b) * 6 + t] = 0.0;
-        continue;
-      }
-      for (int a = 0; a < 6; ++a) red[a][t] = (ob_ == b) ? fr[a] : 0.0;
-      __syncthreads();
-      for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (t < o)
-          for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + o];
-        __syncthreads();
-      }
-      if (t < 6) partials[(blk * nb + b) * 6 + t] = red[t][0];
-      __syncthreads();
+      double* out = contrib + (int64_t)(slot_id[s] - n_soil) * 6;
+      out[0] = f0;
+      out[1] = f1;
+      out[2] = f2;
+      out[3] = rv[1] * f2 - rv[2] * f1;
+      out[4] = rv[2] * f0 - rv[0] * f2;
+      out[5] = rv[0] * f1 - rv[1] * f0;
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_body_reduce(const double* __restrict__ partials, int64_t nblocks,
-                                                        int32_t nb, double* __restrict__ forces) {
+// Sum of the markers' force/torque over each body's contiguous marker-id range
+// [bstart[b], bstart[b + 1]) in a fixed order (strided per thread, then a
+// tree), so the result depends only on the body's markers.
+__global__ __launch_bounds__(kBlock) void k_body_reduce(const double* __restrict__ contrib,
+                                                        const int64_t* __restrict__ bstart,
+                                                        double* __restrict__ forces) {
   __shared__ double red[6][kBlock];
   const int b = blockIdx.x, t = threadIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t k = t; k < nblocks; k += kBlock)
-    for (int a = 0; a < 6; ++a) acc[a] += partials[(k * nb + b) * 6 + a];
+  const int64_t e = bstart[b + 1];
+  for (int64_t k = bstart[b] + t; k < e; k += kBlock)
+    for (int a = 0; a < 6; ++a) acc[a] += contrib[k * 6 + a];
   for (int a = 0; a < 6; ++a) red[a][t] = acc[a];
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -953,11 +939,13 @@ __device__ inline void p_taubar(const float s[6], float& p, float& tb) {
   tb = fsqrt(0.5f * (t0 * t0 + t1 * t1 + t2 * t2 + 2.f * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
 }
 
-// Sec. 2.4: four-step return mapping of the trial stress st with taubar^n from sn.
-__device__ inline void return_map(float st[6], const float sn[6], const Phys& P) {
+// Sec. 2.4: four-step return mapping of the trial stress st with taubar^n from
+// sn, for material M = (mu_s, mu_2, cohesion, p_cri).
+__device__ inline void return_map(float st[6], const float sn[6], const Phys& P, float4 M) {
+  const float mu_s = M.x, mu_2 = M.y, cohesion = M.z;
   float ps, tbs, pn, tbn;
   p_taubar(st, ps, tbs);
-  if (ps < P.p_cri) {
+  if (ps < M.w) {
     for (int a = 0; a < 6; ++a) st[a] = 0.f;
     return;
   }
@@ -965,14 +953,14 @@ __device__ inline void return_map(float st[6], const float sn[6], const Phys& P)
   float gd = (tbs - tbn) * P.inv_Gdt;
   float mu;
   if (!(gd > 0.f)) {
-    mu = P.mu_s;
+    mu = mu_s;
   } else if (ps <= 0.f) {
-    mu = P.mu_2;
+    mu = mu_2;
   } else {
     const float I = gd * P.grain_d * fsqrt(P.rho0 / ps);
-    mu = P.mu_s + (P.mu_2 - P.mu_s) / (1.0f + P.I0 / I);
+    mu = mu_s + (mu_2 - mu_s) / (1.0f + P.I0 / I);
   }
-  float tmax = mu * ps + P.cohesion;
+  float tmax = mu * ps + cohesion;
   tmax = tmax > 0.f ? tmax : 0.f;
   if (tbs <= tmax) return;
   const float f = tmax / tbs;
@@ -1048,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
       float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd0.x, yd0.y};
       float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
                      sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-      return_map(st, sn, P);
+      return_map(st, sn, P, P.mat[__float_as_uint(mb.w) >> 2]);
       A.d[s] = make_float4(st[4], st[5], yd.z, yd.w);
     }
   } else if (gl == 1) {
@@ -1059,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
     float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
                    sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-    return_map(st, sn, P);
+    return_map(st, sn, P, P.mat[__float_as_uint(mb.w) >> 2]);
     A.c[s] = make_float4(st[0], st[1], st[2], st[3]);
   }
 }
@@ -1187,29 +1175,28 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n, const int32_t*
   return hipGetLastError();
 }
 
-int64_t bce_blocks(int64_t n) { return nblk_groups(n); }
-
 hipError_t bce(Planes S, const int32_t* mrows, int64_t n, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, int32_t nb, Phys P, double* partials, hipStream_t s) {
+               const Body* bodies, const int32_t* slot_id, int64_t n_soil, Phys P, double* contrib,
+               hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned gsz = nblk_groups(n);
   if (P.cell) {
-    if (partials)
-      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, partials);
+    if (contrib)
+      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, contrib);
     else
-      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, nullptr);
+      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, nullptr);
   } else {
-    if (partials)
-      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, partials);
+    if (contrib)
+      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, contrib);
     else
-      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, nb, P, nullptr);
+      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, nullptr);
   }
   return hipGetLastError();
 }
 
-hipError_t body_reduce(const double* partials, int64_t nblocks, int32_t nb, double* forces, hipStream_t s) {
+hipError_t body_reduce(const double* contrib, const int64_t* bstart, int32_t nb, double* forces, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  k_body_reduce<<<(unsigned)nb, kBlock, 0, s>>>(partials, nblocks, nb, forces);
+  k_body_reduce<<<(unsigned)nb, kBlock, 0, s>>>(contrib, bstart, forces);
   return hipGetLastError();
 }
 

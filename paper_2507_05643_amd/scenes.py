@@ -283,3 +283,60 @@ def cluster(seed=0, n=6, dx=0.01, vel_scale=0.1, sigma_scale=1.0e3, gravity=(0.0
     hi = ((n + 10) * dx,) * 3
     params = _params(dx=dx, h=h, gravity=gravity, domain_lo=lo, domain_hi=hi)
     return Scene("cluster", params, pos, vel=vel, sigma=sig, meta=dict(seed=seed))
+
+
+def batch_bins(seed=0, n_bins=64, n_min=8.0e3, n_max=2.5e5, dx=0.005, ps_freq=10, gap_cells=24,
+               only=None):
+    """Many independent single-wheel soil bins side by side along x in one domain.
+
+    Bin sizes N_b are drawn log-uniformly in [n_min, n_max] with the bed aspect
+    5:3:1 of the single-wheel bin; the wheel (r, width, grouser height) scales
+    with the bed length. Per bin: friction mu_s in [0.5, 0.9] (material b),
+    slip in [0, 0.6], load in [50, 200] N. Bins are separated by `gap_cells`
+    particle spacings, far more than the 2h support, so no neighbour crosses bins.
+
+    `only` keeps the listed bins (same positions and domain), for comparing a
+    bin run alone with the same bin inside the batch."""
+    rng = np.random.default_rng(seed)
+    N = np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=n_bins))
+    mu = rng.uniform(0.5, 0.9, size=n_bins)
+    slip = rng.uniform(0.0, 0.6, size=n_bins)
+    load = rng.uniform(50.0, 200.0, size=n_bins)
+    h = 1.2 * dx
+    parts, mats, bodies, bins = [], [], [], []
+    x0 = 0.0
+    zmax = ymax = 0.0
+    for b in range(n_bins):
+        nz = max(4, int(round((N[b] / 15.0) ** (1.0 / 3.0))))
+        ny, nx = 3 * nz, 5 * nz
+        bed = (nx * dx, ny * dx, nz * dx)
+        s = bed[0] / 1.0
+        r = max(0.25 * s, 6 * dx)
+        w = max(0.2 * s, 6 * dx)
+        gh = max(dx, round(0.01 * s / dx) * dx)
+        r_g = r + gh
+        keep = only is None or b in only
+        if keep:
+            p = lattice(nx, ny, nz, dx, seed=seed + 1 + b).astype(np.float64) + np.array([x0, 0.0, 0.0])
+            parts.append(_f32(p))
+            mats.append(np.full(p.shape[0], len(bins), dtype=np.uint16))
+            nz_wall = int(math.floor((bed[2] + 2 * h) / dx - 0.5)) + 1
+            bodies.append(Body(markers=box_container(nx, ny, nz_wall, dx), pos=(x0, 0.0, 0.0), name=f"container{b}"))
+            omega = 0.8
+            v = (1.0 - slip[b]) * omega * r_g
+            wm = cylinder_wheel(r, w, dx, layers=3, grousers=12, grouser_h=gh, side_depth=min(0.05, 0.4 * r))
+            bodies.append(Body(markers=wm, pos=(x0 + 0.3 * bed[0], 0.5 * bed[1], bed[2] + r_g),
+                               linvel=(v, 0.0, 0.0), angvel=(0.0, omega, 0.0), name=f"wheel{b}"))
+            bins.append(dict(bin=b, n=nx * ny * nz, mu_s=float(mu[b]), slip=float(slip[b]), load=float(load[b]),
+                             mass=float(load[b]) / 9.81, r_g=r_g, omega=omega, x0=x0))
+        zmax = max(zmax, bed[2] + 2 * r_g)
+        ymax = max(ymax, bed[1])
+        x0 += bed[0] + gap_cells * dx
+    pos = np.concatenate(parts) if parts else np.zeros((0, 3), dtype=np.float32)
+    lo = (-4 * dx, -4 * dx, -4 * dx)
+    hi = (x0, ymax + 4 * dx, zmax + 4 * dx)
+    params = _params(dx=dx, h=h, ps_freq=ps_freq, domain_lo=lo, domain_hi=hi)
+    sc = Scene("batch", params, pos, bodies=bodies,
+               meta=dict(bins=bins, material=np.concatenate(mats) if mats else np.zeros(0, np.uint16),
+                         materials=np.array([[bb["mu_s"], bb["mu_s"], 0.0] for bb in bins]), seed=seed))
+    return sc

@@ -354,3 +354,33 @@ def test_step_output_is_admissible():
     zero = np.all(s == 0, axis=1)
     assert zero.sum() > 0 and (~zero).sum() > 0
     assert np.all(tb[~zero] <= 0.5 * p[~zero] + 100.0 + 1e-9 * (1 + np.abs(p[~zero])))
+
+
+def test_materials_select_the_return_mapping_constants():
+    """Per-particle materials: a table equal to the parameters reproduces the
+    plain run bit for bit; with two frictions every particle ends admissible
+    for its own friction, and the low-friction half is on its yield surface."""
+    base = scenes.cluster(seed=5, n=5, vel_scale=0.5, sigma_scale=5.0e3)
+    base.params.update(mu_s=0.6, mu_2=0.6, cohesion=50.0)
+    a = Oracle(base)
+    a.step(2)
+    b = Oracle(base)
+    b.set_materials([[0.6, 0.6, 50.0], [0.6, 0.6, 50.0]], np.arange(base.n_soil) % 2)
+    b.step(2)
+    for k in ("pos", "vel", "sigma", "rho"):
+        assert np.array_equal(a.state()[k], b.state()[k])
+    mat = np.arange(base.n_soil) % 2
+    tab = np.array([[0.3, 0.3, 50.0], [0.9, 0.9, 50.0]])
+    o = Oracle(base)
+    o.set_materials(tab, mat)
+    o.step(2)
+    s = o.state()["sigma"]
+    p = -s[:, :3].sum(axis=1) / 3
+    dev = s.copy(); dev[:, :3] += p[:, None]
+    tb = np.sqrt(0.5 * (np.sum(dev[:, :3] ** 2, axis=1) + 2 * np.sum(dev[:, 3:] ** 2, axis=1)))
+    mu = tab[mat, 0]
+    zero = np.all(s == 0, axis=1)
+    ok = zero | (tb <= mu * p + 50.0 + 1e-9 * (1 + np.abs(p)))
+    assert np.all(ok)
+    on_yield = (~zero) & (np.abs(tb - (mu * p + 50.0)) < 1e-9 * (1 + np.abs(p)))
+    assert on_yield[mat == 0].sum() > 0
