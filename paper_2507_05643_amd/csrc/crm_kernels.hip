@@ -998,10 +998,11 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
   na.w = ma.w + h * R.drho;
   nd.x = md.x + h * R.s4;
   nd.y = md.y + h * R.s5;
-  if (gl == 0) B.a[s] = na;
-  else if (gl == 1) B.b[s] = make_float4(mb.x + h * R.ax, mb.y + h * R.ay, mb.z + h * R.az, mb.w);
-  else if (gl == 2) B.c[s] = make_float4(mc.x + h * R.s0, mc.y + h * R.s1, mc.z + h * R.s2, mc.w + h * R.s3);
-  else if (gl == 3) B.d[s] = nd;
+  const float4 nb = make_float4(mb.x + h * R.ax, mb.y + h * R.ay, mb.z + h * R.az, mb.w);
+  const float4 nc = make_float4(mc.x + h * R.s0, mc.y + h * R.s1, mc.z + h * R.s2, mc.w + h * R.s3);
+  float4* dst = gl == 0 ? B.a : gl == 1 ? B.b : gl == 2 ? B.c : B.d;
+  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
+  if (gl < 4) dst[s] = v;
 }
 
 // Stage 2: A = A + dt f(B), then the return mapping on the stress.
@@ -1023,33 +1024,26 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   }
   const Rates R = fluid_rhs<CELL>(ma, mb, mc, md, B, k0, k1, nbr, P);
   if (!live) return;
+  // Every lane loads the whole y_n record and computes the whole y_{n+1}
+  // record; one store then writes plane gl from lane gl < 4. The return
+  // mapping needs sigma_n from planes c and d, so no lane may read a plane
+  // after another lane of the group has overwritten it.
   const float h = P.dt;
-  if (gl == 0 || gl == 3) {
-    float4 ya = A.a[s], yd = A.d[s];
-    advance_pos<CELL>(ya, yd, h, R.dx, R.dy, R.dz, P);
-    if (gl == 0) {
-      ya.w += h * R.drho;
-      A.a[s] = ya;
-    } else {
-      const float4 yc = A.c[s];
-      const float4 yd0 = A.d[s];
-      float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd0.x, yd0.y};
-      float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
-                     sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-      return_map(st, sn, P, P.mat[__float_as_uint(mb.w) >> 2]);
-      A.d[s] = make_float4(st[4], st[5], yd.z, yd.w);
-    }
-  } else if (gl == 1) {
-    const float4 yb = A.b[s];
-    A.b[s] = make_float4(yb.x + h * R.ax, yb.y + h * R.ay, yb.z + h * R.az, yb.w);
-  } else if (gl == 2) {
-    const float4 yc = A.c[s], yd = A.d[s];
-    float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
-    float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
-                   sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-    return_map(st, sn, P, P.mat[__float_as_uint(mb.w) >> 2]);
-    A.c[s] = make_float4(st[0], st[1], st[2], st[3]);
-  }
+  const float4 ya = A.a[s], yb = A.b[s], yc = A.c[s], yd = A.d[s];
+  float4 na = ya, nd = yd;
+  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
+  na.w = ya.w + h * R.drho;
+  const float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
+  float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
+                 sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
+  return_map(st, sn, P, P.mat[__float_as_uint(yb.w) >> 2]);
+  nd.x = st[4];
+  nd.y = st[5];
+  const float4 nb = make_float4(yb.x + h * R.ax, yb.y + h * R.ay, yb.z + h * R.az, yb.w);
+  const float4 nc = make_float4(st[0], st[1], st[2], st[3]);
+  float4* dst = gl == 0 ? A.a : gl == 1 ? A.b : gl == 2 ? A.c : A.d;
+  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
+  if (gl < 4) dst[s] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* __restrict__ rows, int64_t n,

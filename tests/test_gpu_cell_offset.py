@@ -80,20 +80,28 @@ def test_cell_offset_parity_far_from_origin(crm, steps, tol):
     sim.close()
 
 
-def test_cell_offset_equals_plain_near_origin(crm):
-    """Near the origin both forms resolve the motion and agree to FP32 rounding."""
-    a = scenes.column(seed=1, pos_mode=1)
-    b = scenes.column(seed=1, pos_mode=0)
-    sa, sb = crm.Simulation(a), crm.Simulation(b)
-    sa.step(50)
-    sb.step(50)
-    ga, gb = sa.state(), sb.state()
-    x0 = world_positions(a)
-    n = a.n_soil
-    assert normwise(ga["pos"][:n] - x0[:n], gb["pos"][:n] - x0[:n]) < 1e-4
-    assert normwise(ga["sigma"][:n], gb["sigma"][:n]) < 1e-4
-    sa.close()
-    sb.close()
+def test_both_forms_near_origin_against_oracle(crm):
+    """Near the origin both forms resolve the motion. Plain FP32 positions round
+    every step's increment (the spacing at 0.15 m is 1.5e-8 m against ~1e-7 m of
+    motion per step); the cell-offset form accumulates the increment in FP64, so
+    its displacements are at least as close to the oracle's."""
+    errs = {}
+    for mode in (0, 1):
+        sc = scenes.column(seed=1, pos_mode=mode)
+        x0 = world_positions(sc)
+        sim = crm.Simulation(sc)
+        orc = Oracle(sc, nbr_mode="cells")
+        sim.step(50)
+        orc.step(50)
+        g, r = sim.state(), orc.state()
+        n = sc.n_soil
+        errs[mode] = (normwise(g["pos"][:n] - x0[:n], r["pos"][:n] - x0[:n]),
+                      normwise(g["sigma"][:n], r["sigma"][:n]))
+        sim.close()
+    say("near origin, 50 steps (displacement, sigma): plain", errs[0], "cell-offset", errs[1])
+    assert errs[0][0] < 0.1 and errs[1][0] < 1e-2
+    assert errs[1][0] <= max(errs[0][0], 1e-3)
+    assert errs[0][1] <= 1e-3 and errs[1][1] <= 1e-3
 
 
 def test_plain_fp32_loses_motion_far_from_origin(crm):
