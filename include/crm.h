@@ -187,6 +187,44 @@ crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
 crm_status crm_debug_export(crm_ctx* ctx, int32_t* sorted_ids, uint32_t* cell_start, int32_t* rows,
                             int64_t* off, int32_t* nbr, int64_t cap, uint8_t* flags);
 
+/* Reverse mode, part 1 (the step map of Sec. 2.3 over the rates of Sec. 2.2,
+ * the BCE of Sec. 2.5.1 and the return mapping of Sec. 2.4, differentiated
+ * with the neighbour lists and activity held fixed). Advances n_steps >= 1
+ * steps exactly as crm_step does and keeps what the reverse sweep needs: the
+ * master state at each list rebuild of the run and the body table (bodies are
+ * frozen during the call, as in crm_step). Device memory: 64 bytes per
+ * particle per list rebuild of the run. The record must start at a list
+ * rebuild (step mod ps_freq = 0, or the first step after crm_init or
+ * crm_set_state). A later crm_step or crm_set_state discards the record.
+ * Errors: CRM_E_INVALID, CRM_E_UNSUPPORTED (active domains on), CRM_E_STATE
+ * (not at a list rebuild), CRM_E_NOMEM, CRM_E_DEVICE. */
+crm_status crm_record(crm_ctx* ctx, int32_t n_steps);
+
+/* Reverse mode, part 2: the vector-Jacobian product of the recorded run for
+ * the linear functional
+ *   L = sum_i (lam_pos_i . x_i + lam_vel_i . u_i + lam_sigma_i . s_i + lam_rho_i rho_i)
+ *       + sum_k sum_b (lam_force_kb . F_kb + lam_torque_kb . T_kb)
+ * of the soil state at the end of the run and of the body forces and torques
+ * of each recorded step k (those crm_get_forces would have returned after it).
+ * Seeds (host, any may be NULL = zero): lam_pos 3 n_soil doubles, lam_vel
+ * 3 n_soil, lam_sigma 6 n_soil (xx, yy, zz, xy, xz, yz), lam_rho n_soil floats,
+ * by particle id; lam_force, lam_torque 3 nb doubles per recorded step, step
+ * by step. Outputs (host, any may be NULL): dL/d(state at the start of the
+ * run) in the same layouts, and out_params = (dL/dE, dL/dnu, then dL/dmu_s,
+ * dL/dmu_2, dL/dcohesion for each material), 2 + 3 n_mat doubles (n_mat = 1
+ * without crm_set_materials). At a branch of the step (unilateral artificial
+ * viscosity, the return-mapping cases, the mu(I) cases) the derivative is that
+ * of the branch taken. The sweep re-runs each segment of steps between list
+ * rebuilds from its snapshot, keeping y_n, y_mid, the velocity gradients and
+ * the trial stresses of the segment (256 bytes per particle per step of the
+ * longest segment), and reverses it step by step. The context ends in the
+ * recorded end state with its current bodies; the record stays valid.
+ * Synchronises. Errors: CRM_E_STATE (no valid record, or the context stepped
+ * since), CRM_E_NOMEM, CRM_E_NONFINITE, CRM_E_DEVICE. */
+crm_status crm_adjoint(crm_ctx* ctx, const double* lam_pos, const float* lam_vel, const float* lam_sigma,
+                       const float* lam_rho, const double* lam_force, const double* lam_torque, double* out_pos,
+                       float* out_vel, float* out_sigma, float* out_rho, double* out_params);
+
 /* enable = 1: run the kernels of each step after its rebuild as one hipGraph,
  * captured on a private stream whenever the working set's buffers or row
  * counts change and launched on the context's stream; results are identical

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrm.so")
-SOURCES = [os.path.join(CSRC, "crm_kernels.hip"), os.path.join(CSRC, "crm_api.cpp")]
-HEADERS = [os.path.join(ROOT, "include", "crm.h"), os.path.join(CSRC, "crm_internal.h")]
+SOURCES = [os.path.join(CSRC, n) for n in ("crm_kernels.hip", "crm_adjoint.hip", "crm_api.cpp")]
+HEADERS = [os.path.join(ROOT, "include", "crm.h")] + [os.path.join(CSRC, n) for n in ("crm_internal.h", "crm_device.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

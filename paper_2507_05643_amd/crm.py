@@ -94,6 +94,10 @@ def _load():
     L.crm_last_error.argtypes = [vp]
     L.crm_destroy.restype = None
     L.crm_destroy.argtypes = [vp]
+    L.crm_record.restype = C.c_int
+    L.crm_record.argtypes = [vp, C.c_int32]
+    L.crm_adjoint.restype = C.c_int
+    L.crm_adjoint.argtypes = [vp, dp, fp, fp, fp, dp, dp, dp, fp, fp, fp, dp]
     return L
 
 
@@ -101,7 +105,8 @@ _lib = _load()
 
 EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_get_forces", "crm_get_state",
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
-            "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy")
+            "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
+            "crm_adjoint")
 
 PROFILE_CLASSES = ("rebuild", "place_markers", "bce_stage1", "soil_stage1", "bce_forces_stage2",
                    "soil_stage2", "body_reduce")
@@ -264,6 +269,28 @@ def crm_debug_export(ctx):
                 flags=flags)
 
 
+def crm_record(ctx, n_steps):
+    _check(ctx, _lib.crm_record(ctx, int(n_steps)))
+
+
+def crm_adjoint(ctx, n_soil, n_mat, lam_pos=None, lam_vel=None, lam_sigma=None, lam_rho=None, lam_force=None,
+                lam_torque=None):
+    """Vector-Jacobian product of the recorded run; returns dict(pos, vel, sigma, rho, params)
+    with params = (dL/dE, dL/dnu, then dL/dmu_s, dL/dmu_2, dL/dcohesion per material)."""
+    a = [None if v is None else np.ascontiguousarray(v, dtype=t)
+         for v, t in ((lam_pos, np.float64), (lam_vel, np.float32), (lam_sigma, np.float32), (lam_rho, np.float32),
+                      (lam_force, np.float64), (lam_torque, np.float64))]
+    out = dict(pos=np.zeros((n_soil, 3)), vel=np.zeros((n_soil, 3), dtype=np.float32),
+               sigma=np.zeros((n_soil, 6), dtype=np.float32), rho=np.zeros(n_soil, dtype=np.float32),
+               params=np.zeros(2 + 3 * n_mat))
+    _check(ctx, _lib.crm_adjoint(ctx, _ptr(a[0], C.c_double), _ptr(a[1], C.c_float), _ptr(a[2], C.c_float),
+                                 _ptr(a[3], C.c_float), _ptr(a[4], C.c_double), _ptr(a[5], C.c_double),
+                                 _ptr(out["pos"], C.c_double), _ptr(out["vel"], C.c_float),
+                                 _ptr(out["sigma"], C.c_float), _ptr(out["rho"], C.c_float),
+                                 _ptr(out["params"], C.c_double)))
+    return out
+
+
 def crm_set_graph(ctx, enable):
     _check(ctx, _lib.crm_set_graph(ctx, 1 if enable else 0))
 
@@ -316,6 +343,13 @@ class Simulation:
 
     def set_materials(self, table, material):
         crm_set_materials(self.ctx, table, material)
+        self.n_mat = np.asarray(table).reshape(-1, 3).shape[0]
+
+    def record(self, n):
+        crm_record(self.ctx, n)
+
+    def adjoint(self, **seeds):
+        return crm_adjoint(self.ctx, self.n_soil, getattr(self, "n_mat", 1), **seeds)
 
     def step(self, n=1):
         crm_step(self.ctx, n)

@@ -53,6 +53,8 @@ struct crm_ctx {
   int32_t* proc_ids = nullptr;
   Body* d_bodies = nullptr;
   float4* d_mat = nullptr;     // material table
+  int32_t n_mat = 1;
+  std::vector<uint16_t> h_mat; // material of each soil particle (empty: all 0)
   std::vector<Body> h_bodies;
   double* d_forces = nullptr;
   uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
@@ -103,6 +105,16 @@ struct crm_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
+
+  // reverse mode: a recorded run of steps (crm_record) and its adjoint sweep
+  bool recording = false;
+  bool rec_valid = false;
+  int32_t rec_n = 0;               // recorded steps
+  int64_t rec_step0 = 0;           // step counter at the start of the record
+  std::vector<int64_t> rec_seg;    // first step (relative) of each rebuild segment
+  std::vector<Body> rec_bodies;    // the body table the record ran with
+  float4* rec_snap = nullptr;      // master planes at each segment start (4 x n_total each)
+  int64_t rec_snap_cap = 0;        // segments the snapshot buffer holds
 
   std::vector<Buf> owned;
 };
@@ -298,6 +310,17 @@ crm_status rebuild(crm_ctx* c) {
   const crm_params& P = c->prm;
   if (c->working_valid)
     HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  if (c->recording) {
+    // the state every later step of this segment follows from (reverse mode)
+    const int64_t k = (int64_t)c->rec_seg.size();
+    if (k >= c->rec_snap_cap) return fail(c, CRM_E_STATE, "more list rebuilds than the record expected");
+    const size_t n = (size_t)c->n_total;
+    float4* dst = c->rec_snap + (size_t)k * 4 * n;
+    const float4* src[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
+    for (int q = 0; q < 4; ++q)
+      HIPCHK(c, hipMemcpyAsync(dst + q * n, src[q], sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
+    c->rec_seg.push_back(c->step - c->rec_step0);
+  }
   HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d, s));
   const double t = (double)c->step * P.dt;
   c->ad_on = P.active_domains && t > P.t_delay;
@@ -381,8 +404,27 @@ void prof_end(crm_ctx* c, int k, hipEvent_t start) {
   c->prof_marks.push_back({k, {start, e}});
 }
 
+// Where a taped step keeps y_n and y_mid (with the markers' extrapolated
+// values of each stage) and the tapes of its two stages.
+struct StepRecord {
+  Planes yn, ym;
+  crm::StageTape t1, t2;
+};
+
+crm_status copy_planes(crm_ctx* c, CPlanes src, Planes dst, int64_t n, hipStream_t s) {
+  const size_t b = sizeof(float4) * (size_t)n;
+  if (n <= 0) return CRM_OK;
+  HIPCHK(c, hipMemcpyAsync(dst.a, src.a, b, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(dst.b, src.b, b, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(dst.c, src.c, b, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(dst.d, src.d, b, hipMemcpyDeviceToDevice, s));
+  return CRM_OK;
+}
+
 // The kernels of one step after the (optional) rebuild, on stream s.
-crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof) {
+crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* rec = nullptr) {
+  const crm::StageTape* tape1 = rec ? &rec->t1 : nullptr;
+  const crm::StageTape* tape2 = rec ? &rec->t2 : nullptr;
   const Phys& P = c->phys;
   hipEvent_t e = prof ? prof_begin(c) : nullptr;
   HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies,
@@ -393,16 +435,24 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof) {
   HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P, nullptr,
                      s));
   if (prof) prof_end(c, 2, e);
+  if (rec) {
+    crm_status st = copy_planes(c, c->A, rec->yn, c->n_proc, s);
+    if (st != CRM_OK) return st;
+  }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, s));
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c);
   HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P,
                      c->contrib, s));
   if (prof) prof_end(c, 4, e);
+  if (rec) {
+    crm_status st = copy_planes(c, c->B, rec->ym, c->n_proc, s);
+    if (st != CRM_OK) return st;
+  }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, s));
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, s));
   if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c);
   HIPCHK(c, crm::body_reduce(c->contrib, c->d_bstart, c->nb, c->d_forces, s));
@@ -446,14 +496,19 @@ crm_status step_graph(crm_ctx* c) {
   return CRM_OK;
 }
 
-crm_status one_step(crm_ctx* c) {
-  if (c->force_rebuild || !c->working_valid || c->step % (int64_t)c->prm.ps_freq == 0) {
+bool rebuild_due(const crm_ctx* c) {
+  return c->force_rebuild || !c->working_valid || c->step % (int64_t)c->prm.ps_freq == 0;
+}
+
+crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
+  if (rebuild_due(c)) {
     hipEvent_t e = prof_begin(c);
     crm_status st = rebuild(c);
     if (st != CRM_OK) return st;
     prof_end(c, 0, e);
   }
-  crm_status st = (c->use_graph && !c->prof) ? step_graph(c) : launch_step(c, c->stream, c->prof);
+  crm_status st = rec ? launch_step(c, c->stream, false, rec)
+                      : (c->use_graph && !c->prof) ? step_graph(c) : launch_step(c, c->stream, c->prof);
   if (st != CRM_OK) return st;
   c->step += 1;
   c->stepped = true;
@@ -576,6 +631,10 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   ph.av_coef = (float)(P.av_gamma * P.h * cs * m);
   ph.xi2 = (float)((P.av_xi_over_h * P.h) * (P.av_xi_over_h * P.h));
   ph.av_mode = (int32_t)P.av_mode;
+  ph.kg = (float)(1.0 / (pi * P.h * P.h * P.h * P.h * P.h * P.h * P.h));
+  ph.G = (float)G;
+  ph.bulk = (float)P.bulk_coeff;
+  ph.inv_2K = (float)(0.5 / K);
   ph.mu_s = (float)P.mu_s;
   ph.mu_2 = (float)P.mu_2;
   ph.I0 = (float)P.I0;
@@ -747,6 +806,8 @@ crm_status crm_set_materials(crm_ctx* c, int32_t n_mat, const double* mu_s, cons
   if (n > 0) HIPCHK(c, hipMemcpyAsync(c->m_b, hb.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->d_mat, tab.data(), sizeof(float4) * (size_t)n_mat, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  c->n_mat = n_mat;
+  c->h_mat.assign(material, material + c->n_soil);
   return CRM_OK;
 }
 
@@ -754,11 +815,233 @@ crm_status crm_step(crm_ctx* c, int32_t n_steps) {
   crm_status st = usable(c);
   if (st != CRM_OK) return st;
   if (n_steps < 0) return fail(c, CRM_E_INVALID, "n_steps must be >= 0");
+  if (n_steps > 0) c->rec_valid = false;
   for (int32_t k = 0; k < n_steps; ++k) {
     st = one_step(c);
     if (st != CRM_OK) return st;
   }
   return CRM_OK;
+}
+
+crm_status crm_record(crm_ctx* c, int32_t n_steps) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (n_steps < 1) return fail(c, CRM_E_INVALID, "n_steps must be >= 1");
+  if (c->prm.active_domains) return fail(c, CRM_E_UNSUPPORTED, "the reverse sweep covers runs without active domains");
+  if (!rebuild_due(c)) return fail(c, CRM_E_STATE, "a record starts at a list rebuild (step mod ps_freq = 0)");
+  const int64_t ps = c->prm.ps_freq;
+  const int64_t segs = (int64_t)n_steps / ps + 2;
+  c->rec_valid = false;
+  dfree(c, c->rec_snap);
+  c->rec_snap = nullptr;
+  c->rec_snap_cap = 0;
+  if (!alloc_n(c, c->rec_snap, segs * 4 * c->n_total)) return fail(c, CRM_E_NOMEM, "record snapshot allocation failed");
+  c->rec_snap_cap = segs;
+  c->rec_bodies = c->h_bodies;
+  c->rec_step0 = c->step;
+  c->rec_seg.clear();
+  c->recording = true;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    st = one_step(c);
+    if (st != CRM_OK) {
+      c->recording = false;
+      return st;
+    }
+  }
+  c->recording = false;
+  c->rec_n = n_steps;
+  c->rec_valid = true;
+  return CRM_OK;
+}
+
+crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, const float* lam_sigma,
+                       const float* lam_rho, const double* lam_force, const double* lam_torque, double* out_pos,
+                       float* out_vel, float* out_sigma, float* out_rho, double* out_params) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (!c->rec_valid) return fail(c, CRM_E_STATE, "no recorded run (crm_record) to reverse");
+  if (c->step != c->rec_step0 + c->rec_n) return fail(c, CRM_E_STATE, "the context has moved since crm_record");
+  hipStream_t s = c->stream;
+  const int64_t ns = c->n_soil, nt = c->n_total;
+  const int32_t nb = c->nb;
+  const int64_t nseg = (int64_t)c->rec_seg.size();
+  int64_t seg_max = 0;
+  for (int64_t g = 0; g < nseg; ++g) {
+    const int64_t k1 = g + 1 < nseg ? c->rec_seg[g + 1] : c->rec_n;
+    seg_max = std::max<int64_t>(seg_max, k1 - c->rec_seg[g]);
+  }
+  const bool force_seed = (lam_force || lam_torque) && nb > 0;
+  const int32_t ngrp = c->n_mat + 1;   // materials, then the markers
+  std::vector<void*> tmp;
+  auto take = [&](auto*& p, int64_t n) {
+    bool ok = alloc_n(c, p, n);
+    if (ok) tmp.push_back((void*)p);
+    return ok;
+  };
+  auto done = [&](crm_status r) {
+    (void)hipStreamSynchronize(s);
+    for (void* p : tmp) dfree(c, p);
+    return r;
+  };
+  auto planes = [&](Planes& P, int64_t n) {
+    return take(P.a, n) && take(P.b, n) && take(P.c, n) && take(P.d, n);
+  };
+  Planes Ln{}, Lm{}, E{}, Lid{};
+  float* pg = nullptr;
+  double *pid = nullptr, *fseed = nullptr, *ptmp = nullptr, *gsum = nullptr;
+  int32_t* perm = nullptr;
+  int64_t* gstart = nullptr;
+  std::vector<StepRecord> recs((size_t)seg_max);
+  bool ok = planes(Ln, nt) && planes(Lm, nt) && planes(E, nt) && planes(Lid, ns > 0 ? ns : 1) && take(pg, 5 * nt) &&
+            take(pid, 6 * nt) && take(ptmp, 6 * nt) && take(gsum, 6 * ngrp) && take(perm, nt) &&
+            take(gstart, ngrp + 1) && (!force_seed || take(fseed, (int64_t)c->rec_n * nb * 6));
+  for (auto& r : recs)
+    ok = ok && planes(r.yn, nt) && planes(r.ym, nt) && take(r.t1.l0, nt) && take(r.t1.l1, nt) &&
+         take(r.t1.l2, nt) && take(r.t2.l0, nt) && take(r.t2.l1, nt) && take(r.t2.l2, nt) && take(r.t2.t0, nt) &&
+         take(r.t2.t1, nt);
+  if (!ok) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+  // seeds on the recorded end state (particle-id order) and on the body forces
+  {
+    std::vector<float4> ha((size_t)ns), hb((size_t)ns), hc((size_t)ns), hd((size_t)ns);
+    for (int64_t i = 0; i < ns; ++i) {
+      ha[i] = make_float4(lam_pos ? (float)lam_pos[3 * i] : 0.f, lam_pos ? (float)lam_pos[3 * i + 1] : 0.f,
+                          lam_pos ? (float)lam_pos[3 * i + 2] : 0.f, lam_rho ? lam_rho[i] : 0.f);
+      hb[i] = make_float4(lam_vel ? lam_vel[3 * i] : 0.f, lam_vel ? lam_vel[3 * i + 1] : 0.f,
+                          lam_vel ? lam_vel[3 * i + 2] : 0.f, 0.f);
+      const float* g = lam_sigma ? lam_sigma + 6 * i : nullptr;
+      hc[i] = g ? make_float4(g[0], g[1], g[2], g[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+      hd[i] = g ? make_float4(g[4], g[5], 0.f, 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (ns > 0) {
+      const size_t b = sizeof(float4) * (size_t)ns;
+      HIPCHK(c, hipMemcpyAsync(Lid.a, ha.data(), b, hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(Lid.b, hb.data(), b, hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(Lid.c, hc.data(), b, hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(Lid.d, hd.data(), b, hipMemcpyHostToDevice, s));
+    }
+    if (force_seed) {
+      std::vector<double> f((size_t)c->rec_n * nb * 6, 0.0);
+      for (int64_t k = 0; k < (int64_t)c->rec_n * nb; ++k)
+        for (int a = 0; a < 3; ++a) {
+          f[6 * k + a] = lam_force ? lam_force[3 * k + a] : 0.0;
+          f[6 * k + 3 + a] = lam_torque ? lam_torque[3 * k + a] : 0.0;
+        }
+      HIPCHK(c, hipMemcpyAsync(fseed, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(c, hipMemsetAsync(pg, 0, sizeof(float) * 5 * (size_t)nt, s));
+    HIPCHK(c, hipMemsetAsync(pid, 0, sizeof(double) * 6 * (size_t)nt, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  const std::vector<Body> cur_bodies = c->h_bodies;
+  auto set_bodies_dev = [&](const std::vector<Body>& B) -> crm_status {
+    HIPCHK(c, hipMemcpyAsync(c->d_bodies, B.data(), sizeof(Body) * B.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->h_bodies = B;
+    return CRM_OK;
+  };
+  auto restore = [&](int64_t g) -> crm_status {
+    const size_t n = (size_t)nt;
+    const float4* src = c->rec_snap + (size_t)g * 4 * n;
+    float4* dst[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
+    for (int q = 0; q < 4; ++q)
+      HIPCHK(c, hipMemcpyAsync(dst[q], src + q * n, sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
+    c->working_valid = false;
+    c->force_rebuild = true;
+    c->step = c->rec_step0 + c->rec_seg[g];
+    return CRM_OK;
+  };
+  st = set_bodies_dev(c->rec_bodies);
+  if (st != CRM_OK) return done(st);
+  const Phys& P = c->phys;
+  for (int64_t g = nseg - 1; g >= 0; --g) {
+    const int64_t k0 = c->rec_seg[g], k1 = g + 1 < nseg ? c->rec_seg[g + 1] : c->rec_n;
+    st = restore(g);
+    if (st != CRM_OK) return done(st);
+    for (int64_t k = k0; k < k1; ++k) {
+      st = one_step(c, &recs[k - k0]);
+      if (st != CRM_OK) return done(st);
+    }
+    HIPCHK(c, crm::adj_to_slots(c->frows, c->n_frows, c->slot_id, Lid, Ln, s));
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const StepRecord& R = recs[k - k0];
+      const double* fs = force_seed ? fseed + (size_t)k * nb * 6 : nullptr;
+      // stage 2 (y* = y_n + dt f(y_mid), return mapping, body forces of y_mid)
+      HIPCHK(c, crm::adj_local2(c->frows, c->n_frows, Ln, Lm, E, R.yn, R.ym, R.t2, P, pg, s));
+      HIPCHK(c, crm::adj_marker(R.ym, E, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, fs, P, pg, s));
+      HIPCHK(c, crm::adj_gather(R.ym, E, c->frows, c->n_frows, c->off_f, c->nbr_f, P, Lm, pg, s));
+      // stage 1 (y_mid = y_n + dt/2 f(y_n))
+      HIPCHK(c, crm::adj_local1(c->frows, c->n_frows, Ln, Lm, E, R.yn, R.t1, P, pg, s));
+      HIPCHK(c, crm::adj_marker(R.yn, E, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, nullptr, P, pg, s));
+      HIPCHK(c, crm::adj_gather(R.yn, E, c->frows, c->n_frows, c->off_f, c->nbr_f, P, Ln, pg, s));
+    }
+    HIPCHK(c, crm::adj_to_ids(c->frows, c->n_frows, c->slot_id, Ln, Lid, s));
+    HIPCHK(c, crm::adj_params_to_ids(c->n_proc, c->slot_id, pg, pid, s));
+  }
+  // parameter sums per material (and the markers) in a fixed order
+  std::vector<int32_t> hperm((size_t)nt);
+  std::vector<int64_t> hstart((size_t)ngrp + 1, 0);
+  {
+    std::vector<int64_t> cnt((size_t)ngrp, 0);
+    for (int64_t i = 0; i < ns; ++i) cnt[c->h_mat.empty() ? 0 : c->h_mat[i]] += 1;
+    cnt[ngrp - 1] = nt - ns;
+    for (int32_t g = 0; g < ngrp; ++g) hstart[g + 1] = hstart[g] + cnt[g];
+    std::vector<int64_t> pos(hstart.begin(), hstart.end() - 1);
+    for (int64_t i = 0; i < ns; ++i) hperm[pos[c->h_mat.empty() ? 0 : c->h_mat[i]]++] = (int32_t)i;
+    for (int64_t i = ns; i < nt; ++i) hperm[pos[ngrp - 1]++] = (int32_t)i;
+  }
+  HIPCHK(c, hipMemcpyAsync(perm, hperm.data(), sizeof(int32_t) * hperm.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(gstart, hstart.data(), sizeof(int64_t) * hstart.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, crm::adj_params_permute(nt, perm, pid, ptmp, s));
+  HIPCHK(c, crm::body_reduce(ptmp, gstart, ngrp, gsum, s));
+  std::vector<double> hsum((size_t)6 * ngrp);
+  HIPCHK(c, hipMemcpyAsync(hsum.data(), gsum, sizeof(double) * hsum.size(), hipMemcpyDeviceToHost, s));
+  // adjoint of the recorded start state
+  {
+    std::vector<float4> ha((size_t)ns), hb((size_t)ns), hc((size_t)ns), hd((size_t)ns);
+    if (ns > 0) {
+      const size_t b = sizeof(float4) * (size_t)ns;
+      HIPCHK(c, hipMemcpyAsync(ha.data(), Lid.a, b, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(hb.data(), Lid.b, b, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(hc.data(), Lid.c, b, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(hd.data(), Lid.d, b, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    bool finite = true;
+    for (int64_t i = 0; i < ns; ++i) {
+      const float v[13] = {ha[i].x, ha[i].y, ha[i].z, ha[i].w, hb[i].x, hb[i].y, hb[i].z,
+                           hc[i].x, hc[i].y, hc[i].z, hc[i].w, hd[i].x, hd[i].y};
+      for (float x : v) finite = finite && std::isfinite(x);
+      if (out_pos) { out_pos[3 * i] = ha[i].x; out_pos[3 * i + 1] = ha[i].y; out_pos[3 * i + 2] = ha[i].z; }
+      if (out_rho) out_rho[i] = ha[i].w;
+      if (out_vel) { out_vel[3 * i] = hb[i].x; out_vel[3 * i + 1] = hb[i].y; out_vel[3 * i + 2] = hb[i].z; }
+      if (out_sigma) {
+        float* o = out_sigma + 6 * i;
+        o[0] = hc[i].x; o[1] = hc[i].y; o[2] = hc[i].z; o[3] = hc[i].w; o[4] = hd[i].x; o[5] = hd[i].y;
+      }
+    }
+    if (out_params) {
+      double dG = 0.0, dK = 0.0;
+      for (int32_t g = 0; g < ngrp; ++g) {
+        dG += hsum[6 * g];
+        dK += hsum[6 * g + 1];
+      }
+      const double E_ = c->prm.E, nu = c->prm.nu;
+      out_params[0] = dG / (2.0 * (1.0 + nu)) + dK / (3.0 * (1.0 - 2.0 * nu));
+      out_params[1] = -dG * E_ / (2.0 * (1.0 + nu) * (1.0 + nu)) + dK * 2.0 * E_ / (3.0 * (1.0 - 2.0 * nu) * (1.0 - 2.0 * nu));
+      for (int32_t m = 0; m < c->n_mat; ++m)
+        for (int a = 0; a < 3; ++a) out_params[2 + 3 * m + a] = hsum[6 * m + 2 + a];
+      for (int k = 0; k < 2 + 3 * c->n_mat; ++k) finite = finite && std::isfinite(out_params[k]);
+    }
+    if (!finite) st = fail(c, CRM_E_NONFINITE, "non-finite adjoint");
+  }
+  // back to the recorded end state: the last segment again, forward
+  if (st == CRM_OK) {
+    const int64_t g = nseg - 1;
+    st = restore(g);
+    for (int64_t k = c->rec_seg[g]; st == CRM_OK && k < c->rec_n; ++k) st = one_step(c);
+  }
+  if (st == CRM_OK) st = set_bodies_dev(cur_bodies);
+  return done(st);
 }
 
 crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque) {
@@ -846,6 +1129,7 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
   }
   c->working_valid = false;
   c->force_rebuild = true;
+  c->rec_valid = false;
   return CRM_OK;
 }
 

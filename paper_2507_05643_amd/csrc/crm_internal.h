@@ -84,6 +84,10 @@ struct Phys {
   float av_coef;  // gamma_a h c_s m
   float xi2;      // (xi_over_h h)^2
   int32_t av_mode;
+  float kg;       // 1 / (pi h^7): the radial derivative of f(q) kf, over r, is kg g2(q)
+  float G;        // shear modulus, bulk factor and 1 / (2K) for the adjoint's
+  float bulk;     // parameter derivatives
+  float inv_2K;
   float mu_s, mu_2, I0, grain_d, cohesion, p_cri, inv_Gdt;
   int32_t cell;   // positions stored as cell index + FP32 offset
   float Sf;       // cell size 2h in FP32 (cell-offset positions)
@@ -166,11 +170,36 @@ hipError_t body_reduce(const double* contrib, const int64_t* bstart, int32_t nb,
                        hipStream_t s);
 
 // Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
-// mapping (Sec. 2.4).
+// mapping (Sec. 2.4). With a tape, the velocity gradient of each row (and in
+// stage 2 its trial stress) is also written, by slot.
+struct StageTape {
+  float4* l0;   // (L00, L01, L02, L10)
+  float4* l1;   // (L11, L12, L20, L21)
+  float4* l2;   // (L22, -, -, -)
+  float4* t0;   // trial stress (sxx, syy, szz, sxy), stage 2
+  float4* t1;   // (sxz, syz, -, -), stage 2
+};
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s);
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s);
+
+// Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
+// the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.
+hipError_t adj_local2(const int32_t* rows, int64_t n, Planes Ln, Planes Lm, Planes E, CPlanes Yn, CPlanes Ym,
+                      const StageTape& T, Phys P, float* pg, hipStream_t s);
+hipError_t adj_local1(const int32_t* rows, int64_t n, Planes Ln, CPlanes Lm, Planes E, CPlanes Yn,
+                      const StageTape& T, Phys P, float* pg, hipStream_t s);
+hipError_t adj_marker(CPlanes Y, Planes E, const int32_t* mrows, int64_t n, const uint64_t* off,
+                      const uint32_t* nbr, const Body* bodies, const double* fs, Phys P, float* pg, hipStream_t s);
+hipError_t adj_gather(CPlanes Y, CPlanes E, const int32_t* rows, int64_t n, const uint64_t* off,
+                      const uint32_t* nbr, Phys P, Planes Lt, float* pg, hipStream_t s);
+hipError_t adj_to_slots(const int32_t* rows, int64_t n, const int32_t* slot_id, CPlanes byid, Planes byslot,
+                        hipStream_t s);
+hipError_t adj_to_ids(const int32_t* rows, int64_t n, const int32_t* slot_id, CPlanes byslot, Planes byid,
+                      hipStream_t s);
+hipError_t adj_params_to_ids(int64_t n_proc, const int32_t* slot_id, float* pg, double* pid, hipStream_t s);
+hipError_t adj_params_permute(int64_t n, const int32_t* perm, const double* pid, double* out, hipStream_t s);
 
 // Scatter working records back to the master planes.
 hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
