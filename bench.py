@@ -37,6 +37,11 @@ BYTES_PER_PARTICLE = 3 * 52 + 16
 BYTES_PER_PAIR = 4
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of k_fluid_stage2 on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy (fetch x2, write x1); the
+# commands and figures are in profiles/wheel_bin_kernels_lds_tiles.md. Valid
+# for the kernel with 768-record LDS tiles; None once the kernel changes.
+STAGE2_TRAFFIC_BYTES = 573.7e6
 
 
 class WheelDriver:
@@ -214,6 +219,33 @@ def run_strip(args):
                         "dt": dt})
 
 
+def adjoint_cost(sim, one_step, k, ps_freq, n_soil, nb):
+    """Wall time of k plain forward steps, of recording k steps and of the
+    adjoint sweep over them (seeded weights on the end state and on every
+    step's body forces), bodies frozen over the k steps as in crm_step."""
+    import torch
+    while sim.counts()["steps"] % ps_freq:
+        one_step()
+    rng = np.random.default_rng(0)
+    seeds = dict(lam_pos=rng.normal(size=(n_soil, 3)), lam_vel=rng.normal(size=(n_soil, 3)),
+                 lam_sigma=rng.normal(size=(n_soil, 6)), lam_rho=rng.normal(size=n_soil),
+                 lam_force=rng.normal(size=(k, nb, 3)), lam_torque=rng.normal(size=(k, nb, 3)))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    t_fwd, _ = timed(lambda: sim.step(k))
+    t_rec, _ = timed(lambda: sim.record(k))
+    t_adj, g = timed(lambda: sim.adjoint(**seeds))
+    return dict(steps=k, forward_ms=round(t_fwd, 3), record_ms=round(t_rec, 3), adjoint_ms=round(t_adj, 3),
+                ratio=round(t_adj / t_fwd, 3), dL_dE=float(g["params"][0]), dL_dmu_s=float(g["params"][2]),
+                note="wall time of each call, host seeds and outputs included")
+
+
 def cpu_baseline(scene, steps):
     from oracle.oracle import Oracle
     orc = Oracle(scene, nbr_mode="cells")
@@ -238,6 +270,9 @@ def main():
     ap.add_argument("--pos-mode", type=int, default=0)
     ap.add_argument("--strip-length", type=float, default=10000.0)
     ap.add_argument("--strip-x", type=float, default=5000.0)
+    ap.add_argument("--adjoint-steps", type=int, default=20,
+                    help="after the timed run, cost of the reverse sweep (crm_record + crm_adjoint) "
+                         "over this many steps against the plain forward steps (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB once (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
@@ -296,10 +331,13 @@ def main():
     tflops = flops / (ms2 * 1e-3) / 1e12
     gbs = bytes_ / (ms2 * 1e-3) / 1e9
     roofline = dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(tflops / PEAK_FP32_TFLOPS, 4), traffic=None,
+                    frac=round(tflops / PEAK_FP32_TFLOPS, 4),
+                    traffic=STAGE2_TRAFFIC_BYTES if args.ps_freq == 10 else None,
                     kernel="k_fluid_stage2", launch_ms=round(ms2, 5), algorithmic_flops=flops,
                     hbm_view=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                                   frac=round(gbs / PEAK_HBM_GBS, 4), algorithmic_bytes=bytes_))
+    adjoint = adjoint_cost(sim, one_step, args.adjoint_steps, args.ps_freq, sc.n_soil, len(sc.bodies)) \
+        if args.adjoint_steps > 0 else None
     breakdown = {k: round(v["ms"] / max(v["launches"], 1), 5) for k, v in prof.items() if isinstance(v, dict)}
     print(json.dumps(dict(profile_ms_per_launch=breakdown, counts=cnt, wheel_force=F[1].tolist(),
                           wheel_torque=T[1].tolist(), wheel_z=float(drv.x[2]))), file=sys.stderr, flush=True)
@@ -336,6 +374,7 @@ def main():
                    "dt": dt},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 

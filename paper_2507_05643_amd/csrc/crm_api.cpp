@@ -75,6 +75,7 @@ struct crm_ctx {
   uint32_t *cnt_f = nullptr, *cnt_m = nullptr;
   uint64_t *off_f = nullptr, *off_m = nullptr, *wtmp = nullptr;
   uint32_t *stash_f = nullptr, *stash_m = nullptr;  // count-pass scratch of the lists
+  uint32_t* tabs = nullptr;       // LDS tile tables of the soil-row blocks
 
   // neighbour entries
   uint32_t* nbr_f = nullptr;
@@ -84,6 +85,7 @@ struct crm_ctx {
 
   double* contrib = nullptr;     // per marker id: force and torque on its body (6 FP64)
   int64_t* d_bstart = nullptr;   // first marker id (relative) of each body, nb + 1
+  crm::SegPlan body_plan;        // chunked per-body force sums
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
   uint64_t* h_counts = nullptr;   // pinned mirror
 
@@ -258,7 +260,7 @@ void quat_to_R(const double q[4], double R[9]) {
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
   void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id,
                   c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->cnt_f, c->cnt_m, c->off_f,
-                  c->off_m, c->wtmp, c->stash_f, c->stash_m};
+                  c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
   for (void* p : olds) dfree(c, p);
   c->A = Planes{};
   c->B = Planes{};
@@ -268,6 +270,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
   c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = nullptr;
   c->off_f = c->off_m = c->wtmp = nullptr;
   c->stash_f = c->stash_m = nullptr;
+  c->tabs = nullptr;
   c->cap = 0;
   bool ok = alloc_n(c, c->A.a, cap) && alloc_n(c, c->A.b, cap) && alloc_n(c, c->A.c, cap) &&
             alloc_n(c, c->A.d, cap) && alloc_n(c, c->B.a, cap) && alloc_n(c, c->B.b, cap) &&
@@ -279,7 +282,8 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
             alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
             alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
             alloc_n(c, c->stash_f, (int64_t)crm::stash_elems(cap)) &&
-            alloc_n(c, c->stash_m, (int64_t)crm::stash_elems(cap));
+            alloc_n(c, c->stash_m, (int64_t)crm::stash_elems(cap)) &&
+            alloc_n(c, c->tabs, crm::tile_table_words(cap));
   if (!ok) return fail(c, CRM_E_NOMEM, "working-set allocation failed");
   c->cap = cap;
   c->working_valid = false;
@@ -294,6 +298,51 @@ crm_status ensure_list(crm_ctx* c, uint32_t*& buf, int64_t& cap, int64_t need) {
   int64_t n = (int64_t)std::ceil(c->prm.grow_G * (double)need) + crm::kWave;
   if (!alloc_n(c, buf, n)) return fail(c, CRM_E_NOMEM, "neighbour-list allocation failed");
   cap = n;
+  return CRM_OK;
+}
+
+// Chunks of the segments [start[g], start[g + 1]) for segment_reduce; device
+// arrays from the context's allocator, listed in `owned` when given (freed by
+// the caller), else kept for the context's lifetime.
+crm_status make_plan(crm_ctx* c, const std::vector<int64_t>& start, crm::SegPlan& plan, std::vector<void*>* owned) {
+  const int32_t nseg = (int32_t)start.size() - 1;
+  const int64_t ch = crm::reduce_chunk();
+  std::vector<int64_t> lo, hi;
+  std::vector<int32_t> first((size_t)nseg + 1, 0);
+  for (int32_t g = 0; g < nseg; ++g) {
+    first[g] = (int32_t)lo.size();
+    for (int64_t k = start[g]; k < start[g + 1]; k += ch) {
+      lo.push_back(k);
+      hi.push_back(std::min(k + ch, start[g + 1]));
+    }
+  }
+  first[nseg] = (int32_t)lo.size();
+  const int64_t nc = (int64_t)lo.size();
+  int64_t *dlo = nullptr, *dhi = nullptr;
+  int32_t* dfirst = nullptr;
+  double* dpart = nullptr;
+  if (!(alloc_n(c, dlo, nc > 0 ? nc : 1) && alloc_n(c, dhi, nc > 0 ? nc : 1) && alloc_n(c, dfirst, nseg + 1) &&
+        alloc_n(c, dpart, 6 * (nc > 0 ? nc : 1))))
+    return fail(c, CRM_E_NOMEM, "reduction plan allocation failed");
+  if (owned) {
+    owned->push_back(dlo);
+    owned->push_back(dhi);
+    owned->push_back(dfirst);
+    owned->push_back(dpart);
+  }
+  hipStream_t s = c->stream;
+  if (nc > 0) {
+    HIPCHK(c, hipMemcpyAsync(dlo, lo.data(), sizeof(int64_t) * (size_t)nc, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(dhi, hi.data(), sizeof(int64_t) * (size_t)nc, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(dfirst, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  plan.nseg = nseg;
+  plan.nchunk = nc;
+  plan.lo = dlo;
+  plan.hi = dhi;
+  plan.first = dfirst;
+  plan.partial = dpart;
   return CRM_OK;
 }
 
@@ -371,6 +420,7 @@ crm_status rebuild(crm_ctx* c) {
                           c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
+  HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, c->grid.cell != 0, s));
   // markers outside the processed set contribute nothing until the next rebuild
   HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mark, s));
   c->working_valid = true;
@@ -440,7 +490,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, s));
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, s));
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c);
@@ -452,10 +502,10 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, s));
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, s));
   if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::body_reduce(c->contrib, c->d_bstart, c->nb, c->d_forces, s));
+  HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_forces, s));
   if (prof) prof_end(c, 6, e);
   return CRM_OK;
 }
@@ -646,7 +696,10 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   ph.Sf = (float)g.S;
   ph.S = g.S;
   ph.invS = g.inv;
-  for (int q = 0; q < 3; ++q) ph.lo[q] = g.lo[q];
+  for (int q = 0; q < 3; ++q) {
+    ph.lo[q] = g.lo[q];
+    ph.gdim[q] = g.dims[q];
+  }
 
   // host staging of the master planes
   std::vector<float4> ha((size_t)n_total), hb((size_t)n_total), hc((size_t)n_total), hd((size_t)n_total);
@@ -728,6 +781,11 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_bstart, bstart.data(), sizeof(int64_t) * bstart.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && nm > 0) e = hipMemsetAsync(c->contrib, 0, sizeof(double) * 6 * (size_t)nm, s);
+  if (e == hipSuccess && make_plan(c, bstart, c->body_plan, nullptr) != CRM_OK) {
+    std::string m2 = c->err;
+    release(c);
+    return fail(nullptr, CRM_E_NOMEM, m2);
+  }
   const float4 mat0 = make_float4((float)P.mu_s, (float)P.mu_2, (float)P.cohesion, (float)(-P.cohesion / P.mu_s));
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_mat, &mat0, sizeof(float4), hipMemcpyHostToDevice, s);
   c->phys.mat = c->d_mat;
@@ -890,11 +948,10 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
   float* pg = nullptr;
   double *pid = nullptr, *fseed = nullptr, *ptmp = nullptr, *gsum = nullptr;
   int32_t* perm = nullptr;
-  int64_t* gstart = nullptr;
   std::vector<StepRecord> recs((size_t)seg_max);
   bool ok = planes(Ln, nt) && planes(Lm, nt) && planes(E, nt) && planes(Lid, ns > 0 ? ns : 1) && take(pg, 5 * nt) &&
             take(pid, 6 * nt) && take(ptmp, 6 * nt) && take(gsum, 6 * ngrp) && take(perm, nt) &&
-            take(gstart, ngrp + 1) && (!force_seed || take(fseed, (int64_t)c->rec_n * nb * 6));
+(!force_seed || take(fseed, (int64_t)c->rec_n * nb * 6));
   for (auto& r : recs)
     ok = ok && planes(r.yn, nt) && planes(r.ym, nt) && take(r.t1.l0, nt) && take(r.t1.l1, nt) &&
          take(r.t1.l2, nt) && take(r.t2.l0, nt) && take(r.t2.l1, nt) && take(r.t2.l2, nt) && take(r.t2.t0, nt) &&
@@ -990,9 +1047,11 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
     for (int64_t i = ns; i < nt; ++i) hperm[pos[ngrp - 1]++] = (int32_t)i;
   }
   HIPCHK(c, hipMemcpyAsync(perm, hperm.data(), sizeof(int32_t) * hperm.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(gstart, hstart.data(), sizeof(int64_t) * hstart.size(), hipMemcpyHostToDevice, s));
+  crm::SegPlan gplan;
+  st = make_plan(c, hstart, gplan, &tmp);
+  if (st != CRM_OK) return done(st);
   HIPCHK(c, crm::adj_params_permute(nt, perm, pid, ptmp, s));
-  HIPCHK(c, crm::body_reduce(ptmp, gstart, ngrp, gsum, s));
+  HIPCHK(c, crm::segment_reduce(ptmp, gplan, gsum, s));
   std::vector<double> hsum((size_t)6 * ngrp);
   HIPCHK(c, hipMemcpyAsync(hsum.data(), gsum, sizeof(double) * hsum.size(), hipMemcpyDeviceToHost, s));
   // adjoint of the recorded start state

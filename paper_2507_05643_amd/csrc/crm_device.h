@@ -173,31 +173,28 @@ __device__ inline Nbr load_nbr(const CPlanes& S, uint32_t j) {
   return n;
 }
 
+// Neighbour records read straight from the four planes in HBM (through L1/L2).
+struct GlobalLoad {
+  static constexpr bool kTile = false;
+  CPlanes S;
+  __device__ Nbr operator()(uint32_t j) const { return load_nbr(S, j); }
+};
+
 // Walks entries k0 + lane, k0 + lane + kGroup, ... < k1 of a CSR row and calls
-// f(record, slot) for each. The gathers are software-pipelined: the index two
-// entries ahead and the record one entry ahead are in flight while f runs.
+// f(record, slot) for each, with the record from `load`.
+template <class Load, class Fn>
+__device__ inline void walk_row_with(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
+                                     Fn&& f) {
+  for (uint64_t k = k0 + group_lane(); k < k1; k += kGroup) {
+    const uint32_t j = nbr[k];
+    f(load(j), j);
+  }
+}
+
 template <class Fn>
 __device__ inline void walk_row(const CPlanes& S, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
                                 Fn&& f) {
-  uint64_t k = k0 + group_lane();
-  if (k >= k1) return;
-  const uint64_t last = k;                       // a valid entry, read when past the end
-  uint32_t j = nbr[k];
-  uint64_t kn = k + kGroup;
-  uint32_t jn = nbr[kn < k1 ? kn : last];
-  Nbr cur = load_nbr(S, j);
-  for (;;) {
-    const bool more = kn < k1;
-    const uint64_t knn = kn + kGroup;
-    const uint32_t jnn = nbr[knn < k1 ? knn : last];
-    const Nbr nxt = load_nbr(S, jn);
-    f(cur, j);
-    if (!more) break;
-    cur = nxt;
-    j = jn;
-    jn = jnn;
-    kn = knn;
-  }
+  walk_row_with(GlobalLoad{S}, k0, k1, nbr, f);
 }
 
 // Own position of a row for pair separations: coordinates (FP32 absolute) or

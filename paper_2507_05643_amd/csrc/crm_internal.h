@@ -93,6 +93,7 @@ struct Phys {
   float Sf;       // cell size 2h in FP32 (cell-offset positions)
   double S, invS; // cell size and its inverse in FP64
   double lo[3];   // grid origin
+  int32_t gdim[3];  // cells per axis
   const float4* mat;  // per material: (mu_s, mu_2, cohesion, -cohesion / mu_s)
 };
 
@@ -165,9 +166,20 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const in
 hipError_t bce(Planes S, const int32_t* mrows, int64_t n_mrows, const uint64_t* off, const uint32_t* nbr,
                const Body* bodies, const int32_t* slot_id, int64_t n_soil, Phys P, double* contrib,
                hipStream_t s);
-// forces[b] = sum of contrib over body b's marker ids [bstart[b], bstart[b + 1]).
-hipError_t body_reduce(const double* contrib, const int64_t* bstart, int32_t nb, double* forces,
-                       hipStream_t s);
+// Deterministic sums of 6 doubles per entry over contiguous segments: the
+// plan cuts segment g = [start[g], start[g + 1]) into chunks of at most
+// reduce_chunk() entries (lo/hi per chunk, first[g] = first chunk of g,
+// partial = 6 per chunk); out gets 6 per segment.
+struct SegPlan {
+  int32_t nseg = 0;
+  int64_t nchunk = 0;
+  const int64_t* lo = nullptr;
+  const int64_t* hi = nullptr;
+  const int32_t* first = nullptr;
+  double* partial = nullptr;
+};
+int64_t reduce_chunk();
+hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s);
 
 // Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
 // mapping (Sec. 2.4). With a tape, the velocity gradient of each row (and in
@@ -179,10 +191,17 @@ struct StageTape {
   float4* t0;   // trial stress (sxx, syy, szz, sxy), stage 2
   float4* t1;   // (sxz, syz, -, -), stage 2
 };
+// tabs: the per-block tile tables of the soil rows (tile_tables, after each
+// list rebuild).
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, hipStream_t s);
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, hipStream_t s);
+// Per block of soil rows: the nine slot ranges its rows' neighbours lie in,
+// and whether they fit the block's LDS tile (tile_table_words(rows_cap) words).
+int64_t tile_table_words(int64_t rows_cap);
+hipError_t tile_tables(const int32_t* frows, int64_t n_frows, const uint32_t* skey, const uint32_t* cell_start,
+                       Phys P, uint32_t* tabs, bool cell, hipStream_t s);
 
 // Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
 // the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.

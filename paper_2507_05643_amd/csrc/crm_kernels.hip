@@ -581,18 +581,24 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
   }
 }
 
-// Sum of the markers' force/torque over each body's contiguous marker-id range
-// [bstart[b], bstart[b + 1]) in a fixed order (strided per thread, then a
-// tree), so the result depends only on the body's markers.
-__global__ __launch_bounds__(kBlock) void k_body_reduce(const double* __restrict__ contrib,
-                                                        const int64_t* __restrict__ bstart,
-                                                        double* __restrict__ forces) {
+// Deterministic segmented sums of 6 doubles per entry (the markers' force
+// and torque per body; also parameter sums by group): each segment is cut into
+// chunks of at most kRedChunk entries; a block sums one chunk in a fixed order
+// (strided per thread, then a tree), then each segment sums its chunks' partials
+// in chunk order.
+constexpr int64_t kRedChunk = 4 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_chunk_reduce(const double* __restrict__ in,
+                                                         const int64_t* __restrict__ lo,
+                                                         const int64_t* __restrict__ hi,
+                                                         double* __restrict__ partial) {
   __shared__ double red[6][kBlock];
-  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int t = threadIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int64_t e = bstart[b + 1];
-  for (int64_t k = bstart[b] + t; k < e; k += kBlock)
-    for (int a = 0; a < 6; ++a) acc[a] += contrib[k * 6 + a];
+  const int64_t e = hi[c];
+  for (int64_t k = lo[c] + t; k < e; k += kBlock)
+    for (int a = 0; a < 6; ++a) acc[a] += in[k * 6 + a];
   for (int a = 0; a < 6; ++a) red[a][t] = acc[a];
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -600,7 +606,28 @@ __global__ __launch_bounds__(kBlock) void k_body_reduce(const double* __restrict
       for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + o];
     __syncthreads();
   }
-  if (t < 6) forces[b * 6 + t] = red[t][0];
+  if (t < 6) partial[c * 6 + t] = red[t][0];
+}
+
+// One block per segment: thread t sums chunks first + t, first + t + kBlock,
+// ... in order, then a tree over the threads.
+__global__ __launch_bounds__(kBlock) void k_segment_sum(const double* __restrict__ partial,
+                                                        const int32_t* __restrict__ first,
+                                                        double* __restrict__ out) {
+  __shared__ double red[6][kBlock];
+  const int32_t g = blockIdx.x;
+  const int t = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int32_t c = first[g] + t; c < first[g + 1]; c += kBlock)
+    for (int a = 0; a < 6; ++a) acc[a] += partial[(int64_t)c * 6 + a];
+  for (int a = 0; a < 6; ++a) red[a][t] = acc[a];
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (t < o)
+      for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + o];
+    __syncthreads();
+  }
+  if (t < 6) out[(int64_t)g * 6 + t] = red[t][0];
 }
 
 // ------------------------------------------------------------- fluid ---
@@ -617,8 +644,8 @@ struct Rates {
 // with the sign that repels approaching pairs); ds/dt = Om s - s Om + 2G D +
 // (bulk K - 2G/3) tr D I with D, Om the symmetric and skew parts of L.
 // The group's lanes take the row's neighbours k = lane, lane + kGroup, ...
-template <bool CELL>
-__device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, CPlanes S, uint64_t k0,
+template <bool CELL, class Load>
+__device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, const Load& load, uint64_t k0,
                                   uint64_t k1, const uint32_t* __restrict__ nbr, const Phys& P) {
   const Own me = own_pos<CELL>(ma, md);
   const float rhoi = ma.w;
@@ -626,7 +653,7 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, CP
   const float s0 = mc.x, s1 = mc.y, s2 = mc.z, s3 = mc.w, s4 = md.x, s5 = md.y;
   float L00 = 0.f, L01 = 0.f, L02 = 0.f, L10 = 0.f, L11 = 0.f, L12 = 0.f, L20 = 0.f, L21 = 0.f, L22 = 0.f;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-  walk_row(S, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+  auto pair = [&](const Nbr& o, uint32_t) {
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -647,7 +674,9 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, CP
     const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
     const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhoi + o.a.w) * (r2 + P.xi2)) : 0.f;
     v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
-  });
+  };
+  if constexpr (Load::kTile) walk_row_ahead(load, k0, k1, nbr, pair);
+  else walk_row_with(load, k0, k1, nbr, pair);
   L00 = group_sum(L00); L01 = group_sum(L01); L02 = group_sum(L02);
   L10 = group_sum(L10); L11 = group_sum(L11); L12 = group_sum(L12);
   L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
@@ -717,6 +746,229 @@ __device__ inline void return_map(float st[6], const float sn[6], const Phys& P,
   st[5] *= f;
 }
 
+// ------------------------------------------------- LDS-staged neighbours ---
+// A workgroup serves kRows consecutive soil rows (cell-sorted). When they all
+// lie in one (y, z) row of cells, every neighbour of every row lies in one of
+// nine contiguous slot ranges: the cells x0 - 1 .. x1 + 1 of the nine (y, z)
+// rows around it. The block copies these ranges into LDS once, with coalesced
+// loads, and the pair loop reads neighbours from LDS instead of making an L1
+// line lookup per plane per pair. Blocks whose rows span two cell rows, or
+// whose ranges exceed the tile, read from global memory as before.
+constexpr int kRows = kBlock / kGroup;
+
+// FP32 positions: 52-byte records (sigma_xz in b.w, where the aux word sits in
+// HBM; sigma_yz apart), 768 of them (40 KB: four blocks per CU); cell-offset
+// positions: 64-byte records (plane d carries the cells), 832 of them (53 KB:
+// three blocks per CU). On the wheel bin 84 % of the 32-row blocks fit 768.
+template <bool CELL>
+struct StageTile;
+template <>
+struct StageTile<false> {
+  static constexpr uint32_t kCap = 768;
+  float4 a[kCap], b[kCap], c[kCap];
+  float s5[kCap];
+};
+template <>
+struct StageTile<true> {
+  static constexpr uint32_t kCap = 832;
+  float4 a[kCap], b[kCap], c[kCap], d[kCap];
+};
+
+// Per block of kRows rows, computed once per list rebuild (k_tile_tables):
+// words 0-8 first slot of each of the nine ranges (~0: outside the grid),
+// 9-17 offset o_k (slot j of range k sits at tile index j - o_k), 18 total
+// records, 19 whether the block uses the tile.
+constexpr int kTabWords = 20;
+
+__global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows, int64_t n,
+                                                        const uint32_t* __restrict__ skey,
+                                                        const uint32_t* __restrict__ cs, Phys P, uint32_t cap,
+                                                        uint32_t* __restrict__ tabs) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r0 = b * kRows;
+  if (r0 >= n) return;
+  uint32_t* t = tabs + b * kTabWords;
+  const int64_t rl = (r0 + kRows - 1 < n) ? r0 + kRows - 1 : n - 1;
+  const uint32_t X = (uint32_t)P.gdim[0], Y = (uint32_t)P.gdim[1], Z = (uint32_t)P.gdim[2];
+  const uint32_t c0 = skey[rows[r0]], c1 = skey[rows[rl]];
+  const uint32_t x0 = c0 % X, y0 = (c0 / X) % Y, z0 = c0 / (X * Y);
+  const uint32_t x1 = c1 % X, y1 = (c1 / X) % Y, z1 = c1 / (X * Y);
+  uint32_t total = 0;
+  uint32_t ok = (y0 == y1 && z0 == z1) ? 1u : 0u;
+  const uint32_t xl = x0 > 0 ? x0 - 1 : 0, xh = x1 + 1 < X ? x1 + 1 : X - 1;
+  int k = 0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy, ++k) {
+      const int64_t yy = (int64_t)y0 + dy, zz = (int64_t)z0 + dz;
+      if (!ok || yy < 0 || yy >= (int64_t)Y || zz < 0 || zz >= (int64_t)Z) {
+        t[k] = 0xffffffffu;
+        t[9 + k] = 0;
+        continue;
+      }
+      const uint64_t base = ((uint64_t)zz * Y + (uint64_t)yy) * X;
+      const uint32_t s0 = cs[base + xl], s1 = cs[base + xh + 1];
+      t[k] = s0;
+      t[9 + k] = s0 - total;
+      total += s1 - s0;
+    }
+  if (total > cap) ok = 0;
+  t[18] = total;
+  t[19] = ok;
+}
+
+// Slot -> tile index through the nine ranges, as scalars (block-uniform,
+// kept in SGPRs). Slot j of range k sits at tile index j - o_k; with d_k the
+// step of o from the previous range that exists, o_k is o_0 plus the d_m of
+// the ranges m <= k that start at or before j (a range outside the grid
+// starts at ~0 and never counts). Written as sums so that no select picks
+// between two loaded values. The same holds in tile-index space with the
+// ranges' first tile indices b_k, for the copy into the tile.
+template <bool CELL>
+struct TileLoad {
+  static constexpr bool kTile = true;
+  const StageTile<CELL>* T;
+  uint32_t s1, s2, s3, s4, s5, s6, s7, s8;
+  uint32_t b1, b2, b3, b4, b5, b6, b7, b8;
+  uint32_t o0, d1, d2, d3, d4, d5, d6, d7, d8;
+  __device__ uint32_t offset(uint32_t j, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4, uint32_t a5,
+                             uint32_t a6, uint32_t a7, uint32_t a8) const {
+    uint32_t o = o0;
+    o += j >= a1 ? d1 : 0u;
+    o += j >= a2 ? d2 : 0u;
+    o += j >= a3 ? d3 : 0u;
+    o += j >= a4 ? d4 : 0u;
+    o += j >= a5 ? d5 : 0u;
+    o += j >= a6 ? d6 : 0u;
+    o += j >= a7 ? d7 : 0u;
+    o += j >= a8 ? d8 : 0u;
+    return o;
+  }
+  __device__ uint32_t index(uint32_t j) const {
+    const uint32_t i = j - offset(j, s1, s2, s3, s4, s5, s6, s7, s8);
+    return i < StageTile<CELL>::kCap ? i : StageTile<CELL>::kCap - 1;
+  }
+  __device__ uint32_t slot(uint32_t t) const { return t + offset(t, b1, b2, b3, b4, b5, b6, b7, b8); }
+  __device__ Nbr operator()(uint32_t j) const {
+    const uint32_t i = index(j);
+    Nbr n;
+    n.a = T->a[i];
+    n.b = T->b[i];
+    n.c = T->c[i];
+    if constexpr (CELL) {
+      n.d = T->d[i];
+    } else {
+      n.d = make_float4(n.b.w, T->s5[i], 0.f, 0.f);
+    }
+    return n;
+  }
+};
+
+// The block's loader from its table (uniform loads).
+template <bool CELL>
+__device__ inline TileLoad<CELL> tile_loader(const StageTile<CELL>& T, const uint32_t* __restrict__ tb) {
+  uint32_t st[9], of[9], d[9], bs[9];
+  uint32_t prev = tb[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    st[k] = tb[k];
+    of[k] = tb[9 + k];
+    const bool none = st[k] == 0xffffffffu;
+    d[k] = none ? 0u : of[k] - prev;
+    prev = none ? prev : of[k];
+    bs[k] = none ? 0xffffffffu : st[k] - of[k];
+  }
+  TileLoad<CELL> l;
+  l.T = &T;
+  l.s1 = st[1]; l.s2 = st[2]; l.s3 = st[3]; l.s4 = st[4]; l.s5 = st[5]; l.s6 = st[6]; l.s7 = st[7]; l.s8 = st[8];
+  l.b1 = bs[1]; l.b2 = bs[2]; l.b3 = bs[3]; l.b4 = bs[4]; l.b5 = bs[5]; l.b6 = bs[6]; l.b7 = bs[7]; l.b8 = bs[8];
+  l.o0 = of[0];
+  l.d1 = d[1]; l.d2 = d[2]; l.d3 = d[3]; l.d4 = d[4]; l.d5 = d[5]; l.d6 = d[6]; l.d7 = d[7]; l.d8 = d[8];
+  return l;
+}
+
+// The walk of a row through the tile. The CSR indices four entries ahead are
+// in flight while the current pair is computed: the index load from HBM/L2 is
+// the walk's longest wait (the tile read is short). Past the row's end the
+// walk reads its first entry again (a valid index).
+template <class Load, class Fn>
+__device__ inline void walk_row_ahead(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
+                                      Fn&& f) {
+  constexpr uint64_t G = kGroup;
+  const uint64_t kf = k0 + group_lane();
+  if (kf >= k1) return;
+  auto idx = [&](uint64_t kk) { return nbr[kk < k1 ? kk : kf]; };
+  uint64_t k = kf;
+  uint32_t j0 = idx(k), j1 = idx(k + G), j2 = idx(k + 2 * G), j3 = idx(k + 3 * G);
+  for (;;) {
+    const bool more = k + G < k1;
+    const uint32_t j4 = idx(k + 4 * G);
+    f(load(j0), j0);
+    if (!more) break;
+    j0 = j1;
+    j1 = j2;
+    j2 = j3;
+    j3 = j4;
+    k += G;
+  }
+}
+
+// One record on its way into the tile.
+struct Rec {
+  float4 a, b, c, d;
+};
+
+template <bool CELL>
+__device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL>& ld, uint32_t t, uint32_t total) {
+  Rec r;
+  if (t < total) {
+    const uint32_t j = ld.slot(t);
+    r.a = S.a[j];
+    r.b = S.b[j];
+    r.c = S.c[j];
+    r.d = S.d[j];
+  } else {
+    r.a = r.b = r.c = r.d = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  return r;
+}
+
+template <bool CELL>
+__device__ inline void rec_store(StageTile<CELL>& T, const Rec& r, uint32_t t, uint32_t total) {
+  if (t >= total) return;
+  T.a[t] = r.a;
+  T.c[t] = r.c;
+  if constexpr (CELL) {
+    T.b[t] = r.b;
+    T.d[t] = r.d;
+  } else {
+    T.b[t] = make_float4(r.b.x, r.b.y, r.b.z, r.d.x);
+    T.s5[t] = r.d.y;
+  }
+}
+
+// Copies the block's ranges into its tile, each thread's (at most four)
+// records loaded together before any is stored. Every thread of the block
+// calls it; returns whether the block uses the tile.
+template <bool CELL>
+__device__ inline bool stage_tile(StageTile<CELL>& T, CPlanes S, const uint32_t* __restrict__ tb,
+                                  const TileLoad<CELL>& ld) {
+  static_assert(StageTile<CELL>::kCap <= 4 * kBlock, "four records per thread");
+  const bool ok = tb[19] != 0;
+  if (ok) {
+    const uint32_t total = tb[18], t0 = threadIdx.x;
+    const Rec r0 = rec_load<CELL>(S, ld, t0, total);
+    const Rec r1 = rec_load<CELL>(S, ld, t0 + kBlock, total);
+    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kBlock, total);
+    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kBlock, total);
+    rec_store<CELL>(T, r0, t0, total);
+    rec_store<CELL>(T, r1, t0 + kBlock, total);
+    rec_store<CELL>(T, r2, t0 + 2 * kBlock, total);
+    rec_store<CELL>(T, r3, t0 + 3 * kBlock, total);
+  }
+  __syncthreads();
+  return ok;
+}
+
 // Tape of a stage for the reverse sweep: L in planes l0..l2 and, in stage 2,
 // the trial stress in planes t0..t1; plane k is written by lane k (mod group).
 __device__ inline void tape_write(const StageTape& T, int32_t s, const float L[9], const float* st, int np) {
@@ -738,8 +990,11 @@ __device__ inline void tape_write(const StageTape& T, int32_t s, const float L[9
 template <bool CELL, bool TAPE>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
-                                                         const uint32_t* __restrict__ nbr, Phys P, StageTape T) {
-  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+                                                         const uint32_t* __restrict__ nbr, Phys P, StageTape T,
+                                                         const uint32_t* __restrict__ tabs) {
+  __shared__ StageTile<CELL> tile;
+  const int64_t blk = xcd_block();
+  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
   const bool live = r < n;
   int32_t s = 0;
@@ -751,7 +1006,14 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     k0 = off[r];
     k1 = off[r + 1];
   }
-  const Rates R = fluid_rhs<CELL>(ma, mb, mc, md, A, k0, k1, nbr, P);
+  const uint32_t* tb = tabs + blk * kTabWords;
+  const TileLoad<CELL> tl = tile_loader<CELL>(tile, tb);
+  const bool staged = stage_tile<CELL>(tile, A, tb, tl);
+  Rates R;
+  if (staged)
+    R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
+  else
+    R = fluid_rhs<CELL>(ma, mb, mc, md, GlobalLoad{A}, k0, k1, nbr, P);
   if (!live) return;
   const float h = P.half_dt;
   float4 na = ma, nd = md;
@@ -772,8 +1034,11 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
 template <bool CELL, bool TAPE>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
-                                                         const uint32_t* __restrict__ nbr, Phys P, StageTape T) {
-  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+                                                         const uint32_t* __restrict__ nbr, Phys P, StageTape T,
+                                                         const uint32_t* __restrict__ tabs) {
+  __shared__ StageTile<CELL> tile;
+  const int64_t blk = xcd_block();
+  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
   const bool live = r < n;
   int32_t s = 0;
@@ -785,7 +1050,14 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     k0 = off[r];
     k1 = off[r + 1];
   }
-  const Rates R = fluid_rhs<CELL>(ma, mb, mc, md, B, k0, k1, nbr, P);
+  const uint32_t* tb = tabs + blk * kTabWords;
+  const TileLoad<CELL> tl = tile_loader<CELL>(tile, tb);
+  const bool staged = stage_tile<CELL>(tile, B, tb, tl);
+  Rates R;
+  if (staged)
+    R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
+  else
+    R = fluid_rhs<CELL>(ma, mb, mc, md, GlobalLoad{B}, k0, k1, nbr, P);
   if (!live) return;
   // Every lane loads the whole y_n record and computes the whole y_{n+1}
   // record; one store then writes plane gl from lane gl < 4. The return
@@ -953,36 +1225,53 @@ hipError_t bce(Planes S, const int32_t* mrows, int64_t n, const uint64_t* off, c
   return hipGetLastError();
 }
 
-hipError_t body_reduce(const double* contrib, const int64_t* bstart, int32_t nb, double* forces, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  k_body_reduce<<<(unsigned)nb, kBlock, 0, s>>>(contrib, bstart, forces);
+int64_t reduce_chunk() { return kRedChunk; }
+
+hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s) {
+  if (plan.nseg <= 0) return hipSuccess;
+  if (plan.nchunk > 0)
+    k_chunk_reduce<<<(unsigned)plan.nchunk, kBlock, 0, s>>>(in, plan.lo, plan.hi, plan.partial);
+  k_segment_sum<<<(unsigned)plan.nseg, kBlock, 0, s>>>(plan.partial, plan.first, out);
   return hipGetLastError();
 }
 
+hipError_t tile_tables(const int32_t* rows, int64_t n, const uint32_t* skey, const uint32_t* cs, Phys P,
+                       uint32_t* tabs, bool cell, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kRows - 1) / kRows;
+  const uint32_t cap = cell ? StageTile<true>::kCap : StageTile<false>::kCap;
+  k_tile_tables<<<nblk(nb), kBlock, 0, s>>>(rows, n, skey, cs, P, cap, tabs);
+  return hipGetLastError();
+}
+
+int64_t tile_table_words(int64_t rows_cap) { return ((rows_cap + kRows - 1) / kRows + 1) * kTabWords; }
+
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s) {
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
   if (P.cell) {
-    if (tape) k_fluid_stage1<true, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T);
-    else k_fluid_stage1<true, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T);
+    if (tape) k_fluid_stage1<true, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage1<true, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
   } else {
-    if (tape) k_fluid_stage1<false, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T);
-    else k_fluid_stage1<false, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T);
+    if (tape) k_fluid_stage1<false, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage1<false, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
   }
   return hipGetLastError();
 }
 
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, hipStream_t s) {
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
   if (P.cell) {
-    if (tape) k_fluid_stage2<true, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T);
-    else k_fluid_stage2<true, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T);
+    if (tape) k_fluid_stage2<true, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage2<true, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
   } else {
-    if (tape) k_fluid_stage2<false, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T);
-    else k_fluid_stage2<false, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T);
+    if (tape) k_fluid_stage2<false, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage2<false, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
   }
   return hipGetLastError();
 }
