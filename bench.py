@@ -140,6 +140,8 @@ def run_batch(args):
         F, _ = sim.forces()
         drv.advance(F[1::2, 2], dt)
 
+    step_batched()
+    tile = sim.autotune()
     wall = timed(step_batched, args.warmup, args.steps)
     n_proc = sim.counts()["n_proc"]
     sim.close()
@@ -153,6 +155,9 @@ def run_batch(args):
         s1 = crm.Simulation(one, device=0)
         s1.set_materials(one.meta["materials"], one.meta["material"])
         s1.graph(True)
+        s1.set_bodies(*drv2.state([k]))
+        s1.step(1)
+        s1.autotune()
         sims.append(s1)
 
     def step_separate():
@@ -172,7 +177,8 @@ def run_batch(args):
                                     "particles (seed 0), per-bin friction 0.5-0.9, slip 0-0.6, load 50-200 N, "
                                     "one context, step kernels replayed as a hipGraph",
                         "n_particles": int(sc.n_total), "n_processed": int(n_proc), "ps_freq": args.ps_freq,
-                        "dt": dt, "separate_contexts_particle_steps_per_s": value2,
+                        "dt": dt, "lds_tile": ("none", "small", "large")[tile],
+                        "separate_contexts_particle_steps_per_s": value2,
                         "batched_over_separate": value / value2})
 
 
@@ -270,6 +276,9 @@ def main():
     ap.add_argument("--pos-mode", type=int, default=0)
     ap.add_argument("--strip-length", type=float, default=10000.0)
     ap.add_argument("--strip-x", type=float, default=5000.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the soil-stage tile configurations after the warm-up and keep the fastest "
+                         "(default: the small tile)")
     ap.add_argument("--adjoint-steps", type=int, default=20,
                     help="after the timed run, cost of the reverse sweep (crm_record + crm_adjoint) "
                          "over this many steps against the plain forward steps (0: skip)")
@@ -307,6 +316,7 @@ def main():
 
     for _ in range(args.warmup):
         one_step()
+    tile = sim.autotune() if args.autotune else sim.autotune(crm.TILE_SMALL)
     torch.cuda.synchronize()
     sim.profiling(True)
     torch.cuda.synchronize()
@@ -332,7 +342,7 @@ def main():
     gbs = bytes_ / (ms2 * 1e-3) / 1e9
     roofline = dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / PEAK_FP32_TFLOPS, 4),
-                    traffic=STAGE2_TRAFFIC_BYTES if args.ps_freq == 10 else None,
+                    traffic=STAGE2_TRAFFIC_BYTES if (args.ps_freq == 10 and tile == crm.TILE_SMALL) else None,
                     kernel="k_fluid_stage2", launch_ms=round(ms2, 5), algorithmic_flops=flops,
                     hbm_view=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                                   frac=round(gbs / PEAK_HBM_GBS, 4), algorithmic_bytes=bytes_))
@@ -371,7 +381,7 @@ def main():
                                "+ 3-layer container + grousered wheel r 0.25 m, slip 0.3, load 100 N; "
                                "co-simulation exchange every step",
                    "n_particles": cnt["n_total"], "n_processed": n_proc, "ps_freq": args.ps_freq,
-                   "dt": dt},
+                   "dt": dt, "lds_tile": ("none", "small", "large")[tile]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": adjoint,

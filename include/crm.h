@@ -231,6 +231,22 @@ crm_status crm_adjoint(crm_ctx* ctx, const double* lam_pos, const float* lam_vel
  * to direct launches. Not used while profiling. enable = 0: direct launches. */
 crm_status crm_set_graph(crm_ctx* ctx, int32_t enable);
 
+/* LDS tile configurations of the soil-stage kernels (the neighbour records of
+ * a block of 32 cell-sorted rows staged in LDS once per stage). */
+#define CRM_TILE_NONE 0   /* neighbours read through L1/L2; highest occupancy */
+#define CRM_TILE_SMALL 1  /* 768 records (640 with cell-offset positions), 4 blocks per CU */
+#define CRM_TILE_LARGE 2  /* 1024 records (832), 3 blocks per CU */
+
+/* Tile configuration of the soil-stage kernels. config = CRM_TILE_NONE,
+ * _SMALL or _LARGE selects it; config < 0 times the stage-1 kernel with each
+ * on the current state and list (three launches each; only the midpoint
+ * state, which the next step recomputes, is written) and keeps the fastest.
+ * chosen (may be NULL) receives the configuration in use. Every
+ * configuration gives bit-identical results. Default CRM_TILE_SMALL.
+ * Errors: CRM_E_INVALID, CRM_E_STATE (autotuning before the first step),
+ * CRM_E_DEVICE. Synchronises when autotuning. */
+crm_status crm_autotune(crm_ctx* ctx, int32_t config, int32_t* chosen);
+
 /* Kernel timing for measurement. enable = 1 starts recording HIP events around
  * each kernel class of every following step on the context's stream (and
  * clears earlier records); enable = 0 stops recording. */

@@ -94,6 +94,8 @@ def _load():
     L.crm_last_error.argtypes = [vp]
     L.crm_destroy.restype = None
     L.crm_destroy.argtypes = [vp]
+    L.crm_autotune.restype = C.c_int
+    L.crm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
     L.crm_record.restype = C.c_int
     L.crm_record.argtypes = [vp, C.c_int32]
     L.crm_adjoint.restype = C.c_int
@@ -106,7 +108,9 @@ _lib = _load()
 EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_get_forces", "crm_get_state",
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
-            "crm_adjoint")
+            "crm_adjoint", "crm_autotune")
+
+TILE_NONE, TILE_SMALL, TILE_LARGE = 0, 1, 2
 
 PROFILE_CLASSES = ("rebuild", "place_markers", "bce_stage1", "soil_stage1", "bce_forces_stage2",
                    "soil_stage2", "body_reduce")
@@ -269,6 +273,15 @@ def crm_debug_export(ctx):
                 flags=flags)
 
 
+def crm_autotune(ctx, config=-1):
+    """config in (TILE_NONE, TILE_SMALL, TILE_LARGE) selects the soil-stage tile
+    configuration; -1 times each on the current state and keeps the fastest.
+    Returns the configuration in use."""
+    out = C.c_int32(0)
+    _check(ctx, _lib.crm_autotune(ctx, int(config), C.byref(out)))
+    return int(out.value)
+
+
 def crm_record(ctx, n_steps):
     _check(ctx, _lib.crm_record(ctx, int(n_steps)))
 
@@ -344,6 +357,9 @@ class Simulation:
     def set_materials(self, table, material):
         crm_set_materials(self.ctx, table, material)
         self.n_mat = np.asarray(table).reshape(-1, 3).shape[0]
+
+    def autotune(self, config=-1):
+        return crm_autotune(self.ctx, config)
 
     def record(self, n):
         crm_record(self.ctx, n)

@@ -76,6 +76,7 @@ struct crm_ctx {
   uint64_t *off_f = nullptr, *off_m = nullptr, *wtmp = nullptr;
   uint32_t *stash_f = nullptr, *stash_m = nullptr;  // count-pass scratch of the lists
   uint32_t* tabs = nullptr;       // LDS tile tables of the soil-row blocks
+  int32_t tile_cfg = CRM_TILE_SMALL;  // LDS tile configuration of the soil stages
 
   // neighbour entries
   uint32_t* nbr_f = nullptr;
@@ -420,7 +421,7 @@ crm_status rebuild(crm_ctx* c) {
                           c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
-  HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, c->grid.cell != 0, s));
+  HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, s));
   // markers outside the processed set contribute nothing until the next rebuild
   HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mark, s));
   c->working_valid = true;
@@ -490,7 +491,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, s));
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, c->tile_cfg, s));
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c);
@@ -502,7 +503,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, s));
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, c->tile_cfg, s));
   if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c);
   HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_forces, s));
@@ -521,7 +522,8 @@ void drop_graph(crm_ctx* c) {
 // Everything the captured kernels bake in: buffers and row counts.
 std::vector<const void*> graph_key(const crm_ctx* c) {
   return {c->A.a, c->B.a, c->frows, c->mrows, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->slot_id,
-          c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows};
+          c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows,
+          (const void*)(intptr_t)c->tile_cfg};
 }
 
 crm_status step_graph(crm_ctx* c) {
@@ -1261,6 +1263,54 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
     emit(mr, om, em);
     if (off) off[row] = e;
   }
+  return CRM_OK;
+}
+
+crm_status crm_autotune(crm_ctx* c, int32_t config, int32_t* chosen) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (config > CRM_TILE_LARGE) return fail(c, CRM_E_INVALID, "unknown tile configuration");
+  if (config >= 0) {
+    c->tile_cfg = config;
+    if (chosen) *chosen = config;
+    return CRM_OK;
+  }
+  if (!c->working_valid || c->n_frows == 0) {
+    if (chosen) *chosen = c->tile_cfg;
+    return c->working_valid ? CRM_OK : fail(c, CRM_E_STATE, "autotuning needs a list rebuild (take a step first)");
+  }
+  // stage 1 writes only y_mid, which the next step recomputes: time it on the
+  // current state with each configuration
+  hipStream_t s = c->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best = 0.f;
+  int32_t pick = c->tile_cfg;
+  for (int32_t cfg = CRM_TILE_NONE; cfg <= CRM_TILE_LARGE; ++cfg) {
+    hipError_t e = crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, nullptr, c->tabs,
+                                     cfg, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r)
+      e = crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, nullptr, c->tabs, cfg, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(c, CRM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    if (cfg == CRM_TILE_NONE || ms < best) {
+      best = ms;
+      pick = cfg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile_cfg = pick;
+  if (chosen) *chosen = pick;
   return CRM_OK;
 }
 

@@ -193,15 +193,19 @@ struct StageTape {
 };
 // tabs: the per-block tile tables of the soil rows (tile_tables, after each
 // list rebuild).
+// cfg: the LDS tile configuration (0 none, 1 small, 2 large); every
+// configuration gives bit-identical results.
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
+                        hipStream_t s);
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, hipStream_t s);
-// Per block of soil rows: the nine slot ranges its rows' neighbours lie in,
-// and whether they fit the block's LDS tile (tile_table_words(rows_cap) words).
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
+                        hipStream_t s);
+// Per block of soil rows: the nine slot ranges its rows' neighbours lie in
+// (tile_table_words(rows_cap) words).
 int64_t tile_table_words(int64_t rows_cap);
 hipError_t tile_tables(const int32_t* frows, int64_t n_frows, const uint32_t* skey, const uint32_t* cell_start,
-                       Phys P, uint32_t* tabs, bool cell, hipStream_t s);
+                       Phys P, uint32_t* tabs, hipStream_t s);
 
 // Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
 // the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.

@@ -757,32 +757,40 @@ __device__ inline void return_map(float st[6], const float sn[6], const Phys& P,
 constexpr int kRows = kBlock / kGroup;
 
 // FP32 positions: 52-byte records (sigma_xz in b.w, where the aux word sits in
-// HBM; sigma_yz apart), 768 of them (40 KB: four blocks per CU); cell-offset
-// positions: 64-byte records (plane d carries the cells), 832 of them (53 KB:
-// three blocks per CU). On the wheel bin 84 % of the 32-row blocks fit 768.
-template <bool CELL>
+// HBM; sigma_yz apart); cell-offset positions: 64-byte records (plane d
+// carries the cells). Tile configurations (chosen per context, see
+// crm_autotune): 0 no tile, 1 small (768 or 640 records, 40 KB: four blocks
+// per CU), 2 large (1024 or 832 records, 53 KB: three blocks per CU). On the
+// wheel bin 84 % of the 32-row blocks fit 768 records and 99.8 % fit 1024.
+template <bool CELL, uint32_t CAP>
 struct StageTile;
-template <>
-struct StageTile<false> {
-  static constexpr uint32_t kCap = 768;
-  float4 a[kCap], b[kCap], c[kCap];
-  float s5[kCap];
+template <uint32_t CAP>
+struct StageTile<false, CAP> {
+  static constexpr uint32_t kCap = CAP;
+  float4 a[CAP], b[CAP], c[CAP];
+  float s5[CAP];
 };
-template <>
-struct StageTile<true> {
-  static constexpr uint32_t kCap = 832;
-  float4 a[kCap], b[kCap], c[kCap], d[kCap];
+template <uint32_t CAP>
+struct StageTile<true, CAP> {
+  static constexpr uint32_t kCap = CAP;
+  float4 a[CAP], b[CAP], c[CAP], d[CAP];
 };
+
+template <bool CELL, int CFG>
+constexpr uint32_t tile_cap() {
+  return CFG == 0 ? 1u : CFG == 1 ? (CELL ? 640u : 768u) : (CELL ? 832u : 1024u);
+}
 
 // Per block of kRows rows, computed once per list rebuild (k_tile_tables):
 // words 0-8 first slot of each of the nine ranges (~0: outside the grid),
 // 9-17 offset o_k (slot j of range k sits at tile index j - o_k), 18 total
-// records, 19 whether the block uses the tile.
+// records, 19 whether the block's rows lie in one row of cells. A block uses
+// its tile when they do and the total fits the tile.
 constexpr int kTabWords = 20;
 
 __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows, int64_t n,
                                                         const uint32_t* __restrict__ skey,
-                                                        const uint32_t* __restrict__ cs, Phys P, uint32_t cap,
+                                                        const uint32_t* __restrict__ cs, Phys P,
                                                         uint32_t* __restrict__ tabs) {
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t r0 = b * kRows;
@@ -811,7 +819,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restric
       t[9 + k] = s0 - total;
       total += s1 - s0;
     }
-  if (total > cap) ok = 0;
   t[18] = total;
   t[19] = ok;
 }
@@ -823,10 +830,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restric
 // starts at ~0 and never counts). Written as sums so that no select picks
 // between two loaded values. The same holds in tile-index space with the
 // ranges' first tile indices b_k, for the copy into the tile.
-template <bool CELL>
+template <bool CELL, uint32_t CAP>
 struct TileLoad {
   static constexpr bool kTile = true;
-  const StageTile<CELL>* T;
+  const StageTile<CELL, CAP>* T;
   uint32_t s1, s2, s3, s4, s5, s6, s7, s8;
   uint32_t b1, b2, b3, b4, b5, b6, b7, b8;
   uint32_t o0, d1, d2, d3, d4, d5, d6, d7, d8;
@@ -845,7 +852,7 @@ struct TileLoad {
   }
   __device__ uint32_t index(uint32_t j) const {
     const uint32_t i = j - offset(j, s1, s2, s3, s4, s5, s6, s7, s8);
-    return i < StageTile<CELL>::kCap ? i : StageTile<CELL>::kCap - 1;
+    return i < CAP ? i : CAP - 1;
   }
   __device__ uint32_t slot(uint32_t t) const { return t + offset(t, b1, b2, b3, b4, b5, b6, b7, b8); }
   __device__ Nbr operator()(uint32_t j) const {
@@ -864,8 +871,8 @@ struct TileLoad {
 };
 
 // The block's loader from its table (uniform loads).
-template <bool CELL>
-__device__ inline TileLoad<CELL> tile_loader(const StageTile<CELL>& T, const uint32_t* __restrict__ tb) {
+template <bool CELL, uint32_t CAP>
+__device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>& T, const uint32_t* __restrict__ tb) {
   uint32_t st[9], of[9], d[9], bs[9];
   uint32_t prev = tb[9];
 #pragma unroll
@@ -877,7 +884,7 @@ __device__ inline TileLoad<CELL> tile_loader(const StageTile<CELL>& T, const uin
     prev = none ? prev : of[k];
     bs[k] = none ? 0xffffffffu : st[k] - of[k];
   }
-  TileLoad<CELL> l;
+  TileLoad<CELL, CAP> l;
   l.T = &T;
   l.s1 = st[1]; l.s2 = st[2]; l.s3 = st[3]; l.s4 = st[4]; l.s5 = st[5]; l.s6 = st[6]; l.s7 = st[7]; l.s8 = st[8];
   l.b1 = bs[1]; l.b2 = bs[2]; l.b3 = bs[3]; l.b4 = bs[4]; l.b5 = bs[5]; l.b6 = bs[6]; l.b7 = bs[7]; l.b8 = bs[8];
@@ -917,8 +924,8 @@ struct Rec {
   float4 a, b, c, d;
 };
 
-template <bool CELL>
-__device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL>& ld, uint32_t t, uint32_t total) {
+template <bool CELL, uint32_t CAP>
+__device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL, CAP>& ld, uint32_t t, uint32_t total) {
   Rec r;
   if (t < total) {
     const uint32_t j = ld.slot(t);
@@ -932,8 +939,8 @@ __device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL>& ld, uint32_t t, 
   return r;
 }
 
-template <bool CELL>
-__device__ inline void rec_store(StageTile<CELL>& T, const Rec& r, uint32_t t, uint32_t total) {
+template <bool CELL, uint32_t CAP>
+__device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t t, uint32_t total) {
   if (t >= total) return;
   T.a[t] = r.a;
   T.c[t] = r.c;
@@ -949,21 +956,22 @@ __device__ inline void rec_store(StageTile<CELL>& T, const Rec& r, uint32_t t, u
 // Copies the block's ranges into its tile, each thread's (at most four)
 // records loaded together before any is stored. Every thread of the block
 // calls it; returns whether the block uses the tile.
-template <bool CELL>
-__device__ inline bool stage_tile(StageTile<CELL>& T, CPlanes S, const uint32_t* __restrict__ tb,
-                                  const TileLoad<CELL>& ld) {
-  static_assert(StageTile<CELL>::kCap <= 4 * kBlock, "four records per thread");
-  const bool ok = tb[19] != 0;
+template <bool CELL, uint32_t CAP>
+__device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint32_t* __restrict__ tb,
+                                  const TileLoad<CELL, CAP>& ld) {
+  static_assert(CAP <= 4 * kBlock, "four records per thread");
+  const uint32_t total = tb[18];
+  const bool ok = tb[19] != 0 && total <= CAP;
   if (ok) {
-    const uint32_t total = tb[18], t0 = threadIdx.x;
-    const Rec r0 = rec_load<CELL>(S, ld, t0, total);
-    const Rec r1 = rec_load<CELL>(S, ld, t0 + kBlock, total);
-    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kBlock, total);
-    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kBlock, total);
-    rec_store<CELL>(T, r0, t0, total);
-    rec_store<CELL>(T, r1, t0 + kBlock, total);
-    rec_store<CELL>(T, r2, t0 + 2 * kBlock, total);
-    rec_store<CELL>(T, r3, t0 + 3 * kBlock, total);
+    const uint32_t t0 = threadIdx.x;
+    const Rec r0 = rec_load(S, ld, t0, total);
+    const Rec r1 = rec_load(S, ld, t0 + kBlock, total);
+    const Rec r2 = rec_load(S, ld, t0 + 2 * kBlock, total);
+    const Rec r3 = rec_load(S, ld, t0 + 3 * kBlock, total);
+    rec_store(T, r0, t0, total);
+    rec_store(T, r1, t0 + kBlock, total);
+    rec_store(T, r2, t0 + 2 * kBlock, total);
+    rec_store(T, r3, t0 + 3 * kBlock, total);
   }
   __syncthreads();
   return ok;
@@ -987,12 +995,13 @@ __device__ inline void tape_write(const StageTape& T, int32_t s, const float L[9
 // Stage 1 of the explicit midpoint rule (Sec. 2.3): B = A + dt/2 f(A).
 // Lanes 0-3 of the group write the four planes of the row's record. With TAPE
 // the velocity gradient L is also kept.
-template <bool CELL, bool TAPE>
+template <bool CELL, bool TAPE, int CFG>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
                                                          const uint32_t* __restrict__ tabs) {
-  __shared__ StageTile<CELL> tile;
+  constexpr uint32_t CAP = tile_cap<CELL, CFG>();
+  __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
   const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
@@ -1007,8 +1016,8 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL> tl = tile_loader<CELL>(tile, tb);
-  const bool staged = stage_tile<CELL>(tile, A, tb, tl);
+  const TileLoad<CELL, CAP> tl = tile_loader(tile, tb);
+  const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl);
   Rates R;
   if (staged)
     R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
@@ -1031,12 +1040,13 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
 
 // Stage 2: A = A + dt f(B), then the return mapping on the stress. With TAPE
 // the velocity gradient and the trial stress are also kept.
-template <bool CELL, bool TAPE>
+template <bool CELL, bool TAPE, int CFG>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
                                                          const uint32_t* __restrict__ tabs) {
-  __shared__ StageTile<CELL> tile;
+  constexpr uint32_t CAP = tile_cap<CELL, CFG>();
+  __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
   const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
@@ -1051,8 +1061,8 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL> tl = tile_loader<CELL>(tile, tb);
-  const bool staged = stage_tile<CELL>(tile, B, tb, tl);
+  const TileLoad<CELL, CAP> tl = tile_loader(tile, tb);
+  const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl);
   Rates R;
   if (staged)
     R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
@@ -1236,43 +1246,60 @@ hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hi
 }
 
 hipError_t tile_tables(const int32_t* rows, int64_t n, const uint32_t* skey, const uint32_t* cs, Phys P,
-                       uint32_t* tabs, bool cell, hipStream_t s) {
+                       uint32_t* tabs, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = (n + kRows - 1) / kRows;
-  const uint32_t cap = cell ? StageTile<true>::kCap : StageTile<false>::kCap;
-  k_tile_tables<<<nblk(nb), kBlock, 0, s>>>(rows, n, skey, cs, P, cap, tabs);
+  k_tile_tables<<<nblk(nb), kBlock, 0, s>>>(rows, n, skey, cs, P, tabs);
   return hipGetLastError();
 }
 
 int64_t tile_table_words(int64_t rows_cap) { return ((rows_cap + kRows - 1) / kRows + 1) * kTabWords; }
 
+template <int CFG>
+void launch_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
+                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, hipStream_t s) {
+  const unsigned g = nblk_groups(n);
+  if (P.cell) {
+    if (tape) k_fluid_stage1<true, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage1<true, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+  } else {
+    if (tape) k_fluid_stage1<false, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage1<false, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+  }
+}
+
+template <int CFG>
+void launch_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
+                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, hipStream_t s) {
+  const unsigned g = nblk_groups(n);
+  if (P.cell) {
+    if (tape) k_fluid_stage2<true, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage2<true, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+  } else {
+    if (tape) k_fluid_stage2<false, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    else k_fluid_stage2<false, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+  }
+}
+
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
-  if (P.cell) {
-    if (tape) k_fluid_stage1<true, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage1<true, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-  } else {
-    if (tape) k_fluid_stage1<false, true><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage1<false, false><<<nblk_groups(n), kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-  }
+  if (cfg == 0) launch_stage1<0>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  else if (cfg == 1) launch_stage1<1>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  else launch_stage1<2>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
   return hipGetLastError();
 }
 
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
-  if (P.cell) {
-    if (tape) k_fluid_stage2<true, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage2<true, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-  } else {
-    if (tape) k_fluid_stage2<false, true><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage2<false, false><<<nblk_groups(n), kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-  }
+  if (cfg == 0) launch_stage2<0>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  else if (cfg == 1) launch_stage2<1>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  else launch_stage2<2>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
   return hipGetLastError();
 }
 

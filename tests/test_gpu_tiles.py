@@ -1,0 +1,66 @@
+"""LDS tile configurations of the soil-stage kernels.
+
+Every configuration (no tile, small, large) reads the same neighbour records
+in the same order, so states and body forces are bit-identical across them;
+the autotuner only chooses among them and leaves the run unchanged.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_05643_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def crm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_05643_amd import crm as C
+    return C
+
+
+def _run(crm, sc, cfg, steps):
+    sim = crm.Simulation(sc)
+    assert sim.autotune(cfg) == cfg
+    sim.step(steps)
+    st = sim.state()
+    F, T = sim.forces()
+    sim.close()
+    return st, F, T
+
+
+@pytest.mark.parametrize("scene", ["wheel", "column_far"])
+def test_tile_configurations_bit_identical(crm, scene):
+    if scene == "wheel":
+        sc = scenes.wheel_bin(seed=0, nx=60, ny=40, nz=20, ps_freq=5)
+    else:
+        sc = scenes.column(seed=0, origin=(9999.0, 0.0, 0.0), pos_mode=1, ps_freq=3)
+    ref = _run(crm, sc, crm.TILE_NONE, 12)
+    for cfg in (crm.TILE_SMALL, crm.TILE_LARGE):
+        got = _run(crm, sc, cfg, 12)
+        for k in ("pos", "vel", "sigma", "rho"):
+            assert np.array_equal(got[0][k], ref[0][k]), (cfg, k)
+        assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2]), cfg
+
+
+def test_autotune_keeps_the_run(crm):
+    sc = scenes.wheel_bin(seed=1, nx=60, ny=40, nz=20, ps_freq=5)
+    a = crm.Simulation(sc)
+    with pytest.raises(crm.CrmError):
+        a.autotune()                     # no list yet
+    b = crm.Simulation(sc)
+    a.step(1)
+    b.step(1)
+    cfg = a.autotune()
+    assert cfg in (crm.TILE_NONE, crm.TILE_SMALL, crm.TILE_LARGE)
+    a.step(10)
+    b.step(10)
+    sa, sb = a.state(), b.state()
+    for k in ("pos", "vel", "sigma", "rho"):
+        assert np.array_equal(sa[k], sb[k]), k
+    with pytest.raises(crm.CrmError):
+        a.autotune(7)
+    a.close()
+    b.close()
