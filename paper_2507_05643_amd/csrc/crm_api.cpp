@@ -56,6 +56,7 @@ struct crm_ctx {
   int32_t n_mat = 1;
   std::vector<uint16_t> h_mat; // material of each soil particle (empty: all 0)
   std::vector<Body> h_bodies;
+  std::vector<int64_t> h_nmark;  // markers per body
   double* d_forces = nullptr;
   uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
 
@@ -70,6 +71,7 @@ struct crm_ctx {
   float4* pos4 = nullptr;
   int4* cpos = nullptr;          // cells of the sorted slots (cell-offset positions)
   int32_t* slot_id = nullptr;
+  int32_t* slot_k = nullptr;     // processed index (position in the processed id list)
   uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
   int32_t *frows = nullptr, *mrows = nullptr;
   uint32_t *cnt_f = nullptr, *cnt_m = nullptr;
@@ -86,7 +88,13 @@ struct crm_ctx {
 
   double* contrib = nullptr;     // per marker id: force and torque on its body (6 FP64)
   int64_t* d_bstart = nullptr;   // first marker id (relative) of each body, nb + 1
-  crm::SegPlan body_plan;        // chunked per-body force sums
+  crm::SegPlan body_plan;        // chunked per-body force sums over the processed markers
+  int64_t plan_cap = 0;          // chunk capacity of body_plan
+  int64_t* d_branges = nullptr;  // per body: first processed-marker rank (nb + 1)
+  bool plan_all = false;         // body_plan covers all markers (every particle processed)
+  int64_t kbase = 0;             // rank of the first processed marker in the processed list
+  std::vector<Body> placed;      // body poses of the markers' last placement in the master store
+  bool place_all = true;         // place every body's markers at the next placement
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
   uint64_t* h_counts = nullptr;   // pinned mirror
 
@@ -259,7 +267,7 @@ void quat_to_R(const double q[4], double R[9]) {
   } while (0)
 
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
-  void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id,
+  void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id, c->slot_k,
                   c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->cnt_f, c->cnt_m, c->off_f,
                   c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
   for (void* p : olds) dfree(c, p);
@@ -267,7 +275,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
   c->B = Planes{};
   c->pos4 = nullptr;
   c->cpos = nullptr;
-  c->slot_id = c->frows = c->mrows = nullptr;
+  c->slot_id = c->slot_k = c->frows = c->mrows = nullptr;
   c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = nullptr;
   c->off_f = c->off_m = c->wtmp = nullptr;
   c->stash_f = c->stash_m = nullptr;
@@ -277,7 +285,8 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
             alloc_n(c, c->A.d, cap) && alloc_n(c, c->B.a, cap) && alloc_n(c, c->B.b, cap) &&
             alloc_n(c, c->B.c, cap) && alloc_n(c, c->B.d, cap) && alloc_n(c, c->pos4, cap) &&
             alloc_n(c, c->cpos, c->grid.cell ? cap : 1) &&
-            alloc_n(c, c->slot_id, cap) && alloc_n(c, c->skey, cap) && alloc_n(c, c->key, cap) &&
+            alloc_n(c, c->slot_id, cap) && alloc_n(c, c->slot_k, cap) && alloc_n(c, c->skey, cap) &&
+            alloc_n(c, c->key, cap) &&
             alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->frows, cap) &&
             alloc_n(c, c->mrows, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
             alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
@@ -347,9 +356,94 @@ crm_status make_plan(crm_ctx* c, const std::vector<int64_t>& start, crm::SegPlan
   return CRM_OK;
 }
 
+// Writes the chunk plan of the segments [start[g], start[g + 1]) into the
+// plan's existing arrays (capacity cap chunks).
+crm_status fill_plan(crm_ctx* c, const std::vector<int64_t>& start, crm::SegPlan& plan, int64_t cap) {
+  const int32_t nseg = (int32_t)start.size() - 1;
+  const int64_t ch = crm::reduce_chunk();
+  std::vector<int64_t> lo, hi;
+  std::vector<int32_t> first((size_t)nseg + 1, 0);
+  for (int32_t g = 0; g < nseg; ++g) {
+    first[g] = (int32_t)lo.size();
+    for (int64_t k = start[g]; k < start[g + 1]; k += ch) {
+      lo.push_back(k);
+      hi.push_back(std::min(k + ch, start[g + 1]));
+    }
+  }
+  first[nseg] = (int32_t)lo.size();
+  const int64_t nc = (int64_t)lo.size();
+  if (nc > cap) return fail(c, CRM_E_STATE, "force-sum plan exceeds its capacity");
+  hipStream_t s = c->stream;
+  if (nc > 0) {
+    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.lo), lo.data(), sizeof(int64_t) * (size_t)nc,
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.hi), hi.data(), sizeof(int64_t) * (size_t)nc,
+                             hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(const_cast<int32_t*>(plan.first), first.data(), sizeof(int32_t) * first.size(),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  plan.nseg = nseg;
+  plan.nchunk = nc;
+  return CRM_OK;
+}
+
 crm_status read_counts(crm_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(uint64_t) * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CRM_OK;
+}
+
+// Markers of the bodies that moved since their last placement in the master
+// store (all of them after init or a restore): x = X + R l.
+// World-axis box around the body's active box grown by ext on every local
+// axis, widened by a margin far above FP64 rounding: a superset of the grown
+// box used only to skip its exact test.
+void set_box_bounds(Body& B, double ext) {
+  double mag = 1.0;
+  for (int a = 0; a < 3; ++a) mag += std::fabs(B.X[a]) + B.half[a] + ext;
+  const double margin = 1e-9 * mag;
+  for (int k = 0; k < 3; ++k) {
+    double r = 0.0;
+    for (int a = 0; a < 3; ++a) r += std::fabs(B.R[3 * k + a]) * (B.half[a] + ext);
+    B.alo[k] = B.X[k] - r - margin;
+    B.ahi[k] = B.X[k] + r + margin;
+  }
+}
+
+crm_status place_master_markers(crm_ctx* c) {
+  std::vector<int64_t> bs((size_t)c->nb + 1, 0);
+  for (int b = 0; b < c->nb; ++b) bs[b + 1] = bs[b] + c->h_nmark[b];
+  if (c->placed.size() != (size_t)c->nb) {
+    c->placed.assign((size_t)c->nb, Body{});
+    c->place_all = true;
+  }
+  for (int b = 0; b < c->nb; ++b) {
+    const Body& B = c->h_bodies[b];
+    const Body& Q = c->placed[b];
+    const bool moved = c->place_all || std::memcmp(B.X, Q.X, sizeof(B.X)) != 0 || std::memcmp(B.R, Q.R, sizeof(B.R)) != 0;
+    if (!moved) continue;
+    HIPCHK(c, crm::place_markers_master(c->local, bs[b], bs[b + 1], c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d,
+                                        c->stream));
+    c->placed[b] = B;
+  }
+  c->place_all = false;
+  return CRM_OK;
+}
+
+// Chunks of the per-body force sums over the processed markers: all markers by
+// id when every particle is processed (a fixed plan), else the bodies' ranges
+// in the processed list, found on the device and read back.
+crm_status update_body_plan(crm_ctx* c, const int32_t* ids) {
+  if (c->nb == 0) return CRM_OK;
+  if (!ids && c->plan_all) return CRM_OK;
+  HIPCHK(c, crm::body_ranges(ids, c->n_proc, c->n_soil, c->d_bstart, c->nb, c->kbase, c->d_branges, c->stream));
+  std::vector<int64_t> r((size_t)c->nb + 1);
+  HIPCHK(c, hipMemcpyAsync(r.data(), c->d_branges, sizeof(int64_t) * r.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  crm_status st = fill_plan(c, r, c->body_plan, c->plan_cap);
+  if (st != CRM_OK) return st;
+  c->plan_all = (ids == nullptr);
   return CRM_OK;
 }
 
@@ -371,7 +465,10 @@ crm_status rebuild(crm_ctx* c) {
       HIPCHK(c, hipMemcpyAsync(dst + q * n, src[q], sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
     c->rec_seg.push_back(c->step - c->rec_step0);
   }
-  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d, s));
+  {
+    crm_status st0 = place_master_markers(c);
+    if (st0 != CRM_OK) return st0;
+  }
   const double t = (double)c->step * P.dt;
   c->ad_on = P.active_domains && t > P.t_delay;
   int64_t n_proc = c->n_total;
@@ -396,7 +493,8 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
   HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, c->tmp, s));
   HIPCHK(c, crm::gather_sorted(c->tmp, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
-                               c->m_d, c->A, c->B, c->pos4, c->cpos, c->slot_id, c->skey, c->grid.cell != 0, s));
+                               c->m_d, c->A, c->B, c->pos4, c->cpos, c->slot_id, c->slot_k, c->skey,
+                               c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
   HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
@@ -422,8 +520,10 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
   HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, s));
-  // markers outside the processed set contribute nothing until the next rebuild
-  HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mark, s));
+  // per-body ranges of the processed markers for the force sums
+  c->kbase = c->n_proc - c->n_mrows;
+  st = update_body_plan(c, ids);
+  if (st != CRM_OK) return st;
   c->working_valid = true;
   c->force_rebuild = false;
   c->rebuilds += 1;
@@ -483,7 +583,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   if (prof) prof_end(c, 1, e);
   // stage 1 at y_n
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P, nullptr,
+  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P, nullptr,
                      s));
   if (prof) prof_end(c, 2, e);
   if (rec) {
@@ -495,7 +595,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_id, c->n_soil, P,
+  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
                      c->contrib, s));
   if (prof) prof_end(c, 4, e);
   if (rec) {
@@ -523,7 +623,8 @@ void drop_graph(crm_ctx* c) {
 std::vector<const void*> graph_key(const crm_ctx* c) {
   return {c->A.a, c->B.a, c->frows, c->mrows, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->slot_id,
           c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows,
-          (const void*)(intptr_t)c->tile_cfg};
+          (const void*)(intptr_t)c->tile_cfg, (const void*)(intptr_t)c->body_plan.nchunk,
+          (const void*)(intptr_t)c->kbase};
 }
 
 crm_status step_graph(crm_ctx* c) {
@@ -746,11 +847,12 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     B.R[0] = B.R[4] = B.R[8] = 1.0;
     for (int a = 0; a < 3; ++a) B.half[a] = bodies[b].active_half[a];
     B.has_box = (B.half[0] > 0.0 || B.half[1] > 0.0 || B.half[2] > 0.0) ? 1 : 0;
+    set_box_bounds(B, g.ext);
   }
 
   const int64_t nbk = crm::compact_tmp_elems(n_total);
   bool ok = alloc_n(c, c->m_a, n_total) && alloc_n(c, c->m_b, n_total) && alloc_n(c, c->m_c, n_total) &&
-            alloc_n(c, c->m_d, n_total) && alloc_n(c, c->local, nm) && alloc_n(c, c->flags, n_total) &&
+            alloc_n(c, c->m_d, n_total) && alloc_n(c, c->local, nm) && alloc_n(c, c->flags, crm::flags_padded(n_total)) &&
             alloc_n(c, c->proc_ids, n_total) && alloc_n(c, c->d_bodies, n_bodies > 0 ? n_bodies : 1) &&
             alloc_n(c, c->d_forces, 6 * (n_bodies > 0 ? n_bodies : 1)) && alloc_n(c, c->ctmp, nbk) &&
             alloc_n(c, c->cell_cnt, M) && alloc_n(c, c->cell_start, M + 1) &&
@@ -777,17 +879,37 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     e = hipMemcpyAsync(c->local, hl.data(), sizeof(float4) * (size_t)nm, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_bodies, c->h_bodies.data(), sizeof(Body) * c->h_bodies.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, (size_t)crm::flags_padded(n_total), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->d_forces, 0, sizeof(double) * 6 * (size_t)(n_bodies > 0 ? n_bodies : 1), s);
   std::vector<int64_t> bstart((size_t)n_bodies + 1, 0);
   for (int b = 0; b < n_bodies; ++b) bstart[b + 1] = bstart[b] + bodies[b].n_markers;
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_bstart, bstart.data(), sizeof(int64_t) * bstart.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && nm > 0) e = hipMemsetAsync(c->contrib, 0, sizeof(double) * 6 * (size_t)nm, s);
-  if (e == hipSuccess && make_plan(c, bstart, c->body_plan, nullptr) != CRM_OK) {
+  c->h_nmark.resize((size_t)n_bodies);
+  for (int b = 0; b < n_bodies; ++b) c->h_nmark[b] = bodies[b].n_markers;
+  c->plan_cap = nm / crm::reduce_chunk() + n_bodies + 2;
+  {
+    int64_t *dlo = nullptr, *dhi = nullptr;
+    int32_t* dfirst = nullptr;
+    double* dpart = nullptr;
+    if (!(alloc_n(c, dlo, c->plan_cap) && alloc_n(c, dhi, c->plan_cap) && alloc_n(c, dfirst, n_bodies + 1) &&
+          alloc_n(c, dpart, 6 * c->plan_cap) && alloc_n(c, c->d_branges, n_bodies + 1))) {
+      release(c);
+      return fail(nullptr, CRM_E_NOMEM, "device allocation failed");
+    }
+    c->body_plan.lo = dlo;
+    c->body_plan.hi = dhi;
+    c->body_plan.first = dfirst;
+    c->body_plan.partial = dpart;
+  }
+  if (e == hipSuccess && n_bodies > 0 && fill_plan(c, bstart, c->body_plan, c->plan_cap) != CRM_OK) {
     std::string m2 = c->err;
     release(c);
-    return fail(nullptr, CRM_E_NOMEM, m2);
+    return fail(nullptr, CRM_E_DEVICE, m2);
   }
+  c->plan_all = true;
+  c->kbase = n_soil;
   const float4 mat0 = make_float4((float)P.mu_s, (float)P.mu_2, (float)P.cohesion, (float)(-P.cohesion / P.mu_s));
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_mat, &mat0, sizeof(float4), hipMemcpyHostToDevice, s);
   c->phys.mat = c->d_mat;
@@ -827,6 +949,7 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
     }
     quat_to_R(q, B.R);
     B.has_acc = (linacc || angacc) ? 1 : 0;
+    set_box_bounds(B, c->grid.ext);
   }
   hipError_t e = hipMemcpyAsync(c->d_bodies, hb.data(), sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
@@ -1006,6 +1129,7 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
       HIPCHK(c, hipMemcpyAsync(dst[q], src + q * n, sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
     c->working_valid = false;
     c->force_rebuild = true;
+    c->place_all = true;
     c->step = c->rec_step0 + c->rec_seg[g];
     return CRM_OK;
   };
@@ -1129,7 +1253,10 @@ crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, floa
   crm_status st = usable(c);
   if (st != CRM_OK) return st;
   hipStream_t s = c->stream;
-  HIPCHK(c, crm::place_markers_master(c->local, c->n_mark, c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d, s));
+  {
+    crm_status st0 = place_master_markers(c);
+    if (st0 != CRM_OK) return st0;
+  }
   if (c->working_valid) {
     HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
     HIPCHK(c, crm::scatter_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));

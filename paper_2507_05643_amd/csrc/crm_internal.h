@@ -47,6 +47,8 @@ struct Body {
   double A[3];    // linear acceleration
   double Al[3];   // angular acceleration
   double half[3]; // active box half extents (all zero: none)
+  double alo[3];  // world-axis box around the box grown by 2h (a superset,
+  double ahi[3];  // for a quick rejection before the exact test)
   int32_t has_acc;
   int32_t has_box;
 };
@@ -109,15 +111,22 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // dst[0] = *a, dst[1] = *b (device-side totals gathered for one read-back).
 hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStream_t s);
 
-// Marker world positions x = X + R l (FP64, rounded to FP32) into master plane 0.
-hipError_t place_markers_master(const float4* local, int64_t n_markers, int64_t n_soil,
-                                const Body* bodies, Grid g, float4* m_a, float4* m_d, hipStream_t s);
+// World positions x = X + R l (FP64, stored FP32 or cell + offset) of the
+// markers with local indices [k0, k1) into the master planes.
+hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int64_t n_soil, const Body* bodies,
+                                Grid g, float4* m_a, float4* m_d, hipStream_t s);
+// out[b], b = 0..nb: first processed-marker rank of body b (markers processed
+// in id order; ids = the processed ids, NULL when all particles are processed).
+hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const int64_t* bstart, int32_t nb,
+                       int64_t kbase, int64_t* out, hipStream_t s);
 
 // Activity flags of all particles (Sec. 4.2 item 2).
 hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies,
                           int32_t nb, Grid g, uint8_t* flags, hipStream_t s);
 
 // Order-preserving compaction of ids with flags != 0 (block counts, scan, write).
+// The flag array must hold flags_padded(n) bytes, zero beyond n.
+int64_t flags_padded(int64_t n);
 size_t compact_tmp_elems(int64_t n);
 hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst,
                          uint32_t* tmp, hipStream_t s);
@@ -133,7 +142,8 @@ hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t
                          const uint32_t* cell_start, int64_t n_proc, int64_t n_soil,
                          const uint8_t* flags, const float4* m_a, const float4* m_b,
                          const float4* m_c, const float4* m_d, Planes A, Planes B, float4* pos4,
-                         int4* cpos, int32_t* slot_id, uint32_t* skey, bool cell, hipStream_t s);
+                         int4* cpos, int32_t* slot_id, int32_t* slot_k, uint32_t* skey, bool cell,
+                         hipStream_t s);
 
 // Row lists (slots owning a neighbour list): active soil rows and marker rows.
 hipError_t compact_kind(const float4* pos4, int64_t n_proc, uint32_t kind, int32_t* rows,
@@ -162,9 +172,10 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const in
 
 // BCE extrapolation at state S (Sec. 2.5.1); with contrib != nullptr also the
 // marker accelerations and each processed marker's force and torque on its
-// body (FP64, 6 per marker, indexed by marker id = particle id - n_soil).
+// body (FP64, 6 per marker, at entry cidx[slot] - cbase: the marker's rank
+// among the processed markers in id order).
 hipError_t bce(Planes S, const int32_t* mrows, int64_t n_mrows, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, const int32_t* slot_id, int64_t n_soil, Phys P, double* contrib,
+               const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
                hipStream_t s);
 // Deterministic sums of 6 doubles per entry over contiguous segments: the
 // plan cuts segment g = [start[g], start[g + 1]) into chunks of at most

@@ -158,6 +158,46 @@ __global__ __launch_bounds__(kBlock) void k_pred_write(Pred pr, int64_t n, const
   if (p) out[pre + (uint32_t)__popcll(m & lanemask_lt())] = (int32_t)i;
 }
 
+// Compaction of the activity flags (all N particles at every activity
+// rebuild): each thread takes 16 flags with one 16-byte load (the flag array is
+// padded with zeros to a multiple of 16), so both passes stream the flags at
+// close to HBM speed. Order-preserving: thread ranges are in index order.
+constexpr int kFlagsPer = 16;
+constexpr int64_t kFlagsTile = (int64_t)kBlock * kFlagsPer;
+
+__device__ inline uint32_t flag_mask(const uint4* __restrict__ f16, int64_t chunk, int64_t nchunks) {
+  if (chunk >= nchunks) return 0u;
+  const uint4 v = f16[chunk];
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) m |= ((w[q] >> (8 * b)) & 0xffu) ? (1u << (4 * q + b)) : 0u;
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flags_count(const uint4* __restrict__ f16, int64_t nchunks,
+                                                        uint32_t* __restrict__ bcnt) {
+  const int64_t chunk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t tot;
+  block_excl_scan((uint32_t)__popc(flag_mask(f16, chunk, nchunks)), tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flags_write(const uint4* __restrict__ f16, int64_t nchunks,
+                                                        const uint32_t* __restrict__ boff, int32_t* __restrict__ out) {
+  const int64_t chunk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t m = flag_mask(f16, chunk, nchunks);
+  uint32_t tot;
+  uint32_t pos = boff[blockIdx.x] + block_excl_scan((uint32_t)__popc(m), tot);
+  while (m) {
+    const int b = __builtin_ctz(m);
+    out[pos++] = (int32_t)(chunk * kFlagsPer + b);
+    m &= m - 1u;
+  }
+}
+
 __global__ void k_copy2(uint64_t* dst, const uint64_t* a, const uint64_t* b) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     dst[0] = *a;
@@ -207,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_master(const float4* _
 
 // Sec. 4.2 item 2: Active inside an oriented box (|R^T (x - X)| <= half per
 // local axis), Extended-Active inside the box grown by 2h, else Inactive.
+template <bool CELL>
 __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
                                                      int64_t n, const Body* __restrict__ bodies, int32_t nb, Grid g,
                                                      uint8_t* __restrict__ flags) {
@@ -214,11 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ 
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   double xw[3];
-  abs_pos(m_a[i], g.cell ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f), g, xw);
+  abs_pos(m_a[i], CELL ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f), g, xw);
   uint8_t best = 0;
   for (int b = 0; b < nb; ++b) {
     const Body& B = bodies[b];
     if (!B.has_box) continue;
+    // world box around the grown oriented box (a superset: decides nothing)
+    if (!(xw[0] >= B.alo[0] && xw[0] <= B.ahi[0] && xw[1] >= B.alo[1] && xw[1] <= B.ahi[1] &&
+          xw[2] >= B.alo[2] && xw[2] <= B.ahi[2]))
+      continue;
     double d[3], l[3];
     for (int a = 0; a < 3; ++a) d[a] = xw[a] - B.X[a];
     for (int a = 0; a < 3; ++a) l[a] = (B.R[a] * d[0] + B.R[3 + a] * d[1]) + B.R[6 + a] * d[2];
@@ -234,6 +279,27 @@ __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ 
   flags[i] = best;
 }
 
+// Processed-marker range of each body: markers are processed in id order and
+// body b owns ids n_soil + [bstart[b], bstart[b + 1]), so its processed
+// markers are entries [lower_bound(ids, n_soil + bstart[b]) - kbase, ...).
+__global__ void k_body_ranges(const int32_t* __restrict__ ids, int64_t n_proc, int64_t n_soil,
+                              const int64_t* __restrict__ bstart, int32_t nb, int64_t kbase,
+                              int64_t* __restrict__ out) {
+  const int32_t b = (int32_t)((int64_t)blockIdx.x * kBlock + threadIdx.x);
+  if (b > nb) return;
+  const int64_t target = n_soil + bstart[b];
+  int64_t lo = 0, hi = n_proc;
+  if (ids) {
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if ((int64_t)ids[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+  } else {
+    lo = target;
+  }
+  out[b] = lo - kbase;
+}
 
 // ------------------------------------------------------ hashing and sort ---
 // Sec. 4.1 step 1: c = z * (Y * X) + y * X + x with cell size 2h. The arrival
@@ -282,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
     const uint32_t* __restrict__ cs, int64_t n, int64_t n_soil, const uint8_t* __restrict__ flags,
     const float4* __restrict__ m_a, const float4* __restrict__ m_b, const float4* __restrict__ m_c,
     const float4* __restrict__ m_d, Planes A, Planes B, float4* __restrict__ pos4, int4* __restrict__ cpos,
-    int cell, int32_t* __restrict__ slot_id, uint32_t* __restrict__ skey) {
+    int cell, int32_t* __restrict__ slot_id, int32_t* __restrict__ slot_k, uint32_t* __restrict__ skey) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
   uint32_t k = tmp[p];
@@ -293,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   uint32_t f = lo + r;
   int64_t id = ids ? ids[k] : (int64_t)k;
   slot_id[f] = (int32_t)id;
+  slot_k[f] = (int32_t)k;
   skey[f] = c;
   float4 a = m_a[id], b = m_b[id], cc = m_c[id], d = m_d[id];
   uint32_t aux = __float_as_uint(b.w) & ~3u;
@@ -449,12 +516,14 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
 // Sec. 2.5.1: Adami velocity u~ = sum u_f W / sum W, no-slip u_s = 2 u_body - u~;
 // stress s_s = [sum s_f W - ((g - a_s) . sum rho_f (x_s - x_f) W) I] / sum W.
 // With `contrib`, the marker acceleration from the momentum equation over the
-// soil neighbours (no body force) and the marker's force and torque on its body.
+// soil neighbours (no body force) and the marker's force and torque on its
+// body, at entry cidx[s] - cbase (the marker's rank among the processed
+// markers in id order).
 template <bool FORCE, bool CELL>
 __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows, int64_t n,
                                                 const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbr,
-                                                const Body* __restrict__ bodies, const int32_t* __restrict__ slot_id,
-                                                int64_t n_soil, Phys P, double* __restrict__ contrib) {
+                                                const Body* __restrict__ bodies, const int32_t* __restrict__ cidx,
+                                                int64_t cbase, Phys P, double* __restrict__ contrib) {
   const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
   const bool live = r < n;
@@ -570,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
       const double f0 = (double)P.m * (double)(a0 * ir + v0);
       const double f1 = (double)P.m * (double)(a1 * ir + v1);
       const double f2 = (double)P.m * (double)(a2 * ir + v2);
-      double* out = contrib + (int64_t)(slot_id[s] - n_soil) * 6;
+      double* out = contrib + ((int64_t)cidx[s] - cbase) * 6;
       out[0] = f0;
       out[1] = f1;
       out[2] = f2;
@@ -1136,17 +1205,24 @@ hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStr
   return hipGetLastError();
 }
 
-hipError_t place_markers_master(const float4* local, int64_t nm, int64_t n_soil, const Body* bodies, Grid g,
-                                float4* m_a, float4* m_d, hipStream_t s) {
-  if (nm <= 0) return hipSuccess;
-  k_place_markers_master<<<nblk(nm), kBlock, 0, s>>>(local, nm, n_soil, bodies, g, m_a, m_d);
+hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int64_t n_soil, const Body* bodies,
+                                Grid g, float4* m_a, float4* m_d, hipStream_t s) {
+  if (k1 <= k0) return hipSuccess;
+  k_place_markers_master<<<nblk(k1 - k0), kBlock, 0, s>>>(local + k0, k1 - k0, n_soil + k0, bodies, g, m_a, m_d);
+  return hipGetLastError();
+}
+
+hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const int64_t* bstart, int32_t nb,
+                       int64_t kbase, int64_t* out, hipStream_t s) {
+  k_body_ranges<<<nblk((int64_t)nb + 1), kBlock, 0, s>>>(ids, n_proc, n_soil, bstart, nb, kbase, out);
   return hipGetLastError();
 }
 
 hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
                           uint8_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_activity<<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
+  if (g.cell) k_activity<true><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
+  else k_activity<false><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
   return hipGetLastError();
 }
 
@@ -1157,8 +1233,25 @@ size_t compact_tmp_elems(int64_t n) {
 
 hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst,
                          uint32_t* tmp, hipStream_t s) {
-  return compact_impl(PredFlags{flags}, n, out_ids, count_dst, tmp, s);
+  if (n <= 0) {
+    k_set_one<uint64_t><<<1, 64, 0, s>>>(count_dst, 0ull);
+    return hipGetLastError();
+  }
+  const int64_t nchunks = (n + kFlagsPer - 1) / kFlagsPer;
+  const int64_t nb = (n + kFlagsTile - 1) / kFlagsTile;
+  uint32_t* bcnt = tmp;
+  uint32_t* boff = tmp + nb;
+  uint32_t* stmp = boff + nb + 1;
+  const uint4* f16 = reinterpret_cast<const uint4*>(flags);
+  k_flags_count<<<(unsigned)nb, kBlock, 0, s>>>(f16, nchunks, bcnt);
+  hipError_t e = scan_impl<uint32_t, uint32_t>(bcnt, boff, nb, stmp, s);
+  if (e != hipSuccess) return e;
+  k_flags_write<<<(unsigned)nb, kBlock, 0, s>>>(f16, nchunks, boff, out_ids);
+  k_store_count<<<1, 64, 0, s>>>(count_dst, boff + nb);
+  return hipGetLastError();
 }
+
+int64_t flags_padded(int64_t n) { return (n + kFlagsPer - 1) / kFlagsPer * kFlagsPer; }
 
 hipError_t compact_kind(const float4* pos4, int64_t n, uint32_t kind, int32_t* rows, uint64_t* count_dst,
                         uint32_t* tmp, hipStream_t s) {
@@ -1182,10 +1275,11 @@ hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_
 hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* ids, const uint32_t* cs,
                          int64_t n, int64_t n_soil, const uint8_t* flags, const float4* m_a,
                          const float4* m_b, const float4* m_c, const float4* m_d, Planes A, Planes B,
-                         float4* pos4, int4* cpos, int32_t* slot_id, uint32_t* skey, bool cell, hipStream_t s) {
+                         float4* pos4, int4* cpos, int32_t* slot_id, int32_t* slot_k, uint32_t* skey, bool cell,
+                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_gather_sorted<<<nblk(n), kBlock, 0, s>>>(tmp, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d, A, B,
-                                             pos4, cpos, cell ? 1 : 0, slot_id, skey);
+                                             pos4, cpos, cell ? 1 : 0, slot_id, slot_k, skey);
   return hipGetLastError();
 }
 
@@ -1217,20 +1311,20 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n, const int32_t*
 }
 
 hipError_t bce(Planes S, const int32_t* mrows, int64_t n, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, const int32_t* slot_id, int64_t n_soil, Phys P, double* contrib,
+               const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
                hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned gsz = nblk_groups(n);
   if (P.cell) {
     if (contrib)
-      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, contrib);
+      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, nullptr);
+      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, nullptr);
   } else {
     if (contrib)
-      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, contrib);
+      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, slot_id, n_soil, P, nullptr);
+      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, nullptr);
   }
   return hipGetLastError();
 }
