@@ -38,9 +38,13 @@ from oracle.oracle import Oracle
 DT = torch.float64
 
 
-def _W(r, h):
-    """Cubic spline, support 2h, 3-D normalisation 1/(pi h^3) (Sec. 4.1)."""
+def _W(r, h, kernel=0):
+    """Cubic spline, support 2h, 3-D normalisation 1/(pi h^3) (Sec. 4.1); or
+    the quintic Wendland kernel a (1 - q/2)^4 (2q + 1), a = 21/(16 pi h^3)."""
     q = r / h
+    if kernel == 1:
+        t = torch.clamp(1.0 - 0.5 * q, min=0.0)
+        return 21.0 / (16.0 * math.pi * h ** 3) * t ** 4 * (2.0 * q + 1.0)
     s = 1.0 / (math.pi * h ** 3)
     w1 = s * (1.0 - 1.5 * q * q + 0.75 * q * q * q)
     t = torch.clamp(2.0 - q, min=0.0)
@@ -48,8 +52,11 @@ def _W(r, h):
     return torch.where(q < 1.0, w1, w2)
 
 
-def _dWdr(r, h):
+def _dWdr(r, h, kernel=0):
     q = r / h
+    if kernel == 1:
+        t = torch.clamp(1.0 - 0.5 * q, min=0.0)
+        return -5.0 * 21.0 / (16.0 * math.pi * h ** 3) * q * t ** 3 / h
     s = 1.0 / (math.pi * h ** 4)
     d1 = s * (-3.0 * q + 2.25 * q * q)
     t = torch.clamp(2.0 - q, min=0.0)
@@ -120,6 +127,7 @@ class DiffStep:
         self.xi2 = (p["av_xi_over_h"] * p["h"]) ** 2
         self.av_mode = int(p["av_mode"])
         self.bulk = float(p["bulk_coeff"])
+        self.kernel = int(p.get("kernel", 0))
         body = np.full(self.n, -1, dtype=np.int64)
         k = self.ns
         for b, B in enumerate(sc.bodies):
@@ -172,7 +180,7 @@ class DiffStep:
     # --- pieces of the step -------------------------------------------------
     def _grad(self, d):
         r = torch.sqrt((d * d).sum(-1))
-        return r, (_dWdr(r, self.h) / r)[:, None] * d
+        return r, (_dWdr(r, self.h, self.kernel) / r)[:, None] * d
 
     def bce(self, x, u, s, rho, mr, mc):
         """Marker velocity and stress (Sec. 2.5.1) for all markers."""
@@ -180,7 +188,7 @@ class DiffStep:
         i = mr - self.ns
         d = x[mr] - x[mc]
         r = torch.sqrt((d * d).sum(-1))
-        w = _W(r, self.h)
+        w = _W(r, self.h, self.kernel)
         sw = torch.zeros(nm, dtype=DT).index_add(0, i, w)
         su = torch.zeros(nm, 3, dtype=DT).index_add(0, i, u[mc] * w[:, None])
         ss = torch.zeros(nm, 6, dtype=DT).index_add(0, i, s[mc] * w[:, None])

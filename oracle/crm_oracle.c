@@ -56,6 +56,7 @@ typedef struct orc_params {
   double bulk_coeff;      /* factor on the bulk term K tr(D) I (1 = continuum form) */
   int32_t pos_mode;       /* stored position form of the kernel: 0 FP32 absolute,
                              1 cell index + FP32 offset */
+  int32_t kernel;         /* smoothing kernel: 0 cubic spline, 1 quintic Wendland */
 } orc_params;
 
 /* ------------------------------------------------------------------ kernel */
@@ -76,10 +77,36 @@ double orc_dWdr(double r, double h) {
   return 0.0;
 }
 
+/* Quintic Wendland C2 kernel (Wendland 1995; the alternative the paper's
+ * solver offers, Sec. 4.1), support q < 2, 3-D normalisation 21/(16 pi h^3):
+ * W = a (1 - q/2)^4 (2q + 1). */
+double orc_W_wendland(double r, double h) {
+  double q = r / h;
+  if (q >= 2.0) return 0.0;
+  double a = 21.0 / (16.0 * ORC_PI * h * h * h), t = 1.0 - 0.5 * q;
+  return a * t * t * t * t * (2.0 * q + 1.0);
+}
+
+/* dW/dr of the Wendland kernel: -5 a q (1 - q/2)^3 / h. */
+double orc_dWdr_wendland(double r, double h) {
+  double q = r / h;
+  if (q >= 2.0) return 0.0;
+  double a = 21.0 / (16.0 * ORC_PI * h * h * h), t = 1.0 - 0.5 * q;
+  return -5.0 * a * q * t * t * t / h;
+}
+
+static double kern_W(const orc_params* P, double r) {
+  return P->kernel == 1 ? orc_W_wendland(r, P->h) : orc_W(r, P->h);
+}
+
+static double kern_dWdr(const orc_params* P, double r) {
+  return P->kernel == 1 ? orc_dWdr_wendland(r, P->h) : orc_dWdr(r, P->h);
+}
+
 /* grad_i W_ij = dW/dr * (x_i - x_j) / r; zero for r = 0 (the self pair). */
-static void gradW(const double rij[3], double r, double h, double out[3]) {
+static void gradW(const orc_params* P, const double rij[3], double r, double out[3]) {
   if (r <= 0.0) { out[0] = out[1] = out[2] = 0.0; return; }
-  double f = orc_dWdr(r, h) / r;
+  double f = kern_dWdr(P, r) / r;
   out[0] = f * rij[0]; out[1] = f * rij[1]; out[2] = f * rij[2];
 }
 
@@ -605,7 +632,7 @@ static void bce(orc_ctx* c, const double* X, double* U, double* S, const double*
       double d[3];
       sep(P, X + 3 * (int64_t)i, X + 3 * (int64_t)j, d);
       double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      double W = orc_W(rr, P->h);
+      double W = kern_W(P, rr);
       sw += W;
       for (int k = 0; k < 3; ++k) su[k] += U[3 * (int64_t)j + k] * W;
       for (int k = 0; k < 6; ++k) ss[k] += S[6 * (int64_t)j + k] * W;
@@ -664,7 +691,7 @@ static void marker_forces(orc_ctx* c, const double* X, const double* U, const do
         double d[3], gw[3], t[3], ss[6], v[3];
         sep(P, X + 3 * (int64_t)i, X + 3 * (int64_t)j, d);
         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        gradW(d, sqrt(r2), P->h, gw);
+        gradW(P, d, sqrt(r2), gw);
         double Vj = c->m / RHO[j];
         for (int k = 0; k < 6; ++k) ss[k] = S[6 * (int64_t)i + k] + S[6 * (int64_t)j + k];
         sdot(ss, gw, t);
@@ -706,7 +733,7 @@ static void rhs(orc_ctx* c, const double* X, const double* U, const double* S, c
       double d[3], gw[3], t[3], ss[6], du_[3], v[3];
       sep(P, X + 3 * (int64_t)i, X + 3 * (int64_t)j, d);
       double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      gradW(d, sqrt(r2), P->h, gw);
+      gradW(P, d, sqrt(r2), gw);
       double Vj = c->m / RHO[j];
       for (int k = 0; k < 3; ++k) du_[k] = U[3 * (int64_t)j + k] - U[3 * (int64_t)i + k];
       for (int aa = 0; aa < 3; ++aa)
@@ -843,7 +870,7 @@ void orc_fluid_acc_from_body(orc_ctx* c, int32_t bsel, double* out) {
       double d[3], gw[3], t[3], ss[6], v[3];
       sep(P, X + 3 * (int64_t)i, X + 3 * (int64_t)j, d);
       double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      gradW(d, sqrt(r2), P->h, gw);
+      gradW(P, d, sqrt(r2), gw);
       double Vj = c->m / RHO[j];
       for (int k = 0; k < 6; ++k) ss[k] = S[6 * (int64_t)i + k] + S[6 * (int64_t)j + k];
       sdot(ss, gw, t);

@@ -43,6 +43,7 @@ class OrcParams(C.Structure):
         ("nbr_mode", C.c_int32),
         ("bulk_coeff", C.c_double),
         ("pos_mode", C.c_int32),
+        ("kernel", C.c_int32),
     ]
 
 
@@ -62,6 +63,7 @@ def make_params(p: dict, nbr_mode: int = 0, periodic=(0, 0, 0)) -> OrcParams:
     o.shrink_interval = int(p["shrink_interval"])
     o.nbr_mode = int(nbr_mode)
     o.pos_mode = int(p.get("pos_mode", 0))
+    o.kernel = int(p.get("kernel", 0))
     return o
 
 
@@ -83,6 +85,9 @@ def lib():
         L.orc_W.argtypes = [C.c_double, C.c_double]
         L.orc_dWdr.restype = C.c_double
         L.orc_dWdr.argtypes = [C.c_double, C.c_double]
+        for name in ("orc_W_wendland", "orc_dWdr_wendland"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double, C.c_double]
         L.orc_mu_I.restype = C.c_double
         L.orc_mu_I.argtypes = [pp, C.c_double, C.c_double]
         L.orc_return_map.restype = C.c_int
@@ -142,12 +147,15 @@ def _d(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def W(r, h):
-    return lib().orc_W(float(r), float(h))
+def W(r, h, kernel=0):
+    """Smoothing kernel: 0 cubic spline, 1 quintic Wendland."""
+    f = lib().orc_W_wendland if kernel == 1 else lib().orc_W
+    return f(float(r), float(h))
 
 
-def dWdr(r, h):
-    return lib().orc_dWdr(float(r), float(h))
+def dWdr(r, h, kernel=0):
+    f = lib().orc_dWdr_wendland if kernel == 1 else lib().orc_dWdr
+    return f(float(r), float(h))
 
 
 def return_map(params: dict, s_star, s_n):

@@ -22,9 +22,10 @@ from paper_2507_05643_amd import scenes
 K = 4
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=[0, 1], ids=["cubic", "wendland"])
+def setup(request):
     sc = scenes.column(seed=0, n=8, ps_freq=2)
+    sc.params["kernel"] = request.param
     o = Oracle(sc, nbr_mode="cells")
     o.step(30)
     st = o.state()

@@ -68,3 +68,36 @@ def test_lattice_partition_of_unity(orc):
                     tot += dx ** 3 * orc.W(r, H)
     assert cnt == 57
     assert abs(tot - 1.0) < 2e-3
+
+
+# --- quintic Wendland C2 kernel (the second kernel the paper's solver offers,
+# Sec. 4.1): W = a (1 - q/2)^4 (2q + 1), a = 21 / (16 pi h^3), support 2h.
+
+def test_wendland_normalisation(orc):
+    v, _ = integrate.quad(lambda r: 4 * math.pi * r * r * orc.W(r, H, kernel=1), 0, 2 * H,
+                          epsabs=1e-15, epsrel=1e-14, limit=200)
+    assert abs(v - 1.0) < 1e-12
+
+
+def test_wendland_support_smoothness_and_peak(orc):
+    W = lambda r: orc.W(r, H, kernel=1)
+    dW = lambda r: orc.dWdr(r, H, kernel=1)
+    assert W(2 * H) == 0.0 and dW(2 * H) == 0.0 and W(2.5 * H) == 0.0
+    assert dW(0.0) == 0.0
+    assert abs(W(0.0) * 16 * math.pi * H ** 3 / 21 - 1.0) < 1e-14
+    # C2 at the support edge: W'' -> 0 as q -> 2 (it is (1 - q/2)^2 times bounded terms)
+    d = 1e-4 * H
+    w2 = (dW(2 * H - d) - dW(2 * H - 2 * d)) / d
+    w2_mid = (dW(H + d) - dW(H - d)) / (2 * d)
+    assert abs(w2) < 1e-6 * abs(w2_mid)
+    r = np.linspace(0, 2 * H, 200)
+    w = np.array([W(x) for x in r])
+    assert np.all(w >= 0) and np.all(np.diff(w) <= 0)
+
+
+def test_wendland_derivative_matches_finite_difference(orc):
+    for q in (0.05, 0.3, 0.77, 1.0, 1.4, 1.9):
+        r = q * H
+        d = 1e-7 * H
+        fd = (orc.W(r + d, H, kernel=1) - orc.W(r - d, H, kernel=1)) / (2 * d)
+        assert abs(fd - orc.dWdr(r, H, kernel=1)) < 1e-6 * abs(orc.dWdr(r, H, kernel=1)) + 1e-6

@@ -98,8 +98,10 @@ def test_rigid_rotation_gives_jaumann_spin_only():
     assert np.abs(r["drho"][ii]).max() < 1e-9            # volume preserving
 
 
-def test_uniform_velocity_gives_zero_rates_exactly():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_uniform_velocity_gives_zero_rates_exactly(kernel):
     sc = scenes.cluster(seed=2, n=6, vel_scale=0.0, sigma_scale=0.0)
+    sc.params["kernel"] = kernel
     sc.vel = np.tile(np.array([0.3, -0.2, 0.1], dtype=np.float32), (sc.n_soil, 1))
     sc.sigma = np.tile(np.array([-500, -600, -700, 10, 20, 30], dtype=np.float32), (sc.n_soil, 1))
     o = Oracle(sc)
@@ -108,10 +110,11 @@ def test_uniform_velocity_gives_zero_rates_exactly():
     assert np.all(r["ds"] == 0.0)
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("av_mode", [0, 1, 2])
-def test_momentum_conserved_isolated_cluster(av_mode):
+def test_momentum_conserved_isolated_cluster(av_mode, kernel):
     sc = scenes.cluster(seed=7, n=6, vel_scale=0.05, sigma_scale=2.0e3)
-    sc.params.update(av_mode=av_mode, av_gamma=0.5, ps_freq=5, cohesion=5e3)
+    sc.params.update(av_mode=av_mode, av_gamma=0.5, ps_freq=5, cohesion=5e3, kernel=kernel)
     o = Oracle(sc, nbr_mode="cells")
     m = o.mass
     p0 = m * o.state()["vel"].sum(axis=0)
@@ -299,8 +302,10 @@ def test_adami_no_slip_moving_body():
     assert np.abs(mu[near] - (2 * V - u)).max() < 1e-14
 
 
-def test_hydrostatic_stress_extrapolation_is_exact():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_hydrostatic_stress_extrapolation_is_exact(kernel):
     sc = scenes.column(seed=4, n=8)
+    sc.params["kernel"] = kernel
     H = 0.2
     z = sc.pos[:, 2].astype(np.float64)
     ps = RHO0 * 9.81 * (H - z)
