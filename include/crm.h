@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CRM_ABI_VERSION 1u
+#define CRM_ABI_VERSION 2u
 
 typedef enum {
   CRM_OK = 0,
@@ -61,6 +61,11 @@ enum { CRM_AV_OFF = 0, CRM_AV_BILATERAL = 1, CRM_AV_UNILATERAL = 2 };
  * (km-scale terrain, Sec. 5); offsets are advanced in FP64 and renormalised into
  * their cell every stage. Requires fewer than 32768 cells along y and z. */
 enum { CRM_POS_FP32 = 0, CRM_POS_CELL_OFFSET = 1 };
+
+/* Smoothing kernels (Sec. 4.1; both have support 2h in 3-D). CRM_KERNEL_CUBIC:
+ * the cubic spline (Monaghan 1985). CRM_KERNEL_WENDLAND: the quintic Wendland C2
+ * kernel (Wendland 1995), W = 21/(16 pi h^3) (1 - q/2)^4 (2q + 1), q = r/h. */
+enum { CRM_KERNEL_CUBIC = 0, CRM_KERNEL_WENDLAND = 1 };
 
 typedef struct crm_ctx crm_ctx;
 
@@ -94,6 +99,8 @@ typedef struct {
   uint32_t shrink_interval;
   uint32_t pos_mode;     /* CRM_POS_FP32 or CRM_POS_CELL_OFFSET */
   double bulk_coeff;
+  uint32_t kernel;       /* CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND */
+  uint32_t reserved;     /* must be 0 */
 } crm_params;
 
 /* A rigid body: BCE markers fixed in its frame (Sec. 2.5.1: layers at spacing

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # CRM_LIB_PATH selects another build of the same library (e.g. for A/B timing).
 LIB_PATH = os.environ.get("CRM_LIB_PATH") or os.path.join(HERE, "libcrm.so")
 
-CRM_ABI_VERSION = 1
+CRM_ABI_VERSION = 2
 STATUS = {0: "CRM_OK", -1: "CRM_E_INVALID", -2: "CRM_E_NOMEM", -3: "CRM_E_DEVICE",
           -4: "CRM_E_STATE", -5: "CRM_E_NONFINITE", -6: "CRM_E_UNSUPPORTED"}
 
@@ -44,6 +44,7 @@ class crm_params(C.Structure):
         ("grow_G", C.c_double), ("shrink_S", C.c_double),
         ("shrink_interval", C.c_uint32), ("pos_mode", C.c_uint32),
         ("bulk_coeff", C.c_double),
+        ("kernel", C.c_uint32), ("reserved", C.c_uint32),
     ]
 
 
@@ -144,6 +145,7 @@ def make_params(p: dict) -> crm_params:
     o.active_domains = int(p["active_domains"])
     o.shrink_interval = int(p["shrink_interval"])
     o.pos_mode = int(p.get("pos_mode", 0))
+    o.kernel = int(p.get("kernel", 0))
     return o
 
 

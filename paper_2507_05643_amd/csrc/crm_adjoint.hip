@@ -27,13 +27,23 @@
 namespace crm {
 namespace {
 
-// (dF/dr) / r for F(r) = W'(r) / r, as kg g2(q) with kg = 1 / (pi h^7).
+// Cubic spline: (dF/dr) / r for F(r) = W'(r) / r, as kg g2(q) with kg = 1 / (pi h^7).
 __device__ inline float kernel_g2(float q, float kg) {
   const float t = fmaxf(2.0f - q, 0.0f);
   const float iq = __builtin_amdgcn_rcpf(q);
   const float inner = 2.25f * kg * iq;
   const float outer = 0.75f * kg * (2.0f * t * q + t * t) * iq * iq * iq;
   return q < 1.0f ? inner : outer;
+}
+
+// Wendland: (dF/dr) / r = kg t^2 / q, t = 1 - q/2, kg = 15 kw / (2 h^4).
+__device__ inline float wendland_g2(float q, float kg) {
+  const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+  return kg * t * t * __builtin_amdgcn_rcpf(q);
+}
+
+__device__ inline float sph_g2(float q, const Phys& P) {
+  return P.kern == 1 ? wendland_g2(q, P.kg) : kernel_g2(q, P.kg);
 }
 
 __device__ inline void sym_mv(const float s[6], const float v[3], float o[3]) {
@@ -343,8 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_marker(CPlanes Y, Planes E, cons
     pair_sep<CELL>(me, o, P.Sf, d[0], d[1], d[2]);
     const float r2 = dot3(d, d);
     const float q = fsqrt(r2) * P.inv_h;
-    const float F = kernel_f(q, P.kf);
-    const float W = kernel_w(q, P.kw);
+    const float F = sph_f(q, P);
+    const float W = sph_w(q, P);
     float uf[3], sf[6];
     load_state(o, uf, sf);
     const float rhof = o.a.w;
@@ -451,8 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(CPlanes Y, CPlanes E, con
     const float r2 = dot3(d, d);
     if (!(r2 > 0.f)) return;
     const float q = fsqrt(r2) * P.inv_h;
-    const float F = kernel_f(q, P.kf);
-    const float G2 = kernel_g2(q, P.kg);
+    const float F = sph_f(q, P);
+    const float G2 = sph_g2(q, P);
     float uq[3], sq[6];
     load_state(o, uq, sq);
     const float rhoq = o.a.w;
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(CPlanes Y, CPlanes E, con
       }
       if (is_marker) {
         // the marker's extrapolation sums over this soil particle (Sec. 2.5.1)
-        const float W = kernel_w(q, P.kw);
+        const float W = sph_w(q, P);
         const float lsu[3] = {fa.x, fa.y, fa.z};
         const float lss[6] = {fb.x, fb.y, fb.z, fb.w, fc.x, fc.y};
         const float lsr[3] = {fc.z, fc.w, fd.x};

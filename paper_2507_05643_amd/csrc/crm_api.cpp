@@ -181,6 +181,8 @@ std::string check_params(const crm_params* p) {
   if (!p) return "params is NULL";
   if (p->abi_version != CRM_ABI_VERSION) return "abi_version mismatch";
   if (p->pos_mode > 1) return "pos_mode must be CRM_POS_FP32 or CRM_POS_CELL_OFFSET";
+  if (p->kernel > 1) return "kernel must be CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND";
+  if (p->reserved != 0) return "reserved must be 0";
   auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
   if (!pos(p->dx)) return "dx must be > 0";
   if (!pos(p->h)) return "h must be > 0";
@@ -770,8 +772,18 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   const double pi = 3.14159265358979323846;
   Phys& ph = c->phys;
   ph.inv_h = (float)(1.0 / P.h);
-  ph.kw = (float)(1.0 / (pi * P.h * P.h * P.h));
-  ph.kf = (float)(1.0 / (pi * P.h * P.h * P.h * P.h * P.h));
+  const double h2 = P.h * P.h, h3 = h2 * P.h;
+  ph.kern = (int32_t)P.kernel;
+  if (P.kernel == CRM_KERNEL_WENDLAND) {
+    const double a = 21.0 / (16.0 * pi * h3);
+    ph.kw = (float)a;
+    ph.kf = (float)(5.0 * a / h2);
+    ph.kg = (float)(7.5 * a / (h2 * h2));
+  } else {
+    ph.kw = (float)(1.0 / (pi * h3));
+    ph.kf = (float)(1.0 / (pi * h3 * h2));
+    ph.kg = (float)(1.0 / (pi * h3 * h2 * h2));
+  }
   ph.dt = (float)P.dt;
   ph.half_dt = (float)(0.5 * P.dt);
   ph.gx = (float)P.gravity[0];
@@ -784,7 +796,6 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   ph.av_coef = (float)(P.av_gamma * P.h * cs * m);
   ph.xi2 = (float)((P.av_xi_over_h * P.h) * (P.av_xi_over_h * P.h));
   ph.av_mode = (int32_t)P.av_mode;
-  ph.kg = (float)(1.0 / (pi * P.h * P.h * P.h * P.h * P.h * P.h * P.h));
   ph.G = (float)G;
   ph.bulk = (float)P.bulk_coeff;
   ph.inv_2K = (float)(0.5 / K);

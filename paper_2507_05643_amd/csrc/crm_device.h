@@ -154,6 +154,28 @@ __device__ inline float kernel_w(float q, float kw) {
 
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Quintic Wendland C2: W = kw t^4 (2q + 1) and W'(r) / r = -kf t^3, t = 1 - q/2
+// (zero beyond q = 2).
+__device__ inline float wendland_w(float q, float kw) {
+  const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+  const float t2 = t * t;
+  return kw * t2 * t2 * (2.0f * q + 1.0f);
+}
+
+__device__ inline float wendland_f(float q, float kf) {
+  const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+  return -kf * t * t * t;
+}
+
+// The context's smoothing kernel (uniform over a launch).
+__device__ inline float sph_w(float q, const Phys& P) {
+  return P.kern == 1 ? wendland_w(q, P.kw) : kernel_w(q, P.kw);
+}
+
+__device__ inline float sph_f(float q, const Phys& P) {
+  return P.kern == 1 ? wendland_f(q, P.kf) : kernel_f(q, P.kf);
+}
+
 // A neighbour's record, loaded from the four planes with a 32-bit byte offset
 // from each plane's base (slots < 2^28).
 struct Nbr {

@@ -75,8 +75,8 @@ __host__ __device__ inline int32_t unpack_z(uint32_t w) { return (int32_t)(int16
 // FP32 constants of the stage kernels.
 struct Phys {
   float inv_h;
-  float kw;       // 1 / (pi h^3): W = kw * w(q)
-  float kf;       // 1 / (pi h^5): grad W = kf * f(q) * (x_i - x_j)
+  float kw;       // W = kw * w(q) (cubic: 1 / (pi h^3); Wendland: 21 / (16 pi h^3))
+  float kf;       // grad W = kf * f(q) * (x_i - x_j) (cubic: 1 / (pi h^5); Wendland: 5 kw / h^2)
   float dt, half_dt;
   float gx, gy, gz;
   float m;        // particle mass rho0 dx^3
@@ -86,7 +86,8 @@ struct Phys {
   float av_coef;  // gamma_a h c_s m
   float xi2;      // (xi_over_h h)^2
   int32_t av_mode;
-  float kg;       // 1 / (pi h^7): the radial derivative of f(q) kf, over r, is kg g2(q)
+  int32_t kern;   // smoothing kernel: 0 cubic spline, 1 quintic Wendland
+  float kg;       // second-derivative scale: (dF/dr) / r = kg g2(q), F = W'(r) / r
   float G;        // shear modulus, bulk factor and 1 / (2K) for the adjoint's
   float bulk;     // parameter derivatives
   float inv_2K;

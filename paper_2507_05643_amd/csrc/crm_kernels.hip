@@ -247,15 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_master(const float4* _
 
 // Sec. 4.2 item 2: Active inside an oriented box (|R^T (x - X)| <= half per
 // local axis), Extended-Active inside the box grown by 2h, else Inactive.
-template <bool CELL>
-__global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
-                                                     int64_t n, const Body* __restrict__ bodies, int32_t nb, Grid g,
-                                                     uint8_t* __restrict__ flags) {
+// Activity flag of one FP64 position against all active boxes.
+__device__ inline uint8_t flag_of(const double xw[3], const Body* __restrict__ bodies, int32_t nb, double ext) {
 #pragma clang fp contract(off)
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double xw[3];
-  abs_pos(m_a[i], CELL ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f), g, xw);
   uint8_t best = 0;
   for (int b = 0; b < nb; ++b) {
     const Body& B = bodies[b];
@@ -267,16 +261,41 @@ __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ 
     double d[3], l[3];
     for (int a = 0; a < 3; ++a) d[a] = xw[a] - B.X[a];
     for (int a = 0; a < 3; ++a) l[a] = (B.R[a] * d[0] + B.R[3 + a] * d[1]) + B.R[6 + a] * d[2];
-    bool in = true, ext = true;
+    bool in = true, grown = true;
     for (int a = 0; a < 3; ++a) {
       double al = fabs(l[a]);
       if (!(al <= B.half[a])) in = false;
-      if (!(al <= B.half[a] + g.ext)) ext = false;
+      if (!(al <= B.half[a] + ext)) grown = false;
     }
-    if (in) { best = 2; break; }
-    if (ext) best = 1;
+    if (in) return 2;
+    if (grown) best = 1;
   }
-  flags[i] = best;
+  return best;
+}
+
+// Four particles per thread (i, i + T, i + 2T, i + 3T for T threads in the
+// grid), their loads issued before any test: the pass streams all N particles.
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
+                                                     int64_t n, const Body* __restrict__ bodies, int32_t nb, Grid g,
+                                                     uint8_t* __restrict__ flags) {
+  const int64_t T = (int64_t)gridDim.x * kBlock;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float4 a[4], d[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = i0 + q * T;
+    a[q] = i < n ? m_a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    d[q] = (CELL && i < n) ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = i0 + q * T;
+    if (i >= n) break;
+    double xw[3];
+    abs_pos(a[q], d[q], g, xw);
+    flags[i] = flag_of(xw, bodies, nb, g.ext);
+  }
 }
 
 // Processed-marker range of each body: markers are processed in id order and
@@ -548,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float q = fsqrt(dx * dx + dy * dy + dz * dz) * P.inv_h;
-    const float w = kernel_w(q, P.kw);
+    const float w = sph_w(q, P);
     sw += w;
     su0 += o.b.x * w; su1 += o.b.y * w; su2 += o.b.z * w;
     ss0 += o.c.x * w; ss1 += o.c.y * w; ss2 += o.c.z * w;
@@ -618,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
       pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float q = fsqrt(r2) * P.inv_h;
-      const float F = kernel_f(q, P.kf);
+      const float F = sph_f(q, P);
       const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;
       const float wx = VF * dx, wy = VF * dy, wz = VF * dz;
       const float sxx = sg[0] + o.c.x, syy = sg[1] + o.c.y, szz = sg[2] + o.c.z;
@@ -727,7 +746,7 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, co
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float q = fsqrt(r2) * P.inv_h;
-    const float F = kernel_f(q, P.kf);
+    const float F = sph_f(q, P);
     const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;   // V_j * (gradW / r_ij)
     const float wx = VF * dx, wy = VF * dy, wz = VF * dz;       // V_j grad_i W_ij
     const float dux = o.b.x - ux, duy = o.b.y - uy, duz = o.b.z - uz;
@@ -1221,8 +1240,9 @@ hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const
 hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
                           uint8_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (g.cell) k_activity<true><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
-  else k_activity<false><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
+  const unsigned grid = nblk((n + 3) / 4);
+  if (g.cell) k_activity<true><<<grid, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
+  else k_activity<false><<<grid, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
   return hipGetLastError();
 }
 

@@ -155,3 +155,15 @@ def test_adjoint_error_paths(crm):
     with pytest.raises(crm.CrmError):
         s2.record(1)
     s2.close()
+
+
+def test_adjoint_wendland_kernel(crm):
+    sc = scenes.column(seed=4, n=8, ps_freq=2)
+    sc.params["kernel"] = 1
+    sc = _warm(sc, 30)
+    sim, got, ref, rep = _run(crm, sc, 4, seed=13)
+    say("wendland adjoint vs oracle", rep)
+    for k in ("x", "u", "s", "rho"):
+        assert rep[k] <= 1e-3, (k, rep[k])
+    assert rep["params"] <= 1e-2, rep["params"]
+    sim.close()

@@ -388,3 +388,22 @@ def test_full_size_wheel_bin_one_step(crm):
             want = want[want < sc.n_soil]
         assert np.array_equal(a, want), i
     sim.close()
+
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-5), (100, 1e-3)])
+def test_wendland_kernel_parity(crm, steps, tol):
+    """The quintic Wendland kernel (Sec. 4.1) against the oracle with the same kernel."""
+    sc = scenes.column(seed=5, ps_freq=4)
+    sc.params["kernel"] = 1
+    sim = crm.Simulation(sc)
+    orc = Oracle(sc, nbr_mode="cells")
+    sim.step(steps)
+    orc.step(steps)
+    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
+    print("wendland", steps, rep, flush=True)
+    for k, v in rep.items():
+        assert v <= tol, (k, v)
+    F, _ = sim.forces()
+    Fr, _ = orc.forces()
+    assert normwise(F, Fr) <= tol
+    sim.close()
