@@ -83,7 +83,13 @@ typedef void (*crm_free_fn)(void* ptr, void* user, void* hip_stream);
  *   active_domains, t_delay, grow_G (G), shrink_S (S), shrink_interval (S_I): Sec. 4.2.
  * domain_lo/hi bound the cell grid (cell size 2h); particles outside are
  * binned into the edge cells. bulk_coeff multiplies the bulk term K tr(D) I of
- * the stress rate (1 = the continuum form of eq. stress_rate_hypoelastic). */
+ * the stress rate (1 = the continuum form of eq. stress_rate_hypoelastic).
+ * skin = 0: the paper's persistent lists of the pairs within 2h, rebuilt every
+ * ps_freq steps (Alg. 2). skin > 0: Verlet lists of the pairs within 2h + skin
+ * (cells of that size; active boxes grown by 2h + skin), rebuilt when a
+ * processed particle has moved more than skin / 2 since the last rebuild, or
+ * after ps_freq steps. Since the kernel vanishes beyond 2h, the sums then equal
+ * those over the exact 2h neighbours of every step (up to summation order). */
 typedef struct {
   uint32_t abi_version;  /* must be CRM_ABI_VERSION */
   uint32_t av_mode;
@@ -101,6 +107,7 @@ typedef struct {
   double bulk_coeff;
   uint32_t kernel;       /* CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND */
   uint32_t reserved;     /* must be 0 */
+  double skin;           /* Verlet-list skin (m, >= 0), see below */
 } crm_params;
 
 /* A rigid body: BCE markers fixed in its frame (Sec. 2.5.1: layers at spacing

@@ -44,7 +44,7 @@ class crm_params(C.Structure):
         ("grow_G", C.c_double), ("shrink_S", C.c_double),
         ("shrink_interval", C.c_uint32), ("pos_mode", C.c_uint32),
         ("bulk_coeff", C.c_double),
-        ("kernel", C.c_uint32), ("reserved", C.c_uint32),
+        ("kernel", C.c_uint32), ("reserved", C.c_uint32), ("skin", C.c_double),
     ]
 
 
@@ -146,6 +146,7 @@ def make_params(p: dict) -> crm_params:
     o.shrink_interval = int(p["shrink_interval"])
     o.pos_mode = int(p.get("pos_mode", 0))
     o.kernel = int(p.get("kernel", 0))
+    o.skin = float(p.get("skin", 0.0))
     return o
 
 

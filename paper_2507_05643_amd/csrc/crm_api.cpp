@@ -95,6 +95,13 @@ struct crm_ctx {
   int64_t kbase = 0;             // rank of the first processed marker in the processed list
   std::vector<Body> placed;      // body poses of the markers' last placement in the master store
   bool place_all = true;         // place every body's markers at the next placement
+  // Verlet lists (skin > 0): steps of the last rebuild, largest squared
+  // displacement since (device word, pinned mirror, event of its copy)
+  int64_t last_rebuild = 0;
+  uint32_t* d_disp = nullptr;
+  uint32_t* h_disp = nullptr;
+  hipEvent_t disp_ev = nullptr;
+  bool disp_pending = false;
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
   uint64_t* h_counts = nullptr;   // pinned mirror
 
@@ -183,6 +190,7 @@ std::string check_params(const crm_params* p) {
   if (p->pos_mode > 1) return "pos_mode must be CRM_POS_FP32 or CRM_POS_CELL_OFFSET";
   if (p->kernel > 1) return "kernel must be CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND";
   if (p->reserved != 0) return "reserved must be 0";
+  if (!(std::isfinite(p->skin) && p->skin >= 0.0)) return "skin must be >= 0";
   auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
   if (!pos(p->dx)) return "dx must be > 0";
   if (!pos(p->h)) return "h must be > 0";
@@ -529,6 +537,11 @@ crm_status rebuild(crm_ctx* c) {
   c->working_valid = true;
   c->force_rebuild = false;
   c->rebuilds += 1;
+  c->last_rebuild = c->step;
+  if (c->prm.skin > 0.0) {
+    HIPCHK(c, crm::fill_u32(c->d_disp, 0u, 1, s));
+    c->disp_pending = false;
+  }
   return CRM_OK;
 }
 
@@ -651,8 +664,32 @@ crm_status step_graph(crm_ctx* c) {
   return CRM_OK;
 }
 
-bool rebuild_due(const crm_ctx* c) {
-  return c->force_rebuild || !c->working_valid || c->step % (int64_t)c->prm.ps_freq == 0;
+// Squared displacement read back after the last step exceeds (skin / 2)^2.
+bool moved_beyond_half_skin(crm_ctx* c) {
+  if (!c->disp_pending) return false;
+  (void)hipEventSynchronize(c->disp_ev);
+  float d2;
+  std::memcpy(&d2, c->h_disp, 4);
+  const double half = 0.5 * c->prm.skin;
+  return (double)d2 > half * half;
+}
+
+bool rebuild_due(crm_ctx* c) {
+  if (c->force_rebuild || !c->working_valid) return true;
+  if (c->prm.skin <= 0.0) return c->step % (int64_t)c->prm.ps_freq == 0;
+  return c->step - c->last_rebuild >= (int64_t)c->prm.ps_freq || moved_beyond_half_skin(c);
+}
+
+// Verlet lists: the largest displacement since the rebuild, read back
+// asynchronously for the next step's decision.
+crm_status track_displacement(crm_ctx* c) {
+  if (c->prm.skin <= 0.0) return CRM_OK;
+  hipStream_t s = c->stream;
+  HIPCHK(c, crm::max_disp(c->A, c->pos4, c->cpos, c->n_proc, c->grid.cell != 0, c->phys.Sf, c->d_disp, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_disp, c->d_disp, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipEventRecord(c->disp_ev, s));
+  c->disp_pending = true;
+  return CRM_OK;
 }
 
 crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
@@ -665,6 +702,8 @@ crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
   crm_status st = rec ? launch_step(c, c->stream, false, rec)
                       : (c->use_graph && !c->prof) ? step_graph(c) : launch_step(c, c->stream, c->prof);
   if (st != CRM_OK) return st;
+  st = track_displacement(c);
+  if (st != CRM_OK) return st;
   c->step += 1;
   c->stepped = true;
   return CRM_OK;
@@ -676,6 +715,8 @@ void release(crm_ctx* c) {
   std::vector<Buf> all = c->owned;
   for (auto& b : all) dfree(c, b.p);
   if (c->h_counts) (void)hipHostFree(c->h_counts);
+  if (c->h_disp) (void)hipHostFree(c->h_disp);
+  if (c->disp_ev) (void)hipEventDestroy(c->disp_ev);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -727,11 +768,12 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   for (int64_t i = 0; i < 3 * n_soil; ++i)
     if (!std::isfinite(pos[i])) return fail(nullptr, CRM_E_INVALID, "non-finite position");
   Grid g{};
-  const double two_h = 2.0 * params->h;
-  g.inv = 1.0 / two_h;
-  g.R2 = two_h * two_h;
-  g.ext = two_h;
-  g.S = two_h;
+  // list radius and cell size: 2h, or 2h + skin for Verlet lists
+  const double radius = 2.0 * params->h + params->skin;
+  g.inv = 1.0 / radius;
+  g.R2 = radius * radius;
+  g.ext = radius;
+  g.S = radius;
   g.cell = params->pos_mode == CRM_POS_CELL_OFFSET ? 1 : 0;
   int64_t M = 1;
   for (int a = 0; a < 3; ++a) {
@@ -879,6 +921,14 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     release(c);
     return fail(nullptr, CRM_E_NOMEM, "pinned allocation failed");
   }
+  if (params->skin > 0.0) {
+    if (!alloc_n(c, c->d_disp, 1) || hipHostMalloc((void**)&c->h_disp, 4, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->disp_ev, hipEventDisableTiming) != hipSuccess) {
+      c->h_disp = nullptr;
+      release(c);
+      return fail(nullptr, CRM_E_NOMEM, "displacement tracking allocation failed");
+    }
+  }
   hipStream_t s = c->stream;
   hipError_t e = hipSuccess;
   const size_t f4 = sizeof(float4) * (size_t)n_total;
@@ -1022,6 +1072,7 @@ crm_status crm_record(crm_ctx* c, int32_t n_steps) {
   if (st != CRM_OK) return st;
   if (n_steps < 1) return fail(c, CRM_E_INVALID, "n_steps must be >= 1");
   if (c->prm.active_domains) return fail(c, CRM_E_UNSUPPORTED, "the reverse sweep covers runs without active domains");
+  if (c->prm.skin > 0.0) c->force_rebuild = true;   // Verlet lists: the record starts with a rebuild
   if (!rebuild_due(c)) return fail(c, CRM_E_STATE, "a record starts at a list rebuild (step mod ps_freq = 0)");
   const int64_t ps = c->prm.ps_freq;
   const int64_t segs = (int64_t)n_steps / ps + 2;

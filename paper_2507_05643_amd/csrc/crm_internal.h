@@ -166,6 +166,11 @@ hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, con
                     const uint32_t* cnt, const uint32_t* stash, const uint64_t* off, uint32_t* nbr,
                     hipStream_t s);
 
+// Largest squared displacement of the n processed slots since the last list
+// rebuild, folded into *out (float bits, integer max; *out starts at 0).
+hipError_t max_disp(CPlanes A, const float4* pos4, const int4* cpos, int64_t n, bool cell, float Sf, uint32_t* out,
+                    hipStream_t s);
+
 // Per step: marker positions of the processed markers into A and B.
 hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const int32_t* slot_id,
                                  int64_t n_soil, const float4* local, const Body* bodies, Grid g,

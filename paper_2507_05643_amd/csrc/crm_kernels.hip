@@ -298,6 +298,33 @@ __global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ 
   }
 }
 
+// Largest squared displacement of a processed particle since the last list
+// rebuild (A against the rebuild positions in pos4 / cpos), as the bits of a
+// non-negative float folded in with an integer atomic max (exact and
+// independent of the order).
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_max_disp(CPlanes A, const float4* __restrict__ pos4,
+                                                     const int4* __restrict__ cpos, int64_t n, float Sf,
+                                                     uint32_t* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float d2 = 0.f;
+  if (s < n) {
+    const float4 a = A.a[s], p = pos4[s];
+    float dx = a.x - p.x, dy = a.y - p.y, dz = a.z - p.z;
+    if (CELL) {
+      const float4 d = A.d[s];
+      const int4 c = cpos[s];
+      const uint32_t w = __float_as_uint(d.w);
+      dx += (float)((int32_t)__float_as_uint(d.z) - c.x) * Sf;
+      dy += (float)(unpack_y(w) - c.y) * Sf;
+      dz += (float)(unpack_z(w) - c.z) * Sf;
+    }
+    d2 = dx * dx + dy * dy + dz * dz;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, kWave));
+  if (lane_id() == 0) atomicMax(out, __float_as_uint(d2));
+}
+
 // Processed-marker range of each body: markers are processed in id order and
 // body b owns ids n_soil + [bstart[b], bstart[b + 1]), so its processed
 // markers are entries [lower_bound(ids, n_soil + bstart[b]) - kbase, ...).
@@ -981,10 +1008,11 @@ __device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>& T,
   return l;
 }
 
-// The walk of a row through the tile. The CSR indices four entries ahead are
-// in flight while the current pair is computed: the index load from HBM/L2 is
-// the walk's longest wait (the tile read is short). Past the row's end the
-// walk reads its first entry again (a valid index).
+// The walk of a row through the tile, two entries per lane and iteration: both
+// tile reads are issued before either pair is computed, and the CSR indices
+// four entries ahead are in flight meanwhile (the index load from HBM/L2 is the
+// walk's longest wait). The pairs are still taken in entry order. Past the
+// row's end the walk reads its first entry again (a valid index).
 template <class Load, class Fn>
 __device__ inline void walk_row_ahead(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
                                       Fn&& f) {
@@ -995,15 +1023,19 @@ __device__ inline void walk_row_ahead(const Load& load, uint64_t k0, uint64_t k1
   uint64_t k = kf;
   uint32_t j0 = idx(k), j1 = idx(k + G), j2 = idx(k + 2 * G), j3 = idx(k + 3 * G);
   for (;;) {
-    const bool more = k + G < k1;
-    const uint32_t j4 = idx(k + 4 * G);
-    f(load(j0), j0);
+    const bool has1 = k + G < k1;
+    const bool more = k + 2 * G < k1;
+    const uint32_t j4 = idx(k + 4 * G), j5 = idx(k + 5 * G);
+    const Nbr a = load(j0);
+    const Nbr b = load(j1);
+    f(a, j0);
+    if (has1) f(b, j1);
     if (!more) break;
-    j0 = j1;
-    j1 = j2;
-    j2 = j3;
-    j3 = j4;
-    k += G;
+    j0 = j2;
+    j1 = j3;
+    j2 = j4;
+    j3 = j5;
+    k += 2 * G;
   }
 }
 
@@ -1228,6 +1260,14 @@ hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int
                                 Grid g, float4* m_a, float4* m_d, hipStream_t s) {
   if (k1 <= k0) return hipSuccess;
   k_place_markers_master<<<nblk(k1 - k0), kBlock, 0, s>>>(local + k0, k1 - k0, n_soil + k0, bodies, g, m_a, m_d);
+  return hipGetLastError();
+}
+
+hipError_t max_disp(CPlanes A, const float4* pos4, const int4* cpos, int64_t n, bool cell, float Sf, uint32_t* out,
+                    hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (cell) k_max_disp<true><<<nblk(n), kBlock, 0, s>>>(A, pos4, cpos, n, Sf, out);
+  else k_max_disp<false><<<nblk(n), kBlock, 0, s>>>(A, pos4, cpos, n, Sf, out);
   return hipGetLastError();
 }
 

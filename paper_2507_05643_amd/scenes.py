@@ -42,7 +42,7 @@ DEFAULT_PARAMS = dict(
     domain_lo=(0.0, 0.0, 0.0), domain_hi=(1.0, 1.0, 1.0),
     active_domains=0, t_delay=0.0,
     grow_G=1.2, shrink_S=0.75, shrink_interval=50,
-    bulk_coeff=1.0, pos_mode=0, kernel=0,
+    bulk_coeff=1.0, pos_mode=0, kernel=0, skin=0.0,
 )
 
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(crm):
 
 def test_params_layout(crm):
     # two uint32, 3 + 3 doubles, 8 + 2 doubles, 6 doubles, 2 uint32, 3 doubles, 2 uint32, 1 double
-    assert C.sizeof(crm.crm_params) == 8 + 8 * 6 + 8 * 10 + 8 * 6 + 8 + 8 * 3 + 8 + 8 + 8
+    assert C.sizeof(crm.crm_params) == 8 + 8 * 6 + 8 * 10 + 8 * 6 + 8 + 8 * 3 + 8 + 8 + 8 + 8
     assert crm.crm_params.ps_freq.offset == 8 + 8 * 6 + 8 * 10 + 8 * 6
     assert C.sizeof(crm.crm_body_desc) == 40
 
@@ -62,7 +62,7 @@ def _raw_init(crm, p, pos):
 @pytest.mark.parametrize("key,val", [("dx", 0.0), ("h", -1.0), ("dt", float("nan")), ("nu", 0.5),
                                      ("mu_s", 0.0), ("av_mode", 3), ("ps_freq", 0), ("grow_G", 0.9),
                                      ("shrink_S", 1.5), ("shrink_interval", 0), ("cohesion", -1.0),
-                                     ("kernel", 2), ("pos_mode", 2)])
+                                     ("kernel", 2), ("pos_mode", 2), ("skin", -1.0)])
 def test_invalid_params_rejected(crm, key, val):
     from paper_2507_05643_amd import scenes
     p = dict(scenes.DEFAULT_PARAMS)
