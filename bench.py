@@ -38,10 +38,9 @@ BYTES_PER_PAIR = 4
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of k_fluid_stage2 on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy (fetch x2, write x1); the
-# commands and figures are in profiles/wheel_bin_kernels_lds_tiles.md (small
-# LDS tile, two tile reads per lane and iteration). None once the kernel changes.
-STAGE2_TRAFFIC_BYTES = 573.7e6
+# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy; None until measured for
+# the current kernel.
+STAGE2_TRAFFIC_BYTES = None
 
 
 class WheelDriver:

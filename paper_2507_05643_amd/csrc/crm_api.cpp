@@ -74,6 +74,8 @@ struct crm_ctx {
   int32_t* slot_k = nullptr;     // processed index (position in the processed id list)
   uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
   int32_t *frows = nullptr, *mrows = nullptr;
+  int32_t* near = nullptr;       // marker rows (indices into mrows) with soil neighbours
+  int64_t n_near = 0;
   uint32_t *cnt_f = nullptr, *cnt_m = nullptr;
   uint64_t *off_f = nullptr, *off_m = nullptr, *wtmp = nullptr;
   uint32_t *stash_f = nullptr, *stash_m = nullptr;  // count-pass scratch of the lists
@@ -83,6 +85,8 @@ struct crm_ctx {
   // neighbour entries
   uint32_t* nbr_f = nullptr;
   int64_t nbr_f_cap = 0;
+  uint16_t* tix_f = nullptr;     // tile positions of the soil entries (nbr_f_cap)
+  int64_t tix_f_cap = 0;
   uint32_t* nbr_m = nullptr;
   int64_t nbr_m_cap = 0;
 
@@ -103,6 +107,7 @@ struct crm_ctx {
   hipEvent_t disp_ev = nullptr;
   bool disp_pending = false;
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
+                                 // [5] marker rows with soil neighbours
   uint64_t* h_counts = nullptr;   // pinned mirror
 
   int64_t n_proc = 0, n_frows = 0, n_mrows = 0, ent_f = 0, ent_m = 0;
@@ -278,14 +283,14 @@ void quat_to_R(const double q[4], double R[9]) {
 
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
   void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id, c->slot_k,
-                  c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->cnt_f, c->cnt_m, c->off_f,
+                  c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->near, c->cnt_f, c->cnt_m, c->off_f,
                   c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
   for (void* p : olds) dfree(c, p);
   c->A = Planes{};
   c->B = Planes{};
   c->pos4 = nullptr;
   c->cpos = nullptr;
-  c->slot_id = c->slot_k = c->frows = c->mrows = nullptr;
+  c->slot_id = c->slot_k = c->frows = c->mrows = c->near = nullptr;
   c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = nullptr;
   c->off_f = c->off_m = c->wtmp = nullptr;
   c->stash_f = c->stash_m = nullptr;
@@ -298,7 +303,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
             alloc_n(c, c->slot_id, cap) && alloc_n(c, c->slot_k, cap) && alloc_n(c, c->skey, cap) &&
             alloc_n(c, c->key, cap) &&
             alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->frows, cap) &&
-            alloc_n(c, c->mrows, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
+            alloc_n(c, c->mrows, cap) && alloc_n(c, c->near, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
             alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
             alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
             alloc_n(c, c->stash_f, (int64_t)crm::stash_elems(cap)) &&
@@ -514,15 +519,27 @@ crm_status rebuild(crm_ctx* c) {
                            true, c->cnt_m, c->stash_m, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->cnt_m, c->off_m, n_proc, c->wtmp, s));
   HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->off_f + n_proc, c->off_m + n_proc, s));
+  HIPCHK(c, crm::compact_nonzero(c->cnt_m, n_proc, c->near, c->d_counts + 5, c->ctmp, s));
   crm_status st = read_counts(c);
   if (st != CRM_OK) return st;
   c->n_frows = (int64_t)c->h_counts[1];
   c->n_mrows = (int64_t)c->h_counts[2];
+  c->n_near = (int64_t)c->h_counts[5];
+  // the force entries of markers without soil neighbours stay zero until the
+  // next rebuild (the BCE passes skip them)
+  HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mrows, s));
   const int64_t ef = (int64_t)c->h_counts[3], em = (int64_t)c->h_counts[4];
   st = ensure_list(c, c->nbr_f, c->nbr_f_cap, ef);
   if (st != CRM_OK) return st;
   st = ensure_list(c, c->nbr_m, c->nbr_m_cap, em);
   if (st != CRM_OK) return st;
+  if (c->tix_f_cap != c->nbr_f_cap) {
+    dfree(c, c->tix_f);
+    c->tix_f = nullptr;
+    c->tix_f_cap = 0;
+    if (!alloc_n(c, c->tix_f, c->nbr_f_cap)) return fail(c, CRM_E_NOMEM, "neighbour-list allocation failed");
+    c->tix_f_cap = c->nbr_f_cap;
+  }
   c->ent_f = ef;
   c->ent_m = em;
   HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, false,
@@ -530,6 +547,7 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
   HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, s));
+  HIPCHK(c, crm::tile_index(c->n_frows, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
   // per-body ranges of the processed markers for the force sums
   c->kbase = c->n_proc - c->n_mrows;
   st = update_body_plan(c, ids);
@@ -593,24 +611,25 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   const crm::StageTape* tape2 = rec ? &rec->t2 : nullptr;
   const Phys& P = c->phys;
   hipEvent_t e = prof ? prof_begin(c) : nullptr;
-  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->slot_id, c->n_soil, c->local, c->d_bodies,
-                                       c->grid, c->A, c->B, s));
+  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->cnt_m, c->slot_id, c->n_soil, c->local,
+                                       c->d_bodies, c->grid, P, c->A, c->B, s));
   if (prof) prof_end(c, 1, e);
   // stage 1 at y_n
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->A, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P, nullptr,
-                     s));
+  HIPCHK(c, crm::bce(c->A, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
+                     nullptr, s));
   if (prof) prof_end(c, 2, e);
   if (rec) {
     crm_status st = copy_planes(c, c->A, rec->yn, c->n_proc, s);
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, c->tile_cfg, s));
+  HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, c->tix_f,
+                              c->tile_cfg, s));
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::bce(c->B, c->mrows, c->n_mrows, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
+  HIPCHK(c, crm::bce(c->B, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
                      c->contrib, s));
   if (prof) prof_end(c, 4, e);
   if (rec) {
@@ -618,7 +637,8 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, c->tile_cfg, s));
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, c->tix_f,
+                              c->tile_cfg, s));
   if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c);
   HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_forces, s));
@@ -636,8 +656,9 @@ void drop_graph(crm_ctx* c) {
 
 // Everything the captured kernels bake in: buffers and row counts.
 std::vector<const void*> graph_key(const crm_ctx* c) {
-  return {c->A.a, c->B.a, c->frows, c->mrows, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->slot_id,
+  return {c->A.a, c->B.a, c->frows, c->mrows, c->near, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->tix_f, c->slot_id,
           c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows,
+          (const void*)(intptr_t)c->n_near,
           (const void*)(intptr_t)c->tile_cfg, (const void*)(intptr_t)c->body_plan.nchunk,
           (const void*)(intptr_t)c->kbase};
 }
@@ -1478,10 +1499,11 @@ crm_status crm_autotune(crm_ctx* c, int32_t config, int32_t* chosen) {
   int32_t pick = c->tile_cfg;
   for (int32_t cfg = CRM_TILE_NONE; cfg <= CRM_TILE_LARGE; ++cfg) {
     hipError_t e = crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, nullptr, c->tabs,
-                                     cfg, s);
+                                     c->tix_f, cfg, s);
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int r = 0; r < 3 && e == hipSuccess; ++r)
-      e = crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, nullptr, c->tabs, cfg, s);
+      e = crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, nullptr, c->tabs,
+                            c->tix_f, cfg, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

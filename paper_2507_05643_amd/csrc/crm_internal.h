@@ -149,6 +149,9 @@ hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t
 // Row lists (slots owning a neighbour list): active soil rows and marker rows.
 hipError_t compact_kind(const float4* pos4, int64_t n_proc, uint32_t kind, int32_t* rows,
                         uint64_t* count_dst, uint32_t* tmp, hipStream_t s);
+// Indices i < n with cnt[i] != 0, in order; count to *count_dst (device).
+hipError_t compact_nonzero(const uint32_t* cnt, int64_t n, int32_t* rows, uint64_t* count_dst, uint32_t* tmp,
+                           hipStream_t s);
 
 // Neighbour lists (Alg. 1) in CSR: counts per row, offsets by an exclusive
 // scan of the counts (u64, rows + 1), then the fill. A group of 8 lanes serves
@@ -172,16 +175,21 @@ hipError_t max_disp(CPlanes A, const float4* pos4, const int4* cpos, int64_t n, 
                     hipStream_t s);
 
 // Per step: marker positions of the processed markers into A and B.
-hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const int32_t* slot_id,
-                                 int64_t n_soil, const float4* local, const Body* bodies, Grid g,
+// cnt: the marker rows' soil-neighbour counts; rows with none also get their
+// (empty-sum) BCE values here, for both states.
+hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const uint32_t* cnt, const int32_t* slot_id,
+                                 int64_t n_soil, const float4* local, const Body* bodies, Grid g, Phys P,
                                  Planes A, Planes B, hipStream_t s);
 
 // BCE extrapolation at state S (Sec. 2.5.1); with contrib != nullptr also the
 // marker accelerations and each processed marker's force and torque on its
 // body (FP64, 6 per marker, at entry cidx[slot] - cbase: the marker's rank
 // among the processed markers in id order).
-hipError_t bce(Planes S, const int32_t* mrows, int64_t n_mrows, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
+// Rows: near[0 .. n_near) index the marker rows (into mrows, off) that have
+// soil neighbours (compact_nonzero of the counts); the others are placed with
+// their values by place_markers_working and their contrib entries stay zero.
+hipError_t bce(Planes S, const int32_t* mrows, const int32_t* near, int64_t n_near, const uint64_t* off,
+               const uint32_t* nbr, const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
                hipStream_t s);
 // Deterministic sums of 6 doubles per entry over contiguous segments: the
 // plan cuts segment g = [start[g], start[g + 1]) into chunks of at most
@@ -209,20 +217,24 @@ struct StageTape {
   float4* t1;   // (sxz, syz, -, -), stage 2
 };
 // tabs: the per-block tile tables of the soil rows (tile_tables, after each
-// list rebuild).
+// list rebuild); tix: the entries' tile positions (tile_index, after them).
 // cfg: the LDS tile configuration (0 none, 1 small, 2 large); every
 // configuration gives bit-identical results.
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
-                        hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint16_t* tix, int cfg, hipStream_t s);
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_frows, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
-                        hipStream_t s);
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint16_t* tix, int cfg, hipStream_t s);
 // Per block of soil rows: the nine slot ranges its rows' neighbours lie in
 // (tile_table_words(rows_cap) words).
 int64_t tile_table_words(int64_t rows_cap);
 hipError_t tile_tables(const int32_t* frows, int64_t n_frows, const uint32_t* skey, const uint32_t* cell_start,
                        Phys P, uint32_t* tabs, hipStream_t s);
+// Tile position (16-bit) of each soil-row list entry of the blocks that can
+// stage their neighbours (one entry per nbr entry; the others untouched).
+hipError_t tile_index(int64_t n_frows, const uint64_t* off, const uint32_t* nbr, const uint32_t* tabs,
+                      uint16_t* tix, hipStream_t s);
 
 // Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
 // the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.

@@ -129,6 +129,11 @@ struct PredKind {
   __device__ bool operator()(int64_t i) const { return (__float_as_uint(p[i].w) & 3u) == kind; }
 };
 
+struct PredNonzero {
+  const uint32_t* c;
+  __device__ bool operator()(int64_t i) const { return c[i] != 0u; }
+};
+
 template <class Pred>
 __global__ __launch_bounds__(kBlock) void k_pred_count(Pred pr, int64_t n, uint32_t* __restrict__ bcnt) {
   __shared__ uint32_t ws[kBlock / kWave];
@@ -538,22 +543,75 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__
 }
 
 // ------------------------------------------------------------ markers ---
+// A marker's lever arm from its body's origin, from the stored position (FP64).
+template <bool CELL>
+__device__ inline void marker_arm(const Own& me, const Body& Bd, const Phys& P, double rv[3]) {
+  if (CELL) {
+    rv[0] = from_cell(me.cx, me.x, P.lo[0], P.S) - Bd.X[0];
+    rv[1] = from_cell(me.cy, me.y, P.lo[1], P.S) - Bd.X[1];
+    rv[2] = from_cell(me.cz, me.z, P.lo[2], P.S) - Bd.X[2];
+  } else {
+    rv[0] = (double)me.x - Bd.X[0];
+    rv[1] = (double)me.y - Bd.X[1];
+    rv[2] = (double)me.z - Bd.X[2];
+  }
+}
+
+// Rigid-body velocity ub = V + W x r and acceleration as = A + Al x r +
+// W x (W x r) at lever arm r (FP64, rounded once).
+__device__ inline void body_motion(const Body& Bd, const double rv[3], float ub[3], float as[3]) {
+  const double wr[3] = {Bd.W[1] * rv[2] - Bd.W[2] * rv[1], Bd.W[2] * rv[0] - Bd.W[0] * rv[2],
+                        Bd.W[0] * rv[1] - Bd.W[1] * rv[0]};
+  const double wwr[3] = {Bd.W[1] * wr[2] - Bd.W[2] * wr[1], Bd.W[2] * wr[0] - Bd.W[0] * wr[2],
+                         Bd.W[0] * wr[1] - Bd.W[1] * wr[0]};
+  for (int a = 0; a < 3; ++a) ub[a] = (float)(Bd.V[a] + wr[a]);
+  if (Bd.has_acc) {
+    const double ar[3] = {Bd.Al[1] * rv[2] - Bd.Al[2] * rv[1], Bd.Al[2] * rv[0] - Bd.Al[0] * rv[2],
+                          Bd.Al[0] * rv[1] - Bd.Al[1] * rv[0]};
+    for (int a = 0; a < 3; ++a) as[a] = (float)(Bd.A[a] + ar[a] + wwr[a]);
+  } else {
+    for (int a = 0; a < 3; ++a) as[a] = (float)wwr[a];
+  }
+}
+
+// Places every processed marker at x = X + R l (both stage states). A marker
+// row without soil neighbours (cnt[r] = 0) takes no part in any sum (the
+// neighbour relation is symmetric), so the BCE passes skip it: its
+// extrapolated values are those of an empty sum, the body velocity at the
+// marker and zero stress, written here for both stage states.
+template <bool CELL>
 __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t* __restrict__ mrows, int64_t n,
+                                                                  const uint32_t* __restrict__ cnt,
                                                                   const int32_t* __restrict__ slot_id, int64_t n_soil,
                                                                   const float4* __restrict__ local,
-                                                                  const Body* __restrict__ bodies, Grid g,
+                                                                  const Body* __restrict__ bodies, Grid g, Phys P,
                                                                   Planes A, Planes B) {
   int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
   int32_t s = mrows[r];
   float4 l = local[slot_id[s] - n_soil];
+  const Body& Bd = bodies[__float_as_uint(l.w)];
   double x[3];
-  body_point(bodies[__float_as_uint(l.w)], l.x, l.y, l.z, x);
+  body_point(Bd, l.x, l.y, l.z, x);
   float4 a = A.a[s], d = A.d[s];
   store_pos(x, g, a, d);
   A.a[s] = a;
   B.a[s] = a;
-  if (g.cell) {
+  const bool far = cnt[r] == 0;
+  if (far) {
+    double rv[3];
+    float ub[3], as[3];
+    marker_arm<CELL>(own_pos<CELL>(a, d), Bd, P, rv);
+    body_motion(Bd, rv, ub, as);
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    A.b[s] = make_float4(ub[0], ub[1], ub[2], A.b[s].w);
+    B.b[s] = make_float4(ub[0], ub[1], ub[2], B.b[s].w);
+    A.c[s] = zero;
+    B.c[s] = zero;
+    d.x = 0.f;
+    d.y = 0.f;
+  }
+  if (CELL || far) {
     A.d[s] = d;
     B.d[s] = d;
   }
@@ -566,18 +624,20 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
 // body, at entry cidx[s] - cbase (the marker's rank among the processed
 // markers in id order).
 template <bool FORCE, bool CELL>
-__global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows,
+                                                const int32_t* __restrict__ near, int64_t n,
                                                 const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbr,
                                                 const Body* __restrict__ bodies, const int32_t* __restrict__ cidx,
                                                 int64_t cbase, Phys P, double* __restrict__ contrib) {
-  const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
+  const int64_t i = (xcd_block() * kBlock + threadIdx.x) / kGroup;
   const int gl = group_lane();
-  const bool live = r < n;
+  const bool live = i < n;
   int body = -1;
   int32_t s = 0;
   float4 ma = make_float4(0.f, 0.f, 0.f, 0.f), mb = ma, md = ma;
   uint64_t k0 = 0, k1 = 0;
   if (live) {
+    const int64_t r = near[i];
     s = mrows[r];
     ma = S.a[s];
     mb = S.b[s];
@@ -612,28 +672,9 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
   if (live) {
     const Body& Bd = bodies[body];
     // body velocity and acceleration at the marker (FP64 lever arm)
-    if (CELL) {
-      rv[0] = from_cell(me.cx, me.x, P.lo[0], P.S) - Bd.X[0];
-      rv[1] = from_cell(me.cy, me.y, P.lo[1], P.S) - Bd.X[1];
-      rv[2] = from_cell(me.cz, me.z, P.lo[2], P.S) - Bd.X[2];
-    } else {
-      rv[0] = (double)me.x - Bd.X[0];
-      rv[1] = (double)me.y - Bd.X[1];
-      rv[2] = (double)me.z - Bd.X[2];
-    }
-    double wr[3] = {Bd.W[1] * rv[2] - Bd.W[2] * rv[1], Bd.W[2] * rv[0] - Bd.W[0] * rv[2],
-                    Bd.W[0] * rv[1] - Bd.W[1] * rv[0]};
-    double wwr[3] = {Bd.W[1] * wr[2] - Bd.W[2] * wr[1], Bd.W[2] * wr[0] - Bd.W[0] * wr[2],
-                     Bd.W[0] * wr[1] - Bd.W[1] * wr[0]};
+    marker_arm<CELL>(me, Bd, P, rv);
     float ub[3], as[3];
-    for (int a = 0; a < 3; ++a) ub[a] = (float)(Bd.V[a] + wr[a]);
-    if (Bd.has_acc) {
-      double ar[3] = {Bd.Al[1] * rv[2] - Bd.Al[2] * rv[1], Bd.Al[2] * rv[0] - Bd.Al[0] * rv[2],
-                      Bd.Al[0] * rv[1] - Bd.Al[1] * rv[0]};
-      for (int a = 0; a < 3; ++a) as[a] = (float)(Bd.A[a] + ar[a] + wwr[a]);
-    } else {
-      for (int a = 0; a < 3; ++a) as[a] = (float)wwr[a];
-    }
+    body_motion(Bd, rv, ub, as);
     if (sw > 0.f) {
       const float iw = 1.0f / sw;
       const float gd = ((P.gx - as[0]) * sr0 + (P.gy - as[1]) * sr1) + (P.gz - as[2]) * sr2;
@@ -758,17 +799,17 @@ struct Rates {
 // a = (1/rho_i) sum_j V_j (s_i + s_j) . gradW + g + Pi_a (F3, artificial viscosity
 // with the sign that repels approaching pairs); ds/dt = Om s - s Om + 2G D +
 // (bulk K - 2G/3) tr D I with D, Om the symmetric and skew parts of L.
-// The group's lanes take the row's neighbours k = lane, lane + kGroup, ...
-template <bool CELL, class Load>
-__device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, const Load& load, uint64_t k0,
-                                  uint64_t k1, const uint32_t* __restrict__ nbr, const Phys& P) {
+// The group's lanes take the row's neighbours k = lane, lane + kGroup, ...;
+// walk(pair) calls pair(record) for each of the lane's neighbours.
+template <bool CELL, class Walk>
+__device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Walk&& walk, const Phys& P) {
   const Own me = own_pos<CELL>(ma, md);
   const float rhoi = ma.w;
   const float ux = mb.x, uy = mb.y, uz = mb.z;
   const float s0 = mc.x, s1 = mc.y, s2 = mc.z, s3 = mc.w, s4 = md.x, s5 = md.y;
   float L00 = 0.f, L01 = 0.f, L02 = 0.f, L10 = 0.f, L11 = 0.f, L12 = 0.f, L20 = 0.f, L21 = 0.f, L22 = 0.f;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-  auto pair = [&](const Nbr& o, uint32_t) {
+  auto pair = [&](const Nbr& o) {
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -790,8 +831,7 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, co
     const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhoi + o.a.w) * (r2 + P.xi2)) : 0.f;
     v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
   };
-  if constexpr (Load::kTile) walk_row_ahead(load, k0, k1, nbr, pair);
-  else walk_row_with(load, k0, k1, nbr, pair);
+  walk(pair);
   L00 = group_sum(L00); L01 = group_sum(L01); L02 = group_sum(L02);
   L10 = group_sum(L10); L11 = group_sum(L11); L12 = group_sum(L12);
   L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
@@ -965,29 +1005,14 @@ struct TileLoad {
     o += j >= a8 ? d8 : 0u;
     return o;
   }
-  __device__ uint32_t index(uint32_t j) const {
-    const uint32_t i = j - offset(j, s1, s2, s3, s4, s5, s6, s7, s8);
-    return i < CAP ? i : CAP - 1;
-  }
+  __device__ uint32_t index(uint32_t j) const { return j - offset(j, s1, s2, s3, s4, s5, s6, s7, s8); }
   __device__ uint32_t slot(uint32_t t) const { return t + offset(t, b1, b2, b3, b4, b5, b6, b7, b8); }
-  __device__ Nbr operator()(uint32_t j) const {
-    const uint32_t i = index(j);
-    Nbr n;
-    n.a = T->a[i];
-    n.b = T->b[i];
-    n.c = T->c[i];
-    if constexpr (CELL) {
-      n.d = T->d[i];
-    } else {
-      n.d = make_float4(n.b.w, T->s5[i], 0.f, 0.f);
-    }
-    return n;
-  }
 };
 
-// The block's loader from its table (uniform loads).
+// The block's loader from its table (uniform loads); T may be null where only
+// the index maps are used.
 template <bool CELL, uint32_t CAP>
-__device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>& T, const uint32_t* __restrict__ tb) {
+__device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>* T, const uint32_t* __restrict__ tb) {
   uint32_t st[9], of[9], d[9], bs[9];
   uint32_t prev = tb[9];
 #pragma unroll
@@ -1000,7 +1025,7 @@ __device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>& T,
     bs[k] = none ? 0xffffffffu : st[k] - of[k];
   }
   TileLoad<CELL, CAP> l;
-  l.T = &T;
+  l.T = T;
   l.s1 = st[1]; l.s2 = st[2]; l.s3 = st[3]; l.s4 = st[4]; l.s5 = st[5]; l.s6 = st[6]; l.s7 = st[7]; l.s8 = st[8];
   l.b1 = bs[1]; l.b2 = bs[2]; l.b3 = bs[3]; l.b4 = bs[4]; l.b5 = bs[5]; l.b6 = bs[6]; l.b7 = bs[7]; l.b8 = bs[8];
   l.o0 = of[0];
@@ -1008,34 +1033,80 @@ __device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>& T,
   return l;
 }
 
+// Largest tile (records): blocks whose ranges exceed it never stage.
+constexpr uint32_t kTileMax = 1024;
+
+// Tile positions of the soil rows' list entries, once per list rebuild: the
+// entry of slot j holds 16 i (i = j's tile index: the record's byte offset in
+// each 16-byte tile plane), for the blocks whose rows lie in one row of cells
+// and whose ranges fit kTileMax records; other blocks' entries are not
+// written. A block's rows are consecutive, so their entries form one
+// contiguous range, read and written here by one workgroup.
+__global__ __launch_bounds__(kBlock) void k_tile_index(int64_t n, const uint64_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ nbr,
+                                                       const uint32_t* __restrict__ tabs,
+                                                       uint16_t* __restrict__ tix) {
+  const int64_t b = blockIdx.x;
+  const uint32_t* tb = tabs + b * kTabWords;
+  if (tb[19] == 0 || tb[18] > kTileMax) return;
+  const int64_t r0 = b * kRows;
+  const int64_t r1 = r0 + kRows < n ? r0 + kRows : n;
+  const TileLoad<false, kTileMax> ld = tile_loader<false, kTileMax>(nullptr, tb);
+  const uint64_t e1 = off[r1];
+  for (uint64_t k = off[r0] + threadIdx.x; k < e1; k += kBlock) tix[k] = (uint16_t)(ld.index(nbr[k]) << 4);
+}
+
+// A neighbour's record from the tile at byte offset o of each plane.
+template <bool CELL, uint32_t CAP>
+__device__ inline Nbr tile_rec(const StageTile<CELL, CAP>& T, uint32_t o) {
+  auto at_ = [&](const float4* p) { return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + o); };
+  Nbr n;
+  n.a = at_(T.a);
+  n.b = at_(T.b);
+  n.c = at_(T.c);
+  if constexpr (CELL) {
+    n.d = at_(T.d);
+  } else {
+    n.d = make_float4(n.b.w, *reinterpret_cast<const float*>(reinterpret_cast<const char*>(T.s5) + (o >> 2)), 0.f,
+                      0.f);
+  }
+  return n;
+}
+
 // The walk of a row through the tile, two entries per lane and iteration: both
-// tile reads are issued before either pair is computed, and the CSR indices
-// four entries ahead are in flight meanwhile (the index load from HBM/L2 is the
-// walk's longest wait). The pairs are still taken in entry order. Past the
-// row's end the walk reads its first entry again (a valid index).
-template <class Load, class Fn>
-__device__ inline void walk_row_ahead(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
-                                      Fn&& f) {
-  constexpr uint64_t G = kGroup;
-  const uint64_t kf = k0 + group_lane();
-  if (kf >= k1) return;
-  auto idx = [&](uint64_t kk) { return nbr[kk < k1 ? kk : kf]; };
-  uint64_t k = kf;
-  uint32_t j0 = idx(k), j1 = idx(k + G), j2 = idx(k + 2 * G), j3 = idx(k + 3 * G);
+// tile reads are issued before either pair is computed, and the tile positions
+// four entries ahead are in flight meanwhile (their load from HBM/L2 is the
+// walk's longest wait). The pairs are still taken in entry order. `tix` is the
+// block's first entry, e0..e1 the row's entries relative to it; past the
+// row's end the walk reads its first entry again (a valid position).
+template <bool CELL, uint32_t CAP, class Fn>
+__device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* __restrict__ tix, uint32_t e0,
+                                 uint32_t e1, Fn&& f) {
+  constexpr uint32_t G = kGroup;
+  constexpr uint32_t omax = (CAP - 1) << 4;
+  const uint32_t ef = e0 + group_lane();
+  if (ef >= e1) return;
+  auto pos = [&](uint32_t e) {
+    const uint32_t k = e < e1 ? e : ef;
+    const uint32_t o = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(tix) + 2u * k);
+    return o < omax ? o : omax;
+  };
+  uint32_t e = ef;
+  uint32_t o0 = pos(e), o1 = pos(e + G), o2 = pos(e + 2 * G), o3 = pos(e + 3 * G);
   for (;;) {
-    const bool has1 = k + G < k1;
-    const bool more = k + 2 * G < k1;
-    const uint32_t j4 = idx(k + 4 * G), j5 = idx(k + 5 * G);
-    const Nbr a = load(j0);
-    const Nbr b = load(j1);
-    f(a, j0);
-    if (has1) f(b, j1);
+    const bool has1 = e + G < e1;
+    const bool more = e + 2 * G < e1;
+    const uint32_t o4 = pos(e + 4 * G), o5 = pos(e + 5 * G);
+    const Nbr a = tile_rec(T, o0);
+    const Nbr b = tile_rec(T, o1);
+    f(a);
+    if (has1) f(b);
     if (!more) break;
-    j0 = j2;
-    j1 = j3;
-    j2 = j4;
-    j3 = j5;
-    k += 2 * G;
+    o0 = o2;
+    o1 = o3;
+    o2 = o4;
+    o3 = o5;
+    e += 2 * G;
   }
 }
 
@@ -1119,7 +1190,8 @@ template <bool CELL, bool TAPE, int CFG>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
-                                                         const uint32_t* __restrict__ tabs) {
+                                                         const uint32_t* __restrict__ tabs,
+                                                         const uint16_t* __restrict__ tix) {
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
@@ -1136,13 +1208,18 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL, CAP> tl = tile_loader(tile, tb);
+  const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
   const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl);
   Rates R;
-  if (staged)
-    R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
-  else
-    R = fluid_rhs<CELL>(ma, mb, mc, md, GlobalLoad{A}, k0, k1, nbr, P);
+  if (staged) {
+    const uint64_t kb = off[blk * kRows];
+    const uint32_t e0 = live ? uint32_t(k0 - kb) : 0u, e1 = live ? uint32_t(k1 - kb) : 0u;
+    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
+  } else {
+    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
+      walk_row_with(GlobalLoad{A}, k0, k1, nbr, [&](const Nbr& o, uint32_t) { f(o); });
+    }, P);
+  }
   if (!live) return;
   const float h = P.half_dt;
   float4 na = ma, nd = md;
@@ -1164,7 +1241,8 @@ template <bool CELL, bool TAPE, int CFG>
 __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
-                                                         const uint32_t* __restrict__ tabs) {
+                                                         const uint32_t* __restrict__ tabs,
+                                                         const uint16_t* __restrict__ tix) {
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
@@ -1181,13 +1259,18 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL, CAP> tl = tile_loader(tile, tb);
+  const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
   const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl);
   Rates R;
-  if (staged)
-    R = fluid_rhs<CELL>(ma, mb, mc, md, tl, k0, k1, nbr, P);
-  else
-    R = fluid_rhs<CELL>(ma, mb, mc, md, GlobalLoad{B}, k0, k1, nbr, P);
+  if (staged) {
+    const uint64_t kb = off[blk * kRows];
+    const uint32_t e0 = live ? uint32_t(k0 - kb) : 0u, e1 = live ? uint32_t(k1 - kb) : 0u;
+    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
+  } else {
+    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
+      walk_row_with(GlobalLoad{B}, k0, k1, nbr, [&](const Nbr& o, uint32_t) { f(o); });
+    }, P);
+  }
   if (!live) return;
   // Every lane loads the whole y_n record and computes the whole y_{n+1}
   // record; one store then writes plane gl from lane gl < 4. The return
@@ -1318,6 +1401,11 @@ hipError_t compact_kind(const float4* pos4, int64_t n, uint32_t kind, int32_t* r
   return compact_impl(PredKind{pos4, kind}, n, rows, count_dst, tmp, s);
 }
 
+hipError_t compact_nonzero(const uint32_t* cnt, int64_t n, int32_t* rows, uint64_t* count_dst, uint32_t* tmp,
+                           hipStream_t s) {
+  return compact_impl(PredNonzero{cnt}, n, rows, count_dst, tmp, s);
+}
+
 hipError_t hash_count(const int32_t* ids, int64_t n, const float4* m_a, const float4* m_d, Grid g, uint32_t* key,
                       uint32_t* rank, uint32_t* cnt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -1363,28 +1451,33 @@ hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, con
   return hipGetLastError();
 }
 
-hipError_t place_markers_working(const int32_t* mrows, int64_t n, const int32_t* slot_id, int64_t n_soil,
-                                 const float4* local, const Body* bodies, Grid g, Planes A, Planes B, hipStream_t s) {
+hipError_t place_markers_working(const int32_t* mrows, int64_t n, const uint32_t* cnt, const int32_t* slot_id,
+                                 int64_t n_soil, const float4* local, const Body* bodies, Grid g, Phys P, Planes A,
+                                 Planes B, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_place_markers_working<<<nblk(n), kBlock, 0, s>>>(mrows, n, slot_id, n_soil, local, bodies, g, A, B);
+  if (g.cell)
+    k_place_markers_working<true><<<nblk(n), kBlock, 0, s>>>(mrows, n, cnt, slot_id, n_soil, local, bodies, g, P, A, B);
+  else
+    k_place_markers_working<false><<<nblk(n), kBlock, 0, s>>>(mrows, n, cnt, slot_id, n_soil, local, bodies, g, P, A,
+                                                              B);
   return hipGetLastError();
 }
 
-hipError_t bce(Planes S, const int32_t* mrows, int64_t n, const uint64_t* off, const uint32_t* nbr,
-               const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
+hipError_t bce(Planes S, const int32_t* mrows, const int32_t* near, int64_t n, const uint64_t* off,
+               const uint32_t* nbr, const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
                hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned gsz = nblk_groups(n);
   if (P.cell) {
     if (contrib)
-      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, contrib);
+      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, nullptr);
+      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, nullptr);
   } else {
     if (contrib)
-      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, contrib);
+      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, n, off, nbr, bodies, cidx, cbase, P, nullptr);
+      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, nullptr);
   }
   return hipGetLastError();
 }
@@ -1407,53 +1500,62 @@ hipError_t tile_tables(const int32_t* rows, int64_t n, const uint32_t* skey, con
   return hipGetLastError();
 }
 
+hipError_t tile_index(int64_t n, const uint64_t* off, const uint32_t* nbr, const uint32_t* tabs, uint16_t* tix,
+                      hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_tile_index<<<(unsigned)((n + kRows - 1) / kRows), kBlock, 0, s>>>(n, off, nbr, tabs, tix);
+  return hipGetLastError();
+}
+
 int64_t tile_table_words(int64_t rows_cap) { return ((rows_cap + kRows - 1) / kRows + 1) * kTabWords; }
 
 template <int CFG>
 void launch_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
-                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, hipStream_t s) {
+                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, const uint16_t* tix,
+                   hipStream_t s) {
   const unsigned g = nblk_groups(n);
   if (P.cell) {
-    if (tape) k_fluid_stage1<true, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage1<true, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    if (tape) k_fluid_stage1<true, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage1<true, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
   } else {
-    if (tape) k_fluid_stage1<false, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage1<false, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs);
+    if (tape) k_fluid_stage1<false, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage1<false, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
   }
 }
 
 template <int CFG>
 void launch_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
-                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, hipStream_t s) {
+                   const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, const uint16_t* tix,
+                   hipStream_t s) {
   const unsigned g = nblk_groups(n);
   if (P.cell) {
-    if (tape) k_fluid_stage2<true, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage2<true, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    if (tape) k_fluid_stage2<true, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage2<true, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
   } else {
-    if (tape) k_fluid_stage2<false, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
-    else k_fluid_stage2<false, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs);
+    if (tape) k_fluid_stage2<false, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage2<false, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
   }
 }
 
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
-                        hipStream_t s) {
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint16_t* tix, int cfg, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
-  if (cfg == 0) launch_stage1<0>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
-  else if (cfg == 1) launch_stage1<1>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
-  else launch_stage1<2>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  if (cfg == 0) launch_stage1<0>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
+  else if (cfg == 1) launch_stage1<1>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
+  else launch_stage1<2>(A, B, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
   return hipGetLastError();
 }
 
 hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off,
-                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs, int cfg,
-                        hipStream_t s) {
+                        const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
+                        const uint16_t* tix, int cfg, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const StageTape T = tape ? *tape : StageTape{};
-  if (cfg == 0) launch_stage2<0>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
-  else if (cfg == 1) launch_stage2<1>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
-  else launch_stage2<2>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, s);
+  if (cfg == 0) launch_stage2<0>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
+  else if (cfg == 1) launch_stage2<1>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
+  else launch_stage2<2>(B, A, rows, n, off, nbr, P, T, tape != nullptr, tabs, tix, s);
   return hipGetLastError();
 }
 
