@@ -795,6 +795,9 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   g.R2 = radius * radius;
   g.ext = radius;
   g.S = radius;
+  g.Sf = (float)radius;
+  g.R2lo = std::nextafter((float)(g.R2 * (1.0 - 0x1p-14)), 0.0f);
+  g.R2hi = std::nextafter((float)(g.R2 * (1.0 + 0x1p-14)), INFINITY);
   g.cell = params->pos_mode == CRM_POS_CELL_OFFSET ? 1 : 0;
   int64_t M = 1;
   for (int a = 0; a < 3; ++a) {

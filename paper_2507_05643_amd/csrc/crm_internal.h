@@ -62,6 +62,11 @@ struct Grid {
   double S;       // cell size 2h
   int32_t dims[3];
   int32_t cell;   // positions stored as cell index + FP32 offset
+  // FP32 pre-test of the list radius: an FP32 squared distance below R2lo
+  // (above R2hi) is one whose FP64 value is below (above) R2; R2 (1 -+ 2^-14),
+  // rounded outwards, far wider than the FP32 rounding of the distance.
+  float R2lo, R2hi;
+  float Sf;       // S rounded to FP32
 };
 
 // Cell-offset positions: cx is kept in d.z, cy and cz as two 16-bit signed

@@ -441,10 +441,18 @@ __device__ inline double dist2_cell(float4 pi, int4 ci, float4 pj, int4 cj, doub
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-template <bool FILL>
+// The group's scan of the 27 cells around cell c for the neighbours of a row
+// at (pi, ci). Every candidate is first tested in FP32 against the widened
+// radius band [R2lo, R2hi]; only a distance inside the band takes the exact
+// FP64 test, so every decision is that of the FP64 test. The FP32 distance
+// is within a few FP32 ulps of the exact one: |dx| rounds once (FP32 mode),
+// or to within (|dc| + 2) ulps of S (cell mode, dc the cell difference of
+// the stored positions), and squaring and summing add a few ulps of the result;
+// the band's half-width 2^-14 R2 exceeds these bounds by far.
+template <bool FILL, bool CELL, bool SOIL_ONLY>
 __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const float4* __restrict__ pos4,
                                       const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
-                                      const Grid& g, bool soil_only, uint32_t* __restrict__ out, uint32_t limit) {
+                                      const Grid& g, uint32_t* __restrict__ out, uint32_t limit) {
   const int X = g.dims[0], Y = g.dims[1], Z = g.dims[2];
   const int gl = group_lane();
   int cx = 0, cy = 0, cz = 0;
@@ -456,6 +464,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
   }
   const int x0 = cx > 0 ? cx - 1 : 0;
   const int x1 = cx < X - 1 ? cx + 1 : X - 1;
+  const float lo2 = g.R2lo, hi2 = g.R2hi, Sf = g.Sf;
   uint32_t count = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     for (int dy = -1; dy <= 1; ++dy) {
@@ -470,15 +479,26 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         const uint32_t j = j0 + gl;
         bool hit = false;
         if (j < e) {
-          const float4 pj = pos4[j];
-          if (!(soil_only && (__float_as_uint(pj.w) & 3u) == kMarker))
-            hit = (g.cell ? dist2_cell(pi, ci, pj, cpos[j], g.S) : dist2_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z)) <
-                  g.R2;
+          const float4 pj = at(pos4, j);
+          if (!SOIL_ONLY || (__float_as_uint(pj.w) & 3u) != kMarker) {
+            float sx = pi.x - pj.x, sy = pi.y - pj.y, sz = pi.z - pj.z;
+            int4 cj = make_int4(0, 0, 0, 0);
+            if (CELL) {
+              cj = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(cpos) + (j << 4));
+              sx += (float)(ci.x - cj.x) * Sf;
+              sy += (float)(ci.y - cj.y) * Sf;
+              sz += (float)(ci.z - cj.z) * Sf;
+            }
+            const float d2 = sx * sx + sy * sy + sz * sz;
+            hit = d2 < lo2;
+            if (!hit && d2 <= hi2)
+              hit = (CELL ? dist2_cell(pi, ci, pj, cj, g.S) : dist2_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z)) < g.R2;
+          }
         }
         const uint32_t m = group_bits(__ballot(hit));
         if (FILL && hit) {
-          const uint32_t at = count + __popc(m & ((1u << gl) - 1u));
-          if (at < limit) out[at] = j;
+          const uint32_t at_ = count + __popc(m & ((1u << gl) - 1u));
+          if (at_ < limit) out[at_] = j;
         }
         count += __popc(m);
       }
@@ -487,12 +507,27 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
   return count;
 }
 
+// The row scan with the position form and the candidate filter as template
+// arguments (uniform over a launch).
+template <bool FILL>
+__device__ inline uint32_t group_scan_any(bool live, float4 pi, int4 ci, uint32_t c, const float4* __restrict__ pos4,
+                                          const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
+                                          const Grid& g, bool soil_only, uint32_t* __restrict__ out, uint32_t limit) {
+  if (g.cell) {
+    return soil_only ? group_scan<FILL, true, true>(live, pi, ci, c, pos4, cpos, cs, g, out, limit)
+                     : group_scan<FILL, true, false>(live, pi, ci, c, pos4, cpos, cs, g, out, limit);
+  }
+  return soil_only ? group_scan<FILL, false, true>(live, pi, ci, c, pos4, cpos, cs, g, out, limit)
+                   : group_scan<FILL, false, false>(live, pi, ci, c, pos4, cpos, cs, g, out, limit);
+}
+
 // Count pass: counts every row's neighbours and keeps the first kStash of them
 // in a fixed-stride scratch, so that the fill pass is a copy (rows with more
 // are scanned again there). The grid covers rows_cap rows; the live row count
 // is read on the device and only the blocks that carry live rows are spread
 // over the XCDs.
 constexpr uint32_t kStash = 80;
+static_assert(kStash % kGroup == 0, "whole stash rows per lane");
 
 __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict__ rows, int64_t rows_cap,
                                                       const uint64_t* __restrict__ n_rows_dev,
@@ -515,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict_
     c = skey[s];
     out = stash + (uint64_t)r * kStash;
   }
-  const uint32_t count = group_scan<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, out, kStash);
+  const uint32_t count = group_scan_any<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, out, kStash);
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
@@ -531,14 +566,26 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__
   const uint32_t count = live ? cnt[r] : 0u;
   const bool rescan = count > kStash;                 // uniform within the group
   if (live && !rescan) {
+    // all of the lane's stashed entries are loaded before any is stored
     const uint64_t base = off[r];
     const uint32_t* src = stash + (uint64_t)r * kStash;
-    for (uint32_t k = group_lane(); k < count; k += kGroup) nbr[base + k] = src[k];
+    constexpr int kPer = (int)(kStash / kGroup);
+    uint32_t v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+      v[q] = k < count ? src[k] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+      if (k < count) nbr[base + k] = v[q];
+    }
   }
   if (rescan) {
     const int32_t s = rows[r];
     const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
-    group_scan<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, soil_only != 0, nbr + off[r], 0xffffffffu);
+    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, soil_only != 0, nbr + off[r], 0xffffffffu);
   }
 }
 

@@ -83,6 +83,31 @@ def test_neighbour_lists_bit_exact(crm):
         sim.close()
 
 
+@pytest.mark.parametrize("pos_mode", [0, 1])
+def test_lists_exact_on_the_radius(crm, pos_mode):
+    """An unjittered lattice with 2h = 2 dx: every axis pair two spacings
+    apart lies on the list radius, where the kernels' FP32 pre-test defers to
+    the exact FP64 test; the lists still equal the oracle's bit for bit."""
+    sc = scenes.column(seed=0, n=10, jitter=0.0, pos_mode=pos_mode)
+    sc.params["h"] = sc.params["dx"]
+    x = world_positions(sc)
+    R2 = (2.0 * sc.params["h"]) ** 2
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    on_radius = int((np.abs(d2 / R2 - 1.0) < 2.0 ** -14).sum())
+    say("pairs on the radius", on_radius)
+    assert on_radius > 1000
+    sim = _sim(crm, sc)
+    sim.step(1)
+    ex = sim.export()
+    off, nbr = O.neighbors(sc.params, x, mode="cells")
+    ref = csr_rows(off, nbr)
+    got = csr_rows(ex["off"], ex["nbr"], ex["rows"])
+    for i in range(sc.n_total):
+        want = ref[i] if i < sc.n_soil else ref[i][ref[i] < sc.n_soil]
+        assert np.array_equal(got[i], want), i
+    sim.close()
+
+
 def _run_pair(crm, sc, steps, nbr_mode="cells"):
     sim = _sim(crm, sc)
     orc = Oracle(sc, nbr_mode=nbr_mode)
