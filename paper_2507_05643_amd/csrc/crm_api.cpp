@@ -512,8 +512,9 @@ crm_status rebuild(crm_ctx* c) {
                                c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
-  HIPCHK(c, crm::nbr_count(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
-                           false, c->cnt_f, c->stash_f, s));
+  HIPCHK(c, crm::tile_tables(c->frows, n_proc, c->d_counts + 1, c->skey, c->cell_start, c->phys, c->tabs, s));
+  HIPCHK(c, crm::nbr_count_soil(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
+                                c->tabs, c->cnt_f, c->stash_f, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->cnt_f, c->off_f, n_proc, c->wtmp, s));
   HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
                            true, c->cnt_m, c->stash_m, s));
@@ -546,7 +547,6 @@ crm_status rebuild(crm_ctx* c) {
                           c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
-  HIPCHK(c, crm::tile_tables(c->frows, c->n_frows, c->skey, c->cell_start, c->phys, c->tabs, s));
   HIPCHK(c, crm::tile_index(c->n_frows, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
   // per-body ranges of the processed markers for the force sums
   c->kbase = c->n_proc - c->n_mrows;

@@ -169,6 +169,12 @@ hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_ro
                      const float4* pos4, const int4* cpos, const uint32_t* skey,
                      const uint32_t* cell_start, Grid g, bool soil_only, uint32_t* cnt, uint32_t* stash,
                      hipStream_t s);
+// The count pass of the soil rows (not soil-only) with each block's
+// candidates staged in LDS through the tile tables (tile_tables, computed for
+// the same rows and device count before it); same results as nbr_count.
+hipError_t nbr_count_soil(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
+                          const int4* cpos, const uint32_t* skey, const uint32_t* cell_start, Grid g,
+                          const uint32_t* tabs, uint32_t* cnt, uint32_t* stash, hipStream_t s);
 hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos,
                     const uint32_t* skey, const uint32_t* cell_start, Grid g, bool soil_only,
                     const uint32_t* cnt, const uint32_t* stash, const uint64_t* off, uint32_t* nbr,
@@ -232,10 +238,10 @@ hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_fro
                         const uint32_t* nbr, Phys P, const StageTape* tape, const uint32_t* tabs,
                         const uint16_t* tix, int cfg, hipStream_t s);
 // Per block of soil rows: the nine slot ranges its rows' neighbours lie in
-// (tile_table_words(rows_cap) words).
+// (tile_table_words(rows_cap) words); the row count is read on the device.
 int64_t tile_table_words(int64_t rows_cap);
-hipError_t tile_tables(const int32_t* frows, int64_t n_frows, const uint32_t* skey, const uint32_t* cell_start,
-                       Phys P, uint32_t* tabs, hipStream_t s);
+hipError_t tile_tables(const int32_t* frows, int64_t rows_cap, const uint64_t* n_frows_dev, const uint32_t* skey,
+                       const uint32_t* cell_start, Phys P, uint32_t* tabs, hipStream_t s);
 // Tile position (16-bit) of each soil-row list entry of the blocks that can
 // stage their neighbours (one entry per nbr entry; the others untouched).
 hipError_t tile_index(int64_t n_frows, const uint64_t* off, const uint32_t* nbr, const uint32_t* tabs,

@@ -449,10 +449,22 @@ __device__ inline double dist2_cell(float4 pi, int4 ci, float4 pj, int4 cj, doub
 // or to within (|dc| + 2) ulps of S (cell mode, dc the cell difference of
 // the stored positions), and squaring and summing add a few ulps of the result;
 // the band's half-width 2^-14 R2 exceeds these bounds by far.
-template <bool FILL, bool CELL, bool SOIL_ONLY>
-__device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const float4* __restrict__ pos4,
-                                      const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
-                                      const Grid& g, uint32_t* __restrict__ out, uint32_t limit) {
+// Candidate j of the (dz, dy) run k = 3 (dz + 1) + dy + 1, straight from the
+// planes.
+template <bool CELL>
+struct ScanLoad {
+  const float4* pos4;
+  const int4* cpos;
+  __device__ void operator()(uint32_t j, int, float4& p, int4& cj) const {
+    p = at(pos4, j);
+    if (CELL) cj = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(cpos) + (j << 4));
+  }
+};
+
+template <bool FILL, bool CELL, bool SOIL_ONLY, class Load>
+__device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const Load& load,
+                                      const uint32_t* __restrict__ cs, const Grid& g, uint32_t* __restrict__ out,
+                                      uint32_t limit) {
   const int X = g.dims[0], Y = g.dims[1], Z = g.dims[2];
   const int gl = group_lane();
   int cx = 0, cy = 0, cz = 0;
@@ -468,6 +480,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
   uint32_t count = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     for (int dy = -1; dy <= 1; ++dy) {
+      const int k = 3 * (dz + 1) + dy + 1;
       const int z = cz + dz, y = cy + dy;
       uint32_t b = 0, e = 0;
       if (live && z >= 0 && z < Z && y >= 0 && y < Y) {
@@ -479,12 +492,12 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         const uint32_t j = j0 + gl;
         bool hit = false;
         if (j < e) {
-          const float4 pj = at(pos4, j);
+          float4 pj;
+          int4 cj = make_int4(0, 0, 0, 0);
+          load(j, k, pj, cj);
           if (!SOIL_ONLY || (__float_as_uint(pj.w) & 3u) != kMarker) {
             float sx = pi.x - pj.x, sy = pi.y - pj.y, sz = pi.z - pj.z;
-            int4 cj = make_int4(0, 0, 0, 0);
             if (CELL) {
-              cj = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(cpos) + (j << 4));
               sx += (float)(ci.x - cj.x) * Sf;
               sy += (float)(ci.y - cj.y) * Sf;
               sz += (float)(ci.z - cj.z) * Sf;
@@ -514,11 +527,13 @@ __device__ inline uint32_t group_scan_any(bool live, float4 pi, int4 ci, uint32_
                                           const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
                                           const Grid& g, bool soil_only, uint32_t* __restrict__ out, uint32_t limit) {
   if (g.cell) {
-    return soil_only ? group_scan<FILL, true, true>(live, pi, ci, c, pos4, cpos, cs, g, out, limit)
-                     : group_scan<FILL, true, false>(live, pi, ci, c, pos4, cpos, cs, g, out, limit);
+    const ScanLoad<true> ld{pos4, cpos};
+    return soil_only ? group_scan<FILL, true, true>(live, pi, ci, c, ld, cs, g, out, limit)
+                     : group_scan<FILL, true, false>(live, pi, ci, c, ld, cs, g, out, limit);
   }
-  return soil_only ? group_scan<FILL, false, true>(live, pi, ci, c, pos4, cpos, cs, g, out, limit)
-                   : group_scan<FILL, false, false>(live, pi, ci, c, pos4, cpos, cs, g, out, limit);
+  const ScanLoad<false> ld{pos4, cpos};
+  return soil_only ? group_scan<FILL, false, true>(live, pi, ci, c, ld, cs, g, out, limit)
+                   : group_scan<FILL, false, false>(live, pi, ci, c, ld, cs, g, out, limit);
 }
 
 // Count pass: counts every row's neighbours and keeps the first kStash of them
@@ -990,10 +1005,12 @@ constexpr uint32_t tile_cap() {
 // its tile when they do and the total fits the tile.
 constexpr int kTabWords = 20;
 
-__global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows,
+                                                        const uint64_t* __restrict__ n_dev,
                                                         const uint32_t* __restrict__ skey,
                                                         const uint32_t* __restrict__ cs, Phys P,
                                                         uint32_t* __restrict__ tabs) {
+  const int64_t n = (int64_t)*n_dev;
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t r0 = b * kRows;
   if (r0 >= n) return;
@@ -1100,7 +1117,119 @@ __global__ __launch_bounds__(kBlock) void k_tile_index(int64_t n, const uint64_t
   const int64_t r1 = r0 + kRows < n ? r0 + kRows : n;
   const TileLoad<false, kTileMax> ld = tile_loader<false, kTileMax>(nullptr, tb);
   const uint64_t e1 = off[r1];
-  for (uint64_t k = off[r0] + threadIdx.x; k < e1; k += kBlock) tix[k] = (uint16_t)(ld.index(nbr[k]) << 4);
+  // eight entries per thread and pass, all loaded before any is converted
+  constexpr int kPer = 8;
+  for (uint64_t k0 = off[r0] + threadIdx.x; k0 < e1; k0 += (uint64_t)kPer * kBlock) {
+    uint32_t v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint64_t k = k0 + (uint64_t)q * kBlock;
+      v[q] = k < e1 ? nbr[k] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint64_t k = k0 + (uint64_t)q * kBlock;
+      if (k < e1) tix[k] = (uint16_t)(ld.index(v[q]) << 4);
+    }
+  }
+}
+
+// ------------------------------------------- LDS-staged neighbour count ---
+// The count pass of the soil rows with the candidates of each block's nine
+// ranges staged in LDS (positions, and cells with cell-offset positions): a
+// row's run of candidates in cells x - 1 .. x + 1 of one (y, z) row lies
+// inside the block's range of that (y, z) row, at tile index slot - o_k. Blocks
+// whose rows span two cell rows, or whose ranges exceed kScanCap records,
+// read the candidates from the planes.
+constexpr uint32_t kScanCap = 1024;
+
+template <bool CELL>
+struct ScanTile;
+template <>
+struct ScanTile<false> {
+  float4 p[kScanCap];
+};
+template <>
+struct ScanTile<true> {
+  float4 p[kScanCap];
+  int4 c[kScanCap];
+};
+
+template <bool CELL>
+struct ScanTileLoad {
+  const ScanTile<CELL>* T;
+  uint32_t o[9];
+  __device__ void operator()(uint32_t j, int k, float4& p, int4& cj) const {
+    const uint32_t t = j - o[k];
+    p = T->p[t];
+    if constexpr (CELL) cj = T->c[t];
+  }
+};
+
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __restrict__ rows, int64_t rows_cap,
+                                                           const uint64_t* __restrict__ n_rows_dev,
+                                                           const float4* __restrict__ pos4,
+                                                           const int4* __restrict__ cpos,
+                                                           const uint32_t* __restrict__ skey,
+                                                           const uint32_t* __restrict__ cs, Grid g,
+                                                           const uint32_t* __restrict__ tabs,
+                                                           uint32_t* __restrict__ cnt, uint32_t* __restrict__ stash) {
+  __shared__ ScanTile<CELL> tile;
+  const int64_t nr = (int64_t)*n_rows_dev;
+  const int64_t nb_live = (nr * kGroup + kBlock - 1) / kBlock;
+  const int64_t blk = xcd_block_n(nb_live);
+  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
+  const bool live = r < nr;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  int4 ci = make_int4(0, 0, 0, 0);
+  uint32_t c = 0;
+  uint32_t* out = stash;
+  if (live) {
+    const int32_t s = rows[r];
+    pi = pos4[s];
+    if (CELL) ci = cpos[s];
+    c = skey[s];
+    out = stash + (uint64_t)r * kStash;
+  }
+  bool staged = false;
+  ScanTileLoad<CELL> tl;
+  tl.T = &tile;
+  if (blk < nb_live) {                      // uniform over the block
+    const uint32_t* tb = tabs + blk * kTabWords;
+    const uint32_t total = tb[18];
+    staged = tb[19] != 0 && total <= kScanCap;
+    if (staged) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) tl.o[k] = tb[9 + k];
+      const TileLoad<false, kTileMax> ld = tile_loader<false, kTileMax>(nullptr, tb);
+      constexpr int kPer = (int)(kScanCap / kBlock);
+      float4 p[kPer];
+      int4 q[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t t = threadIdx.x + (uint32_t)(u * kBlock);
+        if (t < total) {
+          const uint32_t j = ld.slot(t);
+          p[u] = pos4[j];
+          if (CELL) q[u] = cpos[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t t = threadIdx.x + (uint32_t)(u * kBlock);
+        if (t < total) {
+          tile.p[t] = p[u];
+          if constexpr (CELL) tile.c[t] = q[u];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t count = staged ? group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, out, kStash)
+                                : group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g,
+                                                                out, kStash);
+  if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
 // A neighbour's record from the tile at byte offset o of each plane.
@@ -1489,6 +1618,19 @@ hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_ro
   return hipGetLastError();
 }
 
+hipError_t nbr_count_soil(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
+                          const int4* cpos, const uint32_t* skey, const uint32_t* cs, Grid g, const uint32_t* tabs,
+                          uint32_t* cnt, uint32_t* stash, hipStream_t s) {
+  if (rows_cap <= 0) return hipSuccess;
+  if (g.cell)
+    k_nbr_count_soil<true><<<nblk_groups(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs, g,
+                                                                    tabs, cnt, stash);
+  else
+    k_nbr_count_soil<false><<<nblk_groups(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs,
+                                                                     g, tabs, cnt, stash);
+  return hipGetLastError();
+}
+
 hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos, const uint32_t* skey,
                     const uint32_t* cs, Grid g, bool soil_only, const uint32_t* cnt, const uint32_t* stash,
                     const uint64_t* off, uint32_t* nbr, hipStream_t s) {
@@ -1539,11 +1681,11 @@ hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hi
   return hipGetLastError();
 }
 
-hipError_t tile_tables(const int32_t* rows, int64_t n, const uint32_t* skey, const uint32_t* cs, Phys P,
-                       uint32_t* tabs, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t nb = (n + kRows - 1) / kRows;
-  k_tile_tables<<<nblk(nb), kBlock, 0, s>>>(rows, n, skey, cs, P, tabs);
+hipError_t tile_tables(const int32_t* rows, int64_t rows_cap, const uint64_t* n_dev, const uint32_t* skey,
+                       const uint32_t* cs, Phys P, uint32_t* tabs, hipStream_t s) {
+  if (rows_cap <= 0) return hipSuccess;
+  const int64_t nb = (rows_cap + kRows - 1) / kRows;
+  k_tile_tables<<<nblk(nb), kBlock, 0, s>>>(rows, n_dev, skey, cs, P, tabs);
   return hipGetLastError();
 }
 
