@@ -850,6 +850,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     ph.kf = (float)(1.0 / (pi * h3 * h2));
     ph.kg = (float)(1.0 / (pi * h3 * h2 * h2));
   }
+  ph.h = (float)P.h;
   ph.dt = (float)P.dt;
   ph.half_dt = (float)(0.5 * P.dt);
   ph.gx = (float)P.gravity[0];

@@ -176,6 +176,15 @@ __device__ inline float sph_f(float q, const Phys& P) {
   return P.kern == 1 ? wendland_f(q, P.kf) : kernel_f(q, P.kf);
 }
 
+// The same with 1 / q supplied (iq; only the cubic's outer piece uses it).
+__device__ inline float sph_f_iq(float q, float iq, const Phys& P) {
+  if (P.kern == 1) return wendland_f(q, P.kf);
+  const float t = fmaxf(2.0f - q, 0.0f);
+  const float outer = -0.75f * P.kf * t * t * iq;
+  const float inner = P.kf * (2.25f * q - 3.0f);
+  return q < 1.0f ? inner : outer;
+}
+
 // A neighbour's record, loaded from the four planes with a 32-bit byte offset
 // from each plane's base (slots < 2^28).
 struct Nbr {

@@ -80,6 +80,7 @@ __host__ __device__ inline int32_t unpack_z(uint32_t w) { return (int32_t)(int16
 // FP32 constants of the stage kernels.
 struct Phys {
   float inv_h;
+  float h;
   float kw;       // W = kw * w(q) (cubic: 1 / (pi h^3); Wendland: 21 / (16 pi h^3))
   float kf;       // grad W = kf * f(q) * (x_i - x_j) (cubic: 1 / (pi h^5); Wendland: 5 kw / h^2)
   float dt, half_dt;

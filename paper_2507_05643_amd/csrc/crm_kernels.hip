@@ -862,7 +862,11 @@ struct Rates {
 // with the sign that repels approaching pairs); ds/dt = Om s - s Om + 2G D +
 // (bulk K - 2G/3) tr D I with D, Om the symmetric and skew parts of L.
 // The group's lanes take the row's neighbours k = lane, lane + kGroup, ...;
-// walk(pair) calls pair(record) for each of the lane's neighbours.
+// walk(pair) calls pair(record) for each of the lane's neighbours, with the
+// neighbour's volume V_j = m / rho_j in place of its density (a.w). One
+// reciprocal square root gives q and 1 / q; with rho_j = m / V_j the
+// viscosity's mean density enters as 1 / rho_bar = 2 V_j / (rho_i V_j + m).
+// The own stress's share of F3 is s_i . sum_j V_j gradW, taken once per row.
 template <bool CELL, class Walk>
 __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Walk&& walk, const Phys& P) {
   const Own me = own_pos<CELL>(ma, md);
@@ -871,26 +875,29 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
   const float s0 = mc.x, s1 = mc.y, s2 = mc.z, s3 = mc.w, s4 = md.x, s5 = md.y;
   float L00 = 0.f, L01 = 0.f, L02 = 0.f, L10 = 0.f, L11 = 0.f, L12 = 0.f, L20 = 0.f, L21 = 0.f, L22 = 0.f;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum_j V_j grad_i W_ij (sigma_i's share of F3, applied once per row)
+  const float av2 = 2.0f * P.av_coef;
   auto pair = [&](const Nbr& o) {
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
-    const float q = fsqrt(r2) * P.inv_h;
-    const float F = sph_f(q, P);
-    const float VF = P.m * __builtin_amdgcn_rcpf(o.a.w) * F;   // V_j * (gradW / r_ij)
+    const float rs = __builtin_amdgcn_rsqf(fmaxf(r2, 1.0e-30f));   // 1 / r (finite for the self pair)
+    const float q = r2 * rs * P.inv_h;
+    const float F = sph_f_iq(q, P.h * rs, P);
+    const float V = o.a.w;
+    const float VF = V * F;                                       // V_j * (gradW / r_ij)
     const float wx = VF * dx, wy = VF * dy, wz = VF * dz;       // V_j grad_i W_ij
     const float dux = o.b.x - ux, duy = o.b.y - uy, duz = o.b.z - uz;
     L00 += dux * wx; L01 += dux * wy; L02 += dux * wz;
     L10 += duy * wx; L11 += duy * wy; L12 += duy * wz;
     L20 += duz * wx; L21 += duz * wy; L22 += duz * wz;
-    const float sxx = s0 + o.c.x, syy = s1 + o.c.y, szz = s2 + o.c.z;
-    const float sxy = s3 + o.c.w, sxz = s4 + o.d.x, syz = s5 + o.d.y;
-    a0 += sxx * wx + sxy * wy + sxz * wz;
-    a1 += sxy * wx + syy * wy + syz * wz;
-    a2 += sxz * wx + syz * wy + szz * wz;
+    g0 += wx; g1 += wy; g2 += wz;
+    a0 += o.c.x * wx + o.c.w * wy + o.d.x * wz;
+    a1 += o.c.w * wx + o.c.y * wy + o.d.y * wz;
+    a2 += o.d.x * wx + o.d.y * wy + o.c.z * wz;
     const float vr = -(dux * dx + duy * dy + duz * dz);         // v_ij . r_ij
     const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
-    const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhoi + o.a.w) * (r2 + P.xi2)) : 0.f;
+    const float cf = av ? av2 * vr * VF * __builtin_amdgcn_rcpf((rhoi * V + P.m) * (r2 + P.xi2)) : 0.f;
     v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
   };
   walk(pair);
@@ -899,6 +906,10 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
   L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
   a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
   v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
+  g0 = group_sum(g0); g1 = group_sum(g1); g2 = group_sum(g2);
+  a0 += s0 * g0 + s3 * g1 + s4 * g2;
+  a1 += s3 * g0 + s1 * g1 + s5 * g2;
+  a2 += s4 * g0 + s5 * g1 + s2 * g2;
   Rates R;
   const float ir = 1.0f / rhoi;
   R.dx = ux; R.dy = uy; R.dz = uz;
@@ -1306,10 +1317,13 @@ __device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL, CAP>& ld, uint32_
   return r;
 }
 
+// The tile holds the neighbour's volume m / rho in place of its density.
+__device__ inline float volume(float m, float rho) { return m * __builtin_amdgcn_rcpf(rho); }
+
 template <bool CELL, uint32_t CAP>
-__device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t t, uint32_t total) {
+__device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t t, uint32_t total, float m) {
   if (t >= total) return;
-  T.a[t] = r.a;
+  T.a[t] = make_float4(r.a.x, r.a.y, r.a.z, volume(m, r.a.w));
   T.c[t] = r.c;
   if constexpr (CELL) {
     T.b[t] = r.b;
@@ -1325,7 +1339,7 @@ __device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t
 // calls it; returns whether the block uses the tile.
 template <bool CELL, uint32_t CAP>
 __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint32_t* __restrict__ tb,
-                                  const TileLoad<CELL, CAP>& ld) {
+                                  const TileLoad<CELL, CAP>& ld, float m) {
   static_assert(CAP <= 4 * kBlock, "four records per thread");
   const uint32_t total = tb[18];
   const bool ok = tb[19] != 0 && total <= CAP;
@@ -1335,10 +1349,10 @@ __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint
     const Rec r1 = rec_load(S, ld, t0 + kBlock, total);
     const Rec r2 = rec_load(S, ld, t0 + 2 * kBlock, total);
     const Rec r3 = rec_load(S, ld, t0 + 3 * kBlock, total);
-    rec_store(T, r0, t0, total);
-    rec_store(T, r1, t0 + kBlock, total);
-    rec_store(T, r2, t0 + 2 * kBlock, total);
-    rec_store(T, r3, t0 + 3 * kBlock, total);
+    rec_store(T, r0, t0, total, m);
+    rec_store(T, r1, t0 + kBlock, total, m);
+    rec_store(T, r2, t0 + 2 * kBlock, total, m);
+    rec_store(T, r3, t0 + 3 * kBlock, total, m);
   }
   __syncthreads();
   return ok;
@@ -1385,7 +1399,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
   }
   const uint32_t* tb = tabs + blk * kTabWords;
   const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
-  const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl);
+  const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl, P.m);
   Rates R;
   if (staged) {
     const uint64_t kb = off[blk * kRows];
@@ -1393,7 +1407,11 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
   } else {
     R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
-      walk_row_with(GlobalLoad{A}, k0, k1, nbr, [&](const Nbr& o, uint32_t) { f(o); });
+      walk_row_with(GlobalLoad{A}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+        Nbr v = o;
+        v.a.w = volume(P.m, o.a.w);
+        f(v);
+      });
     }, P);
   }
   if (!live) return;
@@ -1436,7 +1454,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   }
   const uint32_t* tb = tabs + blk * kTabWords;
   const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
-  const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl);
+  const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl, P.m);
   Rates R;
   if (staged) {
     const uint64_t kb = off[blk * kRows];
@@ -1444,7 +1462,11 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
   } else {
     R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
-      walk_row_with(GlobalLoad{B}, k0, k1, nbr, [&](const Nbr& o, uint32_t) { f(o); });
+      walk_row_with(GlobalLoad{B}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+        Nbr v = o;
+        v.a.w = volume(P.m, o.a.w);
+        f(v);
+      });
     }, P);
   }
   if (!live) return;
