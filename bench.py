@@ -57,22 +57,27 @@ class WheelDriver:
         self.x = np.array(scene.bodies[1].pos, dtype=np.float64)
         self.vz = 0.0
         self.theta = 0.0
+        nb = len(self.bodies)
+        self._pos = np.array([b.pos for b in self.bodies], dtype=np.float64)
+        self._quat = np.tile([1.0, 0.0, 0.0, 0.0], (nb, 1))
+        self._lin = np.zeros((nb, 3))
+        self._ang = np.zeros((nb, 3))
+        self._ang[1, 1] = self.omega
 
     def state(self):
-        nb = len(self.bodies)
-        pos = np.array([b.pos for b in self.bodies], dtype=np.float64)
-        quat = np.tile([1.0, 0.0, 0.0, 0.0], (nb, 1))
-        lin = np.zeros((nb, 3))
-        ang = np.zeros((nb, 3))
-        pos[1] = self.x
-        quat[1] = [math.cos(0.5 * self.theta), 0.0, math.sin(0.5 * self.theta), 0.0]
-        lin[1] = [self.v, 0.0, self.vz]
-        ang[1] = [0.0, self.omega, 0.0]
-        return pos, quat, lin, ang
+        """Body states (reused arrays, overwritten by the next call)."""
+        self._pos[1] = self.x
+        h = 0.5 * self.theta
+        self._quat[1, 0] = math.cos(h)
+        self._quat[1, 2] = math.sin(h)
+        self._lin[1, 0] = self.v
+        self._lin[1, 2] = self.vz
+        return self._pos, self._quat, self._lin, self._ang
 
     def advance(self, force, dt):
         self.vz += dt * (force[2] / self.mass - self.g)
-        self.x += dt * np.array([self.v, 0.0, self.vz])
+        self.x[0] += dt * self.v
+        self.x[2] += dt * self.vz
         self.theta += dt * self.omega
 
 
@@ -308,9 +313,7 @@ def main():
     dt = sc.params["dt"]
 
     def one_step():
-        sim.set_bodies(*drv.state())
-        sim.step(1)
-        F, _ = sim.forces()
+        F, _ = sim.cosim_step(*drv.state())
         drv.advance(F[1], dt)
 
     for _ in range(args.warmup):

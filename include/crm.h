@@ -163,9 +163,17 @@ crm_status crm_step(crm_ctx* ctx, int32_t n_steps);
 /* Force (N, world frame) and torque (N m, about the body origin) the soil
  * exerts on each body, from the stage-2 evaluation of the last step
  * (Sec. 2.5.1: sum of marker mass times marker acceleration). force, torque:
- * 3*nb doubles. Synchronises the stream. Errors: CRM_E_INVALID, CRM_E_STATE
- * (no step taken yet), CRM_E_NONFINITE, CRM_E_DEVICE. */
+ * 3*nb doubles. Waits for the stream (by polling). Errors: CRM_E_INVALID,
+ * CRM_E_STATE (no step taken yet), CRM_E_NONFINITE, CRM_E_DEVICE. */
 crm_status crm_get_forces(crm_ctx* ctx, int32_t nb, double* force, double* torque);
+
+/* One co-simulation exchange (the FSI loop of Sec. 2.5 with the multibody
+ * side on the host): crm_set_bodies with the given states, crm_step(ctx, 1),
+ * then crm_get_forces into force and torque; arguments and errors as there.
+ * A host loop that calls it once per step makes one library call per step. */
+crm_status crm_cosim_step(crm_ctx* ctx, int32_t nb, const double* pos, const double* quat,
+                          const double* linvel, const double* angvel, const double* linacc,
+                          const double* angacc, double* force, double* torque);
 
 /* State of all n_total particles by id (soil, then markers: world positions,
  * extrapolated velocity and stress of their last evaluation, rho0). Any

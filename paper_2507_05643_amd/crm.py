@@ -75,6 +75,8 @@ def _load():
     L.crm_step.argtypes = [vp, C.c_int32]
     L.crm_get_forces.restype = C.c_int
     L.crm_get_forces.argtypes = [vp, C.c_int32, dp, dp]
+    L.crm_cosim_step.restype = C.c_int
+    L.crm_cosim_step.argtypes = [vp, C.c_int32] + [vp] * 8   # raw addresses (see crm_cosim_step below)
     L.crm_get_state.restype = C.c_int
     L.crm_get_state.argtypes = [vp, dp, fp, fp, fp]
     L.crm_set_state.restype = C.c_int
@@ -109,7 +111,7 @@ _lib = _load()
 EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_get_forces", "crm_get_state",
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
-            "crm_adjoint", "crm_autotune")
+            "crm_adjoint", "crm_autotune", "crm_cosim_step")
 
 TILE_NONE, TILE_SMALL, TILE_LARGE = 0, 1, 2
 
@@ -232,6 +234,25 @@ def crm_get_forces(ctx, nb):
     T = np.zeros((max(nb, 1), 3))
     _check(ctx, _lib.crm_get_forces(ctx, nb, _ptr(F, C.c_double), _ptr(T, C.c_double)))
     return F[:nb], T[:nb]
+
+
+def _addr(a):
+    """Address of a float64 C-contiguous array (None for None), for the
+    per-step exchange where ctypes pointer objects would dominate the call."""
+    if a is None:
+        return None
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("exchange arrays must be C-contiguous float64")
+    return a.ctypes.data
+
+
+def crm_cosim_step(ctx, nb, pos, quat, linvel, angvel, linacc, angacc, force, torque):
+    """One exchange: body states in, one step, forces and torques out (into the
+    given (nb, 3) float64 arrays)."""
+    if pos.shape[0] != nb or force.shape[0] < nb or torque.shape[0] < nb:
+        raise ValueError("array sizes differ from the body count")
+    _check(ctx, _lib.crm_cosim_step(ctx, nb, _addr(pos), _addr(quat), _addr(linvel), _addr(angvel), _addr(linacc),
+                                    _addr(angacc), _addr(force), _addr(torque)))
 
 
 def crm_get_counts(ctx):
@@ -375,6 +396,15 @@ class Simulation:
 
     def forces(self):
         return crm_get_forces(self.ctx, self.nb)
+
+    def cosim_step(self, pos, quat, linvel=None, angvel=None, linacc=None, angacc=None):
+        """set_bodies + step(1) + forces() in one library call; returns views of
+        (force, torque) buffers that the next call overwrites."""
+        if not hasattr(self, "_xf"):
+            self._xf = np.zeros((max(self.nb, 1), 3))
+            self._xt = np.zeros((max(self.nb, 1), 3))
+        crm_cosim_step(self.ctx, self.nb, pos, quat, linvel, angvel, linacc, angacc, self._xf, self._xt)
+        return self._xf[:self.nb], self._xt[:self.nb]
 
     def state(self):
         return crm_get_state(self.ctx, self.n_total)

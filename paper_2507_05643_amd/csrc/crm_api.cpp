@@ -104,6 +104,12 @@ struct crm_ctx {
   int64_t last_rebuild = 0;
   uint32_t* d_disp = nullptr;
   uint32_t* h_disp = nullptr;
+  // co-simulation exchange through pinned staging: body states up, forces and
+  // torques back (6 per body), each with its completion event
+  Body* h_bpin = nullptr;
+  double* h_fpin = nullptr;
+  hipEvent_t bpin_ev = nullptr, fpin_ev = nullptr;
+  bool bpin_pending = false;
   hipEvent_t disp_ev = nullptr;
   bool disp_pending = false;
   uint64_t* d_counts = nullptr;   // [0] n_proc [1] soil rows [2] marker rows [3] f entries [4] m entries
@@ -737,11 +743,24 @@ void release(crm_ctx* c) {
   for (auto& b : all) dfree(c, b.p);
   if (c->h_counts) (void)hipHostFree(c->h_counts);
   if (c->h_disp) (void)hipHostFree(c->h_disp);
+  if (c->h_bpin) (void)hipHostFree(c->h_bpin);
+  if (c->h_fpin) (void)hipHostFree(c->h_fpin);
+  if (c->bpin_ev) (void)hipEventDestroy(c->bpin_ev);
+  if (c->fpin_ev) (void)hipEventDestroy(c->fpin_ev);
   if (c->disp_ev) (void)hipEventDestroy(c->disp_ev);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
+}
+
+// Waits for ev by polling (a co-simulation exchange waits for every step:
+// polling avoids the wake-up latency of a blocking wait).
+hipError_t poll_event(hipEvent_t ev) {
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e != hipErrorNotReady) return e;
+  }
 }
 
 crm_status usable(crm_ctx* c) {
@@ -946,6 +965,17 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     release(c);
     return fail(nullptr, CRM_E_NOMEM, "pinned allocation failed");
   }
+  {
+    const size_t nbp = (size_t)(n_bodies > 0 ? n_bodies : 1);
+    if (hipHostMalloc((void**)&c->h_bpin, sizeof(Body) * nbp, hipHostMallocDefault) != hipSuccess) c->h_bpin = nullptr;
+    if (hipHostMalloc((void**)&c->h_fpin, sizeof(double) * 6 * nbp, hipHostMallocDefault) != hipSuccess)
+      c->h_fpin = nullptr;
+    if (!c->h_bpin || !c->h_fpin || hipEventCreateWithFlags(&c->bpin_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fpin_ev, hipEventDisableTiming) != hipSuccess) {
+      release(c);
+      return fail(nullptr, CRM_E_NOMEM, "pinned allocation failed");
+    }
+  }
   if (params->skin > 0.0) {
     if (!alloc_n(c, c->d_disp, 1) || hipHostMalloc((void**)&c->h_disp, 4, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->disp_ev, hipEventDisableTiming) != hipSuccess) {
@@ -1037,8 +1067,15 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
     B.has_acc = (linacc || angacc) ? 1 : 0;
     set_box_bounds(B, c->grid.ext);
   }
-  hipError_t e = hipMemcpyAsync(c->d_bodies, hb.data(), sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
+  // the staging buffer is reused once its last upload has been read
+  hipError_t e = c->bpin_pending ? hipEventSynchronize(c->bpin_ev) : hipSuccess;
+  if (e == hipSuccess) {
+    std::memcpy(c->h_bpin, hb.data(), sizeof(Body) * (size_t)nb);
+    e = hipMemcpyAsync(c->d_bodies, c->h_bpin, sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(c->bpin_ev, c->stream);
   if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
+  c->bpin_pending = true;
   c->h_bodies = hb;
   return CRM_OK;
 }
@@ -1323,17 +1360,29 @@ crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque)
   if ((!force || !torque) && nb > 0) return fail(c, CRM_E_INVALID, "force and torque are required");
   if (!c->stepped) return fail(c, CRM_E_STATE, "no step taken yet");
   if (nb == 0) return CRM_OK;
-  std::vector<double> h((size_t)(6 * nb));
-  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_forces, sizeof(double) * 6 * (size_t)nb, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_fpin, c->d_forces, sizeof(double) * 6 * (size_t)nb, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
+  HIPCHK(c, poll_event(c->fpin_ev));
+  const double* h = c->h_fpin;
   for (int b = 0; b < nb; ++b)
     for (int a = 0; a < 3; ++a) {
       force[3 * b + a] = h[6 * b + a];
       torque[3 * b + a] = h[6 * b + 3 + a];
     }
-  for (double v : h)
-    if (!std::isfinite(v)) return fail(c, CRM_E_NONFINITE, "non-finite body force or torque");
+  for (int k = 0; k < 6 * nb; ++k)
+    if (!std::isfinite(h[k])) return fail(c, CRM_E_NONFINITE, "non-finite body force or torque");
   return CRM_OK;
+}
+
+crm_status crm_cosim_step(crm_ctx* c, int32_t nb, const double* pos, const double* quat, const double* linvel,
+                          const double* angvel, const double* linacc, const double* angacc, double* force,
+                          double* torque) {
+  crm_status st = crm_set_bodies(c, nb, pos, quat, linvel, angvel, linacc, angacc);
+  if (st != CRM_OK) return st;
+  st = crm_step(c, 1);
+  if (st != CRM_OK) return st;
+  return crm_get_forces(c, nb, force, torque);
 }
 
 crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, float* rho) {

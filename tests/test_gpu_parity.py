@@ -156,6 +156,34 @@ def test_persistent_lists_parity(crm):
     sim.close()
 
 
+def test_cosim_step_equals_separate_calls(crm):
+    """crm_cosim_step is crm_set_bodies + crm_step(1) + crm_get_forces, bit for
+    bit, with body states that change every step (and list rebuilds)."""
+    sc = scenes.plate_patch(seed=1, nx=16, ny=16, nz=8, ps_freq=3)
+    a, b = _sim(crm, sc), _sim(crm, sc)
+    nb = len(sc.bodies)
+    pos = np.array([bd.pos for bd in sc.bodies], dtype=np.float64)
+    quat = np.tile([1.0, 0.0, 0.0, 0.0], (nb, 1))
+    lin = np.zeros((nb, 3))
+    ang = np.zeros((nb, 3))
+    for k in range(8):
+        pos[-1, 2] -= 1.0e-4
+        lin[-1] = (0.01 * k, 0.0, -0.04)
+        ang[-1] = (0.0, 0.2, 0.0)
+        a.set_bodies(pos, quat, lin, ang)
+        a.step(1)
+        Fa, Ta = a.forces()
+        Fb, Tb = b.cosim_step(pos, quat, lin, ang)
+        assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb), k
+    sa, sb = a.state(), b.state()
+    for key in ("pos", "vel", "sigma", "rho"):
+        assert np.array_equal(sa[key], sb[key]), key
+    with pytest.raises(crm.CrmError):
+        b.cosim_step(np.full((nb, 3), np.nan), quat, lin, ang)
+    a.close()
+    b.close()
+
+
 def test_plate_forces_parity(crm):
     sc = scenes.plate_patch(seed=0, nx=20, ny=20, nz=8)
     pl = sc.bodies[1]
