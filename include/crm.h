@@ -271,7 +271,10 @@ crm_status crm_autotune(crm_ctx* ctx, int32_t config, int32_t* chosen);
 
 /* Kernel timing for measurement. enable = 1 starts recording HIP events around
  * each kernel class of every following step on the context's stream (and
- * clears earlier records); enable = 0 stops recording. */
+ * clears earlier records); enable = CRM_PROF_CLASSES | m records only the
+ * classes k (numbered as in crm_get_profile) whose bit 1 << k is set in m;
+ * enable = 0 stops recording. Errors: CRM_E_INVALID (other values). */
+#define CRM_PROF_CLASSES 0x100
 crm_status crm_set_profiling(crm_ctx* ctx, int32_t enable);
 
 /* Recorded timings, out: 16 doubles. For class k = 0..6, out[2k] = launches and

@@ -332,8 +332,20 @@ def crm_set_graph(ctx, enable):
     _check(ctx, _lib.crm_set_graph(ctx, 1 if enable else 0))
 
 
-def crm_set_profiling(ctx, enable):
-    _check(ctx, _lib.crm_set_profiling(ctx, 1 if enable else 0))
+PROF_CLASSES = 0x100
+
+
+def crm_set_profiling(ctx, enable, classes=None):
+    """enable: on/off; classes: names from PROFILE_CLASSES to time (default all)."""
+    if not enable:
+        v = 0
+    elif classes is None:
+        v = 1
+    else:
+        v = PROF_CLASSES
+        for k in classes:
+            v |= 1 << PROFILE_CLASSES.index(k)
+    _check(ctx, _lib.crm_set_profiling(ctx, v))
 
 
 def crm_get_profile(ctx):
@@ -421,8 +433,8 @@ class Simulation:
     def graph(self, enable=True):
         crm_set_graph(self.ctx, enable)
 
-    def profiling(self, enable=True):
-        crm_set_profiling(self.ctx, enable)
+    def profiling(self, enable=True, classes=None):
+        crm_set_profiling(self.ctx, enable, classes)
 
     def profile(self):
         return crm_get_profile(self.ctx)

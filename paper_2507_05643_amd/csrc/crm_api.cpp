@@ -131,6 +131,7 @@ struct crm_ctx {
 
   // profiling: event pairs per kernel class
   bool prof = false;
+  uint32_t prof_mask = 0;        // kernel classes timed while profiling (bit k = class k)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
@@ -578,9 +579,9 @@ hipEvent_t prof_event(crm_ctx* c) {
   return c->ev_pool[c->ev_used++];
 }
 
-// Records a start event for kernel class k when profiling; returns it.
-hipEvent_t prof_begin(crm_ctx* c) {
-  if (!c->prof) return nullptr;
+// Records a start event for kernel class k when it is profiled; returns it.
+hipEvent_t prof_begin(crm_ctx* c, int k) {
+  if (!c->prof || !((c->prof_mask >> k) & 1u)) return nullptr;
   hipEvent_t e = prof_event(c);
   if (e) (void)hipEventRecord(e, c->stream);
   return e;
@@ -616,12 +617,12 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   const crm::StageTape* tape1 = rec ? &rec->t1 : nullptr;
   const crm::StageTape* tape2 = rec ? &rec->t2 : nullptr;
   const Phys& P = c->phys;
-  hipEvent_t e = prof ? prof_begin(c) : nullptr;
+  hipEvent_t e = prof ? prof_begin(c, 1) : nullptr;
   HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->cnt_m, c->slot_id, c->n_soil, c->local,
                                        c->d_bodies, c->grid, P, c->A, c->B, s));
   if (prof) prof_end(c, 1, e);
   // stage 1 at y_n
-  if (prof) e = prof_begin(c);
+  if (prof) e = prof_begin(c, 2);
   HIPCHK(c, crm::bce(c->A, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
                      nullptr, s));
   if (prof) prof_end(c, 2, e);
@@ -629,12 +630,12 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     crm_status st = copy_planes(c, c->A, rec->yn, c->n_proc, s);
     if (st != CRM_OK) return st;
   }
-  if (prof) e = prof_begin(c);
+  if (prof) e = prof_begin(c, 3);
   HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, c->tix_f,
                               c->tile_cfg, s));
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
-  if (prof) e = prof_begin(c);
+  if (prof) e = prof_begin(c, 4);
   HIPCHK(c, crm::bce(c->B, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
                      c->contrib, s));
   if (prof) prof_end(c, 4, e);
@@ -642,11 +643,11 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     crm_status st = copy_planes(c, c->B, rec->ym, c->n_proc, s);
     if (st != CRM_OK) return st;
   }
-  if (prof) e = prof_begin(c);
+  if (prof) e = prof_begin(c, 5);
   HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, c->tix_f,
                               c->tile_cfg, s));
   if (prof) prof_end(c, 5, e);
-  if (prof) e = prof_begin(c);
+  if (prof) e = prof_begin(c, 6);
   HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_forces, s));
   if (prof) prof_end(c, 6, e);
   return CRM_OK;
@@ -721,7 +722,7 @@ crm_status track_displacement(crm_ctx* c) {
 
 crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
   if (rebuild_due(c)) {
-    hipEvent_t e = prof_begin(c);
+    hipEvent_t e = prof_begin(c, 0);
     crm_status st = rebuild(c);
     if (st != CRM_OK) return st;
     prof_end(c, 0, e);
@@ -1590,11 +1591,16 @@ crm_status crm_set_profiling(crm_ctx* c, int32_t enable) {
   crm_status st = usable(c);
   if (st != CRM_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (enable) {
+  uint32_t mask;
+  if (enable == 0 || enable == 1) mask = enable ? 0x7fu : 0u;
+  else if ((enable & ~0x7f) == CRM_PROF_CLASSES) mask = (uint32_t)enable & 0x7fu;
+  else return fail(c, CRM_E_INVALID, "enable must be 0, 1 or CRM_PROF_CLASSES | class bits");
+  if (mask) {
     c->prof_marks.clear();
     c->ev_used = 0;
   }
-  c->prof = enable != 0;
+  c->prof = mask != 0;
+  c->prof_mask = mask;
   return CRM_OK;
 }
 

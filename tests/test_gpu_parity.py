@@ -184,6 +184,23 @@ def test_cosim_step_equals_separate_calls(crm):
     b.close()
 
 
+def test_profiling_classes(crm):
+    sc = scenes.column(seed=0, n=8, ps_freq=2)
+    sim = _sim(crm, sc)
+    sim.profiling(True, classes=["soil_stage2"])
+    sim.step(4)
+    pr = sim.profile()
+    assert pr["soil_stage2"]["launches"] == 4 and pr["soil_stage2"]["ms"] > 0
+    assert all(pr[k]["launches"] == 0 for k in crm.PROFILE_CLASSES if k != "soil_stage2")
+    sim.profiling(True)
+    sim.step(2)
+    pr = sim.profile()
+    assert all(pr[k]["launches"] >= 1 for k in crm.PROFILE_CLASSES)
+    for bad in (2, -1, crm.PROF_CLASSES | 0x80):
+        assert crm.lib().crm_set_profiling(sim.ctx, bad) == -1, bad     # CRM_E_INVALID
+    sim.close()
+
+
 def test_plate_forces_parity(crm):
     sc = scenes.plate_patch(seed=0, nx=20, ny=20, nz=8)
     pl = sc.bodies[1]
