@@ -36,6 +36,7 @@ FLOPS_PER_PAIR = 61
 BYTES_PER_PARTICLE = 3 * 52 + 16
 BYTES_PER_PAIR = 4
 PEAK_FP32_TFLOPS = 157.3
+TILE_NAMES = ("none", "small", "large")
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of k_fluid_stage2 on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy; None until measured for
@@ -181,7 +182,7 @@ def run_batch(args):
                                     "particles (seed 0), per-bin friction 0.5-0.9, slip 0-0.6, load 50-200 N, "
                                     "one context, step kernels replayed as a hipGraph",
                         "n_particles": int(sc.n_total), "n_processed": int(n_proc), "ps_freq": args.ps_freq,
-                        "dt": dt, "lds_tile": ("none", "small", "large")[tile],
+                        "dt": dt, "lds_tile": TILE_NAMES[tile],
                         "separate_contexts_particle_steps_per_s": value2,
                         "batched_over_separate": value / value2})
 
@@ -280,6 +281,8 @@ def main():
     ap.add_argument("--pos-mode", type=int, default=0)
     ap.add_argument("--strip-length", type=float, default=10000.0)
     ap.add_argument("--strip-x", type=float, default=5000.0)
+    ap.add_argument("--tile", choices=TILE_NAMES, default="small",
+                    help="LDS tile configuration of the soil stages")
     ap.add_argument("--autotune", action="store_true",
                     help="time the soil-stage tile configurations after the warm-up and keep the fastest "
                          "(default: the small tile)")
@@ -318,7 +321,7 @@ def main():
 
     for _ in range(args.warmup):
         one_step()
-    tile = sim.autotune() if args.autotune else sim.autotune(crm.TILE_SMALL)
+    tile = sim.autotune() if args.autotune else sim.autotune(TILE_NAMES.index(args.tile))
     torch.cuda.synchronize()
     # events around the dominant kernel only, on the context's stream
     sim.profiling(True, classes=["soil_stage2"])
@@ -389,7 +392,7 @@ def main():
                                "+ 3-layer container + grousered wheel r 0.25 m, slip 0.3, load 100 N; "
                                "co-simulation exchange every step",
                    "n_particles": cnt["n_total"], "n_processed": n_proc, "ps_freq": args.ps_freq,
-                   "dt": dt, "lds_tile": ("none", "small", "large")[tile]},
+                   "dt": dt, "lds_tile": TILE_NAMES[tile]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": adjoint,

@@ -877,13 +877,24 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum_j V_j grad_i W_ij (sigma_i's share of F3, applied once per row)
   const float av2 = 2.0f * P.av_coef;
+  // kernel gradient factor F(q) with its constants folded: cubic inner piece
+  // kf (2.25 q - 3), outer piece -0.75 kf (2 - q)^2 / q = -0.75 kf h t^2 / r
+  const float ci1 = 2.25f * P.kf, ci0 = -3.0f * P.kf, co = -0.75f * P.kf * P.h;
   auto pair = [&](const Nbr& o) {
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float rs = __builtin_amdgcn_rsqf(fmaxf(r2, 1.0e-30f));   // 1 / r (finite for the self pair)
     const float q = r2 * rs * P.inv_h;
-    const float F = sph_f_iq(q, P.h * rs, P);
+    float F;
+    if (P.kern == 1) {
+      F = wendland_f(q, P.kf);
+    } else {
+      const float t = fmaxf(2.0f - q, 0.0f);
+      const float outer = t * t * rs * co;
+      const float inner = fmaf(q, ci1, ci0);
+      F = q < 1.0f ? inner : outer;
+    }
     const float V = o.a.w;
     const float VF = V * F;                                       // V_j * (gradW / r_ij)
     const float wx = VF * dx, wy = VF * dy, wz = VF * dz;       // V_j grad_i W_ij
@@ -892,9 +903,9 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
     L10 += duy * wx; L11 += duy * wy; L12 += duy * wz;
     L20 += duz * wx; L21 += duz * wy; L22 += duz * wz;
     g0 += wx; g1 += wy; g2 += wz;
-    a0 += o.c.x * wx + o.c.w * wy + o.d.x * wz;
-    a1 += o.c.w * wx + o.c.y * wy + o.d.y * wz;
-    a2 += o.d.x * wx + o.d.y * wy + o.c.z * wz;
+    a0 = fmaf(o.c.x, wx, a0); a0 = fmaf(o.c.w, wy, a0); a0 = fmaf(o.d.x, wz, a0);
+    a1 = fmaf(o.c.w, wx, a1); a1 = fmaf(o.c.y, wy, a1); a1 = fmaf(o.d.y, wz, a1);
+    a2 = fmaf(o.d.x, wx, a2); a2 = fmaf(o.d.y, wy, a2); a2 = fmaf(o.c.z, wz, a2);
     const float vr = -(dux * dx + duy * dy + duz * dz);         // v_ij . r_ij
     const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
     const float cf = av ? av2 * vr * VF * __builtin_amdgcn_rcpf((rhoi * V + P.m) * (r2 + P.xi2)) : 0.f;
@@ -1262,22 +1273,17 @@ __device__ inline Nbr tile_rec(const StageTile<CELL, CAP>& T, uint32_t o) {
 
 // The walk of a row through the tile, two entries per lane and iteration: both
 // tile reads are issued before either pair is computed, and the tile positions
-// four entries ahead are in flight meanwhile (their load from HBM/L2 is the
-// walk's longest wait). The pairs are still taken in entry order. `tix` is the
-// block's first entry, e0..e1 the row's entries relative to it; past the
-// row's end the walk reads its first entry again (a valid position).
-template <bool CELL, uint32_t CAP, class Fn>
-__device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* __restrict__ tix, uint32_t e0,
-                                 uint32_t e1, Fn&& f) {
+// four entries ahead are in flight meanwhile. The pairs are still taken in
+// entry order. pos(k) is the tile position of entry k (relative to the
+// block's first entry); e0..e1 are the row's entries; past the row's end the
+// walk reads its first entry again (a valid position).
+template <bool CELL, uint32_t CAP, class Pos, class Fn>
+__device__ inline void walk_tile_pos(const StageTile<CELL, CAP>& T, const Pos& pos_of, uint32_t e0, uint32_t e1,
+                                     Fn&& f) {
   constexpr uint32_t G = kGroup;
-  constexpr uint32_t omax = (CAP - 1) << 4;
   const uint32_t ef = e0 + group_lane();
   if (ef >= e1) return;
-  auto pos = [&](uint32_t e) {
-    const uint32_t k = e < e1 ? e : ef;
-    const uint32_t o = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(tix) + 2u * k);
-    return o < omax ? o : omax;
-  };
+  auto pos = [&](uint32_t e) { return pos_of(e < e1 ? e : ef); };
   uint32_t e = ef;
   uint32_t o0 = pos(e), o1 = pos(e + G), o2 = pos(e + 2 * G), o3 = pos(e + 3 * G);
   for (;;) {
@@ -1297,6 +1303,18 @@ __device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* 
   }
 }
 
+// Tile positions read from HBM/L2 (`tix` is the block's first entry); the
+// load from there is the walk's longest wait. Positions are below 16 total
+// (k_tile_index, for blocks that stage); LDS reads past the block's
+// allocation would return zero, never fault.
+template <bool CELL, uint32_t CAP, class Fn>
+__device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* __restrict__ tix, uint32_t e0,
+                                 uint32_t e1, Fn&& f) {
+  walk_tile_pos(T, [&](uint32_t k) {
+    return (uint32_t)*reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(tix) + 2u * k);
+  }, e0, e1, f);
+}
+
 // One record on its way into the tile.
 struct Rec {
   float4 a, b, c, d;
@@ -1310,7 +1328,12 @@ __device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL, CAP>& ld, uint32_
     r.a = S.a[j];
     r.b = S.b[j];
     r.c = S.c[j];
-    r.d = S.d[j];
+    if constexpr (CELL) {
+      r.d = S.d[j];
+    } else {                       // sigma_xz, sigma_yz: the tile keeps no more of plane d
+      const float2 d2 = *reinterpret_cast<const float2*>(&S.d[j]);
+      r.d = make_float4(d2.x, d2.y, 0.f, 0.f);
+    }
   } else {
     r.a = r.b = r.c = r.d = make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -1373,6 +1396,49 @@ __device__ inline void tape_write(const StageTape& T, int32_t s, const float L[9
   }
 }
 
+// Stage-1 update of row s from its record (ma..md) and rates: B = A + dt/2 f;
+// lane gl < 4 of the group stores plane gl.
+template <bool CELL, bool TAPE>
+__device__ inline void finish_stage1(Planes B, int32_t s, int gl, float4 ma, float4 mb, float4 mc, float4 md,
+                                     const Rates& R, const Phys& P, const StageTape& T) {
+  const float h = P.half_dt;
+  float4 na = ma, nd = md;
+  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
+  na.w = ma.w + h * R.drho;
+  nd.x = md.x + h * R.s4;
+  nd.y = md.y + h * R.s5;
+  const float4 nb = make_float4(mb.x + h * R.ax, mb.y + h * R.ay, mb.z + h * R.az, mb.w);
+  const float4 nc = make_float4(mc.x + h * R.s0, mc.y + h * R.s1, mc.z + h * R.s2, mc.w + h * R.s3);
+  float4* dst = gl == 0 ? B.a : gl == 1 ? B.b : gl == 2 ? B.c : B.d;
+  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
+  if (gl < 4) dst[s] = v;
+  if (TAPE) tape_write(T, s, R.L, nullptr, 3);
+}
+
+// Stage-2 update of row s from its y_n record (ya..yd) and the rates at the
+// midpoint: A = A + dt f, then the return mapping; lane gl < 4 stores plane gl.
+template <bool CELL, bool TAPE>
+__device__ inline void finish_stage2(Planes A, int32_t s, int gl, float4 ya, float4 yb, float4 yc, float4 yd,
+                                     const Rates& R, const Phys& P, const StageTape& T) {
+  const float h = P.dt;
+  float4 na = ya, nd = yd;
+  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
+  na.w = ya.w + h * R.drho;
+  const float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
+  float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
+                 sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
+  float trial[6] = {st[0], st[1], st[2], st[3], st[4], st[5]};
+  return_map(st, sn, P, P.mat[__float_as_uint(yb.w) >> 2]);
+  nd.x = st[4];
+  nd.y = st[5];
+  const float4 nb = make_float4(yb.x + h * R.ax, yb.y + h * R.ay, yb.z + h * R.az, yb.w);
+  const float4 nc = make_float4(st[0], st[1], st[2], st[3]);
+  float4* dst = gl == 0 ? A.a : gl == 1 ? A.b : gl == 2 ? A.c : A.d;
+  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
+  if (gl < 4) dst[s] = v;
+  if (TAPE) tape_write(T, s, R.L, trial, 5);
+}
+
 // Stage 1 of the explicit midpoint rule (Sec. 2.3): B = A + dt/2 f(A).
 // Lanes 0-3 of the group write the four planes of the row's record. With TAPE
 // the velocity gradient L is also kept.
@@ -1415,18 +1481,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     }, P);
   }
   if (!live) return;
-  const float h = P.half_dt;
-  float4 na = ma, nd = md;
-  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
-  na.w = ma.w + h * R.drho;
-  nd.x = md.x + h * R.s4;
-  nd.y = md.y + h * R.s5;
-  const float4 nb = make_float4(mb.x + h * R.ax, mb.y + h * R.ay, mb.z + h * R.az, mb.w);
-  const float4 nc = make_float4(mc.x + h * R.s0, mc.y + h * R.s1, mc.z + h * R.s2, mc.w + h * R.s3);
-  float4* dst = gl == 0 ? B.a : gl == 1 ? B.b : gl == 2 ? B.c : B.d;
-  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
-  if (gl < 4) dst[s] = v;
-  if (TAPE) tape_write(T, s, R.L, nullptr, 3);
+  finish_stage1<CELL, TAPE>(B, s, gl, ma, mb, mc, md, R, P, T);
 }
 
 // Stage 2: A = A + dt f(B), then the return mapping on the stress. With TAPE
@@ -1474,24 +1529,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   // record; one store then writes plane gl from lane gl < 4. The return
   // mapping needs sigma_n from planes c and d, so no lane may read a plane
   // after another lane of the group has overwritten it.
-  const float h = P.dt;
-  const float4 ya = A.a[s], yb = A.b[s], yc = A.c[s], yd = A.d[s];
-  float4 na = ya, nd = yd;
-  advance_pos<CELL>(na, nd, h, R.dx, R.dy, R.dz, P);
-  na.w = ya.w + h * R.drho;
-  const float sn[6] = {yc.x, yc.y, yc.z, yc.w, yd.x, yd.y};
-  float st[6] = {sn[0] + h * R.s0, sn[1] + h * R.s1, sn[2] + h * R.s2,
-                 sn[3] + h * R.s3, sn[4] + h * R.s4, sn[5] + h * R.s5};
-  float trial[6] = {st[0], st[1], st[2], st[3], st[4], st[5]};
-  return_map(st, sn, P, P.mat[__float_as_uint(yb.w) >> 2]);
-  nd.x = st[4];
-  nd.y = st[5];
-  const float4 nb = make_float4(yb.x + h * R.ax, yb.y + h * R.ay, yb.z + h * R.az, yb.w);
-  const float4 nc = make_float4(st[0], st[1], st[2], st[3]);
-  float4* dst = gl == 0 ? A.a : gl == 1 ? A.b : gl == 2 ? A.c : A.d;
-  const float4 v = gl == 0 ? na : gl == 1 ? nb : gl == 2 ? nc : nd;
-  if (gl < 4) dst[s] = v;
-  if (TAPE) tape_write(T, s, R.L, trial, 5);
+  finish_stage2<CELL, TAPE>(A, s, gl, A.a[s], A.b[s], A.c[s], A.d[s], R, P, T);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* __restrict__ rows, int64_t n,

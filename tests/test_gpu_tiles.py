@@ -64,3 +64,22 @@ def test_autotune_keeps_the_run(crm):
         a.autotune(7)
     a.close()
     b.close()
+
+
+def test_reverse_sweep_identical_across_tiles(crm):
+    """The taped stage kernels of every configuration give the same adjoint."""
+    from oracle import adjoint as A
+    sc = scenes.wheel_bin(seed=2, nx=40, ny=24, nz=12, ps_freq=4)
+    w = A.loss_weights(3, sc.n_soil, 6, len(sc.bodies))
+    out = {}
+    for cfg in (crm.TILE_NONE, crm.TILE_SMALL):
+        sim = crm.Simulation(sc)
+        sim.step(1)
+        sim.autotune(cfg)
+        sim.step(3)
+        sim.record(6)
+        out[cfg] = sim.adjoint(lam_pos=w["x"], lam_vel=w["u"], lam_sigma=w["s"], lam_rho=w["rho"],
+                               lam_force=w["F"], lam_torque=w["T"])
+        sim.close()
+    for k in out[crm.TILE_NONE]:
+        assert np.array_equal(out[crm.TILE_NONE][k], out[crm.TILE_SMALL][k]), k
