@@ -30,18 +30,19 @@ sys.path.insert(0, ROOT)
 #   FP32 flops per pair: kernel gradient 12, V_j grad W 4, velocity difference
 #   and outer product 21, stress sum and contraction 24, artificial viscosity 19
 #   (only pairs with v.r < 0 in the unilateral form; not counted) -> 61.
-#   HBM bytes per particle: own y_mid 52 + own y_n 52 + y_{n+1} 52, its list
-#   (4 B per pair) and row/count/offset words 16.
+#   HBM bytes per particle: own y_mid 52 + own y_n 52 + y_{n+1} 52 and
+#   row/count/offset words 16; per pair its 16-bit tile position (2 B).
 FLOPS_PER_PAIR = 61
 BYTES_PER_PARTICLE = 3 * 52 + 16
-BYTES_PER_PAIR = 4
+BYTES_PER_PAIR = 2
 PEAK_FP32_TFLOPS = 157.3
 TILE_NAMES = ("none", "small", "large")
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of k_fluid_stage2 on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy; None until measured for
-# the current kernel.
-STAGE2_TRAFFIC_BYTES = None
+# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy (fetch x2, write x1); the
+# commands and figures are in profiles/wheel_bin_kernels_lds_tiles.md (small
+# LDS tile). None once the kernel changes.
+STAGE2_TRAFFIC_BYTES = 480.6e6
 
 
 class WheelDriver:
@@ -140,9 +141,7 @@ def run_batch(args):
     sim.graph(True)
 
     def step_batched():
-        sim.set_bodies(*drv.state())
-        sim.step(1)
-        F, _ = sim.forces()
+        F, _ = sim.cosim_step(*drv.state())
         drv.advance(F[1::2, 2], dt)
 
     step_batched()
@@ -166,10 +165,7 @@ def run_batch(args):
         sims.append(s1)
 
     def step_separate():
-        for k, s1 in enumerate(sims):
-            s1.set_bodies(*drv2.state([k]))
-            s1.step(1)
-        fz = np.array([s1.forces()[0][1, 2] for s1 in sims])
+        fz = np.array([s1.cosim_step(*drv2.state([k]))[0][1, 2] for k, s1 in enumerate(sims)])
         drv2.advance(fz, dt)
 
     n_sep = max(1, args.steps // 4)
@@ -207,9 +203,7 @@ def run_strip(args):
     def one_step():
         p = pos0.copy()
         p[1:, 0] += lin[1:, 0] * dt * state["k"]
-        sim.set_bodies(p, quat, lin, ang)
-        sim.step(1)
-        sim.forces()
+        sim.cosim_step(p, quat, lin, ang)
         state["k"] += 1
 
     for _ in range(args.warmup):
