@@ -269,7 +269,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--ps-freq", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=30,
+                    help="oracle steps of the CPU baseline (about 10-20 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("wheel", "batch", "strip"), default="wheel")
     ap.add_argument("--pos-mode", type=int, default=0)
