@@ -550,11 +550,10 @@ crm_status rebuild(crm_ctx* c) {
   }
   c->ent_f = ef;
   c->ent_m = em;
-  HIPCHK(c, crm::nbr_fill(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, false,
-                          c->cnt_f, c->stash_f, c->off_f, c->nbr_f, s));
+  HIPCHK(c, crm::nbr_fill_soil(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, c->cnt_f,
+                               c->stash_f, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
-  HIPCHK(c, crm::tile_index(c->n_frows, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
   // per-body ranges of the processed markers for the force sums
   c->kbase = c->n_proc - c->n_mrows;
   st = update_body_plan(c, ids);

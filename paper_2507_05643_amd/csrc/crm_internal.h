@@ -229,7 +229,7 @@ struct StageTape {
   float4* t1;   // (sxz, syz, -, -), stage 2
 };
 // tabs: the per-block tile tables of the soil rows (tile_tables, after each
-// list rebuild); tix: the entries' tile positions (tile_index, after them).
+// list rebuild); tix: the entries' tile positions (nbr_fill_soil).
 // cfg: the LDS tile configuration (0 none, 1 small, 2 large); every
 // configuration gives bit-identical results.
 hipError_t fluid_stage1(CPlanes A, Planes B, const int32_t* frows, int64_t n_frows, const uint64_t* off,
@@ -243,10 +243,13 @@ hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_fro
 int64_t tile_table_words(int64_t rows_cap);
 hipError_t tile_tables(const int32_t* frows, int64_t rows_cap, const uint64_t* n_frows_dev, const uint32_t* skey,
                        const uint32_t* cell_start, Phys P, uint32_t* tabs, hipStream_t s);
-// Tile position (16-bit) of each soil-row list entry of the blocks that can
-// stage their neighbours (one entry per nbr entry; the others untouched).
-hipError_t tile_index(int64_t n_frows, const uint64_t* off, const uint32_t* nbr, const uint32_t* tabs,
-                      uint16_t* tix, hipStream_t s);
+// The fill pass of the soil rows, which also writes the tile position
+// (16-bit) of each entry of the blocks that can stage their neighbours (one
+// per nbr entry; the other blocks' entries untouched); tabs from tile_tables.
+hipError_t nbr_fill_soil(const int32_t* frows, int64_t n_frows, const float4* pos4, const int4* cpos,
+                         const uint32_t* skey, const uint32_t* cell_start, Grid g, const uint32_t* cnt,
+                         const uint32_t* stash, const uint64_t* off, uint32_t* nbr, const uint32_t* tabs,
+                         uint16_t* tix, hipStream_t s);
 
 // Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
 // the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.

@@ -461,9 +461,9 @@ struct ScanLoad {
   }
 };
 
-template <bool FILL, bool CELL, bool SOIL_ONLY, class Load>
+template <bool FILL, bool CELL, bool SOIL_ONLY, class Load, class Emit>
 __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const Load& load,
-                                      const uint32_t* __restrict__ cs, const Grid& g, uint32_t* __restrict__ out,
+                                      const uint32_t* __restrict__ cs, const Grid& g, const Emit& emit,
                                       uint32_t limit) {
   const int X = g.dims[0], Y = g.dims[1], Z = g.dims[2];
   const int gl = group_lane();
@@ -511,7 +511,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         const uint32_t m = group_bits(__ballot(hit));
         if (FILL && hit) {
           const uint32_t at_ = count + __popc(m & ((1u << gl) - 1u));
-          if (at_ < limit) out[at_] = j;
+          if (at_ < limit) emit(at_, j);
         }
         count += __popc(m);
       }
@@ -522,19 +522,25 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
 
 // The row scan with the position form and the candidate filter as template
 // arguments (uniform over a launch).
-template <bool FILL>
+template <bool FILL, class Emit>
 __device__ inline uint32_t group_scan_any(bool live, float4 pi, int4 ci, uint32_t c, const float4* __restrict__ pos4,
                                           const int4* __restrict__ cpos, const uint32_t* __restrict__ cs,
-                                          const Grid& g, bool soil_only, uint32_t* __restrict__ out, uint32_t limit) {
+                                          const Grid& g, bool soil_only, const Emit& emit, uint32_t limit) {
   if (g.cell) {
     const ScanLoad<true> ld{pos4, cpos};
-    return soil_only ? group_scan<FILL, true, true>(live, pi, ci, c, ld, cs, g, out, limit)
-                     : group_scan<FILL, true, false>(live, pi, ci, c, ld, cs, g, out, limit);
+    return soil_only ? group_scan<FILL, true, true>(live, pi, ci, c, ld, cs, g, emit, limit)
+                     : group_scan<FILL, true, false>(live, pi, ci, c, ld, cs, g, emit, limit);
   }
   const ScanLoad<false> ld{pos4, cpos};
-  return soil_only ? group_scan<FILL, false, true>(live, pi, ci, c, ld, cs, g, out, limit)
-                   : group_scan<FILL, false, false>(live, pi, ci, c, ld, cs, g, out, limit);
+  return soil_only ? group_scan<FILL, false, true>(live, pi, ci, c, ld, cs, g, emit, limit)
+                   : group_scan<FILL, false, false>(live, pi, ci, c, ld, cs, g, emit, limit);
 }
+
+// Writes entry `at` of a row's list.
+struct EmitTo {
+  uint32_t* out;
+  __device__ void operator()(uint32_t at, uint32_t j) const { out[at] = j; }
+};
 
 // Count pass: counts every row's neighbours and keeps the first kStash of them
 // in a fixed-stride scratch, so that the fill pass is a copy (rows with more
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict_
     c = skey[s];
     out = stash + (uint64_t)r * kStash;
   }
-  const uint32_t count = group_scan_any<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, out, kStash);
+  const uint32_t count = group_scan_any<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, EmitTo{out}, kStash);
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
@@ -600,7 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__
   if (rescan) {
     const int32_t s = rows[r];
     const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
-    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, soil_only != 0, nbr + off[r], 0xffffffffu);
+    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, soil_only != 0, EmitTo{nbr + off[r]},
+                         0xffffffffu);
   }
 }
 
@@ -1071,10 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restric
 // starts at ~0 and never counts). Written as sums so that no select picks
 // between two loaded values. The same holds in tile-index space with the
 // ranges' first tile indices b_k, for the copy into the tile.
-template <bool CELL, uint32_t CAP>
 struct TileLoad {
-  static constexpr bool kTile = true;
-  const StageTile<CELL, CAP>* T;
   uint32_t s1, s2, s3, s4, s5, s6, s7, s8;
   uint32_t b1, b2, b3, b4, b5, b6, b7, b8;
   uint32_t o0, d1, d2, d3, d4, d5, d6, d7, d8;
@@ -1095,10 +1099,8 @@ struct TileLoad {
   __device__ uint32_t slot(uint32_t t) const { return t + offset(t, b1, b2, b3, b4, b5, b6, b7, b8); }
 };
 
-// The block's loader from its table (uniform loads); T may be null where only
-// the index maps are used.
-template <bool CELL, uint32_t CAP>
-__device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>* T, const uint32_t* __restrict__ tb) {
+// The block's index maps from its table (uniform loads).
+__device__ inline TileLoad tile_loader(const uint32_t* __restrict__ tb) {
   uint32_t st[9], of[9], d[9], bs[9];
   uint32_t prev = tb[9];
 #pragma unroll
@@ -1110,8 +1112,7 @@ __device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>* T,
     prev = none ? prev : of[k];
     bs[k] = none ? 0xffffffffu : st[k] - of[k];
   }
-  TileLoad<CELL, CAP> l;
-  l.T = T;
+  TileLoad l;
   l.s1 = st[1]; l.s2 = st[2]; l.s3 = st[3]; l.s4 = st[4]; l.s5 = st[5]; l.s6 = st[6]; l.s7 = st[7]; l.s8 = st[8];
   l.b1 = bs[1]; l.b2 = bs[2]; l.b3 = bs[3]; l.b4 = bs[4]; l.b5 = bs[5]; l.b6 = bs[6]; l.b7 = bs[7]; l.b8 = bs[8];
   l.o0 = of[0];
@@ -1122,37 +1123,60 @@ __device__ inline TileLoad<CELL, CAP> tile_loader(const StageTile<CELL, CAP>* T,
 // Largest tile (records): blocks whose ranges exceed it never stage.
 constexpr uint32_t kTileMax = 1024;
 
-// Tile positions of the soil rows' list entries, once per list rebuild: the
-// entry of slot j holds 16 i (i = j's tile index: the record's byte offset in
-// each 16-byte tile plane), for the blocks whose rows lie in one row of cells
-// and whose ranges fit kTileMax records; other blocks' entries are not
-// written. A block's rows are consecutive, so their entries form one
-// contiguous range, read and written here by one workgroup.
-__global__ __launch_bounds__(kBlock) void k_tile_index(int64_t n, const uint64_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ nbr,
-                                                       const uint32_t* __restrict__ tabs,
-                                                       uint16_t* __restrict__ tix) {
-  const int64_t b = blockIdx.x;
-  const uint32_t* tb = tabs + b * kTabWords;
-  if (tb[19] == 0 || tb[18] > kTileMax) return;
-  const int64_t r0 = b * kRows;
-  const int64_t r1 = r0 + kRows < n ? r0 + kRows : n;
-  const TileLoad<false, kTileMax> ld = tile_loader<false, kTileMax>(nullptr, tb);
-  const uint64_t e1 = off[r1];
-  // eight entries per thread and pass, all loaded before any is converted
-  constexpr int kPer = 8;
-  for (uint64_t k0 = off[r0] + threadIdx.x; k0 < e1; k0 += (uint64_t)kPer * kBlock) {
+// The fill pass of the soil rows (the copy of k_nbr_fill, rescans included)
+// that also writes each entry's tile position: 16 i for slot j at tile index
+// i (the record's byte offset in each 16-byte tile plane), for the blocks whose
+// rows lie in one row of cells and whose ranges fit kTileMax records (other
+// blocks' positions are not written). Workgroup b serves the 32 rows of tile
+// table b, so the table is uniform.
+__global__ __launch_bounds__(kBlock) void k_nbr_fill_soil(const int32_t* __restrict__ rows, int64_t n_rows,
+                                                          const float4* __restrict__ pos4,
+                                                          const int4* __restrict__ cpos,
+                                                          const uint32_t* __restrict__ skey,
+                                                          const uint32_t* __restrict__ cs, Grid g,
+                                                          const uint32_t* __restrict__ cnt,
+                                                          const uint32_t* __restrict__ stash,
+                                                          const uint64_t* __restrict__ off, uint32_t* __restrict__ nbr,
+                                                          const uint32_t* __restrict__ tabs,
+                                                          uint16_t* __restrict__ tix) {
+  const int64_t blk = xcd_block();
+  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
+  const bool live = r < n_rows;
+  const uint32_t* tb = tabs + blk * kTabWords;
+  const bool tiled = tb[19] != 0 && tb[18] <= kTileMax;
+  const TileLoad ld = tile_loader(tb);
+  const uint32_t count = live ? cnt[r] : 0u;
+  const bool rescan = count > kStash;                 // uniform within the group
+  if (live && !rescan) {
+    // all of the lane's stashed entries are loaded before any is stored
+    const uint64_t base = off[r];
+    const uint32_t* src = stash + (uint64_t)r * kStash;
+    constexpr int kPer = (int)(kStash / kGroup);
     uint32_t v[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const uint64_t k = k0 + (uint64_t)q * kBlock;
-      v[q] = k < e1 ? nbr[k] : 0u;
+      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+      v[q] = k < count ? src[k] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const uint64_t k = k0 + (uint64_t)q * kBlock;
-      if (k < e1) tix[k] = (uint16_t)(ld.index(v[q]) << 4);
+      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+      if (k < count) {
+        nbr[base + k] = v[q];
+        if (tiled) tix[base + k] = (uint16_t)(ld.index(v[q]) << 4);
+      }
     }
+  }
+  if (rescan) {
+    const int32_t s = rows[r];
+    const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
+    uint32_t* nb = nbr + off[r];
+    uint16_t* tx = tix + off[r];
+    auto emit = [&](uint32_t at, uint32_t j) {
+      nb[at] = j;
+      if (tiled) tx[at] = (uint16_t)(ld.index(j) << 4);
+    };
+    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, false, emit, 0xffffffffu);
   }
 }
 
@@ -1224,7 +1248,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
     if (staged) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) tl.o[k] = tb[9 + k];
-      const TileLoad<false, kTileMax> ld = tile_loader<false, kTileMax>(nullptr, tb);
+      const TileLoad ld = tile_loader(tb);
       constexpr int kPer = (int)(kScanCap / kBlock);
       float4 p[kPer];
       int4 q[kPer];
@@ -1248,9 +1272,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
     }
     __syncthreads();
   }
-  const uint32_t count = staged ? group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, out, kStash)
+  const uint32_t count = staged ? group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, EmitTo{out}, kStash)
                                 : group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g,
-                                                                out, kStash);
+                                                                EmitTo{out}, kStash);
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
@@ -1305,7 +1329,7 @@ __device__ inline void walk_tile_pos(const StageTile<CELL, CAP>& T, const Pos& p
 
 // Tile positions read from HBM/L2 (`tix` is the block's first entry); the
 // load from there is the walk's longest wait. Positions are below 16 total
-// (k_tile_index, for blocks that stage); LDS reads past the block's
+// (k_nbr_fill_soil, for blocks that stage); LDS reads past the block's
 // allocation would return zero, never fault.
 template <bool CELL, uint32_t CAP, class Fn>
 __device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* __restrict__ tix, uint32_t e0,
@@ -1320,8 +1344,8 @@ struct Rec {
   float4 a, b, c, d;
 };
 
-template <bool CELL, uint32_t CAP>
-__device__ inline Rec rec_load(CPlanes S, const TileLoad<CELL, CAP>& ld, uint32_t t, uint32_t total) {
+template <bool CELL>
+__device__ inline Rec rec_load(CPlanes S, const TileLoad& ld, uint32_t t, uint32_t total) {
   Rec r;
   if (t < total) {
     const uint32_t j = ld.slot(t);
@@ -1362,16 +1386,16 @@ __device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t
 // calls it; returns whether the block uses the tile.
 template <bool CELL, uint32_t CAP>
 __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint32_t* __restrict__ tb,
-                                  const TileLoad<CELL, CAP>& ld, float m) {
+                                  const TileLoad& ld, float m) {
   static_assert(CAP <= 4 * kBlock, "four records per thread");
   const uint32_t total = tb[18];
   const bool ok = tb[19] != 0 && total <= CAP;
   if (ok) {
     const uint32_t t0 = threadIdx.x;
-    const Rec r0 = rec_load(S, ld, t0, total);
-    const Rec r1 = rec_load(S, ld, t0 + kBlock, total);
-    const Rec r2 = rec_load(S, ld, t0 + 2 * kBlock, total);
-    const Rec r3 = rec_load(S, ld, t0 + 3 * kBlock, total);
+    const Rec r0 = rec_load<CELL>(S, ld, t0, total);
+    const Rec r1 = rec_load<CELL>(S, ld, t0 + kBlock, total);
+    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kBlock, total);
+    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kBlock, total);
     rec_store(T, r0, t0, total, m);
     rec_store(T, r1, t0 + kBlock, total, m);
     rec_store(T, r2, t0 + 2 * kBlock, total, m);
@@ -1464,7 +1488,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
+  const TileLoad tl = tile_loader(tb);
   const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl, P.m);
   Rates R;
   if (staged) {
@@ -1508,7 +1532,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     k1 = off[r + 1];
   }
   const uint32_t* tb = tabs + blk * kTabWords;
-  const TileLoad<CELL, CAP> tl = tile_loader(&tile, tb);
+  const TileLoad tl = tile_loader(tb);
   const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl, P.m);
   Rates R;
   if (staged) {
@@ -1749,10 +1773,13 @@ hipError_t tile_tables(const int32_t* rows, int64_t rows_cap, const uint64_t* n_
   return hipGetLastError();
 }
 
-hipError_t tile_index(int64_t n, const uint64_t* off, const uint32_t* nbr, const uint32_t* tabs, uint16_t* tix,
-                      hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_tile_index<<<(unsigned)((n + kRows - 1) / kRows), kBlock, 0, s>>>(n, off, nbr, tabs, tix);
+hipError_t nbr_fill_soil(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos,
+                         const uint32_t* skey, const uint32_t* cs, Grid g, const uint32_t* cnt,
+                         const uint32_t* stash, const uint64_t* off, uint32_t* nbr, const uint32_t* tabs,
+                         uint16_t* tix, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  k_nbr_fill_soil<<<nblk_groups(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, cpos, skey, cs, g, cnt, stash, off, nbr,
+                                                         tabs, tix);
   return hipGetLastError();
 }
 
