@@ -632,6 +632,61 @@ __global__ __launch_bounds__(kBlock) void k_adj_params_permute(int64_t n, const 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned nblk_groups(int64_t rows) { return nblk(rows * kGroup); }
 
+// Seeds of the end state, from the caller's flat arrays (any may be absent)
+// into the adjoint planes by particle id: a = (x, y, z, rho), b = (u, -),
+// c, d = stress.
+__global__ __launch_bounds__(kBlock) void k_adj_pack(int64_t n, const double* __restrict__ pos,
+                                                     const float* __restrict__ vel, const float* __restrict__ sig,
+                                                     const float* __restrict__ rho, Planes out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
+  if (pos) a = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], 0.f);
+  if (rho) a.w = rho[i];
+  if (vel) b = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
+  if (sig) {
+    c = make_float4(sig[6 * i], sig[6 * i + 1], sig[6 * i + 2], sig[6 * i + 3]);
+    d = make_float4(sig[6 * i + 4], sig[6 * i + 5], 0.f, 0.f);
+  }
+  out.a[i] = a;
+  out.b[i] = b;
+  out.c[i] = c;
+  out.d[i] = d;
+}
+
+// The adjoint of the start state into flat arrays (any may be absent); bad
+// is set when any of the 13 values of a particle is not finite.
+__global__ __launch_bounds__(kBlock) void k_adj_unpack(int64_t n, CPlanes in, double* __restrict__ pos,
+                                                       float* __restrict__ vel, float* __restrict__ sig,
+                                                       float* __restrict__ rho, uint32_t* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 a = in.a[i], b = in.b[i], c = in.c[i], d = in.d[i];
+  const float v[13] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, c.x, c.y, c.z, c.w, d.x, d.y};
+  bool fin = true;
+  for (float x : v) fin = fin && isfinite(x);
+  if (!fin) atomicOr(bad, 1u);
+  if (pos) {
+    pos[3 * i] = a.x;
+    pos[3 * i + 1] = a.y;
+    pos[3 * i + 2] = a.z;
+  }
+  if (rho) rho[i] = a.w;
+  if (vel) {
+    vel[3 * i] = b.x;
+    vel[3 * i + 1] = b.y;
+    vel[3 * i + 2] = b.z;
+  }
+  if (sig) {
+    sig[6 * i] = c.x;
+    sig[6 * i + 1] = c.y;
+    sig[6 * i + 2] = c.z;
+    sig[6 * i + 3] = c.w;
+    sig[6 * i + 4] = d.x;
+    sig[6 * i + 5] = d.y;
+  }
+}
+
 }  // namespace
 
 hipError_t adj_local2(const int32_t* rows, int64_t n, Planes Ln, Planes Lm, Planes E, CPlanes Yn, CPlanes Ym,
@@ -689,6 +744,20 @@ hipError_t adj_to_ids(const int32_t* rows, int64_t n, const int32_t* slot_id, CP
 hipError_t adj_params_to_ids(int64_t n_proc, const int32_t* slot_id, float* pg, double* pid, hipStream_t s) {
   if (n_proc <= 0) return hipSuccess;
   k_adj_params_to_ids<<<nblk(n_proc), kBlock, 0, s>>>(n_proc, slot_id, pg, pid);
+  return hipGetLastError();
+}
+
+hipError_t adj_pack(int64_t n, const double* pos, const float* vel, const float* sig, const float* rho, Planes out,
+                    hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_adj_pack<<<nblk(n), kBlock, 0, s>>>(n, pos, vel, sig, rho, out);
+  return hipGetLastError();
+}
+
+hipError_t adj_unpack(int64_t n, CPlanes in, double* pos, float* vel, float* sig, float* rho, uint32_t* bad,
+                      hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_adj_unpack<<<nblk(n), kBlock, 0, s>>>(n, in, pos, vel, sig, rho, bad);
   return hipGetLastError();
 }
 

@@ -1206,24 +1206,21 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
          take(r.t1.l2, nt) && take(r.t2.l0, nt) && take(r.t2.l1, nt) && take(r.t2.l2, nt) && take(r.t2.t0, nt) &&
          take(r.t2.t1, nt);
   if (!ok) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
-  // seeds on the recorded end state (particle-id order) and on the body forces
+  // seeds on the recorded end state (particle-id order): the caller's arrays
+  // as they are, packed on the device; and on the body forces
   {
-    std::vector<float4> ha((size_t)ns), hb((size_t)ns), hc((size_t)ns), hd((size_t)ns);
-    for (int64_t i = 0; i < ns; ++i) {
-      ha[i] = make_float4(lam_pos ? (float)lam_pos[3 * i] : 0.f, lam_pos ? (float)lam_pos[3 * i + 1] : 0.f,
-                          lam_pos ? (float)lam_pos[3 * i + 2] : 0.f, lam_rho ? lam_rho[i] : 0.f);
-      hb[i] = make_float4(lam_vel ? lam_vel[3 * i] : 0.f, lam_vel ? lam_vel[3 * i + 1] : 0.f,
-                          lam_vel ? lam_vel[3 * i + 2] : 0.f, 0.f);
-      const float* g = lam_sigma ? lam_sigma + 6 * i : nullptr;
-      hc[i] = g ? make_float4(g[0], g[1], g[2], g[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
-      hd[i] = g ? make_float4(g[4], g[5], 0.f, 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    double* dpos = nullptr;
+    float *dvel = nullptr, *dsig = nullptr, *drho = nullptr;
     if (ns > 0) {
-      const size_t b = sizeof(float4) * (size_t)ns;
-      HIPCHK(c, hipMemcpyAsync(Lid.a, ha.data(), b, hipMemcpyHostToDevice, s));
-      HIPCHK(c, hipMemcpyAsync(Lid.b, hb.data(), b, hipMemcpyHostToDevice, s));
-      HIPCHK(c, hipMemcpyAsync(Lid.c, hc.data(), b, hipMemcpyHostToDevice, s));
-      HIPCHK(c, hipMemcpyAsync(Lid.d, hd.data(), b, hipMemcpyHostToDevice, s));
+      if (lam_pos && !take(dpos, 3 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (lam_vel && !take(dvel, 3 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (lam_sigma && !take(dsig, 6 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (lam_rho && !take(drho, ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (dpos) HIPCHK(c, hipMemcpyAsync(dpos, lam_pos, sizeof(double) * 3 * ns, hipMemcpyHostToDevice, s));
+      if (dvel) HIPCHK(c, hipMemcpyAsync(dvel, lam_vel, sizeof(float) * 3 * ns, hipMemcpyHostToDevice, s));
+      if (dsig) HIPCHK(c, hipMemcpyAsync(dsig, lam_sigma, sizeof(float) * 6 * ns, hipMemcpyHostToDevice, s));
+      if (drho) HIPCHK(c, hipMemcpyAsync(drho, lam_rho, sizeof(float) * ns, hipMemcpyHostToDevice, s));
+      HIPCHK(c, crm::adj_pack(ns, dpos, dvel, dsig, drho, Lid, s));
     }
     if (force_seed) {
       std::vector<double> f((size_t)c->rec_n * nb * 6, 0.0);
@@ -1304,30 +1301,29 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
   HIPCHK(c, crm::segment_reduce(ptmp, gplan, gsum, s));
   std::vector<double> hsum((size_t)6 * ngrp);
   HIPCHK(c, hipMemcpyAsync(hsum.data(), gsum, sizeof(double) * hsum.size(), hipMemcpyDeviceToHost, s));
-  // adjoint of the recorded start state
+  // adjoint of the recorded start state: unpacked on the device, copied into
+  // the caller's arrays
   {
-    std::vector<float4> ha((size_t)ns), hb((size_t)ns), hc((size_t)ns), hd((size_t)ns);
+    double* dpos = nullptr;
+    float *dvel = nullptr, *dsig = nullptr, *drho = nullptr;
+    uint32_t* dbad = nullptr;
+    if (!take(dbad, 1)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+    HIPCHK(c, crm::fill_u32(dbad, 0u, 1, s));
     if (ns > 0) {
-      const size_t b = sizeof(float4) * (size_t)ns;
-      HIPCHK(c, hipMemcpyAsync(ha.data(), Lid.a, b, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(hb.data(), Lid.b, b, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(hc.data(), Lid.c, b, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(hd.data(), Lid.d, b, hipMemcpyDeviceToHost, s));
+      if (out_pos && !take(dpos, 3 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (out_vel && !take(dvel, 3 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (out_sigma && !take(dsig, 6 * ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      if (out_rho && !take(drho, ns)) return done(fail(c, CRM_E_NOMEM, "adjoint allocation failed"));
+      HIPCHK(c, crm::adj_unpack(ns, Lid, dpos, dvel, dsig, drho, dbad, s));
+      if (dpos) HIPCHK(c, hipMemcpyAsync(out_pos, dpos, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+      if (dvel) HIPCHK(c, hipMemcpyAsync(out_vel, dvel, sizeof(float) * 3 * ns, hipMemcpyDeviceToHost, s));
+      if (dsig) HIPCHK(c, hipMemcpyAsync(out_sigma, dsig, sizeof(float) * 6 * ns, hipMemcpyDeviceToHost, s));
+      if (drho) HIPCHK(c, hipMemcpyAsync(out_rho, drho, sizeof(float) * ns, hipMemcpyDeviceToHost, s));
     }
+    uint32_t hbad = 0;
+    HIPCHK(c, hipMemcpyAsync(&hbad, dbad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    bool finite = true;
-    for (int64_t i = 0; i < ns; ++i) {
-      const float v[13] = {ha[i].x, ha[i].y, ha[i].z, ha[i].w, hb[i].x, hb[i].y, hb[i].z,
-                           hc[i].x, hc[i].y, hc[i].z, hc[i].w, hd[i].x, hd[i].y};
-      for (float x : v) finite = finite && std::isfinite(x);
-      if (out_pos) { out_pos[3 * i] = ha[i].x; out_pos[3 * i + 1] = ha[i].y; out_pos[3 * i + 2] = ha[i].z; }
-      if (out_rho) out_rho[i] = ha[i].w;
-      if (out_vel) { out_vel[3 * i] = hb[i].x; out_vel[3 * i + 1] = hb[i].y; out_vel[3 * i + 2] = hb[i].z; }
-      if (out_sigma) {
-        float* o = out_sigma + 6 * i;
-        o[0] = hc[i].x; o[1] = hc[i].y; o[2] = hc[i].z; o[3] = hc[i].w; o[4] = hd[i].x; o[5] = hd[i].y;
-      }
-    }
+    bool finite = hbad == 0;
     if (out_params) {
       double dG = 0.0, dK = 0.0;
       for (int32_t g = 0; g < ngrp; ++g) {

@@ -267,6 +267,13 @@ hipError_t adj_to_ids(const int32_t* rows, int64_t n, const int32_t* slot_id, CP
                       hipStream_t s);
 hipError_t adj_params_to_ids(int64_t n_proc, const int32_t* slot_id, float* pg, double* pid, hipStream_t s);
 hipError_t adj_params_permute(int64_t n, const int32_t* perm, const double* pid, double* out, hipStream_t s);
+// End-state seeds from flat device arrays (x, y, z doubles; u, stress, rho
+// floats; any may be null) into id-ordered adjoint planes, and the adjoint of
+// the start state back into flat arrays (*bad |= 1 on a non-finite value).
+hipError_t adj_pack(int64_t n, const double* pos, const float* vel, const float* sig, const float* rho, Planes out,
+                    hipStream_t s);
+hipError_t adj_unpack(int64_t n, CPlanes in, double* pos, float* vel, float* sig, float* rho, uint32_t* bad,
+                      hipStream_t s);
 
 // Scatter working records back to the master planes.
 hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
