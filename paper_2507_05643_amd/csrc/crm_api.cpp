@@ -3,6 +3,7 @@
 // hashing, sort, neighbour lists) and the two-stage step of Sec. 2.3.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -57,7 +58,7 @@ struct crm_ctx {
   std::vector<uint16_t> h_mat; // material of each soil particle (empty: all 0)
   std::vector<Body> h_bodies;
   std::vector<int64_t> h_nmark;  // markers per body
-  double* d_forces = nullptr;
+  double* d_fmap = nullptr;       // device alias of h_fpin: the body sums are written there
   uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
 
   // cell grid
@@ -104,8 +105,9 @@ struct crm_ctx {
   int64_t last_rebuild = 0;
   uint32_t* d_disp = nullptr;
   uint32_t* h_disp = nullptr;
-  // co-simulation exchange through pinned staging: body states up, forces and
-  // torques back (6 per body), each with its completion event
+  // co-simulation exchange: body states up through pinned staging; forces and
+  // torques (6 per body) written by the device into mapped pinned memory;
+  // each with its completion event
   Body* h_bpin = nullptr;
   double* h_fpin = nullptr;
   hipEvent_t bpin_ev = nullptr, fpin_ev = nullptr;
@@ -647,7 +649,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
                               c->tile_cfg, s));
   if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c, 6);
-  HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_forces, s));
+  HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_fmap, s));
   if (prof) prof_end(c, 6, e);
   return CRM_OK;
 }
@@ -951,7 +953,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   bool ok = alloc_n(c, c->m_a, n_total) && alloc_n(c, c->m_b, n_total) && alloc_n(c, c->m_c, n_total) &&
             alloc_n(c, c->m_d, n_total) && alloc_n(c, c->local, nm) && alloc_n(c, c->flags, crm::flags_padded(n_total)) &&
             alloc_n(c, c->proc_ids, n_total) && alloc_n(c, c->d_bodies, n_bodies > 0 ? n_bodies : 1) &&
-            alloc_n(c, c->d_forces, 6 * (n_bodies > 0 ? n_bodies : 1)) && alloc_n(c, c->ctmp, nbk) &&
+            alloc_n(c, c->ctmp, nbk) &&
             alloc_n(c, c->cell_cnt, M) && alloc_n(c, c->cell_start, M + 1) &&
             alloc_n(c, c->cell_tmp, (int64_t)crm::scan_tmp_elems(M)) && alloc_n(c, c->d_counts, 8) &&
             alloc_n(c, c->d_mat, crm::kMaxMaterials) && alloc_n(c, c->contrib, 6 * nm) &&
@@ -968,8 +970,15 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   {
     const size_t nbp = (size_t)(n_bodies > 0 ? n_bodies : 1);
     if (hipHostMalloc((void**)&c->h_bpin, sizeof(Body) * nbp, hipHostMallocDefault) != hipSuccess) c->h_bpin = nullptr;
-    if (hipHostMalloc((void**)&c->h_fpin, sizeof(double) * 6 * nbp, hipHostMallocDefault) != hipSuccess)
+    // the force sums go straight to host memory: pinned, mapped, coherent
+    if (hipHostMalloc((void**)&c->h_fpin, sizeof(double) * 6 * nbp, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->d_fmap, c->h_fpin, 0) != hipSuccess) {
+      if (c->h_fpin) (void)hipHostFree(c->h_fpin);
       c->h_fpin = nullptr;
+    } else {
+      std::memset(c->h_fpin, 0, sizeof(double) * 6 * nbp);
+    }
     if (!c->h_bpin || !c->h_fpin || hipEventCreateWithFlags(&c->bpin_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->fpin_ev, hipEventDisableTiming) != hipSuccess) {
       release(c);
@@ -996,7 +1005,6 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_bodies, c->h_bodies.data(), sizeof(Body) * c->h_bodies.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, (size_t)crm::flags_padded(n_total), s);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d_forces, 0, sizeof(double) * 6 * (size_t)(n_bodies > 0 ? n_bodies : 1), s);
   std::vector<int64_t> bstart((size_t)n_bodies + 1, 0);
   for (int b = 0; b < n_bodies; ++b) bstart[b + 1] = bstart[b] + bodies[b].n_markers;
   if (e == hipSuccess)
@@ -1356,10 +1364,10 @@ crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque)
   if ((!force || !torque) && nb > 0) return fail(c, CRM_E_INVALID, "force and torque are required");
   if (!c->stepped) return fail(c, CRM_E_STATE, "no step taken yet");
   if (nb == 0) return CRM_OK;
-  HIPCHK(c, hipMemcpyAsync(c->h_fpin, c->d_forces, sizeof(double) * 6 * (size_t)nb, hipMemcpyDeviceToHost,
-                           c->stream));
+  // the last step's reduction wrote the sums into h_fpin (mapped host memory)
   HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
   HIPCHK(c, poll_event(c->fpin_ev));
+  std::atomic_thread_fence(std::memory_order_acquire);
   const double* h = c->h_fpin;
   for (int b = 0; b < nb; ++b)
     for (int a = 0; a < 3; ++a) {
