@@ -1525,9 +1525,11 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   int32_t s = 0;
   uint64_t k0 = 0, k1 = 0;
   float4 ma = make_float4(0.f, 0.f, 0.f, 1.f), mb = make_float4(0.f, 0.f, 0.f, 0.f), mc = mb, md = mb;
+  float4 ya = mb, yb = mb, yc = mb, yd = mb;
   if (live) {
     s = rows[r];
     ma = B.a[s]; mb = B.b[s]; mc = B.c[s]; md = B.d[s];
+    ya = A.a[s]; yb = A.b[s]; yc = A.c[s]; yd = A.d[s];
     k0 = off[r];
     k1 = off[r + 1];
   }
@@ -1549,11 +1551,12 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
     }, P);
   }
   if (!live) return;
-  // Every lane loads the whole y_n record and computes the whole y_{n+1}
-  // record; one store then writes plane gl from lane gl < 4. The return
-  // mapping needs sigma_n from planes c and d, so no lane may read a plane
-  // after another lane of the group has overwritten it.
-  finish_stage2<CELL, TAPE>(A, s, gl, A.a[s], A.b[s], A.c[s], A.d[s], R, P, T);
+  // Every lane loads the whole y_n record (before the walk, so that the loads
+  // overlap it) and computes the whole y_{n+1} record; one store then writes
+  // plane gl from lane gl < 4. The return mapping needs sigma_n from planes c
+  // and d, so no lane may read a plane after another lane of the group has
+  // overwritten it.
+  finish_stage2<CELL, TAPE>(A, s, gl, ya, yb, yc, yd, R, P, T);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* __restrict__ rows, int64_t n,
