@@ -1022,10 +1022,17 @@ struct StageTile<true, CAP> {
   float4 a[CAP], b[CAP], c[CAP], d[CAP];
 };
 
+// Records per tile: the small tiles are the largest that leave four
+// workgroups per CU (160 KB of LDS, allocated in 512-byte granules: at most
+// 40 KB each), the large ones three.
 template <bool CELL, int CFG>
 constexpr uint32_t tile_cap() {
-  return CFG == 0 ? 1u : CFG == 1 ? (CELL ? 640u : 768u) : (CELL ? 832u : 1024u);
+  return CFG == 0 ? 1u : CFG == 1 ? (CELL ? 640u : 787u) : (CELL ? 832u : 1024u);
 }
+static_assert(sizeof(StageTile<false, tile_cap<false, 1>()>) <= 40960, "four small tiles per CU");
+static_assert(sizeof(StageTile<true, tile_cap<true, 1>()>) <= 40960, "four small tiles per CU");
+static_assert(sizeof(StageTile<false, tile_cap<false, 2>()>) <= 54272, "three large tiles per CU");
+static_assert(sizeof(StageTile<true, tile_cap<true, 2>()>) <= 54272, "three large tiles per CU");
 
 // Per block of kRows rows, computed once per list rebuild (k_tile_tables):
 // words 0-8 first slot of each of the nine ranges (~0: outside the grid),
@@ -1295,35 +1302,48 @@ __device__ inline Nbr tile_rec(const StageTile<CELL, CAP>& T, uint32_t o) {
   return n;
 }
 
-// The walk of a row through the tile, two entries per lane and iteration: both
+// The walk of a row through the tile, two entries per lane and step: both
 // tile reads are issued before either pair is computed, and the tile positions
-// four entries ahead are in flight meanwhile. The pairs are still taken in
-// entry order. pos(k) is the tile position of entry k (relative to the
-// block's first entry); e0..e1 are the row's entries; past the row's end the
-// walk reads its first entry again (a valid position).
+// four entries ahead are in flight meanwhile (the loop body holds two steps,
+// so that the positions in flight need no register moves). The pairs are still
+// taken in entry order. pos(k) is the tile position of entry k (relative to
+// the block's first entry); e0..e1 are the row's entries; past the row's end
+// the walk reads its last entry again (a valid position).
 template <bool CELL, uint32_t CAP, class Pos, class Fn>
 __device__ inline void walk_tile_pos(const StageTile<CELL, CAP>& T, const Pos& pos_of, uint32_t e0, uint32_t e1,
                                      Fn&& f) {
   constexpr uint32_t G = kGroup;
   const uint32_t ef = e0 + group_lane();
   if (ef >= e1) return;
-  auto pos = [&](uint32_t e) { return pos_of(e < e1 ? e : ef); };
+  const uint32_t el = e1 - 1;
+  auto pos = [&](uint32_t e) { return pos_of(e < el ? e : el); };
   uint32_t e = ef;
   uint32_t o0 = pos(e), o1 = pos(e + G), o2 = pos(e + 2 * G), o3 = pos(e + 3 * G);
   for (;;) {
-    const bool has1 = e + G < e1;
-    const bool more = e + 2 * G < e1;
-    const uint32_t o4 = pos(e + 4 * G), o5 = pos(e + 5 * G);
-    const Nbr a = tile_rec(T, o0);
-    const Nbr b = tile_rec(T, o1);
-    f(a);
-    if (has1) f(b);
-    if (!more) break;
-    o0 = o2;
-    o1 = o3;
-    o2 = o4;
-    o3 = o5;
-    e += 2 * G;
+    {
+      const bool has1 = e + G < e1;
+      const bool more = e + 2 * G < e1;
+      const Nbr a = tile_rec(T, o0);
+      const Nbr b = tile_rec(T, o1);
+      o0 = pos(e + 4 * G);
+      o1 = pos(e + 5 * G);
+      f(a);
+      if (has1) f(b);
+      if (!more) break;
+      e += 2 * G;
+    }
+    {
+      const bool has1 = e + G < e1;
+      const bool more = e + 2 * G < e1;
+      const Nbr a = tile_rec(T, o2);
+      const Nbr b = tile_rec(T, o3);
+      o2 = pos(e + 4 * G);
+      o3 = pos(e + 5 * G);
+      f(a);
+      if (has1) f(b);
+      if (!more) break;
+      e += 2 * G;
+    }
   }
 }
 
