@@ -74,6 +74,7 @@ struct crm_ctx {
   int32_t* slot_id = nullptr;
   int32_t* slot_k = nullptr;     // processed index (position in the processed id list)
   uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
+  uint32_t* tmpx = nullptr;     // x order keys beside tmp (sort inside cells)
   int32_t *frows = nullptr, *mrows = nullptr;
   int32_t* near = nullptr;       // marker rows (indices into mrows) with soil neighbours
   int64_t n_near = 0;
@@ -292,7 +293,7 @@ void quat_to_R(const double q[4], double R[9]) {
 
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
   void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id, c->slot_k,
-                  c->skey, c->key, c->rank, c->tmp, c->frows, c->mrows, c->near, c->cnt_f, c->cnt_m, c->off_f,
+                  c->skey, c->key, c->rank, c->tmp, c->tmpx, c->frows, c->mrows, c->near, c->cnt_f, c->cnt_m, c->off_f,
                   c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
   for (void* p : olds) dfree(c, p);
   c->A = Planes{};
@@ -300,7 +301,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
   c->pos4 = nullptr;
   c->cpos = nullptr;
   c->slot_id = c->slot_k = c->frows = c->mrows = c->near = nullptr;
-  c->skey = c->key = c->rank = c->tmp = c->cnt_f = c->cnt_m = nullptr;
+  c->skey = c->key = c->rank = c->tmp = c->tmpx = c->cnt_f = c->cnt_m = nullptr;
   c->off_f = c->off_m = c->wtmp = nullptr;
   c->stash_f = c->stash_m = nullptr;
   c->tabs = nullptr;
@@ -311,7 +312,8 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
             alloc_n(c, c->cpos, c->grid.cell ? cap : 1) &&
             alloc_n(c, c->slot_id, cap) && alloc_n(c, c->slot_k, cap) && alloc_n(c, c->skey, cap) &&
             alloc_n(c, c->key, cap) &&
-            alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->frows, cap) &&
+            alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->tmpx, cap) &&
+            alloc_n(c, c->frows, cap) &&
             alloc_n(c, c->mrows, cap) && alloc_n(c, c->near, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
             alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
             alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
@@ -515,8 +517,8 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, c->M, s));
   HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->m_d, c->grid, c->key, c->rank, c->cell_cnt, s));
   HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
-  HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, c->tmp, s));
-  HIPCHK(c, crm::gather_sorted(c->tmp, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
+  HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, ids, c->m_a, c->tmp, c->tmpx, s));
+  HIPCHK(c, crm::gather_sorted(c->tmp, c->tmpx, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
                                c->m_d, c->A, c->B, c->pos4, c->cpos, c->slot_id, c->slot_k, c->skey,
                                c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));

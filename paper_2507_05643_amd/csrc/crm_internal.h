@@ -141,11 +141,13 @@ hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint
 // Cell hash with per-cell arrival counts (counting sort, part 1).
 hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a, const float4* m_d,
                       Grid g, uint32_t* key, uint32_t* rank, uint32_t* cell_cnt, hipStream_t s);
-// Place into cell order (part 2), then rank by id inside each cell and gather
-// the master state into the sorted working set (part 3).
+// Place into cell order with an x order key per place (part 2), then rank by
+// (x, id) inside each cell and gather the master state into the sorted
+// working set (part 3).
 hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cell_start,
-                        int64_t n_proc, uint32_t* tmp, hipStream_t s);
-hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* proc_ids,
+                        int64_t n_proc, const int32_t* proc_ids, const float4* m_a, uint32_t* tmp,
+                        uint32_t* tmpx, hipStream_t s);
+hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* tmpx, const uint32_t* key, const int32_t* proc_ids,
                          const uint32_t* cell_start, int64_t n_proc, int64_t n_soil,
                          const uint8_t* flags, const float4* m_a, const float4* m_b,
                          const float4* m_c, const float4* m_d, Planes A, Planes B, float4* pos4,
@@ -172,10 +174,13 @@ hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_ro
                      hipStream_t s);
 // The count pass of the soil rows (not soil-only) with each block's
 // candidates staged in LDS through the tile tables (tile_tables, computed for
-// the same rows and device count before it); same results as nbr_count.
+// the same rows and device count right before it); same results as
+// nbr_count. It cuts the ranges of the blocks it stages to the x interval
+// their rows reach and writes the cut ranges back into tabs, so each call
+// needs fresh tables.
 hipError_t nbr_count_soil(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
                           const int4* cpos, const uint32_t* skey, const uint32_t* cell_start, Grid g,
-                          const uint32_t* tabs, uint32_t* cnt, uint32_t* stash, hipStream_t s);
+                          uint32_t* tabs, uint32_t* cnt, uint32_t* stash, hipStream_t s);
 hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos,
                     const uint32_t* skey, const uint32_t* cell_start, Grid g, bool soil_only,
                     const uint32_t* cnt, const uint32_t* stash, const uint64_t* off, uint32_t* nbr,
@@ -240,6 +245,7 @@ hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* frows, int64_t n_fro
                         const uint16_t* tix, int cfg, hipStream_t s);
 // Per block of soil rows: the nine slot ranges its rows' neighbours lie in
 // (tile_table_words(rows_cap) words); the row count is read on the device.
+// nbr_count_soil cuts the ranges of the blocks it stages.
 int64_t tile_table_words(int64_t rows_cap);
 hipError_t tile_tables(const int32_t* frows, int64_t rows_cap, const uint64_t* n_frows_dev, const uint32_t* skey,
                        const uint32_t* cell_start, Phys P, uint32_t* tabs, hipStream_t s);

@@ -383,30 +383,59 @@ __global__ __launch_bounds__(kBlock) void k_hash_count(const int32_t* __restrict
   rank[k] = atomicAdd(&cnt[c], 1u);
 }
 
-__global__ __launch_bounds__(kBlock) void k_place(const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-                                                  const uint32_t* __restrict__ cs, int64_t n,
-                                                  uint32_t* __restrict__ tmp) {
-  int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  tmp[cs[key[k]] + rank[k]] = (uint32_t)k;
+// Order-preserving maps of FP32 / FP64 values onto unsigned integers (total
+// orders, NaNs included), and back.
+__device__ inline uint32_t f32_order_key(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline unsigned long long f64_order_key(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ inline double f64_from_order_key(unsigned long long k) {
+  return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
 }
 
-// Sec. 4.1 step 2 (sort by cell, ties by particle id): the atomic arrival order
-// inside a cell is replaced by the id order (a cell holds ~10-20 particles), and
-// the master state is gathered into the cell-sorted working planes.
+// Arrival position of particle k in its cell, with the x coordinate (the
+// stored one: absolute, or the offset in the cell for cell-offset positions)
+// as an order key beside it.
+__global__ __launch_bounds__(kBlock) void k_place(const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
+                                                  const uint32_t* __restrict__ cs, int64_t n,
+                                                  const int32_t* __restrict__ ids, const float4* __restrict__ m_a,
+                                                  uint32_t* __restrict__ tmp, uint32_t* __restrict__ tmpx) {
+  int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int64_t id = ids ? ids[k] : k;
+  const uint32_t at = cs[key[k]] + rank[k];
+  tmp[at] = (uint32_t)k;
+  tmpx[at] = f32_order_key(m_a[id].x);
+}
+
+// Sec. 4.1 step 2 (sort by cell): the order inside a cell, which the hash sort
+// leaves open, is made deterministic and spatial: by x, ties by particle id
+// (a cell holds ~10-20 particles). A (y, z) row of cells is then ordered by x
+// from end to end, so a block's neighbour ranges can be cut to the x interval
+// its rows reach. The master state is gathered into the cell-sorted working
+// planes.
 __global__ __launch_bounds__(kBlock) void k_gather_sorted(
-    const uint32_t* __restrict__ tmp, const uint32_t* __restrict__ key, const int32_t* __restrict__ ids,
-    const uint32_t* __restrict__ cs, int64_t n, int64_t n_soil, const uint8_t* __restrict__ flags,
-    const float4* __restrict__ m_a, const float4* __restrict__ m_b, const float4* __restrict__ m_c,
-    const float4* __restrict__ m_d, Planes A, Planes B, float4* __restrict__ pos4, int4* __restrict__ cpos,
-    int cell, int32_t* __restrict__ slot_id, int32_t* __restrict__ slot_k, uint32_t* __restrict__ skey) {
+    const uint32_t* __restrict__ tmp, const uint32_t* __restrict__ tmpx, const uint32_t* __restrict__ key,
+    const int32_t* __restrict__ ids, const uint32_t* __restrict__ cs, int64_t n, int64_t n_soil,
+    const uint8_t* __restrict__ flags, const float4* __restrict__ m_a, const float4* __restrict__ m_b,
+    const float4* __restrict__ m_c, const float4* __restrict__ m_d, Planes A, Planes B, float4* __restrict__ pos4,
+    int4* __restrict__ cpos, int cell, int32_t* __restrict__ slot_id, int32_t* __restrict__ slot_k,
+    uint32_t* __restrict__ skey) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
   uint32_t k = tmp[p];
+  const uint32_t xk = tmpx[p];
   uint32_t c = key[k];
   uint32_t lo = cs[c], hi = cs[c + 1];
   uint32_t r = 0;
-  for (uint32_t q = lo; q < hi; ++q) r += (tmp[q] < k) ? 1u : 0u;   // ids ascend with k
+  for (uint32_t q = lo; q < hi; ++q) {   // ids ascend with k
+    const uint32_t xq = tmpx[q];
+    r += (xq < xk || (xq == xk && tmp[q] < k)) ? 1u : 0u;
+  }
   uint32_t f = lo + r;
   int64_t id = ids ? ids[k] : (int64_t)k;
   slot_id[f] = (int32_t)id;
@@ -449,16 +478,18 @@ __device__ inline double dist2_cell(float4 pi, int4 ci, float4 pj, int4 cj, doub
 // or to within (|dc| + 2) ulps of S (cell mode, dc the cell difference of
 // the stored positions), and squaring and summing add a few ulps of the result;
 // the band's half-width 2^-14 R2 exceeds these bounds by far.
-// Candidate j of the (dz, dy) run k = 3 (dz + 1) + dy + 1, straight from the
-// planes.
+// Candidates straight from the planes. run(k, b, e) gives the loader of the
+// (dz, dy) run k = 3 (dz + 1) + dy + 1 and may narrow [b, e) to a part known
+// to hold every neighbour (here the whole run stays).
 template <bool CELL>
 struct ScanLoad {
   const float4* pos4;
   const int4* cpos;
-  __device__ void operator()(uint32_t j, int, float4& p, int4& cj) const {
+  __device__ void operator()(uint32_t j, float4& p, int4& cj) const {
     p = at(pos4, j);
     if (CELL) cj = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(cpos) + (j << 4));
   }
+  __device__ ScanLoad run(int, uint32_t&, uint32_t&) const { return *this; }
 };
 
 template <bool FILL, bool CELL, bool SOIL_ONLY, class Load, class Emit>
@@ -488,13 +519,14 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         b = cs[row + x0];
         e = cs[row + x1 + 1];
       }
+      const auto run = load.run(k, b, e);
       for (uint32_t j0 = b; j0 < e; j0 += kGroup) {
         const uint32_t j = j0 + gl;
         bool hit = false;
         if (j < e) {
           float4 pj;
           int4 cj = make_int4(0, 0, 0, 0);
-          load(j, k, pj, cj);
+          run(j, pj, cj);
           if (!SOIL_ONLY || (__float_as_uint(pj.w) & 3u) != kMarker) {
             float sx = pi.x - pj.x, sy = pi.y - pj.y, sz = pi.z - pj.z;
             if (CELL) {
@@ -1038,7 +1070,9 @@ static_assert(sizeof(StageTile<true, tile_cap<true, 2>()>) <= 54272, "three larg
 // words 0-8 first slot of each of the nine ranges (~0: outside the grid),
 // 9-17 offset o_k (slot j of range k sits at tile index j - o_k), 18 total
 // records, 19 whether the block's rows lie in one row of cells. A block uses
-// its tile when they do and the total fits the tile.
+// its tile when they do and the total fits the tile. The ranges start as
+// whole cells x_first - 1 .. x_last + 1; the count pass then cuts them to
+// the x interval the block's rows reach (k_nbr_count_soil).
 constexpr int kTabWords = 20;
 
 __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows,
@@ -1208,17 +1242,50 @@ struct ScanTile<true> {
   int4 c[kScanCap];
 };
 
+// Candidates from the block's LDS tile: run k reads slot j at tile index
+// j - o_k and is cut to the block's range k [lo_k, hi_k), which holds every
+// neighbour of the block's rows. o, lo, hi: the block's run table in LDS.
 template <bool CELL>
 struct ScanTileLoad {
   const ScanTile<CELL>* T;
-  uint32_t o[9];
-  __device__ void operator()(uint32_t j, int k, float4& p, int4& cj) const {
-    const uint32_t t = j - o[k];
-    p = T->p[t];
-    if constexpr (CELL) cj = T->c[t];
+  const uint32_t* rt;              // o[9], lo[9], hi[9]
+  struct Run {
+    const ScanTile<CELL>* T;
+    uint32_t o;
+    __device__ void operator()(uint32_t j, float4& p, int4& cj) const {
+      const uint32_t t = j - o;
+      p = T->p[t];
+      if constexpr (CELL) cj = T->c[t];
+    }
+  };
+  __device__ Run run(int k, uint32_t& b, uint32_t& e) const {
+    const uint32_t lo = rt[9 + k], hi = rt[18 + k];
+    b = b > lo ? b : lo;
+    e = e < hi ? e : hi;
+    return Run{T, rt[k]};
   }
 };
 
+// x of tile record t in FP64: absolute, or cell index times cell size plus
+// offset.
+template <bool CELL>
+__device__ inline double tile_x(const ScanTile<CELL>& T, uint32_t t, double S) {
+  if constexpr (CELL) return (double)T.c[t].x * S + (double)T.p[t].x;
+  else return (double)T.p[t].x;
+}
+
+// Count pass of the soil rows. A block whose rows lie in one row of cells
+// and whose ranges (whole cells x_first - 1 .. x_last + 1 of the nine (y, z)
+// rows) fit kScanCap records stages their positions in LDS and cuts each
+// range to the slots whose x lies within [x_min - R', x_max + R']: x_min,
+// x_max are the extremes of the block's rows and R' is the list radius
+// widened by 2^-20, far above the FP64 rounding of the separations; every
+// neighbour j of a row i has |x_i - x_j| <= R, so every neighbour of the
+// block stays in. Cells hold their slots in x order, so only the first cell
+// of a range loses a leading run and only the last cell a trailing one. The
+// block then scans its rows' runs cut to the ranges and writes the cut
+// ranges back into its table, so that the fill pass and the stage kernels
+// copy only those records into their tiles.
 template <bool CELL>
 __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __restrict__ rows, int64_t rows_cap,
                                                            const uint64_t* __restrict__ n_rows_dev,
@@ -1226,9 +1293,12 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
                                                            const int4* __restrict__ cpos,
                                                            const uint32_t* __restrict__ skey,
                                                            const uint32_t* __restrict__ cs, Grid g,
-                                                           const uint32_t* __restrict__ tabs,
+                                                           uint32_t* __restrict__ tabs,
                                                            uint32_t* __restrict__ cnt, uint32_t* __restrict__ stash) {
   __shared__ ScanTile<CELL> tile;
+  __shared__ uint32_t rt[27];     // run table: o_k of the staged layout, cut bounds lo_k, hi_k
+  __shared__ uint32_t ct[36];     // per range: first slot, o_k, leading cut, trailing cut
+  __shared__ unsigned long long xext[2];   // order keys of the rows' x extremes
   const int64_t nr = (int64_t)*n_rows_dev;
   const int64_t nb_live = (nr * kGroup + kBlock - 1) / kBlock;
   const int64_t blk = xcd_block_n(nb_live);
@@ -1246,15 +1316,11 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
     out = stash + (uint64_t)r * kStash;
   }
   bool staged = false;
-  ScanTileLoad<CELL> tl;
-  tl.T = &tile;
   if (blk < nb_live) {                      // uniform over the block
-    const uint32_t* tb = tabs + blk * kTabWords;
+    uint32_t* tb = tabs + blk * kTabWords;
     const uint32_t total = tb[18];
     staged = tb[19] != 0 && total <= kScanCap;
     if (staged) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) tl.o[k] = tb[9 + k];
       const TileLoad ld = tile_loader(tb);
       constexpr int kPer = (int)(kScanCap / kBlock);
       float4 p[kPer];
@@ -1268,6 +1334,25 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
           if (CELL) q[u] = cpos[j];
         }
       }
+      // thread t < 18 takes the first (t < 9) or last cell of range k = t % 9
+      const int64_t r0 = blk * kRows;
+      const int64_t rl = (r0 + kRows - 1 < nr) ? r0 + kRows - 1 : nr - 1;
+      const int k = (int)threadIdx.x % 9;
+      uint32_t cb0 = 0, cb1 = 0, st = 0xffffffffu, ok_ = 0;
+      if (threadIdx.x < 18) {
+        st = tb[k];
+        ok_ = tb[9 + k];
+        const uint32_t X = (uint32_t)g.dims[0], Y = (uint32_t)g.dims[1];
+        const uint32_t c0 = skey[rows[r0]], c1 = skey[rows[rl]];
+        const uint32_t x0 = c0 % X, y0 = (c0 / X) % Y, z0 = c0 / (X * Y), x1 = c1 % X;
+        const uint32_t xl = x0 > 0 ? x0 - 1 : 0, xh = x1 + 1 < X ? x1 + 1 : X - 1;
+        if (st != 0xffffffffu) {
+          const uint64_t base = ((uint64_t)(z0 + k / 3 - 1) * Y + (uint64_t)(y0 + k % 3 - 1)) * X;
+          const uint32_t cx = threadIdx.x < 9 ? xl : xh;
+          cb0 = cs[base + cx];
+          cb1 = cs[base + cx + 1];
+        }
+      }
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const uint32_t t = threadIdx.x + (uint32_t)(u * kBlock);
@@ -1276,9 +1361,75 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
           if constexpr (CELL) tile.c[t] = q[u];
         }
       }
+      if (threadIdx.x == 0) {
+        xext[0] = ~0ull;
+        xext[1] = 0ull;
+      }
+      __syncthreads();
+      if (live && group_lane() == 0) {
+        const unsigned long long key = f64_order_key(CELL ? (double)ci.x * g.S + (double)pi.x : (double)pi.x);
+        atomicMin(&xext[0], key);
+        atomicMax(&xext[1], key);
+      }
+      __syncthreads();
+      if (threadIdx.x < 18) {
+        const double Rm = g.S * (1.0 + 0x1p-20);
+        const bool lead = threadIdx.x < 9;
+        const double lim = lead ? f64_from_order_key(xext[0]) - Rm : f64_from_order_key(xext[1]) + Rm;
+        // the cell's slots ascend in x: binary search for the first slot with
+        // x >= lim (leading cut) or x > lim (trailing cut)
+        uint32_t cut = 0;
+        if (st != 0xffffffffu) {
+          uint32_t a = cb0, b = cb1;
+          while (a < b) {
+            const uint32_t m = a + (b - a) / 2;
+            const double x = tile_x(tile, m - ok_, g.S);
+            if (lead ? x < lim : x <= lim) a = m + 1;
+            else b = m;
+          }
+          cut = lead ? a - cb0 : cb1 - a;
+        }
+        if (lead) {
+          ct[k] = st;
+          ct[9 + k] = ok_;
+          ct[18 + k] = cut;
+        } else {
+          ct[27 + k] = cut;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t end = total, nlo[9], nhi[9];
+#pragma unroll
+        for (int m = 8; m >= 0; --m) {
+          const uint32_t sm = ct[m], om = ct[9 + m];
+          if (sm == 0xffffffffu) {
+            nlo[m] = nhi[m] = 0;
+          } else {
+            const uint32_t first = sm - om;
+            nlo[m] = sm + ct[18 + m];
+            nhi[m] = sm + (end - first) - ct[27 + m];
+            if (nhi[m] < nlo[m]) nhi[m] = nlo[m];
+            end = first;
+          }
+        }
+        uint32_t acc = 0;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          rt[m] = ct[9 + m];
+          rt[9 + m] = nlo[m];
+          rt[18 + m] = nhi[m];
+          if (ct[m] == 0xffffffffu) continue;
+          tb[m] = nlo[m];
+          tb[9 + m] = nlo[m] - acc;
+          acc += nhi[m] - nlo[m];
+        }
+        tb[18] = acc;
+      }
     }
     __syncthreads();
   }
+  const ScanTileLoad<CELL> tl{&tile, rt};
   const uint32_t count = staged ? group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, EmitTo{out}, kStash)
                                 : group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g,
                                                                 EmitTo{out}, kStash);
@@ -1696,20 +1847,20 @@ hipError_t hash_count(const int32_t* ids, int64_t n, const float4* m_a, const fl
   return hipGetLastError();
 }
 
-hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cs, int64_t n,
-                        uint32_t* tmp, hipStream_t s) {
+hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cs, int64_t n, const int32_t* ids,
+                        const float4* m_a, uint32_t* tmp, uint32_t* tmpx, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_place<<<nblk(n), kBlock, 0, s>>>(key, rank, cs, n, tmp);
+  k_place<<<nblk(n), kBlock, 0, s>>>(key, rank, cs, n, ids, m_a, tmp, tmpx);
   return hipGetLastError();
 }
 
-hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* key, const int32_t* ids, const uint32_t* cs,
-                         int64_t n, int64_t n_soil, const uint8_t* flags, const float4* m_a,
+hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* tmpx, const uint32_t* key, const int32_t* ids,
+                         const uint32_t* cs, int64_t n, int64_t n_soil, const uint8_t* flags, const float4* m_a,
                          const float4* m_b, const float4* m_c, const float4* m_d, Planes A, Planes B,
                          float4* pos4, int4* cpos, int32_t* slot_id, int32_t* slot_k, uint32_t* skey, bool cell,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_gather_sorted<<<nblk(n), kBlock, 0, s>>>(tmp, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d, A, B,
+  k_gather_sorted<<<nblk(n), kBlock, 0, s>>>(tmp, tmpx, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d, A, B,
                                              pos4, cpos, cell ? 1 : 0, slot_id, slot_k, skey);
   return hipGetLastError();
 }
@@ -1726,7 +1877,7 @@ hipError_t nbr_count(const int32_t* rows, int64_t rows_cap, const uint64_t* n_ro
 }
 
 hipError_t nbr_count_soil(const int32_t* rows, int64_t rows_cap, const uint64_t* n_rows_dev, const float4* pos4,
-                          const int4* cpos, const uint32_t* skey, const uint32_t* cs, Grid g, const uint32_t* tabs,
+                          const int4* cpos, const uint32_t* skey, const uint32_t* cs, Grid g, uint32_t* tabs,
                           uint32_t* cnt, uint32_t* stash, hipStream_t s) {
   if (rows_cap <= 0) return hipSuccess;
   if (g.cell)

@@ -34,3 +34,20 @@ def csr_rows(off, nbr, rows=None):
 
 def fields_report(gpu, ref, n):
     return {k: normwise(gpu[k][:n], ref[k][:n]) for k in ("pos", "vel", "sigma", "rho")}
+
+
+def check_cell_sort(got_ids, sid, cs, ce, x, tol=1e-6):
+    """The GPU's slot order against the oracle's (cell order, ids ascending in
+    a cell). Sec. 4.1 sorts by cell hash and leaves the order inside a cell
+    open: the GPU orders a cell by x. The cells' contents must be equal, and
+    inside every cell the GPU's x must ascend (x: FP64 world positions; tol
+    absorbs the FP32 rounding of the stored positions)."""
+    got = np.asarray(got_ids, dtype=np.int64)
+    sid = np.asarray(sid, dtype=np.int64)
+    assert got.shape == sid.shape
+    cell = np.repeat(np.arange(cs.size), (ce - cs).astype(np.int64))
+    assert cell.size == got.size
+    assert np.array_equal(got[np.lexsort((got, cell))], sid)
+    xs = np.asarray(x, dtype=np.float64)[got, 0]
+    same = cell[1:] == cell[:-1]
+    assert np.all(np.diff(xs)[same] >= -tol)
