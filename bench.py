@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy (fetch x2, write x1); the
 # commands and figures are in profiles/wheel_bin_kernels_lds_tiles.md (small
 # LDS tile). None once the kernel changes.
-STAGE2_TRAFFIC_BYTES = 480.6e6
+STAGE2_TRAFFIC_BYTES = 466.3e6
 
 
 class WheelDriver:
