@@ -212,13 +212,20 @@ struct GlobalLoad {
 };
 
 // Walks entries k0 + lane, k0 + lane + kGroup, ... < k1 of a CSR row and calls
-// f(record, slot) for each, with the record from `load`.
+// f(record, slot) for each, in that order, with the record from `load`. Two
+// entries per lane and step: both slots, then both records, are in flight
+// together (the second pair of loads repeats the first past the row's end).
 template <class Load, class Fn>
 __device__ inline void walk_row_with(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
                                      Fn&& f) {
-  for (uint64_t k = k0 + group_lane(); k < k1; k += kGroup) {
-    const uint32_t j = nbr[k];
-    f(load(j), j);
+  for (uint64_t k = k0 + group_lane(); k < k1; k += 2 * kGroup) {
+    const bool has1 = k + kGroup < k1;
+    const uint32_t j0 = nbr[k];
+    const uint32_t j1 = nbr[has1 ? k + kGroup : k];
+    const Nbr a = load(j0);
+    const Nbr b = load(j1);
+    f(a, j0);
+    if (has1) f(b, j1);
   }
 }
 
