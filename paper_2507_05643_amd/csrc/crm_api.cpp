@@ -77,6 +77,7 @@ struct crm_ctx {
   uint32_t* tmpx = nullptr;     // x order keys beside tmp (sort inside cells)
   int32_t *frows = nullptr, *mrows = nullptr;
   int32_t* near = nullptr;       // marker rows (indices into mrows) with soil neighbours
+  crm::NearRow* nrow = nullptr;  // their slots and list ranges, for the BCE passes
   int64_t n_near = 0;
   uint32_t *cnt_f = nullptr, *cnt_m = nullptr;
   uint64_t *off_f = nullptr, *off_m = nullptr, *wtmp = nullptr;
@@ -293,7 +294,7 @@ void quat_to_R(const double q[4], double R[9]) {
 
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
   void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id, c->slot_k,
-                  c->skey, c->key, c->rank, c->tmp, c->tmpx, c->frows, c->mrows, c->near, c->cnt_f, c->cnt_m, c->off_f,
+                  c->skey, c->key, c->rank, c->tmp, c->tmpx, c->frows, c->mrows, c->near, c->nrow, c->cnt_f, c->cnt_m, c->off_f,
                   c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
   for (void* p : olds) dfree(c, p);
   c->A = Planes{};
@@ -301,6 +302,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
   c->pos4 = nullptr;
   c->cpos = nullptr;
   c->slot_id = c->slot_k = c->frows = c->mrows = c->near = nullptr;
+  c->nrow = nullptr;
   c->skey = c->key = c->rank = c->tmp = c->tmpx = c->cnt_f = c->cnt_m = nullptr;
   c->off_f = c->off_m = c->wtmp = nullptr;
   c->stash_f = c->stash_m = nullptr;
@@ -314,7 +316,7 @@ crm_status realloc_working(crm_ctx* c, int64_t cap) {
             alloc_n(c, c->key, cap) &&
             alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->tmpx, cap) &&
             alloc_n(c, c->frows, cap) &&
-            alloc_n(c, c->mrows, cap) && alloc_n(c, c->near, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
+            alloc_n(c, c->mrows, cap) && alloc_n(c, c->near, cap) && alloc_n(c, c->nrow, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
             alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
             alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
             alloc_n(c, c->stash_f, (int64_t)crm::stash_elems(cap)) &&
@@ -537,6 +539,7 @@ crm_status rebuild(crm_ctx* c) {
   c->n_frows = (int64_t)c->h_counts[1];
   c->n_mrows = (int64_t)c->h_counts[2];
   c->n_near = (int64_t)c->h_counts[5];
+  HIPCHK(c, crm::near_rows(c->mrows, c->near, c->n_near, c->off_m, c->nrow, s));
   // the force entries of markers without soil neighbours stay zero until the
   // next rebuild (the BCE passes skip them)
   HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->contrib), 0u, 12 * c->n_mrows, s));
@@ -626,8 +629,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   if (prof) prof_end(c, 1, e);
   // stage 1 at y_n
   if (prof) e = prof_begin(c, 2);
-  HIPCHK(c, crm::bce(c->A, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
-                     nullptr, s));
+  HIPCHK(c, crm::bce(c->A, c->nrow, c->n_near, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P, nullptr, s));
   if (prof) prof_end(c, 2, e);
   if (rec) {
     crm_status st = copy_planes(c, c->A, rec->yn, c->n_proc, s);
@@ -639,8 +641,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   if (prof) prof_end(c, 3, e);
   // stage 2 at y_mid, body forces from this evaluation
   if (prof) e = prof_begin(c, 4);
-  HIPCHK(c, crm::bce(c->B, c->mrows, c->near, c->n_near, c->off_m, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P,
-                     c->contrib, s));
+  HIPCHK(c, crm::bce(c->B, c->nrow, c->n_near, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P, c->contrib, s));
   if (prof) prof_end(c, 4, e);
   if (rec) {
     crm_status st = copy_planes(c, c->B, rec->ym, c->n_proc, s);
@@ -666,7 +667,7 @@ void drop_graph(crm_ctx* c) {
 
 // Everything the captured kernels bake in: buffers and row counts.
 std::vector<const void*> graph_key(const crm_ctx* c) {
-  return {c->A.a, c->B.a, c->frows, c->mrows, c->near, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->tix_f, c->slot_id,
+  return {c->A.a, c->B.a, c->frows, c->mrows, c->near, c->nrow, c->off_f, c->off_m, c->nbr_f, c->nbr_m, c->tix_f, c->slot_id,
           c->contrib, (const void*)(intptr_t)c->n_frows, (const void*)(intptr_t)c->n_mrows,
           (const void*)(intptr_t)c->n_near,
           (const void*)(intptr_t)c->tile_cfg, (const void*)(intptr_t)c->body_plan.nchunk,

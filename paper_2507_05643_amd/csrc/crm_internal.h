@@ -202,12 +202,21 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const ui
 // marker accelerations and each processed marker's force and torque on its
 // body (FP64, 6 per marker, at entry cidx[slot] - cbase: the marker's rank
 // among the processed markers in id order).
-// Rows: near[0 .. n_near) index the marker rows (into mrows, off) that have
-// soil neighbours (compact_nonzero of the counts); the others are placed with
-// their values by place_markers_working and their contrib entries stay zero.
-hipError_t bce(Planes S, const int32_t* mrows, const int32_t* near, int64_t n_near, const uint64_t* off,
-               const uint32_t* nbr, const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
-               hipStream_t s);
+// Rows: rows[0 .. n_near) are the marker rows that have soil neighbours
+// (near_rows); the others are placed with their values by
+// place_markers_working and their contrib entries stay zero.
+struct NearRow {
+  uint64_t k0;   // first list entry
+  int32_t s;     // slot
+  uint32_t n;    // entries
+};
+// rows[i] = (off[near[i]], mrows[near[i]], off[near[i] + 1] - off[near[i]])
+// for i < n_near, once per list rebuild: the BCE passes then read one record
+// per row instead of three dependent ones.
+hipError_t near_rows(const int32_t* mrows, const int32_t* near, int64_t n_near, const uint64_t* off, NearRow* rows,
+                     hipStream_t s);
+hipError_t bce(Planes S, const NearRow* rows, int64_t n_near, const uint32_t* nbr, const Body* bodies,
+               const int32_t* cidx, int64_t cbase, Phys P, double* contrib, hipStream_t s);
 // Deterministic sums of 6 doubles per entry over contiguous segments: the
 // plan cuts segment g = [start[g], start[g + 1]) into chunks of at most
 // reduce_chunk() entries (lo/hi per chunk, first[g] = first chunk of g,

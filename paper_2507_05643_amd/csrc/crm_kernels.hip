@@ -718,6 +718,17 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
   }
 }
 
+// One record per marker row with soil neighbours (rebuilt with the lists).
+__global__ __launch_bounds__(kBlock) void k_near_rows(const int32_t* __restrict__ mrows,
+                                                      const int32_t* __restrict__ near, int64_t n,
+                                                      const uint64_t* __restrict__ off, NearRow* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = near[i];
+  const uint64_t k0 = off[r];
+  rows[i] = NearRow{k0, mrows[r], (uint32_t)(off[r + 1] - k0)};
+}
+
 // Sec. 2.5.1: Adami velocity u~ = sum u_f W / sum W, no-slip u_s = 2 u_body - u~;
 // stress s_s = [sum s_f W - ((g - a_s) . sum rho_f (x_s - x_f) W) I] / sum W.
 // With `contrib`, the marker acceleration from the momentum equation over the
@@ -725,9 +736,8 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
 // body, at entry cidx[s] - cbase (the marker's rank among the processed
 // markers in id order).
 template <bool FORCE, bool CELL>
-__global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restrict__ mrows,
-                                                const int32_t* __restrict__ near, int64_t n,
-                                                const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbr,
+__global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restrict__ rows, int64_t n,
+                                                const uint32_t* __restrict__ nbr,
                                                 const Body* __restrict__ bodies, const int32_t* __restrict__ cidx,
                                                 int64_t cbase, Phys P, double* __restrict__ contrib) {
   const int64_t i = (xcd_block() * kBlock + threadIdx.x) / kGroup;
@@ -738,14 +748,14 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const int32_t* __restr
   float4 ma = make_float4(0.f, 0.f, 0.f, 0.f), mb = ma, md = ma;
   uint64_t k0 = 0, k1 = 0;
   if (live) {
-    const int64_t r = near[i];
-    s = mrows[r];
+    const NearRow nr = rows[i];
+    s = nr.s;
     ma = S.a[s];
     mb = S.b[s];
     if (CELL) md = S.d[s];
     body = (int)(__float_as_uint(mb.w) >> 2);
-    k0 = off[r];
-    k1 = off[r + 1];
+    k0 = nr.k0;
+    k1 = nr.k0 + nr.n;
   }
   const Own me = own_pos<CELL>(ma, md);
   float sw = 0.f, su0 = 0.f, su1 = 0.f, su2 = 0.f;
@@ -1910,21 +1920,27 @@ hipError_t place_markers_working(const int32_t* mrows, int64_t n, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t bce(Planes S, const int32_t* mrows, const int32_t* near, int64_t n, const uint64_t* off,
-               const uint32_t* nbr, const Body* bodies, const int32_t* cidx, int64_t cbase, Phys P, double* contrib,
-               hipStream_t s) {
+hipError_t near_rows(const int32_t* mrows, const int32_t* near, int64_t n, const uint64_t* off, NearRow* rows,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_near_rows<<<nblk(n), kBlock, 0, s>>>(mrows, near, n, off, rows);
+  return hipGetLastError();
+}
+
+hipError_t bce(Planes S, const NearRow* rows, int64_t n, const uint32_t* nbr, const Body* bodies,
+               const int32_t* cidx, int64_t cbase, Phys P, double* contrib, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned gsz = nblk_groups(n);
   if (P.cell) {
     if (contrib)
-      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, contrib);
+      k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, rows, n, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, nullptr);
+      k_bce<false, true><<<gsz, kBlock, 0, s>>>(S, rows, n, nbr, bodies, cidx, cbase, P, nullptr);
   } else {
     if (contrib)
-      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, contrib);
+      k_bce<true, false><<<gsz, kBlock, 0, s>>>(S, rows, n, nbr, bodies, cidx, cbase, P, contrib);
     else
-      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, mrows, near, n, off, nbr, bodies, cidx, cbase, P, nullptr);
+      k_bce<false, false><<<gsz, kBlock, 0, s>>>(S, rows, n, nbr, bodies, cidx, cbase, P, nullptr);
   }
   return hipGetLastError();
 }
