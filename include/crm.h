@@ -195,7 +195,8 @@ crm_status crm_set_state(crm_ctx* ctx, const double* pos, const float* vel, cons
 crm_status crm_get_counts(crm_ctx* ctx, int64_t* out);
 
 /* Export of the last rebuild for bit-exact checks (Sec. 4.1 steps 1-4):
- * sorted_ids: N_{a+e} particle ids in cell-sorted order (ties by id);
+ * sorted_ids: N_{a+e} particle ids in cell-sorted order (inside a cell by
+ * the stored x coordinate, ties by id);
  * cell_start: M + 1 values, cell_start[c] = first sorted position of cell c
  * (cellEnd[c] = cell_start[c + 1]); rows: ids of the particles that own a list
  * (active soil, then processed markers), off: rows + 1 offsets, nbr: entries
