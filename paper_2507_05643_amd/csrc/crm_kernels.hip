@@ -1284,6 +1284,71 @@ __device__ inline double tile_x(const ScanTile<CELL>& T, uint32_t t, double S) {
   else return (double)T.p[t].x;
 }
 
+// The staged candidates of one row, each run also cut to the row's own x
+// window [x_i - R', x_i + R'] (R' as for the block's cut): only the first
+// cell of a run can hold slots below it and only the last cell slots above
+// it, each in x order, so two binary searches in LDS give the run's part.
+// Lane l of the row's group narrows runs l and (lane 0) 8 before the scan;
+// run(k) hands the group run k's bounds from the lane that narrowed it.
+template <bool CELL>
+struct ScanRowLoad {
+  const ScanTile<CELL>* T;
+  const uint32_t* rt;              // o[9], lo[9], hi[9] (block's cut ranges)
+  uint32_t b0, e0, b1, e1;         // this lane's runs (gl and gl + 8)
+  using Run = typename ScanTileLoad<CELL>::Run;
+  __device__ void prepare(bool live, float4 pi, int4 ci, uint32_t c, const uint32_t* __restrict__ cs,
+                          const Grid& g) {
+    const uint32_t X = (uint32_t)g.dims[0], Y = (uint32_t)g.dims[1], Z = (uint32_t)g.dims[2];
+    const int gl = group_lane();
+    b0 = e0 = b1 = e1 = 0;
+    if (!live) return;
+    const int cx = (int)(c % X), cy = (int)((c / X) % Y), cz = (int)(c / (X * Y));
+    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < (int)X - 1 ? cx + 1 : (int)X - 1;
+    const double xi = CELL ? (double)ci.x * g.S + (double)pi.x : (double)pi.x;
+    const double Rm = g.S * (1.0 + 0x1p-20);
+    const double wlo = xi - Rm, whi = xi + Rm;
+    for (int u = 0; u < 2; ++u) {
+      const int k = gl + kGroup * u;
+      if (k > 8) break;
+      const int z = cz + k / 3 - 1, y = cy + k % 3 - 1;
+      uint32_t b = 0, e = 0;
+      if (z >= 0 && z < (int)Z && y >= 0 && y < (int)Y) {
+        const uint32_t row = ((uint32_t)z * Y + (uint32_t)y) * X;
+        b = cs[row + x0];
+        e = cs[row + x1 + 1];
+        const uint32_t m1 = cs[row + x0 + 1], m2 = cs[row + x1];
+        const uint32_t o = rt[k], lo = rt[9 + k], hi = rt[18 + k];
+        b = b > lo ? b : lo;
+        e = e < hi ? e : hi;
+        // first slot of the first cell at or above wlo
+        uint32_t a = b, z1 = m1 < e ? m1 : e;
+        while (a < z1) {
+          const uint32_t m = a + (z1 - a) / 2;
+          if (tile_x(*T, m - o, g.S) < wlo) a = m + 1;
+          else z1 = m;
+        }
+        b = a;
+        // first slot of the last cell above whi
+        uint32_t a2 = m2 > b ? m2 : b, z2 = e;
+        while (a2 < z2) {
+          const uint32_t m = a2 + (z2 - a2) / 2;
+          if (tile_x(*T, m - o, g.S) <= whi) a2 = m + 1;
+          else z2 = m;
+        }
+        e = a2 > b ? a2 : b;
+      }
+      if (u == 0) { b0 = b; e0 = e; }
+      else { b1 = b; e1 = e; }
+    }
+  }
+  __device__ Run run(int k, uint32_t& b, uint32_t& e) const {
+    const int src = (lane_id() & ~(kGroup - 1)) + (k & (kGroup - 1));
+    b = (uint32_t)__shfl((int)(k < kGroup ? b0 : b1), src);
+    e = (uint32_t)__shfl((int)(k < kGroup ? e0 : e1), src);
+    return Run{T, rt[k]};
+  }
+};
+
 // Count pass of the soil rows. A block whose rows lie in one row of cells
 // and whose ranges (whole cells x_first - 1 .. x_last + 1 of the nine (y, z)
 // rows) fit kScanCap records stages their positions in LDS and cuts each
@@ -1439,10 +1504,14 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
     }
     __syncthreads();
   }
-  const ScanTileLoad<CELL> tl{&tile, rt};
-  const uint32_t count = staged ? group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, EmitTo{out}, kStash)
-                                : group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g,
-                                                                EmitTo{out}, kStash);
+  uint32_t count;
+  if (staged) {
+    ScanRowLoad<CELL> tl{&tile, rt, 0, 0, 0, 0};
+    tl.prepare(live, pi, ci, c, cs, g);
+    count = group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, EmitTo{out}, kStash);
+  } else {
+    count = group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g, EmitTo{out}, kStash);
+  }
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
