@@ -617,18 +617,18 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(const int32_t* __restrict__
   const int64_t r = (xcd_block() * kBlock + threadIdx.x) / kGroup;
   const bool live = r < n_rows;
   const uint32_t count = live ? cnt[r] : 0u;
+  // all of the lane's stash words are loaded at once, without waiting for the
+  // count (the words past it are read but never stored)
+  constexpr int kPer = (int)(kStash / kGroup);
+  uint32_t v[kPer];
+  if (live) {
+    const uint32_t* src = stash + (uint64_t)r * kStash;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v[q] = src[(uint32_t)group_lane() + (uint32_t)(q * kGroup)];
+  }
   const bool rescan = count > kStash;                 // uniform within the group
   if (live && !rescan) {
-    // all of the lane's stashed entries are loaded before any is stored
     const uint64_t base = off[r];
-    const uint32_t* src = stash + (uint64_t)r * kStash;
-    constexpr int kPer = (int)(kStash / kGroup);
-    uint32_t v[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
-      v[q] = k < count ? src[k] : 0u;
-    }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
@@ -1197,18 +1197,18 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill_soil(const int32_t* __restr
   const bool tiled = tb[19] != 0 && tb[18] <= kTileMax;
   const TileLoad ld = tile_loader(tb);
   const uint32_t count = live ? cnt[r] : 0u;
+  // all of the lane's stash words are loaded at once, without waiting for the
+  // count (the words past it are read but never stored)
+  constexpr int kPer = (int)(kStash / kGroup);
+  uint32_t v[kPer];
+  if (live) {
+    const uint32_t* src = stash + (uint64_t)r * kStash;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v[q] = src[(uint32_t)group_lane() + (uint32_t)(q * kGroup)];
+  }
   const bool rescan = count > kStash;                 // uniform within the group
   if (live && !rescan) {
-    // all of the lane's stashed entries are loaded before any is stored
     const uint64_t base = off[r];
-    const uint32_t* src = stash + (uint64_t)r * kStash;
-    constexpr int kPer = (int)(kStash / kGroup);
-    uint32_t v[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
-      v[q] = k < count ? src[k] : 0u;
-    }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
