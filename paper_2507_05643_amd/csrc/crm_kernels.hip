@@ -429,19 +429,21 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   if (p >= n) return;
   uint32_t k = tmp[p];
   const uint32_t xk = tmpx[p];
+  int64_t id = ids ? ids[k] : (int64_t)k;
+  // the record's loads go out before the rank is counted
+  float4 a = m_a[id], b = m_b[id], cc = m_c[id], d = m_d[id];
   uint32_t c = key[k];
   uint32_t lo = cs[c], hi = cs[c + 1];
   uint32_t r = 0;
+#pragma unroll 4
   for (uint32_t q = lo; q < hi; ++q) {   // ids ascend with k
     const uint32_t xq = tmpx[q];
     r += (xq < xk || (xq == xk && tmp[q] < k)) ? 1u : 0u;
   }
   uint32_t f = lo + r;
-  int64_t id = ids ? ids[k] : (int64_t)k;
   slot_id[f] = (int32_t)id;
   slot_k[f] = (int32_t)k;
   skey[f] = c;
-  float4 a = m_a[id], b = m_b[id], cc = m_c[id], d = m_d[id];
   uint32_t aux = __float_as_uint(b.w) & ~3u;
   uint32_t kind = (id < n_soil) ? ((flags == nullptr || flags[id] == 2) ? kSoilActive : kSoilExtended) : kMarker;
   b.w = __uint_as_float(aux | kind);
