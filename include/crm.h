@@ -257,7 +257,7 @@ crm_status crm_set_graph(crm_ctx* ctx, int32_t enable);
 /* LDS tile configurations of the soil-stage kernels (the neighbour records of
  * a block of 32 cell-sorted rows staged in LDS once per stage). */
 #define CRM_TILE_NONE 0   /* neighbours read through L1/L2; highest occupancy */
-#define CRM_TILE_SMALL 1  /* 768 records (640 with cell-offset positions), 4 blocks per CU */
+#define CRM_TILE_SMALL 1  /* 787 records (640 with cell-offset positions), 4 blocks per CU */
 #define CRM_TILE_LARGE 2  /* 1024 records (832), 3 blocks per CU */
 
 /* Tile configuration of the soil-stage kernels. config = CRM_TILE_NONE,
