@@ -59,27 +59,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TIn* __restrict__ 
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-template <typename TOut>
-__global__ __launch_bounds__(kBlock) void k_scan_top(TOut* __restrict__ bsum, int64_t nb,
-                                                     TOut* __restrict__ out_total) {
-  TOut carry = 0;
-  for (int64_t base = 0; base < nb; base += kBlock) {
-    int64_t i = base + threadIdx.x;
-    TOut v = (i < nb) ? bsum[i] : TOut(0);
-    TOut tot;
-    TOut ex = block_excl_scan(v, tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *out_total = carry;
-}
-
+// The apply pass also forms its tile's carry-in, the sum of the earlier
+// tiles' totals (integers, so the order of the sum does not matter), and the
+// last tile writes the grand total: two launches per scan.
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const TIn* __restrict__ in, int64_t n,
-                                                       const TOut* __restrict__ boff,
-                                                       TOut* __restrict__ out) {
+                                                       const TOut* __restrict__ bsum, int64_t nb,
+                                                       TOut* __restrict__ out, TOut* __restrict__ out_total) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  TOut carry = boff[blockIdx.x];
+  TOut part = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlock) part += bsum[i];
+  TOut carry;
+  block_excl_scan(part, carry);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
@@ -89,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const TIn* __restrict__ i
     if (i < n) out[i] = carry + ex;
     carry += tot;
   }
+  if ((int64_t)blockIdx.x == nb - 1 && threadIdx.x == 0) *out_total = carry;
 }
 
 template <typename T>
@@ -104,8 +96,7 @@ hipError_t scan_impl(const TIn* in, TOut* out, int64_t n, TOut* tmp, hipStream_t
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   k_scan_reduce<TIn, TOut><<<(unsigned)nb, kBlock, 0, s>>>(in, n, tmp);
-  k_scan_top<TOut><<<1, kBlock, 0, s>>>(tmp, nb, out + n);
-  k_scan_apply<TIn, TOut><<<(unsigned)nb, kBlock, 0, s>>>(in, n, tmp, out);
+  k_scan_apply<TIn, TOut><<<(unsigned)nb, kBlock, 0, s>>>(in, n, tmp, nb, out, out + n);
   return hipGetLastError();
 }
 
