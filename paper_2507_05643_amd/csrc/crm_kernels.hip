@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_pred_count(Pred pr, int64_t n, uint3
 
 template <class Pred>
 __global__ __launch_bounds__(kBlock) void k_pred_write(Pred pr, int64_t n, const uint32_t* __restrict__ boff,
-                                                       int32_t* __restrict__ out) {
+                                                       int32_t* __restrict__ out, uint64_t* __restrict__ count_dst) {
+  // the count (the scan's total, boff[gridDim.x]) goes out with the last block
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count_dst = (uint64_t)boff[gridDim.x];
   __shared__ uint32_t ws[kBlock / kWave];
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool p = (i < n) && pr(i);
@@ -219,8 +221,7 @@ hipError_t compact_impl(Pred pr, int64_t n, int32_t* out, uint64_t* count_dst, u
   k_pred_count<Pred><<<(unsigned)nb, kBlock, 0, s>>>(pr, n, bcnt);
   hipError_t e = scan_impl<uint32_t, uint32_t>(bcnt, boff, nb, stmp, s);
   if (e != hipSuccess) return e;
-  k_pred_write<Pred><<<(unsigned)nb, kBlock, 0, s>>>(pr, n, boff, out);
-  k_store_count<<<1, 64, 0, s>>>(count_dst, boff + nb);
+  k_pred_write<Pred><<<(unsigned)nb, kBlock, 0, s>>>(pr, n, boff, out, count_dst);
   return hipGetLastError();
 }
 
