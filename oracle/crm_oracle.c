@@ -348,21 +348,32 @@ double orc_mu_I(const orc_params* P, double gamma_dot, double p) {
   return P->mu_s + (P->mu_2 - P->mu_s) / (1.0 + P->I0 / I);
 }
 
+/* Which case of mu(I) applies (readings of the undefined cases): 0 gamma_dot
+ * <= 0 (mu_s), 1 p <= 0 with gamma_dot > 0 (mu_2), 2 the interior formula. */
+static int mu_case(double gamma_dot, double p) {
+  if (!(gamma_dot > 0.0)) return 0;
+  if (p <= 0.0) return 1;
+  return 2;
+}
+
 /* Four-step return mapping (Sec. 2.4) of the elastic trial stress s_star, with
  * taubar^n taken from s_n (the stress at the start of the step). Writes the
- * corrected stress to out. Returns the branch taken: 1 tension cut-off,
- * 3 admissible, 4 radial return. */
-int orc_return_map(const orc_params* P, const double s_star[6], const double s_n[6],
-                   double out[6]) {
+ * corrected stress to out and, if mucase is not NULL, the mu(I) case of step 2
+ * (-1 when step 1 ends the mapping). Returns the branch taken: 1 tension
+ * cut-off, 3 admissible, 4 radial return. */
+int orc_return_map_ex(const orc_params* P, const double s_star[6], const double s_n[6],
+                      double out[6], int* mucase) {
   double G = P->E / (2.0 * (1.0 + P->nu));
   double ps, tbs, pn, tbn;
   p_taubar(s_star, &ps, &tbs);
   p_taubar(s_n, &pn, &tbn);
+  if (mucase) *mucase = -1;
   /* step 1: p_cri = -c / mu_s; p* < p_cri (strict) gives zero stress */
   double p_cri = -P->cohesion / P->mu_s;
   if (ps < p_cri) { for (int k = 0; k < 6; ++k) out[k] = 0.0; return 1; }
   /* step 2: mu(I) with gamma_dot = (taubar* - taubar^n) / (G dt) */
   double gd = (tbs - tbn) / (G * P->dt);
+  if (mucase) *mucase = mu_case(gd, ps);
   double mu = orc_mu_I(P, gd, ps);
   /* step 3: tau_max = mu p* + c (clamped at 0); keep if taubar* <= tau_max */
   double tmax = mu * ps + P->cohesion;
@@ -377,6 +388,11 @@ int orc_return_map(const orc_params* P, const double s_star[6], const double s_n
   out[4] = f * s_star[4];
   out[5] = f * s_star[5];
   return 4;
+}
+
+int orc_return_map(const orc_params* P, const double s_star[6], const double s_n[6],
+                   double out[6]) {
+  return orc_return_map_ex(P, s_star, s_n, out, NULL);
 }
 
 /* ------------------------------------------------------------- rigid bodies */
@@ -421,6 +437,9 @@ typedef struct orc_ctx {
   double* F; double* T;         /* per body, 3 each */
   double* as;                   /* 3n marker accelerations of the last stage 2 */
   int32_t* mat;                 /* material of each soil particle (0 = the parameters) */
+  int8_t* branch;               /* per particle, the last step's return-mapping branch
+                                   (1, 3, 4 as orc_return_map; 0 not updated) */
+  int8_t* mucase;               /* and its mu(I) case (-1 when cut off) */
   int32_t n_mat;
   double* mat_tab;              /* per material: mu_s, mu_2, cohesion */
 } orc_ctx;
@@ -463,6 +482,8 @@ orc_ctx* orc_create(const orc_params* P, int64_t n_soil, const double* pos, cons
   c->T = (double*)calloc(3 * (size_t)(nb > 0 ? nb : 1), sizeof(double));
   c->as = (double*)calloc(1, n3);
   c->mat = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  c->branch = (int8_t*)calloc((size_t)n, 1);
+  c->mucase = (int8_t*)calloc((size_t)n, 1);
   c->n_mat = 1;
   c->mat_tab = (double*)malloc(3 * sizeof(double));
   c->mat_tab[0] = P->mu_s; c->mat_tab[1] = P->mu_2; c->mat_tab[2] = P->cohesion;
@@ -495,6 +516,7 @@ void orc_destroy(orc_ctx* c) {
   free(c->dx_); free(c->du); free(c->ds); free(c->drho);
   free(c->flag); free(c->proc); free(c->slot); free(c->off); free(c->nbr);
   free(c->F); free(c->T); free(c->as); free(c->mat); free(c->mat_tab);
+  free(c->branch); free(c->mucase);
   free(c);
 }
 
@@ -800,6 +822,8 @@ static int one_step(orc_ctx* c) {
   marker_forces(c, c->xm, c->um, c->sm, c->rhom);
   rhs(c, c->xm, c->um, c->sm, c->rhom);
   for (int64_t i = 0; i < c->n; ++i) {
+    c->branch[i] = 0;
+    c->mucase[i] = -1;
     if (!(c->body[i] < 0 && c->flag[i] == 2)) continue;
     for (int k = 0; k < 3; ++k) {
       c->x[3 * i + k] += P->dt * c->dx_[3 * i + k];
@@ -810,7 +834,9 @@ static int one_step(orc_ctx* c) {
     orc_params Pm = *P;             /* the return mapping with the particle's material */
     const double* mt = c->mat_tab + 3 * c->mat[i];
     Pm.mu_s = mt[0]; Pm.mu_2 = mt[1]; Pm.cohesion = mt[2];
-    orc_return_map(&Pm, sstar, sn, c->s + 6 * i);
+    int mc = -1;
+    c->branch[i] = (int8_t)orc_return_map_ex(&Pm, sstar, sn, c->s + 6 * i, &mc);
+    c->mucase[i] = (int8_t)mc;
     c->rho[i] += P->dt * c->drho[i];
   }
   /* marker values of the midpoint are what the step last computed */
@@ -912,6 +938,20 @@ void orc_get_forces(const orc_ctx* c, double* F, double* T) {
 }
 
 void orc_get_flags(const orc_ctx* c, uint8_t* flags) { memcpy(flags, c->flag, (size_t)c->n); }
+
+/* Return-mapping branch and mu(I) case of every particle in the last step. */
+void orc_get_branches(const orc_ctx* c, int8_t* branch, int8_t* mucase) {
+  if (branch) memcpy(branch, c->branch, (size_t)c->n);
+  if (mucase) memcpy(mucase, c->mucase, (size_t)c->n);
+}
+
+/* Stored form of one position (pos_mode 1: integer cell and FP32 offset; pos_mode
+ * 0: the FP32 coordinate in o, c = 0), for checks of the representation. */
+void orc_to_rep(const orc_params* P, const double* x, int64_t* c, double* o) {
+  rep_t r;
+  to_rep(P, x, &r);
+  for (int a = 0; a < 3; ++a) { c[a] = r.c[a]; o[a] = r.o[a]; }
+}
 
 /* Processed set (ascending ids) and its lists, as of the last rebuild. */
 void orc_get_lists(const orc_ctx* c, int32_t* proc, int64_t* off, int32_t* nbr) {

@@ -127,6 +127,12 @@ def lib():
         L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_get_forces.restype = None
         L.orc_get_forces.argtypes = [C.c_void_p, dp, dp]
+        L.orc_return_map_ex.restype = C.c_int
+        L.orc_return_map_ex.argtypes = [pp, dp, dp, dp, C.POINTER(C.c_int)]
+        L.orc_get_branches.restype = None
+        L.orc_get_branches.argtypes = [C.c_void_p, C.POINTER(C.c_int8), C.POINTER(C.c_int8)]
+        L.orc_to_rep.restype = None
+        L.orc_to_rep.argtypes = [pp, dp, i64p, dp]
         L.orc_get_flags.restype = None
         L.orc_get_flags.argtypes = [C.c_void_p, u8p]
         L.orc_get_lists.restype = None
@@ -165,6 +171,31 @@ def return_map(params: dict, s_star, s_n):
     out = np.zeros(6)
     br = lib().orc_return_map(C.byref(P), _p(a, C.c_double), _p(b, C.c_double), _p(out, C.c_double))
     return out, br
+
+
+def return_map_ex(params: dict, s_star, s_n):
+    """(corrected stress, branch, mu(I) case) of the return mapping; case 0: mu_s
+    (no shear-rate increase), 1: mu_2 (p* <= 0), 2: the interior formula,
+    -1: cut off at step 1."""
+    P = make_params(params)
+    a = np.ascontiguousarray(s_star, dtype=np.float64)
+    b = np.ascontiguousarray(s_n, dtype=np.float64)
+    out = np.zeros(6)
+    mc = C.c_int(0)
+    br = lib().orc_return_map_ex(C.byref(P), _p(a, C.c_double), _p(b, C.c_double), _p(out, C.c_double),
+                                 C.byref(mc))
+    return out, br, mc.value
+
+
+def to_rep(params: dict, x):
+    """Stored form of the position x (3,): (integer cell (3,), offset (3,)) for
+    pos_mode 1, (0, FP32 coordinate) for pos_mode 0."""
+    P = make_params(params)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(3)
+    c = np.zeros(3, dtype=np.int64)
+    o = np.zeros(3)
+    lib().orc_to_rep(C.byref(P), _p(xx, C.c_double), _p(c, C.c_int64), _p(o, C.c_double))
+    return c, o
 
 
 def mu_I(params: dict, gamma_dot, p):
@@ -294,6 +325,15 @@ class Oracle:
         f = np.zeros(self.n, dtype=np.uint8)
         lib().orc_get_flags(self.ctx, _p(f, C.c_uint8))
         return f
+
+    def branches(self):
+        """Per particle, the last step's return-mapping branch (0 not updated,
+        1 tension cut-off, 3 admissible, 4 radial return) and mu(I) case
+        (-1 cut off or not updated, 0 mu_s, 1 mu_2, 2 interior formula)."""
+        br = np.zeros(self.n, dtype=np.int8)
+        mc = np.zeros(self.n, dtype=np.int8)
+        lib().orc_get_branches(self.ctx, _p(br, C.c_int8), _p(mc, C.c_int8))
+        return br, mc
 
     def lists(self):
         L = lib()

@@ -96,3 +96,40 @@ def test_friction_gradient_matches_central_differences(setup):
     fd = (L_at(1) - L_at(-1)) / (2 * eps)
     assert abs(g["mat"][0, 0]) > 0.0      # plastic flow is active on this workload
     _check(fd, g["mat"][0, 0], tol=1e-4)
+
+
+@pytest.fixture(scope="module")
+def rate_setup():
+    """A warm column with rate-dependent friction and cohesion (mu_s 0.7,
+    mu_2 0.8, I0 0.08, d 3 mm, c = 100 Pa: the derivative in c is taken at
+    c_0 = 100 Pa, where a relative step is well defined)."""
+    sc = scenes.column(seed=4, n=8, ps_freq=2)
+    sc.params.update(mu_s=0.7, mu_2=0.8, I0=0.08, grain_d=3.0e-3, cohesion=100.0)
+    o = Oracle(sc, nbr_mode="cells")
+    o.step(30)
+    st = o.state()
+    ns = sc.n_soil
+    sc = dataclasses.replace(sc, pos=st["pos"][:ns].copy(), vel=st["vel"][:ns].copy(),
+                             sigma=st["sigma"][:ns].copy(), rho=st["rho"][:ns].copy())
+    rec = A.Recording(sc, K)
+    w = A.loss_weights(3, ns, K, len(sc.bodies))
+    g = A.gradient(rec, w)
+    return sc, rec, w, g
+
+
+@pytest.mark.parametrize("col,name", [(1, "mu_2"), (2, "cohesion")])
+def test_rate_friction_and_cohesion_gradients_match_central_differences(rate_setup, col, name):
+    sc, rec, w, g = rate_setup
+    p = sc.params
+    mat = np.zeros(sc.n_soil, dtype=np.int32)
+    base = np.array([[p["mu_s"], p["mu_2"], p["cohesion"]]])
+    eps = 1e-6 * base[0, col]
+
+    def L_at(sgn):
+        tab = base.copy()
+        tab[0, col] += sgn * eps
+        return A.functional(sc, K, w, materials=(tab, mat))
+
+    fd = (L_at(1) - L_at(-1)) / (2 * eps)
+    assert abs(g["mat"][0, col]) > 0.0, name     # the branch that carries it is taken
+    _check(fd, g["mat"][0, col], tol=1e-4)
