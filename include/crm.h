@@ -157,7 +157,11 @@ crm_status crm_set_materials(crm_ctx* ctx, int32_t n_mat, const double* mu_s, co
  * then two RHS evaluations and the return mapping). Enqueued on the context's
  * stream; returns once enqueued, except on rebuild steps, which wait for the
  * particle and neighbour counts. Errors: CRM_E_INVALID (n_steps < 0),
- * CRM_E_NOMEM, CRM_E_DEVICE, CRM_E_STATE. */
+ * CRM_E_NOMEM, CRM_E_DEVICE, CRM_E_STATE. On CRM_E_NOMEM (a growth of the
+ * working set or of the neighbour lists failed) the steps before the failing
+ * one stay taken (crm_get_counts reports them) and the failing step leaves no
+ * trace: the state, the step counter and every later result are those of a
+ * context where the allocation never failed, once memory is available. */
 crm_status crm_step(crm_ctx* ctx, int32_t n_steps);
 
 /* Force (N, world frame) and torque (N m, about the body origin) the soil
@@ -182,9 +186,32 @@ crm_status crm_cosim_step(crm_ctx* ctx, int32_t nb, const double* pos, const dou
 crm_status crm_get_state(crm_ctx* ctx, double* pos, float* vel, float* sigma, float* rho);
 
 /* Overwrite the soil state (ids 0..n_soil-1); any pointer may be NULL. Takes
- * effect from the next step; the next step rebuilds the neighbour lists. */
+ * effect from the next step; the next step rebuilds the neighbour lists.
+ * Positions must be finite (CRM_E_INVALID otherwise). Velocities, stresses and
+ * densities are taken as given: a non-finite value spreads through the step
+ * and surfaces as CRM_E_NONFINITE at the next force read (crm_get_forces,
+ * crm_cosim_step) once it reaches a body. */
 crm_status crm_set_state(crm_ctx* ctx, const double* pos, const float* vel, const float* sigma,
                          const float* rho);
+
+/* Checkpoints for an exact restart: the master state of every particle in its
+ * stored form (bit for bit, cell-offset positions included), the step counter,
+ * the body states of the last crm_set_bodies and the materials. Taken where
+ * the next step rebuilds the neighbour lists (step mod ps_freq = 0, or after
+ * crm_init, crm_set_state or a restore), so that a context restored from it
+ * continues bit-identically: its first step rebuilds the same lists from the
+ * same state (Alg. 2 and 3 depend only on the state, the step counter and the
+ * bodies). crm_checkpoint_bytes: the size of a checkpoint of ctx.
+ * crm_save_checkpoint: writes it into buf (host, `bytes` >= that size);
+ * synchronises; errors: CRM_E_INVALID (NULL or small buffer), CRM_E_STATE (not
+ * at a list rebuild), CRM_E_DEVICE. crm_load_checkpoint: restores a
+ * checkpoint into a context created with the same particles, bodies and
+ * parameters (sizes and position form are checked); the next step rebuilds.
+ * Errors: CRM_E_INVALID (not a checkpoint, or of another configuration: the
+ * context is unchanged), CRM_E_DEVICE. */
+crm_status crm_checkpoint_bytes(crm_ctx* ctx, size_t* bytes);
+crm_status crm_save_checkpoint(crm_ctx* ctx, void* buf, size_t bytes);
+crm_status crm_load_checkpoint(crm_ctx* ctx, const void* buf, size_t bytes);
 
 /* Sizes: out[0] n_total, out[1] n_soil, out[2] processed particles N_{a+e} of
  * the last rebuild, out[3] active soil rows, out[4] processed marker rows,

@@ -103,6 +103,12 @@ def _load():
     L.crm_record.argtypes = [vp, C.c_int32]
     L.crm_adjoint.restype = C.c_int
     L.crm_adjoint.argtypes = [vp, dp, fp, fp, fp, dp, dp, dp, fp, fp, fp, dp]
+    L.crm_checkpoint_bytes.restype = C.c_int
+    L.crm_checkpoint_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.crm_save_checkpoint.restype = C.c_int
+    L.crm_save_checkpoint.argtypes = [vp, vp, C.c_size_t]
+    L.crm_load_checkpoint.restype = C.c_int
+    L.crm_load_checkpoint.argtypes = [vp, vp, C.c_size_t]
     return L
 
 
@@ -111,7 +117,8 @@ _lib = _load()
 EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_get_forces", "crm_get_state",
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
-            "crm_adjoint", "crm_autotune", "crm_cosim_step")
+            "crm_adjoint", "crm_autotune", "crm_cosim_step", "crm_checkpoint_bytes", "crm_save_checkpoint",
+            "crm_load_checkpoint")
 
 TILE_NONE, TILE_SMALL, TILE_LARGE = 0, 1, 2
 
@@ -177,8 +184,10 @@ class _TorchAllocator:
 # ---- thin functions with the C names ----------------------------------------
 
 def crm_init(params: dict, pos, vel=None, sigma=None, rho=None, bodies=(), device=None, stream=None,
-             torch_allocator=True):
-    """Create a context. bodies: sequence of (marker_local (m,3) float32, active_half (3,))."""
+             torch_allocator=True, allocator=None):
+    """Create a context. bodies: sequence of (marker_local (m,3) float32, active_half (3,)).
+    allocator: an object with ctypes callbacks .alloc (ALLOC_FN) and .free (FREE_FN)
+    used in place of torch's caching allocator."""
     if not torch.cuda.is_available():
         raise RuntimeError("libcrm needs a HIP device")
     dev = torch.cuda.current_device() if device is None else int(device)
@@ -199,7 +208,7 @@ def crm_init(params: dict, pos, vel=None, sigma=None, rho=None, bodies=(), devic
         descs[b].n_markers = ml.shape[0]
         descs[b].marker_local = ml.ctypes.data_as(C.POINTER(C.c_float))
         descs[b].active_half[:] = [float(v) for v in half]
-    alloc = _TorchAllocator(dev) if torch_allocator else None
+    alloc = allocator if allocator is not None else (_TorchAllocator(dev) if torch_allocator else None)
     out = C.c_void_p()
     st = _lib.crm_init(C.byref(P), n, _ptr(pos, C.c_double), _ptr(vel, C.c_float), _ptr(sigma, C.c_float),
                        _ptr(rho, C.c_float), len(bodies), descs,
@@ -328,6 +337,20 @@ def crm_adjoint(ctx, n_soil, n_mat, lam_pos=None, lam_vel=None, lam_sigma=None, 
     return out
 
 
+def crm_save_checkpoint(ctx):
+    """The context's checkpoint as bytes (see crm_save_checkpoint in crm.h)."""
+    n = C.c_size_t(0)
+    _check(ctx, _lib.crm_checkpoint_bytes(ctx, C.byref(n)))
+    buf = (C.c_char * n.value)()
+    _check(ctx, _lib.crm_save_checkpoint(ctx, C.cast(buf, C.c_void_p), n.value))
+    return bytes(buf)
+
+
+def crm_load_checkpoint(ctx, data):
+    buf = C.create_string_buffer(bytes(data), len(data))
+    _check(ctx, _lib.crm_load_checkpoint(ctx, C.cast(buf, C.c_void_p), len(data)))
+
+
 def crm_set_graph(ctx, enable):
     _check(ctx, _lib.crm_set_graph(ctx, 1 if enable else 0))
 
@@ -374,14 +397,15 @@ def crm_destroy(ctx):
 class Simulation:
     """A libcrm context built from a scene (see ``scenes``)."""
 
-    def __init__(self, scene, params=None, device=None, stream=None, torch_allocator=True):
+    def __init__(self, scene, params=None, device=None, stream=None, torch_allocator=True, allocator=None):
         p = dict(scene.params if params is None else params)
         self.params = p
         self.n_soil = scene.n_soil
         self.nb = len(scene.bodies)
         bodies = [(b.markers, b.active_half) for b in scene.bodies]
         self.ctx, self._alloc = crm_init(p, scene.pos, scene.vel, scene.sigma, scene.rho, bodies,
-                                         device=device, stream=stream, torch_allocator=torch_allocator)
+                                         device=device, stream=stream, torch_allocator=torch_allocator,
+                                         allocator=allocator)
         self.n_total = scene.n_total
         if self.nb:
             self.set_bodies(np.array([b.pos for b in scene.bodies]), np.array([b.quat for b in scene.bodies]),
@@ -429,6 +453,12 @@ class Simulation:
 
     def export(self):
         return crm_debug_export(self.ctx)
+
+    def save_checkpoint(self):
+        return crm_save_checkpoint(self.ctx)
+
+    def load_checkpoint(self, data):
+        crm_load_checkpoint(self.ctx, data)
 
     def graph(self, enable=True):
         crm_set_graph(self.ctx, enable)

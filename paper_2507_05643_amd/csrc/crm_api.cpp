@@ -3,6 +3,7 @@
 // hashing, sort, neighbour lists) and the two-stage step of Sec. 2.3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -38,6 +39,7 @@ struct crm_ctx {
   crm_free_fn free_fn = nullptr;
   void* user = nullptr;
   bool poisoned = false;
+  bool noalloc = false;        // set during a call that must not allocate
   std::string err = "no error";
 
   int64_t n_soil = 0, n_mark = 0, n_total = 0;
@@ -56,8 +58,15 @@ struct crm_ctx {
   float4* d_mat = nullptr;     // material table
   int32_t n_mat = 1;
   std::vector<uint16_t> h_mat; // material of each soil particle (empty: all 0)
+  std::vector<float4> h_mattab;  // material table as uploaded (n_mat rows)
   std::vector<Body> h_bodies;
+  std::vector<Body> h_bodies_next;  // validation buffer of crm_set_bodies (nb, kept allocated)
   std::vector<int64_t> h_nmark;  // markers per body
+  std::vector<int64_t> h_bstart; // first marker (relative id) of each body, nb + 1
+  // host buffers of the force-sum plan, sized once at crm_init (a rebuild
+  // step allocates no host memory)
+  std::vector<int64_t> plan_lo, plan_hi, plan_r;
+  std::vector<int32_t> plan_first;
   double* d_fmap = nullptr;       // device alias of h_fpin: the body sums are written there
   uint32_t* ctmp = nullptr;    // compaction scratch (n_total sized)
 
@@ -74,7 +83,7 @@ struct crm_ctx {
   int32_t* slot_id = nullptr;
   int32_t* slot_k = nullptr;     // processed index (position in the processed id list)
   uint32_t *skey = nullptr, *key = nullptr, *rank = nullptr, *tmp = nullptr;
-  uint32_t* tmpx = nullptr;     // x order keys beside tmp (sort inside cells)
+  uint64_t* tmpx = nullptr;     // x order keys beside tmp (sort inside cells)
   int32_t *frows = nullptr, *mrows = nullptr;
   int32_t* near = nullptr;       // marker rows (indices into mrows) with soil neighbours
   crm::NearRow* nrow = nullptr;  // their slots and list ranges, for the BCE passes
@@ -166,6 +175,7 @@ crm_status fail(crm_ctx* c, crm_status st, const std::string& msg) {
 }
 
 void* dalloc(crm_ctx* c, size_t bytes) {
+  if (c->noalloc) return nullptr;   // a call that must not allocate
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
   void* p = nullptr;
@@ -292,49 +302,65 @@ void quat_to_R(const double q[4], double R[9]) {
       return fail(ctx, CRM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// The capacity-sized arrays of the working set, with their element sizes and
+// counts at capacity cap.
+struct WorkBuf {
+  void** field;
+  size_t elem;
+  int64_t count;
+};
+
+std::vector<WorkBuf> work_buffers(crm_ctx* c, int64_t cap) {
+  auto f = [](auto*& p) { return reinterpret_cast<void**>(&p); };
+  return {{f(c->A.a), sizeof(float4), cap},   {f(c->A.b), sizeof(float4), cap},   {f(c->A.c), sizeof(float4), cap},
+          {f(c->A.d), sizeof(float4), cap},   {f(c->B.a), sizeof(float4), cap},   {f(c->B.b), sizeof(float4), cap},
+          {f(c->B.c), sizeof(float4), cap},   {f(c->B.d), sizeof(float4), cap},   {f(c->pos4), sizeof(float4), cap},
+          {f(c->cpos), sizeof(int4), c->grid.cell ? cap : 1},
+          {f(c->slot_id), 4, cap},            {f(c->slot_k), 4, cap},             {f(c->skey), 4, cap},
+          {f(c->key), 4, cap},                {f(c->rank), 4, cap},               {f(c->tmp), 4, cap},
+          {f(c->tmpx), 8, cap},               {f(c->frows), 4, cap},              {f(c->mrows), 4, cap},
+          {f(c->near), 4, cap},               {f(c->nrow), sizeof(crm::NearRow), cap},
+          {f(c->cnt_f), 4, cap},              {f(c->cnt_m), 4, cap},              {f(c->off_f), 8, cap + 1},
+          {f(c->off_m), 8, cap + 1},          {f(c->wtmp), 8, (int64_t)crm::scan_tmp_elems(cap)},
+          {f(c->stash_f), 4, (int64_t)crm::stash_elems(cap)},
+          {f(c->stash_m), 4, (int64_t)crm::stash_elems(cap)},
+          {f(c->tabs), 4, crm::tile_table_words(cap)}};
+}
+
+// New working arrays of capacity cap. All of them are taken before the old
+// ones are released, so a failed allocation leaves the context as it was.
 crm_status realloc_working(crm_ctx* c, int64_t cap) {
-  void* olds[] = {c->A.a, c->A.b, c->A.c, c->A.d, c->B.a, c->B.b, c->B.c, c->B.d, c->pos4, c->cpos, c->slot_id, c->slot_k,
-                  c->skey, c->key, c->rank, c->tmp, c->tmpx, c->frows, c->mrows, c->near, c->nrow, c->cnt_f, c->cnt_m, c->off_f,
-                  c->off_m, c->wtmp, c->stash_f, c->stash_m, c->tabs};
-  for (void* p : olds) dfree(c, p);
-  c->A = Planes{};
-  c->B = Planes{};
-  c->pos4 = nullptr;
-  c->cpos = nullptr;
-  c->slot_id = c->slot_k = c->frows = c->mrows = c->near = nullptr;
-  c->nrow = nullptr;
-  c->skey = c->key = c->rank = c->tmp = c->tmpx = c->cnt_f = c->cnt_m = nullptr;
-  c->off_f = c->off_m = c->wtmp = nullptr;
-  c->stash_f = c->stash_m = nullptr;
-  c->tabs = nullptr;
-  c->cap = 0;
-  bool ok = alloc_n(c, c->A.a, cap) && alloc_n(c, c->A.b, cap) && alloc_n(c, c->A.c, cap) &&
-            alloc_n(c, c->A.d, cap) && alloc_n(c, c->B.a, cap) && alloc_n(c, c->B.b, cap) &&
-            alloc_n(c, c->B.c, cap) && alloc_n(c, c->B.d, cap) && alloc_n(c, c->pos4, cap) &&
-            alloc_n(c, c->cpos, c->grid.cell ? cap : 1) &&
-            alloc_n(c, c->slot_id, cap) && alloc_n(c, c->slot_k, cap) && alloc_n(c, c->skey, cap) &&
-            alloc_n(c, c->key, cap) &&
-            alloc_n(c, c->rank, cap) && alloc_n(c, c->tmp, cap) && alloc_n(c, c->tmpx, cap) &&
-            alloc_n(c, c->frows, cap) &&
-            alloc_n(c, c->mrows, cap) && alloc_n(c, c->near, cap) && alloc_n(c, c->nrow, cap) && alloc_n(c, c->cnt_f, cap) && alloc_n(c, c->cnt_m, cap) &&
-            alloc_n(c, c->off_f, cap + 1) && alloc_n(c, c->off_m, cap + 1) &&
-            alloc_n(c, c->wtmp, (int64_t)crm::scan_tmp_elems(cap)) &&
-            alloc_n(c, c->stash_f, (int64_t)crm::stash_elems(cap)) &&
-            alloc_n(c, c->stash_m, (int64_t)crm::stash_elems(cap)) &&
-            alloc_n(c, c->tabs, crm::tile_table_words(cap));
-  if (!ok) return fail(c, CRM_E_NOMEM, "working-set allocation failed");
+  std::vector<WorkBuf> bufs = work_buffers(c, cap);
+  std::vector<void*> fresh(bufs.size(), nullptr);
+  for (size_t i = 0; i < bufs.size(); ++i) {
+    fresh[i] = dalloc(c, bufs[i].elem * (size_t)(bufs[i].count > 0 ? bufs[i].count : 1));
+    if (!fresh[i]) {
+      for (size_t j = 0; j < i; ++j) dfree(c, fresh[j]);
+      return fail(c, CRM_E_NOMEM, c->noalloc ? "the working set must grow (a call that may allocate is needed)"
+                                             : "working-set allocation failed");
+    }
+  }
+  for (size_t i = 0; i < bufs.size(); ++i) {
+    dfree(c, *bufs[i].field);
+    *bufs[i].field = fresh[i];
+  }
   c->cap = cap;
   c->working_valid = false;
   return CRM_OK;
 }
 
-crm_status ensure_list(crm_ctx* c, uint32_t*& buf, int64_t& cap, int64_t need) {
+// Grows a list buffer to hold `need` entries (new buffer first, then the old
+// one is released).
+template <typename T>
+crm_status ensure_list(crm_ctx* c, T*& buf, int64_t& cap, int64_t need, int64_t want = -1) {
   if (need <= cap && buf) return CRM_OK;
+  const int64_t n = want >= need ? want : (int64_t)std::ceil(c->prm.grow_G * (double)need) + crm::kWave;
+  T* nb = nullptr;
+  if (!alloc_n(c, nb, n))
+    return fail(c, CRM_E_NOMEM, c->noalloc ? "the neighbour lists must grow (a call that may allocate is needed)"
+                                           : "neighbour-list allocation failed");
   dfree(c, buf);
-  buf = nullptr;
-  cap = 0;
-  int64_t n = (int64_t)std::ceil(c->prm.grow_G * (double)need) + crm::kWave;
-  if (!alloc_n(c, buf, n)) return fail(c, CRM_E_NOMEM, "neighbour-list allocation failed");
+  buf = nb;
   cap = n;
   return CRM_OK;
 }
@@ -384,31 +410,39 @@ crm_status make_plan(crm_ctx* c, const std::vector<int64_t>& start, crm::SegPlan
   return CRM_OK;
 }
 
-// Writes the chunk plan of the segments [start[g], start[g + 1]) into the
-// plan's existing arrays (capacity cap chunks).
-crm_status fill_plan(crm_ctx* c, const std::vector<int64_t>& start, crm::SegPlan& plan, int64_t cap) {
-  const int32_t nseg = (int32_t)start.size() - 1;
+// Writes the chunk plan of the segments [start[g], start[g + 1]) (start:
+// nseg + 1 values) into the plan's existing arrays (capacity cap chunks),
+// through the context's host plan buffers.
+crm_status fill_plan(crm_ctx* c, const int64_t* start, int32_t nseg, crm::SegPlan& plan, int64_t cap) {
   const int64_t ch = crm::reduce_chunk();
-  std::vector<int64_t> lo, hi;
-  std::vector<int32_t> first((size_t)nseg + 1, 0);
+  int64_t nc = 0;
+  for (int32_t g = 0; g < nseg; ++g)
+    for (int64_t k = start[g]; k < start[g + 1]; k += ch) ++nc;
+  if (nc > cap) return fail(c, CRM_E_STATE, "force-sum plan exceeds its capacity");
+  if ((int64_t)c->plan_lo.size() < nc || (int64_t)c->plan_first.size() < nseg + 1) {
+    if (c->noalloc) return fail(c, CRM_E_NOMEM, "the force-sum plan must grow (a call that may allocate is needed)");
+    c->plan_lo.resize((size_t)nc);
+    c->plan_hi.resize((size_t)nc);
+    c->plan_first.resize((size_t)nseg + 1);
+  }
+  int64_t* lo = c->plan_lo.data();
+  int64_t* hi = c->plan_hi.data();
+  int32_t* first = c->plan_first.data();
+  int64_t q = 0;
   for (int32_t g = 0; g < nseg; ++g) {
-    first[g] = (int32_t)lo.size();
-    for (int64_t k = start[g]; k < start[g + 1]; k += ch) {
-      lo.push_back(k);
-      hi.push_back(std::min(k + ch, start[g + 1]));
+    first[g] = (int32_t)q;
+    for (int64_t k = start[g]; k < start[g + 1]; k += ch, ++q) {
+      lo[q] = k;
+      hi[q] = std::min(k + ch, start[g + 1]);
     }
   }
-  first[nseg] = (int32_t)lo.size();
-  const int64_t nc = (int64_t)lo.size();
-  if (nc > cap) return fail(c, CRM_E_STATE, "force-sum plan exceeds its capacity");
+  first[nseg] = (int32_t)q;
   hipStream_t s = c->stream;
   if (nc > 0) {
-    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.lo), lo.data(), sizeof(int64_t) * (size_t)nc,
-                             hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.hi), hi.data(), sizeof(int64_t) * (size_t)nc,
-                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.lo), lo, sizeof(int64_t) * (size_t)nc, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(const_cast<int64_t*>(plan.hi), hi, sizeof(int64_t) * (size_t)nc, hipMemcpyHostToDevice, s));
   }
-  HIPCHK(c, hipMemcpyAsync(const_cast<int32_t*>(plan.first), first.data(), sizeof(int32_t) * first.size(),
+  HIPCHK(c, hipMemcpyAsync(const_cast<int32_t*>(plan.first), first, sizeof(int32_t) * (size_t)(nseg + 1),
                            hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   plan.nseg = nseg;
@@ -440,8 +474,7 @@ void set_box_bounds(Body& B, double ext) {
 }
 
 crm_status place_master_markers(crm_ctx* c) {
-  std::vector<int64_t> bs((size_t)c->nb + 1, 0);
-  for (int b = 0; b < c->nb; ++b) bs[b + 1] = bs[b] + c->h_nmark[b];
+  const int64_t* bs = c->h_bstart.data();
   if (c->placed.size() != (size_t)c->nb) {
     c->placed.assign((size_t)c->nb, Body{});
     c->place_all = true;
@@ -466,10 +499,10 @@ crm_status update_body_plan(crm_ctx* c, const int32_t* ids) {
   if (c->nb == 0) return CRM_OK;
   if (!ids && c->plan_all) return CRM_OK;
   HIPCHK(c, crm::body_ranges(ids, c->n_proc, c->n_soil, c->d_bstart, c->nb, c->kbase, c->d_branges, c->stream));
-  std::vector<int64_t> r((size_t)c->nb + 1);
-  HIPCHK(c, hipMemcpyAsync(r.data(), c->d_branges, sizeof(int64_t) * r.size(), hipMemcpyDeviceToHost, c->stream));
+  int64_t* r = c->plan_r.data();
+  HIPCHK(c, hipMemcpyAsync(r, c->d_branges, sizeof(int64_t) * (size_t)(c->nb + 1), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  crm_status st = fill_plan(c, r, c->body_plan, c->plan_cap);
+  crm_status st = fill_plan(c, r, c->nb, c->body_plan, c->plan_cap);
   if (st != CRM_OK) return st;
   c->plan_all = (ids == nullptr);
   return CRM_OK;
@@ -482,6 +515,10 @@ crm_status rebuild(crm_ctx* c) {
   const crm_params& P = c->prm;
   if (c->working_valid)
     HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  // from here until the rebuild completes the master store is the state: a
+  // rebuild that fails (e.g. an allocation) leaves the state as it was, and
+  // the next step starts the rebuild again
+  c->working_valid = false;
   if (c->recording) {
     // the state every later step of this segment follows from (reverse mode)
     const int64_t k = (int64_t)c->rec_seg.size();
@@ -519,7 +556,8 @@ crm_status rebuild(crm_ctx* c) {
   HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, c->M, s));
   HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->m_d, c->grid, c->key, c->rank, c->cell_cnt, s));
   HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
-  HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, ids, c->m_a, c->tmp, c->tmpx, s));
+  HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, ids, c->m_a, c->m_d, c->tmp, c->tmpx,
+                              c->grid.cell != 0, s));
   HIPCHK(c, crm::gather_sorted(c->tmp, c->tmpx, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
                                c->m_d, c->A, c->B, c->pos4, c->cpos, c->slot_id, c->slot_k, c->skey,
                                c->grid.cell != 0, s));
@@ -546,15 +584,10 @@ crm_status rebuild(crm_ctx* c) {
   const int64_t ef = (int64_t)c->h_counts[3], em = (int64_t)c->h_counts[4];
   st = ensure_list(c, c->nbr_f, c->nbr_f_cap, ef);
   if (st != CRM_OK) return st;
+  st = ensure_list(c, c->tix_f, c->tix_f_cap, ef, c->nbr_f_cap);
+  if (st != CRM_OK) return st;
   st = ensure_list(c, c->nbr_m, c->nbr_m_cap, em);
   if (st != CRM_OK) return st;
-  if (c->tix_f_cap != c->nbr_f_cap) {
-    dfree(c, c->tix_f);
-    c->tix_f = nullptr;
-    c->tix_f_cap = 0;
-    if (!alloc_n(c, c->tix_f, c->nbr_f_cap)) return fail(c, CRM_E_NOMEM, "neighbour-list allocation failed");
-    c->tix_f_cap = c->nbr_f_cap;
-  }
   c->ent_f = ef;
   c->ent_m = em;
   HIPCHK(c, crm::nbr_fill_soil(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, c->cnt_f,
@@ -1015,7 +1048,14 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   if (e == hipSuccess && nm > 0) e = hipMemsetAsync(c->contrib, 0, sizeof(double) * 6 * (size_t)nm, s);
   c->h_nmark.resize((size_t)n_bodies);
   for (int b = 0; b < n_bodies; ++b) c->h_nmark[b] = bodies[b].n_markers;
+  c->h_bstart = bstart;
+  c->h_bodies_next = c->h_bodies;
   c->plan_cap = nm / crm::reduce_chunk() + n_bodies + 2;
+  c->plan_lo.resize((size_t)c->plan_cap);
+  c->plan_hi.resize((size_t)c->plan_cap);
+  c->plan_first.resize((size_t)n_bodies + 1);
+  c->plan_r.resize((size_t)n_bodies + 1);
+  c->h_mattab.assign(1, make_float4((float)P.mu_s, (float)P.mu_2, (float)P.cohesion, (float)(-P.cohesion / P.mu_s)));
   {
     int64_t *dlo = nullptr, *dhi = nullptr;
     int32_t* dfirst = nullptr;
@@ -1030,15 +1070,14 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     c->body_plan.first = dfirst;
     c->body_plan.partial = dpart;
   }
-  if (e == hipSuccess && n_bodies > 0 && fill_plan(c, bstart, c->body_plan, c->plan_cap) != CRM_OK) {
+  if (e == hipSuccess && n_bodies > 0 && fill_plan(c, bstart.data(), n_bodies, c->body_plan, c->plan_cap) != CRM_OK) {
     std::string m2 = c->err;
     release(c);
     return fail(nullptr, CRM_E_DEVICE, m2);
   }
   c->plan_all = true;
   c->kbase = n_soil;
-  const float4 mat0 = make_float4((float)P.mu_s, (float)P.mu_2, (float)P.cohesion, (float)(-P.cohesion / P.mu_s));
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_mat, &mat0, sizeof(float4), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_mat, c->h_mattab.data(), sizeof(float4), hipMemcpyHostToDevice, s);
   c->phys.mat = c->d_mat;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -1057,7 +1096,8 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
   if (nb != c->nb) return fail(c, CRM_E_INVALID, "nb differs from crm_init");
   if (nb == 0) return CRM_OK;
   if (!pos || !quat) return fail(c, CRM_E_INVALID, "pos and quat are required");
-  std::vector<Body> hb = c->h_bodies;
+  std::vector<Body>& hb = c->h_bodies_next;   // sized at crm_init: no allocation here
+  std::copy(c->h_bodies.begin(), c->h_bodies.end(), hb.begin());
   for (int b = 0; b < nb; ++b) {
     Body& B = hb[b];
     const double* arrs[] = {pos + 3 * b, linvel ? linvel + 3 * b : nullptr, angvel ? angvel + 3 * b : nullptr,
@@ -1087,7 +1127,7 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
   if (e == hipSuccess) e = hipEventRecord(c->bpin_ev, c->stream);
   if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
   c->bpin_pending = true;
-  c->h_bodies = hb;
+  c->h_bodies.swap(hb);
   return CRM_OK;
 }
 
@@ -1124,6 +1164,7 @@ crm_status crm_set_materials(crm_ctx* c, int32_t n_mat, const double* mu_s, cons
   HIPCHK(c, hipMemcpyAsync(c->d_mat, tab.data(), sizeof(float4) * (size_t)n_mat, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   c->n_mat = n_mat;
+  c->h_mattab = tab;
   c->h_mat.assign(material, material + c->n_soil);
   return CRM_OK;
 }
@@ -1461,6 +1502,128 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
   c->working_valid = false;
   c->force_rebuild = true;
   c->rec_valid = false;
+  return CRM_OK;
+}
+
+namespace {
+
+// Layout of a checkpoint: this header, the four master planes (n_total float4
+// each), the body table (nb Body), the material table (n_mat float4) and, when
+// materials were set, the material of each soil particle (n_soil uint16).
+struct CkptHeader {
+  char magic[8];
+  uint32_t abi_version, pos_mode;
+  int64_t n_total, n_soil;
+  int32_t nb, n_mat;
+  int64_t step;
+  int32_t tile_cfg, has_mat;
+  int64_t payload;   // bytes after the header
+};
+constexpr char kCkptMagic[8] = {'C', 'R', 'M', 'C', 'K', 'P', 'T', '1'};
+
+size_t ckpt_payload(const crm_ctx* c, int32_t n_mat, bool has_mat) {
+  return 4 * sizeof(float4) * (size_t)c->n_total + sizeof(Body) * (size_t)c->nb + sizeof(float4) * (size_t)n_mat +
+         (has_mat ? sizeof(uint16_t) * (size_t)c->n_soil : 0);
+}
+
+}  // namespace
+
+crm_status crm_checkpoint_bytes(crm_ctx* c, size_t* bytes) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (!bytes) return fail(c, CRM_E_INVALID, "bytes is NULL");
+  *bytes = sizeof(CkptHeader) + ckpt_payload(c, c->n_mat, !c->h_mat.empty());
+  return CRM_OK;
+}
+
+crm_status crm_save_checkpoint(crm_ctx* c, void* buf, size_t bytes) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  const bool has_mat = !c->h_mat.empty();
+  const size_t need = sizeof(CkptHeader) + ckpt_payload(c, c->n_mat, has_mat);
+  if (!buf || bytes < need) return fail(c, CRM_E_INVALID, "checkpoint buffer is NULL or too small");
+  if (!rebuild_due(c))
+    return fail(c, CRM_E_STATE, "a checkpoint is taken where the next step rebuilds the lists (step mod ps_freq = 0)");
+  hipStream_t s = c->stream;
+  if (c->working_valid)
+    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, sizeof(h.magic));
+  h.abi_version = CRM_ABI_VERSION;
+  h.pos_mode = (uint32_t)c->grid.cell;
+  h.n_total = c->n_total;
+  h.n_soil = c->n_soil;
+  h.nb = c->nb;
+  h.n_mat = c->n_mat;
+  h.step = c->step;
+  h.tile_cfg = c->tile_cfg;
+  h.has_mat = has_mat ? 1 : 0;
+  h.payload = (int64_t)(need - sizeof(CkptHeader));
+  char* o = static_cast<char*>(buf);
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  const size_t pl = sizeof(float4) * (size_t)c->n_total;
+  const float4* planes[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
+  for (int q = 0; q < 4; ++q, o += pl) HIPCHK(c, hipMemcpyAsync(o, planes[q], pl, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (c->nb > 0) std::memcpy(o, c->h_bodies.data(), sizeof(Body) * (size_t)c->nb);
+  o += sizeof(Body) * (size_t)c->nb;
+  std::memcpy(o, c->h_mattab.data(), sizeof(float4) * (size_t)c->n_mat);
+  o += sizeof(float4) * (size_t)c->n_mat;
+  if (has_mat) std::memcpy(o, c->h_mat.data(), sizeof(uint16_t) * (size_t)c->n_soil);
+  return CRM_OK;
+}
+
+crm_status crm_load_checkpoint(crm_ctx* c, const void* buf, size_t bytes) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  CkptHeader h{};
+  if (!buf || bytes < sizeof(h)) return fail(c, CRM_E_INVALID, "not a checkpoint (too short)");
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, sizeof(h.magic)) != 0 || h.abi_version != CRM_ABI_VERSION)
+    return fail(c, CRM_E_INVALID, "not a checkpoint of this library version");
+  if (h.n_total != c->n_total || h.n_soil != c->n_soil || h.nb != c->nb || h.pos_mode != (uint32_t)c->grid.cell)
+    return fail(c, CRM_E_INVALID, "checkpoint of another configuration (particles, bodies or position form)");
+  if (h.n_mat < 1 || h.n_mat > crm::kMaxMaterials || h.step < 0 || h.tile_cfg < CRM_TILE_NONE ||
+      h.tile_cfg > CRM_TILE_LARGE)
+    return fail(c, CRM_E_INVALID, "corrupt checkpoint header");
+  const size_t need = sizeof(h) + ckpt_payload(c, h.n_mat, h.has_mat != 0);
+  if (h.payload != (int64_t)(need - sizeof(h)) || bytes < need)
+    return fail(c, CRM_E_INVALID, "checkpoint size does not match its header");
+  const char* o = static_cast<const char*>(buf) + sizeof(h);
+  const size_t pl = sizeof(float4) * (size_t)c->n_total;
+  const char* bodies = o + 4 * pl;
+  const char* mattab = bodies + sizeof(Body) * (size_t)c->nb;
+  const char* mats = mattab + sizeof(float4) * (size_t)h.n_mat;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipStreamSynchronize(s));
+  float4* planes[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
+  for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(planes[q], o + q * pl, pl, hipMemcpyHostToDevice, s));
+  std::vector<Body> hb((size_t)(c->nb > 0 ? c->nb : 1));
+  if (c->nb > 0) std::memcpy(hb.data(), bodies, sizeof(Body) * (size_t)c->nb);
+  std::vector<float4> tab((size_t)h.n_mat);
+  std::memcpy(tab.data(), mattab, sizeof(float4) * (size_t)h.n_mat);
+  HIPCHK(c, hipMemcpyAsync(c->d_bodies, hb.data(), sizeof(Body) * hb.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_mat, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->h_bodies = hb;
+  c->h_mattab = tab;
+  c->n_mat = h.n_mat;
+  if (h.has_mat) {
+    c->h_mat.resize((size_t)c->n_soil);
+    std::memcpy(c->h_mat.data(), mats, sizeof(uint16_t) * (size_t)c->n_soil);
+  } else {
+    c->h_mat.clear();
+  }
+  c->step = h.step;
+  c->tile_cfg = h.tile_cfg;
+  c->working_valid = false;
+  c->force_rebuild = true;
+  c->place_all = true;
+  c->rec_valid = false;
+  c->stepped = false;
+  c->disp_pending = false;
+  c->last_rebuild = h.step;
   return CRM_OK;
 }
 

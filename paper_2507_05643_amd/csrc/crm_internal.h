@@ -143,11 +143,12 @@ hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a
                       Grid g, uint32_t* key, uint32_t* rank, uint32_t* cell_cnt, hipStream_t s);
 // Place into cell order with an x order key per place (part 2), then rank by
 // (x, id) inside each cell and gather the master state into the sorted
-// working set (part 3).
+// working set (part 3). tmpx holds n_proc 64-bit keys (32-bit keys in its
+// first half for FP32 positions).
 hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cell_start,
-                        int64_t n_proc, const int32_t* proc_ids, const float4* m_a, uint32_t* tmp,
-                        uint32_t* tmpx, hipStream_t s);
-hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* tmpx, const uint32_t* key, const int32_t* proc_ids,
+                        int64_t n_proc, const int32_t* proc_ids, const float4* m_a, const float4* m_d, uint32_t* tmp,
+                        uint64_t* tmpx, bool cell, hipStream_t s);
+hipError_t gather_sorted(const uint32_t* tmp, const uint64_t* tmpx, const uint32_t* key, const int32_t* proc_ids,
                          const uint32_t* cell_start, int64_t n_proc, int64_t n_soil,
                          const uint8_t* flags, const float4* m_a, const float4* m_b,
                          const float4* m_c, const float4* m_d, Planes A, Planes B, float4* pos4,

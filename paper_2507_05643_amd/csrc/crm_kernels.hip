@@ -389,19 +389,35 @@ __device__ inline double f64_from_order_key(unsigned long long k) {
   return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
 }
 
-// Arrival position of particle k in its cell, with the x coordinate (the
-// stored one: absolute, or the offset in the cell for cell-offset positions)
-// as an order key beside it.
+// Arrival position of particle k in its cell, with an order key of its x
+// coordinate beside it: the FP32 coordinate for absolute positions (K =
+// uint32_t); for cell-offset positions the stored x cell and then the FP32
+// offset inside it (K = uint64_t), which orders by x also where stored cells
+// outside the grid share an edge cell of the hash.
+template <typename K>
+__device__ inline K x_order_key(float4 a, float4 d);
+template <>
+__device__ inline uint32_t x_order_key<uint32_t>(float4 a, float4) {
+  return f32_order_key(a.x);
+}
+template <>
+__device__ inline uint64_t x_order_key<uint64_t>(float4 a, float4 d) {
+  const uint32_t cx = __float_as_uint(d.z) ^ 0x80000000u;   // signed cell -> unsigned order
+  return ((uint64_t)cx << 32) | f32_order_key(a.x);
+}
+
+template <typename K>
 __global__ __launch_bounds__(kBlock) void k_place(const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
                                                   const uint32_t* __restrict__ cs, int64_t n,
                                                   const int32_t* __restrict__ ids, const float4* __restrict__ m_a,
-                                                  uint32_t* __restrict__ tmp, uint32_t* __restrict__ tmpx) {
+                                                  const float4* __restrict__ m_d, uint32_t* __restrict__ tmp,
+                                                  K* __restrict__ tmpx) {
   int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   const int64_t id = ids ? ids[k] : k;
   const uint32_t at = cs[key[k]] + rank[k];
   tmp[at] = (uint32_t)k;
-  tmpx[at] = f32_order_key(m_a[id].x);
+  tmpx[at] = x_order_key<K>(m_a[id], sizeof(K) == 8 ? m_d[id] : make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
 // Sec. 4.1 step 2 (sort by cell): the order inside a cell, which the hash sort
@@ -410,8 +426,9 @@ __global__ __launch_bounds__(kBlock) void k_place(const uint32_t* __restrict__ k
 // from end to end, so a block's neighbour ranges can be cut to the x interval
 // its rows reach. The master state is gathered into the cell-sorted working
 // planes.
+template <typename K>
 __global__ __launch_bounds__(kBlock) void k_gather_sorted(
-    const uint32_t* __restrict__ tmp, const uint32_t* __restrict__ tmpx, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ tmp, const K* __restrict__ tmpx, const uint32_t* __restrict__ key,
     const int32_t* __restrict__ ids, const uint32_t* __restrict__ cs, int64_t n, int64_t n_soil,
     const uint8_t* __restrict__ flags, const float4* __restrict__ m_a, const float4* __restrict__ m_b,
     const float4* __restrict__ m_c, const float4* __restrict__ m_d, Planes A, Planes B, float4* __restrict__ pos4,
@@ -420,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
   uint32_t k = tmp[p];
-  const uint32_t xk = tmpx[p];
+  const K xk = tmpx[p];
   int64_t id = ids ? ids[k] : (int64_t)k;
   // the record's loads go out before the rank is counted
   float4 a = m_a[id], b = m_b[id], cc = m_c[id], d = m_d[id];
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   uint32_t r = 0;
 #pragma unroll 4
   for (uint32_t q = lo; q < hi; ++q) {   // ids ascend with k
-    const uint32_t xq = tmpx[q];
+    const K xq = tmpx[q];
     r += (xq < xk || (xq == xk && tmp[q] < k)) ? 1u : 0u;
   }
   uint32_t f = lo + r;
@@ -1921,20 +1938,29 @@ hipError_t hash_count(const int32_t* ids, int64_t n, const float4* m_a, const fl
 }
 
 hipError_t place_sorted(const uint32_t* key, const uint32_t* rank, const uint32_t* cs, int64_t n, const int32_t* ids,
-                        const float4* m_a, uint32_t* tmp, uint32_t* tmpx, hipStream_t s) {
+                        const float4* m_a, const float4* m_d, uint32_t* tmp, uint64_t* tmpx, bool cell, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_place<<<nblk(n), kBlock, 0, s>>>(key, rank, cs, n, ids, m_a, tmp, tmpx);
+  if (cell)
+    k_place<uint64_t><<<nblk(n), kBlock, 0, s>>>(key, rank, cs, n, ids, m_a, m_d, tmp, tmpx);
+  else
+    k_place<uint32_t><<<nblk(n), kBlock, 0, s>>>(key, rank, cs, n, ids, m_a, m_d, tmp,
+                                                 reinterpret_cast<uint32_t*>(tmpx));
   return hipGetLastError();
 }
 
-hipError_t gather_sorted(const uint32_t* tmp, const uint32_t* tmpx, const uint32_t* key, const int32_t* ids,
+hipError_t gather_sorted(const uint32_t* tmp, const uint64_t* tmpx, const uint32_t* key, const int32_t* ids,
                          const uint32_t* cs, int64_t n, int64_t n_soil, const uint8_t* flags, const float4* m_a,
                          const float4* m_b, const float4* m_c, const float4* m_d, Planes A, Planes B,
                          float4* pos4, int4* cpos, int32_t* slot_id, int32_t* slot_k, uint32_t* skey, bool cell,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_gather_sorted<<<nblk(n), kBlock, 0, s>>>(tmp, tmpx, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d, A, B,
-                                             pos4, cpos, cell ? 1 : 0, slot_id, slot_k, skey);
+  if (cell)
+    k_gather_sorted<uint64_t><<<nblk(n), kBlock, 0, s>>>(tmp, tmpx, key, ids, cs, n, n_soil, flags, m_a, m_b, m_c, m_d,
+                                                         A, B, pos4, cpos, 1, slot_id, slot_k, skey);
+  else
+    k_gather_sorted<uint32_t><<<nblk(n), kBlock, 0, s>>>(tmp, reinterpret_cast<const uint32_t*>(tmpx), key, ids, cs,
+                                                         n, n_soil, flags, m_a, m_b, m_c, m_d, A, B, pos4, cpos, 0,
+                                                         slot_id, slot_k, skey);
   return hipGetLastError();
 }
 
@@ -2009,6 +2035,7 @@ hipError_t bce(Planes S, const NearRow* rows, int64_t n, const uint32_t* nbr, co
 }
 
 int64_t reduce_chunk() { return kRedChunk; }
+
 
 hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s) {
   if (plan.nseg <= 0) return hipSuccess;

@@ -99,6 +99,7 @@ def test_adjoint_cell_offset_positions(crm):
     say("cell-offset adjoint vs oracle", rep)
     for k in ("x", "u", "s", "rho"):
         assert rep[k] <= 1e-3, (k, rep[k])
+    assert rep["params"] <= 1e-2, rep["params"]
     sim.close()
 
 
@@ -111,6 +112,8 @@ def test_adjoint_two_materials(crm):
     say("two-material adjoint vs oracle", rep, got["params"])
     for k in ("x", "u", "s", "rho"):
         assert rep[k] <= 1e-3, (k, rep[k])
+    # friction and cohesion of both materials (what a calibration needs)
+    assert rep["params"] <= 1e-2, rep["params"]
     sim.close()
 
 

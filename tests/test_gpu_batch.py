@@ -10,7 +10,7 @@ import pytest
 
 from oracle.oracle import Oracle
 from paper_2507_05643_amd import scenes
-from tests.parity_util import fields_report, normwise
+from tests.parity_util import check_fields, normwise
 
 pytestmark = pytest.mark.gpu
 
@@ -76,10 +76,7 @@ def test_small_batch_matches_oracle_with_materials(crm):
     orc.set_materials(sc.meta["materials"], sc.meta["material"])
     sim.step(20)
     orc.step(20)
-    rep = fields_report(sim.state(), orc.state(), sc.n_soil)
-    print("batch vs oracle", rep, flush=True)
-    for k, v in rep.items():
-        assert v <= 1e-3, (k, v)
+    check_fields(sim.state(), orc.state(), sc, 20, 1e-3, "batch vs oracle")
     F, _ = sim.forces()
     Fr, _ = orc.forces()
     assert normwise(F, Fr) <= 1e-3

@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from oracle.oracle import Oracle
 from paper_2507_05643_amd import scenes
-from tests.parity_util import check_cell_sort, csr_rows, normwise, world_positions
+from tests.parity_util import check_cell_sort, check_fields, csr_rows, normwise, world_positions
 
 pytestmark = pytest.mark.gpu
 FAR = (9999.0, 0.0, 0.0)
@@ -32,16 +32,6 @@ def crm():
         pytest.skip("no GPU")
     from paper_2507_05643_amd import crm as C
     return C
-
-
-def _local_report(g, r, origin, n):
-    """Normwise errors with positions taken relative to the column's origin, the
-    same normalisation as for a column placed at the coordinate origin."""
-    o = np.asarray(origin, dtype=np.float64)
-    return dict(pos=normwise(g["pos"][:n] - o, r["pos"][:n] - o),
-                vel=normwise(g["vel"][:n], r["vel"][:n]),
-                sigma=normwise(g["sigma"][:n], r["sigma"][:n]),
-                rho=normwise(g["rho"][:n], r["rho"][:n]))
 
 
 @pytest.mark.parametrize("origin", [None, FAR])
@@ -70,38 +60,32 @@ def test_cell_offset_parity_far_from_origin(crm, steps, tol):
     orc = Oracle(sc, nbr_mode="cells")
     sim.step(steps)
     orc.step(steps)
-    rep = _local_report(sim.state(), orc.state(), FAR, sc.n_soil)
-    say("cell-offset at 9999 m", steps, rep)
-    for k, v in rep.items():
-        assert v <= tol, (k, v)
+    check_fields(sim.state(), orc.state(), sc, steps, tol, "cell-offset at 9999 m")
     F, _ = sim.forces()
     Fr, _ = orc.forces()
     assert normwise(F, Fr) <= tol
     sim.close()
 
 
-def test_both_forms_near_origin_against_oracle(crm):
+@pytest.mark.parametrize("steps", [50, 100])
+def test_both_forms_near_origin_against_oracle(crm, steps):
     """Near the origin both forms resolve the motion. Plain FP32 positions round
-    every step's increment (the spacing at 0.15 m is 1.5e-8 m against ~1e-7 m of
-    motion per step); the cell-offset form accumulates the increment in FP64, so
-    its displacements are at least as close to the oracle's."""
+    every step's update at the coordinates' magnitude (half an ulp at 0.15 m is
+    7.5e-9 m against ~1e-7 m of motion per step); the cell-offset form rounds
+    it at the magnitude of the offset inside a cell (half an ulp at 0.024 m is
+    0.9e-9 m), so its displacements hold a bar eight times tighter."""
     errs = {}
     for mode in (0, 1):
         sc = scenes.column(seed=1, pos_mode=mode)
-        x0 = world_positions(sc)
         sim = crm.Simulation(sc)
         orc = Oracle(sc, nbr_mode="cells")
-        sim.step(50)
-        orc.step(50)
-        g, r = sim.state(), orc.state()
-        n = sc.n_soil
-        errs[mode] = (normwise(g["pos"][:n] - x0[:n], r["pos"][:n] - x0[:n]),
-                      normwise(g["sigma"][:n], r["sigma"][:n]))
+        sim.step(steps)
+        orc.step(steps)
+        rep = check_fields(sim.state(), orc.state(), sc, steps, 1e-3, f"near origin, pos_mode {mode}")
+        errs[mode] = rep["disp"]
         sim.close()
-    say("near origin, 50 steps (displacement, sigma): plain", errs[0], "cell-offset", errs[1])
-    assert errs[0][0] < 0.1 and errs[1][0] < 1e-2
-    assert errs[1][0] <= max(errs[0][0], 1e-3)
-    assert errs[0][1] <= 1e-3 and errs[1][1] <= 1e-3
+    say("displacement error: plain", errs[0], "cell-offset", errs[1])
+    assert errs[1] <= errs[0]
 
 
 def test_plain_fp32_loses_motion_far_from_origin(crm):
@@ -125,3 +109,27 @@ def test_plain_fp32_loses_motion_far_from_origin(crm):
     say("displacement error after 40 steps at 9999 m: plain", errs[0], "cell-offset", errs[1])
     assert errs[0] > 0.5
     assert errs[1] < 1e-2
+
+
+@pytest.mark.parametrize("pos_mode", [0, 1])
+def test_lists_with_particles_outside_the_grid(crm, pos_mode):
+    """Particles (soil and markers) below the grid's lower corner along x and y
+    share its edge cells with particles of other stored cells; inside such a
+    cell the slots are still in x order, and the lists equal the brute-force
+    definition |x_i - x_j| < 2h."""
+    sc = scenes.column(seed=4, n=10, pos_mode=pos_mode)
+    sc.params.update(domain_lo=(0.045, 0.045, -0.04))
+    x = world_positions(sc)
+    assert (x[:, 0] < 0.045).sum() > 300
+    sim = crm.Simulation(sc)
+    sim.step(1)
+    ex = sim.export()
+    sid, skey, cs, ce = O.sort_cells(sc.params, x)
+    check_cell_sort(ex["sorted_ids"], sid, cs, ce, x)
+    off, nbr = O.neighbors(sc.params, x, mode="brute")
+    ref = csr_rows(off, nbr)
+    got = csr_rows(ex["off"], ex["nbr"], ex["rows"])
+    for i in range(sc.n_total):
+        want = ref[i] if i < sc.n_soil else ref[i][ref[i] < sc.n_soil]
+        assert np.array_equal(got[i], want), i
+    sim.close()

@@ -49,3 +49,30 @@ def test_normwise():
     assert normwise([1.0, 2.0], [1.0, 2.0]) == 0.0
     assert normwise([1.0, 2.5], [1.0, 2.0]) == pytest.approx(0.25)
     assert normwise([0.5], [0.0]) == 0.5
+
+
+def test_displacement_bar():
+    from tests.parity_util import displacement_bar, half_ulp32
+    assert half_ulp32(1.0) == 2.0 ** -24
+    assert half_ulp32(0.16) == 2.0 ** -27          # 0.16 lies in [0.125, 0.25)
+    # 100 steps near 0.16 m with 3e-5 m of motion: 1e-3 + 101 * 7.45e-9 / 3e-5
+    b = displacement_bar(100, 1e-3, 0.16, 3.0e-5)
+    assert abs(b - (1e-3 + 101 * 2.0 ** -27 / 3.0e-5)) < 1e-15
+    assert displacement_bar(5, 1e-3, 0.16, 0.0) == 0.0
+
+
+def test_check_fields_catches_a_frozen_position():
+    """A path that never moves its particles passes a position check normalised
+    by the coordinates, but not the displacement check."""
+    import types
+    from tests.parity_util import check_fields
+    rng = np.random.default_rng(0)
+    x0 = rng.uniform(0.0, 0.16, size=(500, 3)).astype(np.float32).astype(np.float64)
+    ref = dict(pos=x0 + rng.normal(0.0, 3e-5, size=x0.shape), vel=np.ones((500, 3)), sigma=np.ones((500, 6)),
+               rho=np.ones(500))
+    got = dict(ref, pos=x0.copy())
+    sc = types.SimpleNamespace(n_soil=500, pos=x0, params=dict(pos_mode=0, h=0.012))
+    import pytest
+    with pytest.raises(AssertionError):
+        check_fields(got, ref, sc, 100, 1e-3)
+    check_fields(ref, ref, sc, 100, 1e-3)
