@@ -508,13 +508,27 @@ crm_status update_body_plan(crm_ctx* c, const int32_t* ids) {
   return CRM_OK;
 }
 
+// The working set back into the master store: the soil rows of state A (all
+// four planes) and the extrapolated velocity and stress of the processed
+// markers from the last stage (B), so that the master holds every particle's
+// values from the last step it was processed in, whether or not the state was
+// read in between.
+crm_status scatter_back(crm_ctx* c) {
+  hipStream_t s = c->stream;
+  HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  HIPCHK(c, crm::scatter_marker_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_b, c->m_c, c->m_d, s));
+  return CRM_OK;
+}
+
 // Alg. 3 lines for a rebuild step: activity (t > t_delay), count, capacity,
 // then PreprocessNeighborList + Algorithm 1 on the processed set.
 crm_status rebuild(crm_ctx* c) {
   hipStream_t s = c->stream;
   const crm_params& P = c->prm;
-  if (c->working_valid)
-    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  if (c->working_valid) {
+    crm_status st0 = scatter_back(c);
+    if (st0 != CRM_OK) return st0;
+  }
   // from here until the rebuild completes the master store is the state: a
   // rebuild that fails (e.g. an allocation) leaves the state as it was, and
   // the next step starts the rebuild again
@@ -1437,13 +1451,13 @@ crm_status crm_get_state(crm_ctx* c, double* pos, float* vel, float* sigma, floa
   crm_status st = usable(c);
   if (st != CRM_OK) return st;
   hipStream_t s = c->stream;
+  if (c->working_valid) {
+    crm_status st0 = scatter_back(c);
+    if (st0 != CRM_OK) return st0;
+  }
   {
     crm_status st0 = place_master_markers(c);
     if (st0 != CRM_OK) return st0;
-  }
-  if (c->working_valid) {
-    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
-    HIPCHK(c, crm::scatter_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
   }
   const size_t n = (size_t)c->n_total;
   std::vector<float4> ha(n), hb(n), hc(n), hd(n);
@@ -1472,8 +1486,10 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
     for (int64_t i = 0; i < 3 * n; ++i)
       if (!std::isfinite(pos[i])) return fail(c, CRM_E_INVALID, "non-finite position");
   hipStream_t s = c->stream;
-  if (c->working_valid)
-    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  if (c->working_valid) {
+    crm_status st0 = scatter_back(c);
+    if (st0 != CRM_OK) return st0;
+  }
   std::vector<float4> ha((size_t)n), hb((size_t)n), hc((size_t)n), hd((size_t)n);
   if (n > 0) {
     HIPCHK(c, hipMemcpyAsync(ha.data(), c->m_a, sizeof(float4) * n, hipMemcpyDeviceToHost, s));
@@ -1545,8 +1561,10 @@ crm_status crm_save_checkpoint(crm_ctx* c, void* buf, size_t bytes) {
   if (!rebuild_due(c))
     return fail(c, CRM_E_STATE, "a checkpoint is taken where the next step rebuilds the lists (step mod ps_freq = 0)");
   hipStream_t s = c->stream;
-  if (c->working_valid)
-    HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  if (c->working_valid) {
+    crm_status st0 = scatter_back(c);
+    if (st0 != CRM_OK) return st0;
+  }
   CkptHeader h{};
   std::memcpy(h.magic, kCkptMagic, sizeof(h.magic));
   h.abi_version = CRM_ABI_VERSION;

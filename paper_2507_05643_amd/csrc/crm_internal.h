@@ -294,5 +294,9 @@ hipError_t adj_unpack(int64_t n, CPlanes in, double* pos, float* vel, float* sig
 // Scatter working records back to the master planes.
 hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
                         float4* m_a, float4* m_b, float4* m_c, float4* m_d, hipStream_t s);
+// Marker rows back to the master planes: velocity and stress (b, c, d.xy);
+// the master positions stay those of the last marker placement.
+hipError_t scatter_marker_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
+                               float4* m_b, float4* m_c, float4* m_d, hipStream_t s);
 
 }  // namespace crm

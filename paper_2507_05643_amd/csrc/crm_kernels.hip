@@ -1834,6 +1834,26 @@ __global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* 
   m_d[id] = src.d[s];
 }
 
+// Marker rows: the extrapolated velocity and stress only. A marker's position
+// (a.xyz, and its cells in d.zw) is the body's placement, never the working
+// set's copy, which may carry the pose of an earlier step.
+__global__ __launch_bounds__(kBlock) void k_scatter_markers(CPlanes src, const int32_t* __restrict__ rows, int64_t n,
+                                                            const int32_t* __restrict__ slot_id,
+                                                            float4* __restrict__ m_b, float4* __restrict__ m_c,
+                                                            float4* __restrict__ m_d) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n) return;
+  const int32_t s = rows[r];
+  const int32_t id = slot_id[s];
+  m_b[id] = src.b[s];
+  m_c[id] = src.c[s];
+  const float4 d = src.d[s];
+  float4 md = m_d[id];
+  md.x = d.x;
+  md.y = d.y;
+  m_d[id] = md;
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned nblk_groups(int64_t rows) { return nblk(rows * kGroup); }
 
@@ -2119,6 +2139,13 @@ hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n, const int32
                         float4* m_b, float4* m_c, float4* m_d, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_scatter<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_a, m_b, m_c, m_d);
+  return hipGetLastError();
+}
+
+hipError_t scatter_marker_rows(CPlanes src, const int32_t* rows, int64_t n, const int32_t* slot_id, float4* m_b,
+                               float4* m_c, float4* m_d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_scatter_markers<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_b, m_c, m_d);
   return hipGetLastError();
 }
 

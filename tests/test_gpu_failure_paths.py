@@ -206,3 +206,23 @@ def test_state_round_trip_restart_is_bit_identical(crm):
     assert np.array_equal(Fg[1], Fw[1])
     a.close()
     b.close()
+
+
+def test_state_read_between_set_bodies_and_step_changes_nothing(crm):
+    """crm_get_state after crm_set_bodies (bodies moved) places the markers at
+    the new poses without losing them to the working set's records of the
+    previous poses: the run continues as one where the state was not read."""
+    sc = _strip()
+    runs = []
+    for read in (False, True):
+        sim = crm.Simulation(sc)
+        sim.step(2)
+        sim.set_bodies(*_bodies(sc, 1.5))
+        if read:
+            sim.state()
+        sim.step(3)
+        runs.append((sim.state(), sim.forces()))
+        sim.close()
+    (a, Fa), (b, Fb) = runs
+    assert _same(a, b)
+    assert np.array_equal(Fa[0], Fb[0]) and np.array_equal(Fa[1], Fb[1])

@@ -7,7 +7,7 @@ cohesive cluster pulled apart by a diverging velocity field. The oracle
 reports, per particle and step, the branch of its return mapping (tension
 cut-off, admissible, radial return) and the mu(I) case of the radial returns
 (mu_s: no shear-rate increase; mu_2: tensile trial pressure; the interior
-formula); each is taken at least 100 times over the run. Both sides start
+formula); over the two workloads each is taken at least 100 times. Both sides start
 from the same FP32 state, warmed by oracle steps so that plastic flow is
 under way in the first compared step.
 """
@@ -76,6 +76,15 @@ def _tally(orc, acc):
     acc["radial_mu_I"] += int(((br == 4) & (mc == 2)).sum())
 
 
+# The pressed wheel takes every case (the interior mu(I) formula where the
+# shear rate rises under compression); the pull-apart cluster is there for the
+# tensile cases (cut-off, and radial returns at mu_2 under a tensile trial
+# pressure). Measured over 30 steps: wheel every case >= 100; cluster cut-off
+# 5341, admissible 17834, radial 6825 (mu_s 1345, mu_2 5473, interior 7).
+REQUIRED = {"wheel": ("cut_off", "admissible", "radial", "radial_mu_s", "radial_mu_2", "radial_mu_I"),
+            "cluster": ("cut_off", "admissible", "radial", "radial_mu_s", "radial_mu_2")}
+
+
 @pytest.mark.parametrize("name,warm,steps", [("wheel", 20, 30), ("cluster", 3, 30)])
 def test_return_mapping_branches_parity(crm, name, warm, steps):
     sc = _warm(_wheel() if name == "wheel" else _cluster(), warm)
@@ -93,8 +102,8 @@ def test_return_mapping_branches_parity(crm, name, warm, steps):
         orc.step(1)
         _tally(orc, acc)
     print(name, "branches over", steps, "steps", acc, flush=True)
-    for k, v in acc.items():
-        assert v >= 100, (k, v)
+    for k in REQUIRED[name]:
+        assert acc[k] >= 100, (k, acc[k])
     check_fields(sim.state(), orc.state(), sc, steps, 1e-3, f"plastic {name}")
     if sc.bodies:
         F, T = sim.forces()
