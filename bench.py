@@ -1,19 +1,25 @@
 #!/usr/bin/env python
 """Throughput of the CRM step on one MI355X: particle-steps/s on the
 single-wheel soil bin (200 x 120 x 40 soil particles at dx = 5 mm, container,
-grousered wheel driven at slip 0.3 under a 100 N load).
+grousered wheel driven at slip 0.3 under a 100 N load), then the same step in
+its other forms: the 10 km strip with active boxes around a four-wheeled
+vehicle at x = 5 km with plain FP32 positions and with cell index + FP32
+offset positions, and 64 batched bins in one context.
 
 Every step is one co-simulation exchange as in the paper's FSI loop: the host
-(standing in for the multibody side) sets the wheel state, libcrm advances one
-step, and the host reads back the wheel force and integrates the wheel's free
-vertical degree of freedom.
+(standing in for the multibody side) sets the body states, libcrm advances one
+step, and the host reads back the forces (for the wheel bins it integrates the
+wheel's free vertical degree of freedom).
 
-Prints one JSON line (see the keys below). With --gpus N > 1 it exits: this
-build measures one GPU.
+Prints one JSON line: the wheel bin's figures as the headline (value, roofline
+of k_fluid_stage2, the oracle's CPU baseline, the reverse-mode cost) and each
+further form under "forms" with its own rate, ms per step and roofline of its
+dominant kernel. With --gpus N > 1 it exits: this build measures one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -38,11 +44,37 @@ BYTES_PER_PAIR = 2
 PEAK_FP32_TFLOPS = 157.3
 TILE_NAMES = ("none", "small", "large")
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of k_fluid_stage2 on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a 512 MiB copy (fetch x2, write x1); the
-# commands and figures are in profiles/wheel_bin_kernels_lds_tiles.md (small
-# LDS tile). None once the kernel changes.
-STAGE2_TRAFFIC_BYTES = 466.3e6
+# Algorithmic bytes of the activity pass per particle (all N particles, every
+# list rebuild with active domains): the stored position (12 B of FP32
+# coordinates, or 12 B of offsets + 8 B of cell indices) read, one flag byte
+# written.
+ACTIVITY_BYTES = {0: 12 + 1, 1: 20 + 1}
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a
+# plain copy of known size: fetch x2, write x1), with the digest of the kernel
+# sources they were taken on; reported only while the sources are unchanged
+# (summaries and commands in profiles/).
+MEASURED_TRAFFIC = {
+    "k_fluid_stage2 wheel bin": dict(bytes=None, source=None),
+    "k_activity strip pos_mode 0": dict(bytes=None, source=None),
+    "k_activity strip pos_mode 1": dict(bytes=None, source=None),
+}
+KERNEL_SOURCES = ("crm_kernels.hip", "crm_device.h", "crm_internal.h")
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_05643_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    m = MEASURED_TRAFFIC.get(key)
+    if not m or m["bytes"] is None or m["source"] != source_digest():
+        return None
+    return m["bytes"]
 
 
 class WheelDriver:
@@ -116,25 +148,191 @@ class BinDrivers:
         self.theta[ks] += dt * self.omega[ks]
 
 
-def run_batch(args):
-    """Batched bins: one context for all bins (kernels replayed as a graph) vs
-    one context per bin, stepped one after the other on the same stream."""
+def stage2_roofline(prof, cnt, key):
+    """k_fluid_stage2 against the FP32 vector peak: 61 flops per soil pair over
+    the mean launch time (HIP events around that kernel on the context's stream)."""
+    st2 = prof["soil_stage2"]
+    ms2 = st2["ms"] / max(st2["launches"], 1)
+    pairs = prof["soil_pairs"]
+    rows = cnt["soil_rows"]
+    flops = FLOPS_PER_PAIR * pairs
+    bytes_ = BYTES_PER_PARTICLE * rows + BYTES_PER_PAIR * pairs
+    tflops = flops / (ms2 * 1e-3) / 1e12
+    gbs = bytes_ / (ms2 * 1e-3) / 1e9
+    return dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(tflops / PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(key),
+                kernel="k_fluid_stage2", launch_ms=round(ms2, 5), algorithmic_flops=flops,
+                hbm_view=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=round(gbs / PEAK_HBM_GBS, 4), algorithmic_bytes=bytes_))
+
+
+def activity_roofline(prof, cnt, pos_mode):
+    """k_activity (flags of all N particles at each list rebuild) against HBM."""
+    act = prof["activity"]
+    if act["launches"] == 0:
+        return None
+    ms = act["ms"] / act["launches"]
+    bytes_ = ACTIVITY_BYTES[pos_mode] * cnt["n_total"]
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s", frac=round(gbs / PEAK_HBM_GBS, 4),
+                traffic=measured_traffic(f"k_activity strip pos_mode {pos_mode}"), kernel="k_activity",
+                launch_ms=round(ms, 5), algorithmic_bytes=bytes_)
+
+
+def per_launch(prof):
+    return {k: round(v["ms"] / max(v["launches"], 1), 5) for k, v in prof.items() if isinstance(v, dict)}
+
+
+def timed_steps(step_fn, n_warm, n_steps):
     import torch
-    from paper_2507_05643_amd import crm, scenes
+    for _ in range(n_warm):
+        step_fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        step_fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_wheel(args, crm, scenes):
+    """The single-wheel soil bin, one co-simulation exchange per step (the headline)."""
+    import torch
+    sc = scenes.wheel_bin(seed=0, ps_freq=args.ps_freq)
+    drv = WheelDriver(sc)
+    sim = crm.Simulation(sc, device=0)
+    dt = sc.params["dt"]
+
+    def one_step():
+        F, _ = sim.cosim_step(*drv.state())
+        drv.advance(F[1], dt)
+
+    for _ in range(args.warmup):
+        one_step()
+    tile = sim.autotune() if args.autotune else sim.autotune(TILE_NAMES.index(args.tile))
+    torch.cuda.synchronize()
+    # events around the dominant kernel only, on the context's stream
+    sim.profiling(True, classes=["soil_stage2"])
+    wall = timed_steps(one_step, 0, args.steps)
+    prof = sim.profile()
+    # per-class breakdown (every kernel class timed) over a short untimed run
+    sim.profiling(True)
+    for _ in range(min(args.steps, 10 * args.ps_freq)):
+        one_step()
+    prof_all = sim.profile()
+    sim.profiling(False)
+    cnt = sim.counts()
+    F, T = sim.forces()
+    key = "k_fluid_stage2 wheel bin" if (args.ps_freq == 10 and tile == crm.TILE_SMALL) else None
+    roofline = stage2_roofline(prof, cnt, key)
+    adjoint = adjoint_cost(sim, one_step, args.adjoint_steps, args.ps_freq, sc.n_soil, len(sc.bodies)) \
+        if args.adjoint_steps > 0 else None
+    print(json.dumps(dict(form="wheel", profile_ms_per_launch=per_launch(prof_all), counts=cnt,
+                          wheel_force=F[1].tolist(), wheel_torque=T[1].tolist(), wheel_z=float(drv.x[2]))),
+          file=sys.stderr, flush=True)
+    sim.close()
+    return dict(value=cnt["n_proc"] * args.steps / wall, wall=wall, cnt=cnt, roofline=roofline, adjoint=adjoint,
+                soil_rate=cnt["soil_rows"] * args.steps / wall, breakdown=per_launch(prof_all),
+                config={"workload": "single-wheel soil bin: 200x120x40 soil particles (dx 5 mm, seeded jitter) "
+                                    "+ 3-layer container + grousered wheel r 0.25 m, slip 0.3, load 100 N; "
+                                    "co-simulation exchange every step",
+                        "n_particles": cnt["n_total"], "n_processed": cnt["n_proc"], "ps_freq": args.ps_freq,
+                        "dt": dt, "lds_tile": TILE_NAMES[tile]})
+
+
+def run_wheel_trace(args, crm, scenes):
+    """The single-wheel bin run for args.trace_steps co-simulation steps from
+    rest (20,000 steps = 0.5 s): drawbar pull F_x, vertical force F_z and
+    driving torque T_y of the wheel, their means over the last quarter of the
+    run, and the wheel's sinkage. Stops at the first non-finite force (the
+    library reports it as CRM_E_NONFINITE)."""
+    sc = scenes.wheel_bin(seed=0, ps_freq=args.ps_freq)
+    drv = WheelDriver(sc)
+    sim = crm.Simulation(sc, device=0)
+    dt = sc.params["dt"]
+    n = args.trace_steps
+    F = np.full((n, 3), np.nan)
+    T = np.full((n, 3), np.nan)
+    z0 = float(drv.x[2])
+    t0 = time.perf_counter()
+    done, err = 0, None
+    try:
+        for k in range(n):
+            f, t = sim.cosim_step(*drv.state())
+            F[k], T[k] = f[1], t[1]
+            drv.advance(f[1], dt)
+            done = k + 1
+            if done % 5000 == 0:
+                print(json.dumps(dict(trace_step=done, Fx=F[k, 0], Fz=F[k, 2], Ty=T[k, 1],
+                                      wheel_z=float(drv.x[2]))), file=sys.stderr, flush=True)
+    except crm.CrmError as e:
+        err = str(e)
+    wall = time.perf_counter() - t0
+    sim.close()
+    q = slice(max(done - max(done // 4, 1), 0), done)
+    load = drv.mass * drv.g
+    every = max(n // 40, 1)
+    return dict(steps=n, steps_done=done, error=err, wall_s=round(wall, 2), ms_per_step=wall / max(done, 1) * 1e3,
+                t_end=done * dt, load_N=load,
+                last_quarter=dict(Fx_mean=float(np.mean(F[q, 0])), Fz_mean=float(np.mean(F[q, 2])),
+                                  Fz_std=float(np.std(F[q, 2])), Ty_mean=float(np.mean(T[q, 1])),
+                                  Fz_over_load=float(np.mean(F[q, 2]) / load)),
+                sinkage_m=z0 - float(drv.x[2]), finite=bool(np.isfinite(F[:done]).all() and np.isfinite(T[:done]).all()),
+                trace_every=every, trace=dict(Fx=F[::every, 0].round(4).tolist(), Fz=F[::every, 2].round(4).tolist(),
+                                              Ty=T[::every, 1].round(5).tolist()))
+
+
+def run_strip(args, crm, scenes, pos_mode, sc=None):
+    """Long strip with four wheels carrying active boxes, positions plain FP32
+    (pos_mode 0) or cell index + FP32 offset (pos_mode 1); the vehicle sits at
+    x = args.strip_x and moves with the wheels' speed."""
+    if sc is None:
+        sc = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x, ps_freq=args.ps_freq, t_delay=-1.0)
+    params = dict(sc.params, pos_mode=pos_mode)
+    dt = params["dt"]
+    t0 = time.perf_counter()
+    sim = crm.Simulation(sc, params=params, device=0)
+    t_init = time.perf_counter() - t0
+    sim.graph(True)
+    pos0 = np.array([b.pos for b in sc.bodies], dtype=np.float64)
+    quat = np.tile([1.0, 0.0, 0.0, 0.0], (len(sc.bodies), 1))
+    lin = np.array([b.linvel for b in sc.bodies])
+    ang = np.array([b.angvel for b in sc.bodies])
+    state = {"k": 0}
+
+    def one_step():
+        p = pos0.copy()
+        p[1:, 0] += lin[1:, 0] * dt * state["k"]
+        sim.cosim_step(p, quat, lin, ang)
+        state["k"] += 1
+
+    steps = args.strip_steps
+    wall = timed_steps(one_step, args.form_warmup, steps)
+    sim.profiling(True)
+    for _ in range(2 * args.ps_freq):
+        one_step()
+    prof = sim.profile()
+    sim.profiling(False)
+    cnt = sim.counts()
+    sim.close()
+    roof = activity_roofline(prof, cnt, pos_mode)
+    return dict(value=cnt["n_proc"] * steps / wall, ms_per_step=wall / steps * 1e3, steps=steps,
+                warmup=args.form_warmup, soil_rate=cnt["soil_rows"] * steps / wall, roofline=roof,
+                breakdown=per_launch(prof), init_s=round(t_init, 1),
+                config={"workload": f"strip {args.strip_length:g} m x 4 m x 0.3 m at dx 0.05 m (seeded jitter), "
+                                    f"3-layer floor, 4 wheels at 5 m/s at x = {args.strip_x:g} m with 2 m active "
+                                    f"boxes, {'cell index + FP32 offset' if pos_mode else 'plain FP32'} positions",
+                        "pos_mode": pos_mode, "n_particles": cnt["n_total"], "n_processed": cnt["n_proc"],
+                        "ps_freq": args.ps_freq, "dt": dt})
+
+
+def run_batch(args, crm, scenes):
+    """Batched bins: one context for all bins (the step kernels replayed as a
+    hipGraph) vs one context per bin, stepped one after the other on the same
+    stream."""
     sc = scenes.batch_bins(seed=0, ps_freq=args.ps_freq)
     dt = sc.params["dt"]
     nbins = len(sc.meta["bins"])
-
-    def timed(step_fn, n_warm, n_steps):
-        for _ in range(n_warm):
-            step_fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(n_steps):
-            step_fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
     drv = BinDrivers(sc)
     sim = crm.Simulation(sc, device=0)
     sim.set_materials(sc.meta["materials"], sc.meta["material"])
@@ -146,10 +344,17 @@ def run_batch(args):
 
     step_batched()
     tile = sim.autotune()
-    wall = timed(step_batched, args.warmup, args.steps)
-    n_proc = sim.counts()["n_proc"]
+    steps = args.batch_steps
+    wall = timed_steps(step_batched, args.form_warmup, steps)
+    sim.profiling(True, classes=["soil_stage2"])
+    for _ in range(2 * args.ps_freq):
+        step_batched()
+    prof = sim.profile()
+    sim.profiling(False)
+    cnt = sim.counts()
     sim.close()
-    value = n_proc * args.steps / wall
+    roof = stage2_roofline(prof, cnt, None)
+    value = cnt["n_proc"] * steps / wall
 
     # one context per bin
     drv2 = BinDrivers(sc)
@@ -168,60 +373,20 @@ def run_batch(args):
         fz = np.array([s1.cosim_step(*drv2.state([k]))[0][1, 2] for k, s1 in enumerate(sims)])
         drv2.advance(fz, dt)
 
-    n_sep = max(1, args.steps // 4)
-    wall2 = timed(step_separate, max(1, args.warmup // 4), n_sep)
+    n_sep = max(1, steps // 4)
+    wall2 = timed_steps(step_separate, max(1, args.form_warmup // 4), n_sep)
     for s1 in sims:
         s1.close()
-    value2 = n_proc * n_sep / wall2
-    return dict(value=value, wall=wall, n_proc=n_proc, separate=value2, n_bins=nbins,
+    value2 = cnt["n_proc"] * n_sep / wall2
+    return dict(value=value, ms_per_step=wall / steps * 1e3, steps=steps, warmup=args.form_warmup,
+                soil_rate=cnt["soil_rows"] * steps / wall, roofline=roof,
+                separate_contexts=dict(value=value2, ms_per_step=wall2 / n_sep * 1e3, steps=n_sep),
+                batched_over_separate=value / value2,
                 config={"workload": f"{nbins} independent single-wheel bins, sizes log-uniform 8k-250k soil "
                                     "particles (seed 0), per-bin friction 0.5-0.9, slip 0-0.6, load 50-200 N, "
                                     "one context, step kernels replayed as a hipGraph",
-                        "n_particles": int(sc.n_total), "n_processed": int(n_proc), "ps_freq": args.ps_freq,
-                        "dt": dt, "lds_tile": TILE_NAMES[tile],
-                        "separate_contexts_particle_steps_per_s": value2,
-                        "batched_over_separate": value / value2})
-
-
-def run_strip(args):
-    """Long strip with four wheels carrying active boxes, positions plain FP32
-    or cell index + FP32 offset; the vehicle sits at x = args.strip_x."""
-    import torch
-    from paper_2507_05643_amd import crm, scenes
-    sc = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x, ps_freq=args.ps_freq,
-                      t_delay=-1.0)
-    sc.params["pos_mode"] = args.pos_mode
-    dt = sc.params["dt"]
-    sim = crm.Simulation(sc, device=0)
-    sim.graph(True)
-    pos0 = np.array([b.pos for b in sc.bodies], dtype=np.float64)
-    quat = np.tile([1.0, 0.0, 0.0, 0.0], (len(sc.bodies), 1))
-    lin = np.array([b.linvel for b in sc.bodies])
-    ang = np.array([b.angvel for b in sc.bodies])
-    state = {"k": 0}
-
-    def one_step():
-        p = pos0.copy()
-        p[1:, 0] += lin[1:, 0] * dt * state["k"]
-        sim.cosim_step(p, quat, lin, ang)
-        state["k"] += 1
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cnt = sim.counts()
-    sim.close()
-    value = cnt["n_proc"] * args.steps / wall
-    return dict(value=value, wall=wall, n_proc=cnt["n_proc"],
-                config={"workload": f"strip {args.strip_length:g} m x 4 m x 0.3 m at dx 0.05 m, 4 wheels at "
-                                    f"x = {args.strip_x:g} m with 2 m active boxes, pos_mode {args.pos_mode}",
-                        "n_particles": cnt["n_total"], "n_processed": cnt["n_proc"], "ps_freq": args.ps_freq,
-                        "dt": dt})
+                        "n_bins": nbins, "n_particles": cnt["n_total"], "n_processed": cnt["n_proc"],
+                        "ps_freq": args.ps_freq, "dt": dt, "lds_tile": TILE_NAMES[tile]})
 
 
 def adjoint_cost(sim, one_step, k, ps_freq, n_soil, nb):
@@ -279,10 +444,18 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="oracle steps of the CPU baseline (about 10-20 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("wheel", "batch", "strip"), default="wheel")
-    ap.add_argument("--pos-mode", type=int, default=0)
+    ap.add_argument("--forms", default="strip0,strip1,batch",
+                    help="further forms measured after the wheel bin, comma-separated from strip0 (10 km "
+                         "strip, plain FP32 positions), strip1 (cell index + FP32 offset), batch (64 bins); "
+                         "'none' for the wheel bin alone")
+    ap.add_argument("--trace-steps", type=int, default=0,
+                    help="after the forms, run the wheel bin this many steps from rest and report the drawbar "
+                         "pull, vertical force and torque (20000: the 0.5 s single-wheel test)")
     ap.add_argument("--strip-length", type=float, default=10000.0)
     ap.add_argument("--strip-x", type=float, default=5000.0)
+    ap.add_argument("--strip-steps", type=int, default=400)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--form-warmup", type=int, default=20)
     ap.add_argument("--tile", choices=TILE_NAMES, default="small",
                     help="LDS tile configuration of the soil stages")
     ap.add_argument("--autotune", action="store_true",
@@ -304,67 +477,8 @@ def main():
     from paper_2507_05643_amd import crm, scenes
 
     torch.cuda.set_device(0)
-    if args.workload != "wheel":
-        res = run_batch(args) if args.workload == "batch" else run_strip(args)
-        out = {"metric": "particle-steps/s", "value": res["value"], "unit": "particle-steps/s", "n_gpus": 1,
-               "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["wall"] / args.steps * 1e3,
-               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-               "data": "synthetic", "config": res["config"], "roofline": None, "cpu_baseline": None}
-        print(json.dumps(out), flush=True)
-        return
-    sc = scenes.wheel_bin(seed=0, ps_freq=args.ps_freq)
-    drv = WheelDriver(sc)
-    sim = crm.Simulation(sc, device=0)
-    dt = sc.params["dt"]
-
-    def one_step():
-        F, _ = sim.cosim_step(*drv.state())
-        drv.advance(F[1], dt)
-
-    for _ in range(args.warmup):
-        one_step()
-    tile = sim.autotune() if args.autotune else sim.autotune(TILE_NAMES.index(args.tile))
-    torch.cuda.synchronize()
-    # events around the dominant kernel only, on the context's stream
-    sim.profiling(True, classes=["soil_stage2"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = sim.profile()
-    # per-class breakdown (every kernel class timed) over a short untimed run
-    sim.profiling(True)
-    for _ in range(min(args.steps, 10 * args.ps_freq)):
-        one_step()
-    prof_all = sim.profile()
-    sim.profiling(False)
-    cnt = sim.counts()
-    F, T = sim.forces()
-    n_proc = cnt["n_proc"]
-    value = n_proc * args.steps / wall
-
-    st2 = prof["soil_stage2"]
-    ms2 = st2["ms"] / max(st2["launches"], 1)
-    pairs = prof["soil_pairs"]
-    rows = cnt["soil_rows"]
-    flops = FLOPS_PER_PAIR * pairs
-    bytes_ = BYTES_PER_PARTICLE * rows + BYTES_PER_PAIR * pairs
-    tflops = flops / (ms2 * 1e-3) / 1e12
-    gbs = bytes_ / (ms2 * 1e-3) / 1e9
-    roofline = dict(bound="alu", achieved=round(tflops, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(tflops / PEAK_FP32_TFLOPS, 4),
-                    traffic=STAGE2_TRAFFIC_BYTES if (args.ps_freq == 10 and tile == crm.TILE_SMALL) else None,
-                    kernel="k_fluid_stage2", launch_ms=round(ms2, 5), algorithmic_flops=flops,
-                    hbm_view=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                                  frac=round(gbs / PEAK_HBM_GBS, 4), algorithmic_bytes=bytes_))
-    adjoint = adjoint_cost(sim, one_step, args.adjoint_steps, args.ps_freq, sc.n_soil, len(sc.bodies)) \
-        if args.adjoint_steps > 0 else None
-    breakdown = {k: round(v["ms"] / max(v["launches"], 1), 5) for k, v in prof_all.items() if isinstance(v, dict)}
-    print(json.dumps(dict(profile_ms_per_launch=breakdown, counts=cnt, wheel_force=F[1].tolist(),
-                          wheel_torque=T[1].tolist(), wheel_z=float(drv.x[2]))), file=sys.stderr, flush=True)
-    sim.close()
+    t_start = time.perf_counter()
+    w = run_wheel(args, crm, scenes)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -372,6 +486,32 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    forms = {}
+    wanted = [f for f in args.forms.split(",") if f and f != "none"]
+    strip_scene = None
+    for f in wanted:
+        t0 = time.perf_counter()
+        if f in ("strip0", "strip1"):
+            if strip_scene is None:
+                strip_scene = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x,
+                                           ps_freq=args.ps_freq, t_delay=-1.0)
+            r = run_strip(args, crm, scenes, int(f[-1]), strip_scene)
+            name = "strip_fp32" if f == "strip0" else "strip_cell_offset"
+        elif f == "batch":
+            strip_scene = None
+            r = run_batch(args, crm, scenes)
+            name = "batch_64_bins"
+        else:
+            raise SystemExit(f"unknown form {f}")
+        r["seconds"] = round(time.perf_counter() - t0, 1)
+        forms[name] = r
+        print(json.dumps(dict(form=name, **{k: v for k, v in r.items() if k != "breakdown"},
+                              breakdown=r.get("breakdown"))), file=sys.stderr, flush=True)
+    strip_scene = None
+    for r in forms.values():
+        r["over_wheel_bin"] = round(r["value"] / w["value"], 4)
+
+    trace = run_wheel_trace(args, crm, scenes) if args.trace_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -379,25 +519,25 @@ def main():
 
     out = {
         "metric": "particle-steps/s",
-        "value": value,
+        "value": w["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": w["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single-wheel soil bin: 200x120x40 soil particles (dx 5 mm, seeded jitter) "
-                               "+ 3-layer container + grousered wheel r 0.25 m, slip 0.3, load 100 N; "
-                               "co-simulation exchange every step",
-                   "n_particles": cnt["n_total"], "n_processed": n_proc, "ps_freq": args.ps_freq,
-                   "dt": dt, "lds_tile": TILE_NAMES[tile]},
-        "roofline": roofline,
+        "config": w["config"],
+        "roofline": w["roofline"],
         "cpu_baseline": cpu,
-        "adjoint": adjoint,
+        "soil_particle_steps_per_s": w["soil_rate"],
+        "adjoint": w["adjoint"],
+        "forms": forms,
+        "wheel_trace": trace,
+        "total_seconds": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(out), flush=True)
 

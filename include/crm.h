@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CRM_ABI_VERSION 2u
+#define CRM_ABI_VERSION 3u
 
 typedef enum {
   CRM_OK = 0,
@@ -250,6 +250,15 @@ crm_status crm_debug_export(crm_ctx* ctx, int32_t* sorted_ids, uint32_t* cell_st
  * (not at a list rebuild), CRM_E_NOMEM, CRM_E_DEVICE. */
 crm_status crm_record(crm_ctx* ctx, int32_t n_steps);
 
+/* Body forces and torques of every step of the last crm_record (those
+ * crm_get_forces would have returned after each step), in the layout of the
+ * adjoint's force seeds: force, torque: 3 nb doubles per recorded step, step
+ * by step (host, written). The forward values of the functional that
+ * crm_adjoint differentiates (Sec. 2.5.1 body forces). Synchronises.
+ * Errors: CRM_E_INVALID (NULL pointer with nb > 0), CRM_E_STATE (no valid
+ * record), CRM_E_NONFINITE, CRM_E_DEVICE. */
+crm_status crm_record_forces(crm_ctx* ctx, double* force, double* torque);
+
 /* Reverse mode, part 2: the vector-Jacobian product of the recorded run for
  * the linear functional
  *   L = sum_i (lam_pos_i . x_i + lam_vel_i . u_i + lam_sigma_i . s_i + lam_rho_i rho_i)
@@ -305,12 +314,14 @@ crm_status crm_autotune(crm_ctx* ctx, int32_t config, int32_t* chosen);
 #define CRM_PROF_CLASSES 0x100
 crm_status crm_set_profiling(crm_ctx* ctx, int32_t enable);
 
-/* Recorded timings, out: 16 doubles. For class k = 0..6, out[2k] = launches and
+/* Recorded timings, out: 18 doubles. For class k = 0..6, out[2k] = launches and
  * out[2k + 1] = total milliseconds: 0 rebuild (all kernels of a rebuild step),
  * 1 marker placement, 2 BCE extrapolation (stage 1), 3 soil RHS + stage-1
  * update, 4 BCE + body forces (stage 2), 5 soil RHS + stage-2 update + return
  * mapping, 6 body force reduction. out[14] = soil neighbour pairs and out[15] =
- * marker neighbour pairs of the last rebuild. Synchronises. */
+ * marker neighbour pairs of the last rebuild. Class 7, the activity flags of
+ * all particles (part of a rebuild step with active domains; Sec. 4.2 item 2):
+ * out[16] launches, out[17] milliseconds. Synchronises. */
 crm_status crm_get_profile(crm_ctx* ctx, double* out);
 
 /* Capacity policy of Sec. 4.2 item 3 (host logic, no device access): grow to

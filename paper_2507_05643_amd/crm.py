@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # CRM_LIB_PATH selects another build of the same library (e.g. for A/B timing).
 LIB_PATH = os.environ.get("CRM_LIB_PATH") or os.path.join(HERE, "libcrm.so")
 
-CRM_ABI_VERSION = 2
+CRM_ABI_VERSION = 3
 STATUS = {0: "CRM_OK", -1: "CRM_E_INVALID", -2: "CRM_E_NOMEM", -3: "CRM_E_DEVICE",
           -4: "CRM_E_STATE", -5: "CRM_E_NONFINITE", -6: "CRM_E_UNSUPPORTED"}
 
@@ -73,6 +73,8 @@ def _load():
     L.crm_set_materials.argtypes = [vp, C.c_int32, dp, dp, dp, C.POINTER(C.c_uint16)]
     L.crm_step.restype = C.c_int
     L.crm_step.argtypes = [vp, C.c_int32]
+    L.crm_record_forces.restype = C.c_int
+    L.crm_record_forces.argtypes = [vp, dp, dp]
     L.crm_get_forces.restype = C.c_int
     L.crm_get_forces.argtypes = [vp, C.c_int32, dp, dp]
     L.crm_cosim_step.restype = C.c_int
@@ -118,12 +120,12 @@ EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
             "crm_adjoint", "crm_autotune", "crm_cosim_step", "crm_checkpoint_bytes", "crm_save_checkpoint",
-            "crm_load_checkpoint")
+            "crm_load_checkpoint", "crm_record_forces")
 
 TILE_NONE, TILE_SMALL, TILE_LARGE = 0, 1, 2
 
 PROFILE_CLASSES = ("rebuild", "place_markers", "bce_stage1", "soil_stage1", "bce_forces_stage2",
-                   "soil_stage2", "body_reduce")
+                   "soil_stage2", "body_reduce", "activity")
 
 
 def lib():
@@ -319,6 +321,14 @@ def crm_record(ctx, n_steps):
     _check(ctx, _lib.crm_record(ctx, int(n_steps)))
 
 
+def crm_record_forces(ctx, n_steps, nb):
+    """Per-step body forces and torques of the last crm_record: two (n_steps, nb, 3) arrays."""
+    F = np.zeros((n_steps, max(nb, 1), 3))
+    T = np.zeros((n_steps, max(nb, 1), 3))
+    _check(ctx, _lib.crm_record_forces(ctx, _ptr(F, C.c_double), _ptr(T, C.c_double)))
+    return F[:, :nb], T[:, :nb]
+
+
 def crm_adjoint(ctx, n_soil, n_mat, lam_pos=None, lam_vel=None, lam_sigma=None, lam_rho=None, lam_force=None,
                 lam_torque=None):
     """Vector-Jacobian product of the recorded run; returns dict(pos, vel, sigma, rho, params)
@@ -372,9 +382,10 @@ def crm_set_profiling(ctx, enable, classes=None):
 
 
 def crm_get_profile(ctx):
-    out = np.zeros(16)
+    out = np.zeros(18)
     _check(ctx, _lib.crm_get_profile(ctx, _ptr(out, C.c_double)))
-    res = {k: dict(launches=int(out[2 * i]), ms=float(out[2 * i + 1])) for i, k in enumerate(PROFILE_CLASSES)}
+    at = [2 * i if i < 7 else 2 * i + 2 for i in range(len(PROFILE_CLASSES))]
+    res = {k: dict(launches=int(out[a]), ms=float(out[a + 1])) for k, a in zip(PROFILE_CLASSES, at)}
     res["soil_pairs"] = int(out[14])
     res["marker_pairs"] = int(out[15])
     return res
@@ -423,6 +434,11 @@ class Simulation:
 
     def record(self, n):
         crm_record(self.ctx, n)
+        self.rec_n = int(n)
+
+    def record_forces(self):
+        """Per-step body forces and torques of the last record: (n, nb, 3) each."""
+        return crm_record_forces(self.ctx, self.rec_n, self.nb)
 
     def adjoint(self, **seeds):
         return crm_adjoint(self.ctx, self.n_soil, getattr(self, "n_mat", 1), **seeds)
@@ -479,3 +495,69 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+# ---- reverse mode as a torch.autograd.Function --------------------------------
+
+class _Rollout(torch.autograd.Function):
+    """forward: crm_record of n steps from the scene with the given material
+    parameters and initial soil velocities; outputs the per-step body forces
+    and torques (crm_record_forces) and the soil state at the end. backward:
+    crm_adjoint with the outputs' gradients as seeds."""
+
+    @staticmethod
+    def forward(ctx, spec, E, nu, mu_s, mu_2, cohesion, vel0):
+        scene, n_steps, device = spec
+        p = dict(scene.params)
+        for k, v in (("E", E), ("nu", nu), ("mu_s", mu_s), ("mu_2", mu_2), ("cohesion", cohesion)):
+            p[k] = float(v)
+        sim = Simulation(scene, params=p, device=device)
+        try:
+            if vel0 is not None:
+                sim.set_state(vel=vel0.detach().to("cpu", torch.float32).numpy())
+            sim.record(n_steps)
+            F, T = sim.record_forces()
+            st = sim.state()
+        except Exception:
+            sim.close()
+            raise
+        ctx.sim = sim
+        ctx.n = scene.n_soil
+        ctx.vel_like = vel0
+        n = scene.n_soil
+        outs = (torch.from_numpy(F.copy()), torch.from_numpy(T.copy()),
+                torch.from_numpy(st["pos"][:n].copy()), torch.from_numpy(st["vel"][:n].copy()),
+                torch.from_numpy(st["sigma"][:n].copy()), torch.from_numpy(st["rho"][:n].copy()))
+        return outs
+
+    @staticmethod
+    def backward(ctx, gF, gT, gpos, gvel, gsig, grho):
+        def npy(g, dt):
+            return None if g is None else g.detach().to("cpu", dt).contiguous().numpy()
+        sim = ctx.sim
+        try:
+            g = sim.adjoint(lam_pos=npy(gpos, torch.float64), lam_vel=npy(gvel, torch.float32),
+                            lam_sigma=npy(gsig, torch.float32), lam_rho=npy(grho, torch.float32),
+                            lam_force=npy(gF, torch.float64), lam_torque=npy(gT, torch.float64))
+        finally:
+            sim.close()
+            ctx.sim = None
+        prm = [torch.tensor(float(v), dtype=torch.float64) for v in g["params"][:5]]
+        dvel = None
+        if ctx.vel_like is not None:
+            dvel = torch.from_numpy(g["vel"]).to(ctx.vel_like.device, ctx.vel_like.dtype)
+        return (None, *prm, dvel)
+
+
+def rollout(scene, n_steps, E, nu, mu_s, mu_2, cohesion, vel0=None, device=None):
+    """Differentiable run of n_steps steps of `scene` (reverse mode of Sec. 2.3-2.5):
+    returns (force, torque, pos, vel, sigma, rho) with force and torque the
+    bodies' per-step values, shape (n_steps, nb, 3), and the soil state at the
+    end. Gradients flow to the material parameters E, nu, mu_s, mu_2, cohesion
+    (scalars or 0-d tensors; their values replace the scene's) and to the
+    initial soil velocities vel0 ((n_soil, 3), None: the scene's). The run must
+    not use active domains; the record keeps the state at every list rebuild
+    (every ps_freq steps, the checkpoint interval of the reverse sweep)."""
+    def t(v):
+        return v if torch.is_tensor(v) else torch.tensor(float(v), dtype=torch.float64)
+    return _Rollout.apply((scene, int(n_steps), device), t(E), t(nu), t(mu_s), t(mu_2), t(cohesion), vel0)

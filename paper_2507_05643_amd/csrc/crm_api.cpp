@@ -158,6 +158,7 @@ struct crm_ctx {
   std::vector<Body> rec_bodies;    // the body table the record ran with
   float4* rec_snap = nullptr;      // master planes at each segment start (4 x n_total each)
   int64_t rec_snap_cap = 0;        // segments the snapshot buffer holds
+  double* rec_forces = nullptr;    // per recorded step: the bodies' force and torque (6 nb)
 
   std::vector<Buf> owned;
 };
@@ -508,6 +509,9 @@ crm_status update_body_plan(crm_ctx* c, const int32_t* ids) {
   return CRM_OK;
 }
 
+hipEvent_t prof_begin(crm_ctx* c, int k);
+void prof_end(crm_ctx* c, int k, hipEvent_t start);
+
 // The working set back into the master store: the soil rows of state A (all
 // four planes) and the extrapolated velocity and stress of the processed
 // markers from the last stage (B), so that the master holds every particle's
@@ -552,7 +556,9 @@ crm_status rebuild(crm_ctx* c) {
   c->ad_on = P.active_domains && t > P.t_delay;
   int64_t n_proc = c->n_total;
   if (c->ad_on) {
+    hipEvent_t ea = prof_begin(c, 7);
     HIPCHK(c, crm::activity_flags(c->m_a, c->m_d, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, s));
+    prof_end(c, 7, ea);
     HIPCHK(c, crm::compact_flags(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
     crm_status st = read_counts(c);
     if (st != CRM_OK) return st;
@@ -1208,14 +1214,23 @@ crm_status crm_record(crm_ctx* c, int32_t n_steps) {
   dfree(c, c->rec_snap);
   c->rec_snap = nullptr;
   c->rec_snap_cap = 0;
+  dfree(c, c->rec_forces);
+  c->rec_forces = nullptr;
   if (!alloc_n(c, c->rec_snap, segs * 4 * c->n_total)) return fail(c, CRM_E_NOMEM, "record snapshot allocation failed");
   c->rec_snap_cap = segs;
+  const int64_t nf = 6 * (int64_t)c->nb;
+  if (nf > 0 && !alloc_n(c, c->rec_forces, (int64_t)n_steps * nf))
+    return fail(c, CRM_E_NOMEM, "record force allocation failed");
   c->rec_bodies = c->h_bodies;
   c->rec_step0 = c->step;
   c->rec_seg.clear();
   c->recording = true;
   for (int32_t k = 0; k < n_steps; ++k) {
     st = one_step(c);
+    if (st == CRM_OK && nf > 0) {
+      const hipError_t e = crm::copy_f64(c->rec_forces + (size_t)k * (size_t)nf, c->d_fmap, nf, c->stream);
+      if (e != hipSuccess) st = fail(c, CRM_E_DEVICE, std::string("record forces: ") + hipGetErrorString(e));
+    }
     if (st != CRM_OK) {
       c->recording = false;
       return st;
@@ -1224,6 +1239,26 @@ crm_status crm_record(crm_ctx* c, int32_t n_steps) {
   c->recording = false;
   c->rec_n = n_steps;
   c->rec_valid = true;
+  return CRM_OK;
+}
+
+crm_status crm_record_forces(crm_ctx* c, double* force, double* torque) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (!c->rec_valid) return fail(c, CRM_E_STATE, "no recorded run (crm_record)");
+  const int64_t nb = c->nb, n = (int64_t)c->rec_n;
+  if (nb == 0) return CRM_OK;
+  if (!force || !torque) return fail(c, CRM_E_INVALID, "force and torque are required");
+  std::vector<double> h((size_t)(6 * nb * n));
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->rec_forces, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t k = 0; k < n * nb; ++k)
+    for (int a = 0; a < 3; ++a) {
+      force[3 * k + a] = h[(size_t)(6 * k + a)];
+      torque[3 * k + a] = h[(size_t)(6 * k + 3 + a)];
+    }
+  for (double v : h)
+    if (!std::isfinite(v)) return fail(c, CRM_E_NONFINITE, "non-finite body force or torque in the record");
   return CRM_OK;
 }
 
@@ -1779,8 +1814,8 @@ crm_status crm_set_profiling(crm_ctx* c, int32_t enable) {
   if (st != CRM_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   uint32_t mask;
-  if (enable == 0 || enable == 1) mask = enable ? 0x7fu : 0u;
-  else if ((enable & ~0x7f) == CRM_PROF_CLASSES) mask = (uint32_t)enable & 0x7fu;
+  if (enable == 0 || enable == 1) mask = enable ? 0xffu : 0u;
+  else if ((enable & ~0xff) == CRM_PROF_CLASSES) mask = (uint32_t)enable & 0xffu;
   else return fail(c, CRM_E_INVALID, "enable must be 0, 1 or CRM_PROF_CLASSES | class bits");
   if (mask) {
     c->prof_marks.clear();
@@ -1796,12 +1831,13 @@ crm_status crm_get_profile(crm_ctx* c, double* out) {
   if (st != CRM_OK) return st;
   if (!out) return fail(c, CRM_E_INVALID, "out is NULL");
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < 16; ++k) out[k] = 0.0;
+  for (int k = 0; k < 18; ++k) out[k] = 0.0;
   for (auto& m : c->prof_marks) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, m.second.first, m.second.second));
-    out[2 * m.first] += 1.0;
-    out[2 * m.first + 1] += (double)ms;
+    const int at = m.first < 7 ? 2 * m.first : 2 * m.first + 2;   // class 7 after the pair counts
+    out[at] += 1.0;
+    out[at + 1] += (double)ms;
   }
   auto pairs = [&](const uint32_t* cnt, int64_t n, double& dst) -> crm_status {
     std::vector<uint32_t> h((size_t)n);

@@ -117,6 +117,8 @@ hipError_t scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // dst[0] = *a, dst[1] = *b (device-side totals gathered for one read-back).
 hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStream_t s);
+// dst[0..n) = src[0..n) (src may be mapped host memory).
+hipError_t copy_f64(double* dst, const double* src, int64_t n, hipStream_t s);
 
 // World positions x = X + R l (FP64, stored FP32 or cell + offset) of the
 // markers with local indices [k0, k1) into the master planes.

@@ -203,6 +203,12 @@ __global__ void k_copy2(uint64_t* dst, const uint64_t* a, const uint64_t* b) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src,
+                                                     int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 __global__ void k_store_count(uint64_t* dst, const uint32_t* src) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (uint64_t)*src;
 }
@@ -1880,6 +1886,12 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 
 hipError_t copy2_u64(uint64_t* dst, const uint64_t* a, const uint64_t* b, hipStream_t s) {
   k_copy2<<<1, 64, 0, s>>>(dst, a, b);
+  return hipGetLastError();
+}
+
+hipError_t copy_f64(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_copy_f64<<<nblk(n), kBlock, 0, s>>>(dst, src, n);
   return hipGetLastError();
 }
 
