@@ -164,6 +164,29 @@ crm_status crm_set_materials(crm_ctx* ctx, int32_t n_mat, const double* mu_s, co
  * context where the allocation never failed, once memory is available. */
 crm_status crm_step(crm_ctx* ctx, int32_t n_steps);
 
+/* crm_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving or co-simulation loops, harnesses that forbid
+ * hipMalloc): the same steps with the same kernels and bit-identical results,
+ * but the call allocates nothing. The transient buffers of a step (compaction
+ * block counts, the scans' tile totals, the body-force chunk sums) come from
+ * one static device array of the library, 16 MiB per device, held on each
+ * device the library runs on until the process ends; everything else is the
+ * context's memory from earlier calls. So the context must already hold what
+ * the steps need: the first step of a context is taken by a call that may
+ * allocate (crm_step, crm_cosim_step, crm_record), and when a list rebuild
+ * needs a larger working set, neighbour list or force-sum plan the call
+ * returns CRM_E_NOMEM with the failing step left out exactly as for a failed
+ * allocation in crm_step (a later crm_step grows the buffers and continues
+ * bit for bit). A shrink of the working set that the capacity policy asks for
+ * waits for a call that may allocate. No graph is captured or replayed and no
+ * kernel timing is recorded during the call. Every call on one device shares
+ * that device's array and leaves its contents behind (nothing in it needs to
+ * start at zero); calls that overlap on one device, from two contexts on
+ * different streams or threads, race and must be serialised by the caller.
+ * Errors: as crm_step; CRM_E_INVALID if the context's sizes need more scratch
+ * than the array holds (the message states both sizes); CRM_E_NOMEM as above. */
+crm_status crm_step_noalloc(crm_ctx* ctx, int32_t n_steps);
+
 /* Force (N, world frame) and torque (N m, about the body origin) the soil
  * exerts on each body, from the stage-2 evaluation of the last step
  * (Sec. 2.5.1: sum of marker mass times marker acceleration). force, torque:

@@ -73,6 +73,8 @@ def _load():
     L.crm_set_materials.argtypes = [vp, C.c_int32, dp, dp, dp, C.POINTER(C.c_uint16)]
     L.crm_step.restype = C.c_int
     L.crm_step.argtypes = [vp, C.c_int32]
+    L.crm_step_noalloc.restype = C.c_int
+    L.crm_step_noalloc.argtypes = [vp, C.c_int32]
     L.crm_record_forces.restype = C.c_int
     L.crm_record_forces.argtypes = [vp, dp, dp]
     L.crm_get_forces.restype = C.c_int
@@ -120,7 +122,7 @@ EXPORTED = ("crm_init", "crm_set_bodies", "crm_set_materials", "crm_step", "crm_
             "crm_set_state", "crm_get_counts", "crm_debug_export", "crm_set_graph", "crm_set_profiling",
             "crm_get_profile", "crm_capacity_next", "crm_last_error", "crm_destroy", "crm_record",
             "crm_adjoint", "crm_autotune", "crm_cosim_step", "crm_checkpoint_bytes", "crm_save_checkpoint",
-            "crm_load_checkpoint", "crm_record_forces")
+            "crm_load_checkpoint", "crm_step_noalloc", "crm_record_forces")
 
 TILE_NONE, TILE_SMALL, TILE_LARGE = 0, 1, 2
 
@@ -238,6 +240,10 @@ def crm_set_materials(ctx, table, material):
 
 def crm_step(ctx, n_steps=1):
     _check(ctx, _lib.crm_step(ctx, int(n_steps)))
+
+
+def crm_step_noalloc(ctx, n_steps=1):
+    _check(ctx, _lib.crm_step_noalloc(ctx, int(n_steps)))
 
 
 def crm_get_forces(ctx, nb):

@@ -40,6 +40,7 @@ struct crm_ctx {
   void* user = nullptr;
   bool poisoned = false;
   bool noalloc = false;        // set during a call that must not allocate
+  void* scratch = nullptr;     // this device's static scratch array (crm_step_noalloc)
   std::string err = "no error";
 
   int64_t n_soil = 0, n_mark = 0, n_total = 0;
@@ -566,6 +567,9 @@ crm_status rebuild(crm_ctx* c) {
   }
   // capacity policy (Sec. 4.2 item 3)
   int64_t ncap = crm_capacity_next(c->cap, n_proc, c->step, P.grow_G, P.shrink_S, P.shrink_interval);
+  // a call that must not allocate keeps a larger working set (the results do
+  // not depend on the capacity); the shrink waits for a call that may allocate
+  if (c->noalloc && c->A.a && ncap < c->cap && n_proc <= c->cap) ncap = c->cap;
   if (ncap != c->cap || !c->A.a) {
     crm_status st = realloc_working(c, ncap);
     if (st != CRM_OK) return st;
@@ -827,6 +831,60 @@ crm_status usable(crm_ctx* c) {
   return CRM_OK;
 }
 
+// Sub-ranges of the static scratch array for the transient buffers of a step:
+// compaction block counts, the cell scan's and the list scans' tile totals and
+// the body-force chunk sums. Returns the bytes needed (0 on overflow).
+struct ScratchLayout {
+  uint32_t* ctmp = nullptr;
+  uint32_t* cell_tmp = nullptr;
+  uint64_t* wtmp = nullptr;
+  double* partial = nullptr;
+  size_t bytes = 0;
+};
+
+ScratchLayout scratch_layout(const crm_ctx* c) {
+  ScratchLayout L;
+  auto take = [&](size_t b) {
+    const size_t at = L.bytes;
+    L.bytes += (b + 255) & ~size_t(255);
+    return at;
+  };
+  const size_t o_ctmp = take(sizeof(uint32_t) * crm::compact_tmp_elems(c->n_total));
+  const size_t o_cell = take(sizeof(uint32_t) * crm::scan_tmp_elems(c->M));
+  const size_t o_wtmp = take(sizeof(uint64_t) * crm::scan_tmp_elems(c->cap));
+  const size_t o_part = take(sizeof(double) * 6 * (size_t)(c->plan_cap > 0 ? c->plan_cap : 1));
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  L.ctmp = reinterpret_cast<uint32_t*>(base + o_ctmp);
+  L.cell_tmp = reinterpret_cast<uint32_t*>(base + o_cell);
+  L.wtmp = reinterpret_cast<uint64_t*>(base + o_wtmp);
+  L.partial = reinterpret_cast<double*>(base + o_part);
+  return L;
+}
+
+// For the duration of a call that must not allocate: the context's transient
+// buffers point into the static scratch, and every allocation fails.
+struct NoAllocScope {
+  crm_ctx* c;
+  uint32_t *ctmp, *cell_tmp;
+  uint64_t* wtmp;
+  double* partial;
+  NoAllocScope(crm_ctx* ctx, const ScratchLayout& L)
+      : c(ctx), ctmp(ctx->ctmp), cell_tmp(ctx->cell_tmp), wtmp(ctx->wtmp), partial(ctx->body_plan.partial) {
+    c->ctmp = L.ctmp;
+    c->cell_tmp = L.cell_tmp;
+    c->wtmp = L.wtmp;
+    c->body_plan.partial = L.partial;
+    c->noalloc = true;
+  }
+  ~NoAllocScope() {
+    c->ctmp = ctmp;
+    c->cell_tmp = cell_tmp;
+    c->wtmp = wtmp;
+    c->body_plan.partial = partial;
+    c->noalloc = false;
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -905,6 +963,14 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     delete c;
     return fail(nullptr, CRM_E_DEVICE, "no HIP device");
   }
+  {
+    const hipError_t e = crm::scratch_address(c->device, &c->scratch);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, CRM_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    }
+  }
+  c->placed.assign((size_t)n_bodies, Body{});
 
   // physical constants (Sec. 2.1, 2.2)
   const crm_params& P = *params;
@@ -1199,6 +1265,39 @@ crm_status crm_step(crm_ctx* c, int32_t n_steps) {
     if (st != CRM_OK) return st;
   }
   return CRM_OK;
+}
+
+crm_status crm_step_noalloc(crm_ctx* c, int32_t n_steps) {
+  crm_status st = usable(c);
+  if (st != CRM_OK) return st;
+  if (n_steps < 0) return fail(c, CRM_E_INVALID, "n_steps must be >= 0");
+  if (!c->scratch) return fail(c, CRM_E_STATE, "no scratch address for this context's device");
+  if (!c->A.a) return fail(c, CRM_E_NOMEM, "the working set is not allocated yet (a call that may allocate is needed)");
+  const ScratchLayout L = scratch_layout(c);
+  if (L.bytes > crm::kScratchBytes)
+    return fail(c, CRM_E_INVALID, "the context needs " + std::to_string(L.bytes) + " bytes of scratch, more than the " +
+                                      std::to_string(crm::kScratchBytes) + " the library holds per device");
+  if (n_steps > 0) c->rec_valid = false;
+  const bool prof = c->prof;
+  c->prof = false;   // timing events are created on demand: not recorded here
+  {
+    NoAllocScope scope(c, L);
+    for (int32_t k = 0; k < n_steps; ++k) {
+      // direct launches: capturing or instantiating a graph allocates
+      if (rebuild_due(c)) {
+        st = rebuild(c);
+        if (st != CRM_OK) break;
+      }
+      st = launch_step(c, c->stream, false);
+      if (st != CRM_OK) break;
+      st = track_displacement(c);
+      if (st != CRM_OK) break;
+      c->step += 1;
+      c->stepped = true;
+    }
+  }
+  c->prof = prof;
+  return st;
 }
 
 crm_status crm_record(crm_ctx* c, int32_t n_steps) {

@@ -106,6 +106,13 @@ struct Phys {
   const float4* mat;  // per material: (mu_s, mu_2, cohesion, -cohesion / mu_s)
 };
 
+// ---- static scratch of the step that allocates nothing --------------------
+constexpr size_t kScratchBytes = size_t(16) << 20;  // per device, held until the process ends
+constexpr int kMaxDevices = 64;
+// Device address of the scratch array on `device`, which must be the current
+// device; looked up on the first call per device and kept.
+hipError_t scratch_address(int device, void** out);
+
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 
 // Exclusive scan of n values into out[0..n] (out[n] = total). tmp must hold

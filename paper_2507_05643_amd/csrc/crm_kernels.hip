@@ -4,6 +4,8 @@
 // Nothing here is a dense contraction, so no MFMA: the neighbour interaction
 // is FP32 VALU work over cell-sorted records, the binning/compaction steps are
 // HBM streams built from wave64 ballots and block scans.
+#include <mutex>
+
 #include "crm_device.h"
 
 namespace crm {
@@ -2159,6 +2161,30 @@ hipError_t scatter_marker_rows(CPlanes src, const int32_t* rows, int64_t n, cons
   if (n <= 0) return hipSuccess;
   k_scatter_markers<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_b, m_c, m_d);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ static scratch ---
+// Scratch of the step that allocates nothing: scan tile totals, compaction
+// block counts and the chunk sums of the body-force reduction, carved from one
+// file-scope array. Every device the library runs on holds its own copy until
+// the process ends; in host code the array's name is not a device address, so
+// each device's address is looked up once (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (!out || device < 0 || device >= kMaxDevices) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    addr[device] = ptr;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace crm
