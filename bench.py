@@ -448,7 +448,7 @@ def main():
                     help="further forms measured after the wheel bin, comma-separated from strip0 (10 km "
                          "strip, plain FP32 positions), strip1 (cell index + FP32 offset), batch (64 bins); "
                          "'none' for the wheel bin alone")
-    ap.add_argument("--trace-steps", type=int, default=0,
+    ap.add_argument("--trace-steps", type=int, default=20000,
                     help="after the forms, run the wheel bin this many steps from rest and report the drawbar "
                          "pull, vertical force and torque (20000: the 0.5 s single-wheel test)")
     ap.add_argument("--strip-length", type=float, default=10000.0)

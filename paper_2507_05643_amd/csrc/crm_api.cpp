@@ -463,7 +463,12 @@ crm_status read_counts(crm_ctx* c) {
 // World-axis box around the body's active box grown by ext on every local
 // axis, widened by a margin far above FP64 rounding: a superset of the grown
 // box used only to skip its exact test.
-void set_box_bounds(Body& B, double ext) {
+// The same box as FP32 bounds rounded outwards (a stored FP32 coordinate inside
+// alo..ahi lies inside flo..fhi) and as the cell indices a cell-offset
+// position inside it can carry (its offset stays within one cell of [0, S),
+// so c S lies within 2 S of x - lo).
+void set_box_bounds(Body& B, const Grid& g) {
+  const double ext = g.ext;
   double mag = 1.0;
   for (int a = 0; a < 3; ++a) mag += std::fabs(B.X[a]) + B.half[a] + ext;
   const double margin = 1e-9 * mag;
@@ -472,6 +477,15 @@ void set_box_bounds(Body& B, double ext) {
     for (int a = 0; a < 3; ++a) r += std::fabs(B.R[3 * k + a]) * (B.half[a] + ext);
     B.alo[k] = B.X[k] - r - margin;
     B.ahi[k] = B.X[k] + r + margin;
+    float lo = (float)B.alo[k], hi = (float)B.ahi[k];
+    if ((double)lo > B.alo[k]) lo = std::nextafter(lo, -INFINITY);
+    if ((double)hi < B.ahi[k]) hi = std::nextafter(hi, INFINITY);
+    B.flo[k] = lo;
+    B.fhi[k] = hi;
+    const double cl = std::floor((B.alo[k] - g.lo[k]) * g.inv) - 2.0;
+    const double ch = std::floor((B.ahi[k] - g.lo[k]) * g.inv) + 2.0;
+    B.clo[k] = (int32_t)std::max(cl, -2147483647.0);
+    B.chi[k] = (int32_t)std::min(ch, 2147483647.0);
   }
 }
 
@@ -558,9 +572,9 @@ crm_status rebuild(crm_ctx* c) {
   int64_t n_proc = c->n_total;
   if (c->ad_on) {
     hipEvent_t ea = prof_begin(c, 7);
-    HIPCHK(c, crm::activity_flags(c->m_a, c->m_d, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, s));
+    HIPCHK(c, crm::activity_count(c->m_a, c->m_d, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, c->ctmp, s));
     prof_end(c, 7, ea);
-    HIPCHK(c, crm::compact_flags(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
+    HIPCHK(c, crm::compact_counted(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
     crm_status st = read_counts(c);
     if (st != CRM_OK) return st;
     n_proc = (int64_t)c->h_counts[0];
@@ -1068,7 +1082,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     B.R[0] = B.R[4] = B.R[8] = 1.0;
     for (int a = 0; a < 3; ++a) B.half[a] = bodies[b].active_half[a];
     B.has_box = (B.half[0] > 0.0 || B.half[1] > 0.0 || B.half[2] > 0.0) ? 1 : 0;
-    set_box_bounds(B, g.ext);
+    set_box_bounds(B, g);
   }
 
   const int64_t nbk = crm::compact_tmp_elems(n_total);
@@ -1202,7 +1216,7 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
     }
     quat_to_R(q, B.R);
     B.has_acc = (linacc || angacc) ? 1 : 0;
-    set_box_bounds(B, c->grid.ext);
+    set_box_bounds(B, c->grid);
   }
   // the staging buffer is reused once its last upload has been read
   hipError_t e = c->bpin_pending ? hipEventSynchronize(c->bpin_ev) : hipSuccess;

@@ -49,6 +49,10 @@ struct Body {
   double half[3]; // active box half extents (all zero: none)
   double alo[3];  // world-axis box around the box grown by 2h (a superset,
   double ahi[3];  // for a quick rejection before the exact test)
+  float flo[3];   // alo, ahi rounded outwards to FP32: the same rejection
+  float fhi[3];   // without FP64, exact for FP32 stored coordinates
+  int32_t clo[3]; // cell indices a cell-offset position inside alo..ahi can
+  int32_t chi[3]; // carry (offsets stay within one cell of [0, S))
   int32_t has_acc;
   int32_t has_box;
 };
@@ -136,16 +140,18 @@ hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int
 hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const int64_t* bstart, int32_t nb,
                        int64_t kbase, int64_t* out, hipStream_t s);
 
-// Activity flags of all particles (Sec. 4.2 item 2).
-hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies,
-                          int32_t nb, Grid g, uint8_t* flags, hipStream_t s);
-
-// Order-preserving compaction of ids with flags != 0 (block counts, scan, write).
-// The flag array must hold flags_padded(n) bytes, zero beyond n.
+// Activity flags of all particles (Sec. 4.2 item 2) and the count of flagged
+// particles per tile of compact_counted (its first pass), into tmp.
+hipError_t activity_count(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
+                          uint8_t* flags, uint32_t* tmp, hipStream_t s);
+// Order-preserving compaction of the ids with flags != 0 from those counts
+// (scan, write; tiles without a flagged particle read no flag); count to
+// *count_dst (device). The flag array holds flags_padded(n) bytes, zero
+// beyond n; tmp holds compact_tmp_elems(n) words.
 int64_t flags_padded(int64_t n);
 size_t compact_tmp_elems(int64_t n);
-hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst,
-                         uint32_t* tmp, hipStream_t s);
+hipError_t compact_counted(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst, uint32_t* tmp,
+                           hipStream_t s);
 
 // Cell hash with per-cell arrival counts (counting sort, part 1).
 hipError_t hash_count(const int32_t* proc_ids, int64_t n_proc, const float4* m_a, const float4* m_d,

@@ -177,16 +177,9 @@ __device__ inline uint32_t flag_mask(const uint4* __restrict__ f16, int64_t chun
   return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_flags_count(const uint4* __restrict__ f16, int64_t nchunks,
-                                                        uint32_t* __restrict__ bcnt) {
-  const int64_t chunk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  uint32_t tot;
-  block_excl_scan((uint32_t)__popc(flag_mask(f16, chunk, nchunks)), tot);
-  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
-}
-
 __global__ __launch_bounds__(kBlock) void k_flags_write(const uint4* __restrict__ f16, int64_t nchunks,
                                                         const uint32_t* __restrict__ boff, int32_t* __restrict__ out) {
+  if (boff[blockIdx.x + 1] == boff[blockIdx.x]) return;   // no flagged particle in this tile
   const int64_t chunk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   uint32_t m = flag_mask(f16, chunk, nchunks);
   uint32_t tot;
@@ -278,29 +271,67 @@ __device__ inline uint8_t flag_of(const double xw[3], const Body* __restrict__ b
   return best;
 }
 
-// Four particles per thread (i, i + T, i + 2T, i + 3T for T threads in the
-// grid), their loads issued before any test: the pass streams all N particles.
+// Sec. 4.2 item 2 over all N particles, fused with the first pass of the
+// order-preserving compaction: block b covers the tile of kFlagsTile particles
+// from b kFlagsTile (the tile of k_flags_write), thread t takes the particles
+// b kFlagsTile + k kBlock + t, k = 0..15 (each load of a wave reads 64
+// consecutive records; four in flight per thread), and the block's count of
+// flagged particles goes to bcnt[b]. A pre-test without FP64 (the world box's
+// FP32 bounds rounded outwards for FP32 coordinates, its range of cell indices
+// for cell-offset positions) rejects almost every particle of a long terrain;
+// the others take the exact FP64 test of flag_of, so every flag is flag_of's.
 template <bool CELL>
-__global__ __launch_bounds__(kBlock) void k_activity(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
-                                                     int64_t n, const Body* __restrict__ bodies, int32_t nb, Grid g,
-                                                     uint8_t* __restrict__ flags) {
-  const int64_t T = (int64_t)gridDim.x * kBlock;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  float4 a[4], d[4];
+__global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restrict__ m_a,
+                                                           const float4* __restrict__ m_d, int64_t n,
+                                                           const Body* __restrict__ bodies, int32_t nb, Grid g,
+                                                           uint8_t* __restrict__ flags, uint32_t* __restrict__ bcnt) {
+  const int64_t base = (int64_t)blockIdx.x * kFlagsTile + threadIdx.x;
+  uint32_t cnt = 0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < kFlagsPer; k0 += 4) {
+    float4 p[4];   // a (FP32 coordinates) or d (cells in d.zw)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i = i0 + q * T;
-    a[q] = i < n ? m_a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    d[q] = (CELL && i < n) ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + (int64_t)(k0 + q) * kBlock;
+      p[q] = i < n ? (CELL ? m_d[i] : m_a[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i = i0 + q * T;
-    if (i >= n) break;
-    double xw[3];
-    abs_pos(a[q], d[q], g, xw);
-    flags[i] = flag_of(xw, bodies, nb, g.ext);
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + (int64_t)(k0 + q) * kBlock;
+      if (i < n) {
+        int32_t c[3] = {0, 0, 0};
+        if (CELL) {
+          const uint32_t w = __float_as_uint(p[q].w);
+          c[0] = (int32_t)__float_as_uint(p[q].z);
+          c[1] = unpack_y(w);
+          c[2] = unpack_z(w);
+        }
+        bool cand = false;
+        for (int b = 0; b < nb; ++b) {
+          const Body& B = bodies[b];
+          if (!B.has_box) continue;
+          if (CELL)
+            cand |= c[0] >= B.clo[0] && c[0] <= B.chi[0] && c[1] >= B.clo[1] && c[1] <= B.chi[1] &&
+                    c[2] >= B.clo[2] && c[2] <= B.chi[2];
+          else
+            cand |= p[q].x >= B.flo[0] && p[q].x <= B.fhi[0] && p[q].y >= B.flo[1] && p[q].y <= B.fhi[1] &&
+                    p[q].z >= B.flo[2] && p[q].z <= B.fhi[2];
+        }
+        uint8_t f = 0;
+        if (cand) {
+          const float4 a = CELL ? m_a[i] : p[q];
+          double xw[3];
+          abs_pos(a, p[q], g, xw);
+          f = flag_of(xw, bodies, nb, g.ext);
+        }
+        flags[i] = f;
+        cnt += f != 0 ? 1u : 0u;
+      }
+    }
   }
+  uint32_t tot;
+  block_excl_scan(cnt, tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
 }
 
 // Largest squared displacement of a processed particle since the last list
@@ -1918,33 +1949,32 @@ hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const
   return hipGetLastError();
 }
 
-hipError_t activity_flags(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
-                          uint8_t* flags, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const unsigned grid = nblk((n + 3) / 4);
-  if (g.cell) k_activity<true><<<grid, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
-  else k_activity<false><<<grid, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags);
-  return hipGetLastError();
-}
-
 size_t compact_tmp_elems(int64_t n) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
   return (size_t)(2 * nb + 1) + scan_tmp_elems(nb);
 }
 
-hipError_t compact_flags(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst,
-                         uint32_t* tmp, hipStream_t s) {
+hipError_t activity_count(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
+                          uint8_t* flags, uint32_t* tmp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nt = (n + kFlagsTile - 1) / kFlagsTile;
+  if (g.cell) k_activity_count<true><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags, tmp);
+  else k_activity_count<false><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags, tmp);
+  return hipGetLastError();
+}
+
+hipError_t compact_counted(const uint8_t* flags, int64_t n, int32_t* out_ids, uint64_t* count_dst, uint32_t* tmp,
+                           hipStream_t s) {
   if (n <= 0) {
     k_set_one<uint64_t><<<1, 64, 0, s>>>(count_dst, 0ull);
     return hipGetLastError();
   }
   const int64_t nchunks = (n + kFlagsPer - 1) / kFlagsPer;
   const int64_t nb = (n + kFlagsTile - 1) / kFlagsTile;
-  uint32_t* bcnt = tmp;
+  const uint32_t* bcnt = tmp;
   uint32_t* boff = tmp + nb;
   uint32_t* stmp = boff + nb + 1;
   const uint4* f16 = reinterpret_cast<const uint4*>(flags);
-  k_flags_count<<<(unsigned)nb, kBlock, 0, s>>>(f16, nchunks, bcnt);
   hipError_t e = scan_impl<uint32_t, uint32_t>(bcnt, boff, nb, stmp, s);
   if (e != hipSuccess) return e;
   k_flags_write<<<(unsigned)nb, kBlock, 0, s>>>(f16, nchunks, boff, out_ids);
