@@ -963,34 +963,41 @@ struct Rates {
 // The group's lanes take the row's neighbours k = lane, lane + kGroup, ...;
 // walk(pair) calls pair(record) for each of the lane's neighbours, with the
 // neighbour's volume V_j = m / rho_j in place of its density (a.w). One
-// reciprocal square root gives q and 1 / q; with rho_j = m / V_j the
-// viscosity's mean density enters as 1 / rho_bar = 2 V_j / (rho_i V_j + m).
-// The own stress's share of F3 is s_i . sum_j V_j gradW, taken once per row.
+// reciprocal square root gives q and 1 / q. The own stress's share of F3 is
+// s_i . sum_j V_j gradW, taken once per row. The viscosity term of a pair is
+// a multiple of r_ij, like V_j gradW = w, so it enters the stress sum as an
+// isotropic part: rho_i Pi_ij added to the diagonal of s_j, with
+// Pi_ij = 2 av (v_ij . r_ij) / ((rho_i V_j + m)(r_ij^2 + xi^2)) (the mean
+// density of the pair is (rho_i V_j + m) / (2 V_j)). Every product-sum is an
+// explicit FMA and nothing else is contracted, so each way of walking the
+// neighbours (tile or L1) gives the same bits by construction.
 template <bool CELL, class Walk>
 __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Walk&& walk, const Phys& P) {
+#pragma clang fp contract(off)
   const Own me = own_pos<CELL>(ma, md);
   const float rhoi = ma.w;
   const float ux = mb.x, uy = mb.y, uz = mb.z;
   const float s0 = mc.x, s1 = mc.y, s2 = mc.z, s3 = mc.w, s4 = md.x, s5 = md.y;
   float L00 = 0.f, L01 = 0.f, L02 = 0.f, L10 = 0.f, L11 = 0.f, L12 = 0.f, L20 = 0.f, L21 = 0.f, L22 = 0.f;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum_j V_j grad_i W_ij (sigma_i's share of F3, applied once per row)
-  const float av2 = 2.0f * P.av_coef;
+  const float avr = (2.0f * P.av_coef) * rhoi;
   // kernel gradient factor F(q) with its constants folded: cubic inner piece
   // kf (2.25 q - 3), outer piece -0.75 kf (2 - q)^2 / q = -0.75 kf h t^2 / r
   const float ci1 = 2.25f * P.kf, ci0 = -3.0f * P.kf, co = -0.75f * P.kf * P.h;
   auto pair = [&](const Nbr& o) {
+#pragma clang fp contract(off)
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
-    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     const float rs = __builtin_amdgcn_rsqf(fmaxf(r2, 1.0e-30f));   // 1 / r (finite for the self pair)
-    const float q = r2 * rs * P.inv_h;
+    const float q = (r2 * rs) * P.inv_h;
     float F;
     if (P.kern == 1) {
       F = wendland_f(q, P.kf);
     } else {
       const float t = fmaxf(2.0f - q, 0.0f);
-      const float outer = t * t * rs * co;
+      const float outer = ((t * t) * rs) * co;
       const float inner = fmaf(q, ci1, ci0);
       F = q < 1.0f ? inner : outer;
     }
@@ -998,53 +1005,51 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
     const float VF = V * F;                                       // V_j * (gradW / r_ij)
     const float wx = VF * dx, wy = VF * dy, wz = VF * dz;       // V_j grad_i W_ij
     const float dux = o.b.x - ux, duy = o.b.y - uy, duz = o.b.z - uz;
-    L00 += dux * wx; L01 += dux * wy; L02 += dux * wz;
-    L10 += duy * wx; L11 += duy * wy; L12 += duy * wz;
-    L20 += duz * wx; L21 += duz * wy; L22 += duz * wz;
+    L00 = fmaf(dux, wx, L00); L01 = fmaf(dux, wy, L01); L02 = fmaf(dux, wz, L02);
+    L10 = fmaf(duy, wx, L10); L11 = fmaf(duy, wy, L11); L12 = fmaf(duy, wz, L12);
+    L20 = fmaf(duz, wx, L20); L21 = fmaf(duz, wy, L21); L22 = fmaf(duz, wz, L22);
     g0 += wx; g1 += wy; g2 += wz;
-    a0 = fmaf(o.c.x, wx, a0); a0 = fmaf(o.c.w, wy, a0); a0 = fmaf(o.d.x, wz, a0);
-    a1 = fmaf(o.c.w, wx, a1); a1 = fmaf(o.c.y, wy, a1); a1 = fmaf(o.d.y, wz, a1);
-    a2 = fmaf(o.d.x, wx, a2); a2 = fmaf(o.d.y, wy, a2); a2 = fmaf(o.c.z, wz, a2);
-    const float vr = -(dux * dx + duy * dy + duz * dz);         // v_ij . r_ij
+    const float vr = -fmaf(duz, dz, fmaf(duy, dy, dux * dx));   // v_ij . r_ij
     const bool av = P.av_mode == 1 || (P.av_mode == 2 && vr < 0.f);
-    const float cf = av ? av2 * vr * VF * __builtin_amdgcn_rcpf((rhoi * V + P.m) * (r2 + P.xi2)) : 0.f;
-    v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
+    const float pi = av ? (vr * avr) * __builtin_amdgcn_rcpf(fmaf(rhoi, V, P.m) * (r2 + P.xi2)) : 0.f;
+    a0 = fmaf(o.c.x + pi, wx, a0); a0 = fmaf(o.c.w, wy, a0); a0 = fmaf(o.d.x, wz, a0);
+    a1 = fmaf(o.c.w, wx, a1); a1 = fmaf(o.c.y + pi, wy, a1); a1 = fmaf(o.d.y, wz, a1);
+    a2 = fmaf(o.d.x, wx, a2); a2 = fmaf(o.d.y, wy, a2); a2 = fmaf(o.c.z + pi, wz, a2);
   };
   walk(pair);
   L00 = group_sum(L00); L01 = group_sum(L01); L02 = group_sum(L02);
   L10 = group_sum(L10); L11 = group_sum(L11); L12 = group_sum(L12);
   L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
   a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
-  v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
   g0 = group_sum(g0); g1 = group_sum(g1); g2 = group_sum(g2);
-  a0 += s0 * g0 + s3 * g1 + s4 * g2;
-  a1 += s3 * g0 + s1 * g1 + s5 * g2;
-  a2 += s4 * g0 + s5 * g1 + s2 * g2;
+  a0 = fmaf(s4, g2, fmaf(s3, g1, fmaf(s0, g0, a0)));
+  a1 = fmaf(s5, g2, fmaf(s1, g1, fmaf(s3, g0, a1)));
+  a2 = fmaf(s2, g2, fmaf(s5, g1, fmaf(s4, g0, a2)));
   Rates R;
   const float ir = 1.0f / rhoi;
   R.dx = ux; R.dy = uy; R.dz = uz;
-  R.ax = a0 * ir + v0 + P.gx;
-  R.ay = a1 * ir + v1 + P.gy;
-  R.az = a2 * ir + v2 + P.gz;
-  const float trD = L00 + L11 + L22;
+  R.ax = fmaf(a0, ir, P.gx);
+  R.ay = fmaf(a1, ir, P.gy);
+  R.az = fmaf(a2, ir, P.gz);
+  const float trD = (L00 + L11) + L22;
   R.drho = -rhoi * trD;
   // spin components Om_xy, Om_xz, Om_yz and strain rate D
   const float wxy = 0.5f * (L01 - L10), wxz = 0.5f * (L02 - L20), wyz = 0.5f * (L12 - L21);
   const float Dxy = 0.5f * (L01 + L10), Dxz = 0.5f * (L02 + L20), Dyz = 0.5f * (L12 + L21);
   // M = Om s; Om s - s Om = M + M^T
-  const float Mxx = wxy * s3 + wxz * s4;
-  const float Myy = -wxy * s3 + wyz * s5;
-  const float Mzz = -wxz * s4 - wyz * s5;
-  const float Mxy = wxy * s1 + wxz * s5, Myx = -wxy * s0 + wyz * s4;
-  const float Mxz = wxy * s5 + wxz * s2, Mzx = -wxz * s0 - wyz * s3;
-  const float Myz = -wxy * s4 + wyz * s2, Mzy = -wxz * s3 - wyz * s1;
+  const float Mxx = fmaf(wxz, s4, wxy * s3);
+  const float Myy = fmaf(wyz, s5, -wxy * s3);
+  const float Mzz = fmaf(-wyz, s5, -wxz * s4);
+  const float Mxy = fmaf(wxz, s5, wxy * s1), Myx = fmaf(wyz, s4, -wxy * s0);
+  const float Mxz = fmaf(wxz, s2, wxy * s5), Mzx = fmaf(-wyz, s3, -wxz * s0);
+  const float Myz = fmaf(wyz, s2, -wxy * s4), Mzy = fmaf(-wyz, s1, -wxz * s3);
   const float iso = P.iso * trD;
-  R.s0 = 2.f * Mxx + P.two_G * L00 + iso;
-  R.s1 = 2.f * Myy + P.two_G * L11 + iso;
-  R.s2 = 2.f * Mzz + P.two_G * L22 + iso;
-  R.s3 = Mxy + Myx + P.two_G * Dxy;
-  R.s4 = Mxz + Mzx + P.two_G * Dxz;
-  R.s5 = Myz + Mzy + P.two_G * Dyz;
+  R.s0 = fmaf(2.f, Mxx, fmaf(P.two_G, L00, iso));
+  R.s1 = fmaf(2.f, Myy, fmaf(P.two_G, L11, iso));
+  R.s2 = fmaf(2.f, Mzz, fmaf(P.two_G, L22, iso));
+  R.s3 = fmaf(P.two_G, Dxy, Mxy + Myx);
+  R.s4 = fmaf(P.two_G, Dxz, Mxz + Mzx);
+  R.s5 = fmaf(P.two_G, Dyz, Myz + Mzy);
   R.L[0] = L00; R.L[1] = L01; R.L[2] = L02;
   R.L[3] = L10; R.L[4] = L11; R.L[5] = L12;
   R.L[6] = L20; R.L[7] = L21; R.L[8] = L22;
