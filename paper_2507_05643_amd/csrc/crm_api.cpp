@@ -48,6 +48,8 @@ struct crm_ctx {
   Grid grid{};
   Phys phys{};
   int64_t M = 0;
+  Grid wgrid{};                // the grid of the last rebuild: the domain's, or a window of it
+  int64_t Mw = 0;              // its cells
   bool ad_on = false;  // last rebuild used the activity flags
 
   // master store (by particle id), four planes of float4
@@ -527,6 +529,42 @@ crm_status update_body_plan(crm_ctx* c, const int32_t* ids) {
 hipEvent_t prof_begin(crm_ctx* c, int k);
 void prof_end(crm_ctx* c, int k, hipEvent_t start);
 
+// The cell grid a rebuild sorts into. With active domains every processed
+// particle lies inside the union of the bodies' world boxes (alo..ahi, a
+// superset of the boxes grown by the list radius), so the rebuild sorts into
+// the window of the domain's grid that covers that union with two cells to
+// spare on each side (a stored cell of a cell-offset position is within one
+// cell of its position's): the same cells and order, over a few thousand
+// cells instead of the whole domain's.
+Grid rebuild_grid(const crm_ctx* c, int64_t& cells) {
+  Grid w = c->grid;
+  cells = c->M;
+  if (!c->ad_on) return w;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool any = false;
+  for (int b = 0; b < c->nb; ++b) {
+    const Body& B = c->h_bodies[b];
+    if (!B.has_box) continue;
+    any = true;
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], B.alo[k]);
+      hi[k] = std::max(hi[k], B.ahi[k]);
+    }
+  }
+  if (!any) return w;
+  int64_t m = 1;
+  for (int k = 0; k < 3; ++k) {
+    const double a = std::floor((lo[k] - w.lo[k]) * w.inv) - 2.0, b = std::floor((hi[k] - w.lo[k]) * w.inv) + 2.0;
+    const int32_t c0 = (int32_t)std::max(0.0, std::min(a, (double)(w.gdim[k] - 1)));
+    const int32_t c1 = (int32_t)std::max((double)c0, std::min(b, (double)(w.gdim[k] - 1)));
+    w.org[k] = c0;
+    w.dims[k] = c1 - c0 + 1;
+    m *= (int64_t)w.dims[k];
+  }
+  cells = m;
+  return w;
+}
+
 // The working set back into the master store: the soil rows of state A (all
 // four planes) and the extrapolated velocity and stress of the processed
 // markers from the last stage (B), so that the master holds every particle's
@@ -591,9 +629,15 @@ crm_status rebuild(crm_ctx* c) {
   c->n_proc = n_proc;
   const int32_t* ids = c->ad_on ? c->proc_ids : nullptr;
   const uint8_t* flg = c->ad_on ? c->flags : nullptr;
-  HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, c->M, s));
-  HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->m_d, c->grid, c->key, c->rank, c->cell_cnt, s));
-  HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, c->M, c->cell_tmp, s));
+  int64_t Mw = c->M;
+  const Grid g = rebuild_grid(c, Mw);
+  c->wgrid = g;
+  c->Mw = Mw;
+  Phys pw = c->phys;
+  for (int k = 0; k < 3; ++k) pw.gdim[k] = g.dims[k];
+  HIPCHK(c, crm::fill_u32(c->cell_cnt, 0u, Mw, s));
+  HIPCHK(c, crm::hash_count(ids, n_proc, c->m_a, c->m_d, g, c->key, c->rank, c->cell_cnt, s));
+  HIPCHK(c, crm::scan_u32_to_u32(c->cell_cnt, c->cell_start, Mw, c->cell_tmp, s));
   HIPCHK(c, crm::place_sorted(c->key, c->rank, c->cell_start, n_proc, ids, c->m_a, c->m_d, c->tmp, c->tmpx,
                               c->grid.cell != 0, s));
   HIPCHK(c, crm::gather_sorted(c->tmp, c->tmpx, c->key, ids, c->cell_start, n_proc, c->n_soil, flg, c->m_a, c->m_b, c->m_c,
@@ -601,11 +645,11 @@ crm_status rebuild(crm_ctx* c) {
                                c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
-  HIPCHK(c, crm::tile_tables(c->frows, n_proc, c->d_counts + 1, c->skey, c->cell_start, c->phys, c->tabs, s));
-  HIPCHK(c, crm::nbr_count_soil(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
+  HIPCHK(c, crm::tile_tables(c->frows, n_proc, c->d_counts + 1, c->skey, c->cell_start, pw, c->tabs, s));
+  HIPCHK(c, crm::nbr_count_soil(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, g,
                                 c->tabs, c->cnt_f, c->stash_f, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->cnt_f, c->off_f, n_proc, c->wtmp, s));
-  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, c->grid,
+  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, g,
                            true, c->cnt_m, c->stash_m, s));
   HIPCHK(c, crm::scan_u32_to_u64(c->cnt_m, c->off_m, n_proc, c->wtmp, s));
   HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->off_f + n_proc, c->off_m + n_proc, s));
@@ -628,9 +672,9 @@ crm_status rebuild(crm_ctx* c) {
   if (st != CRM_OK) return st;
   c->ent_f = ef;
   c->ent_m = em;
-  HIPCHK(c, crm::nbr_fill_soil(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, c->cnt_f,
+  HIPCHK(c, crm::nbr_fill_soil(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, g, c->cnt_f,
                                c->stash_f, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
-  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, c->grid, true,
+  HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, g, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
   // per-body ranges of the processed markers for the force sums
   c->kbase = c->n_proc - c->n_mrows;
@@ -954,6 +998,8 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     double d = std::floor((params->domain_hi[a] - params->domain_lo[a]) * g.inv) + 1.0;
     if (!(d >= 1.0 && d < 2.0e9)) return fail(nullptr, CRM_E_UNSUPPORTED, "cell grid too large");
     g.dims[a] = (int32_t)d;
+    g.gdim[a] = g.dims[a];
+    g.org[a] = 0;
     M *= (int64_t)d;
   }
   if (M > (int64_t)0xfffffffe) return fail(nullptr, CRM_E_UNSUPPORTED, "more than 2^32 - 2 cells");
@@ -1817,8 +1863,15 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
   const int64_t np = c->n_proc;
   std::vector<int32_t> sid((size_t)np);
   HIPCHK(c, hipMemcpyAsync(sid.data(), c->slot_id, sizeof(int32_t) * (size_t)np, hipMemcpyDeviceToHost, s));
-  if (cell_start)
-    HIPCHK(c, hipMemcpyAsync(cell_start, c->cell_start, sizeof(uint32_t) * (size_t)(c->M + 1), hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> wcs;
+  if (cell_start) {
+    if (c->Mw == c->M) {
+      HIPCHK(c, hipMemcpyAsync(cell_start, c->cell_start, sizeof(uint32_t) * (size_t)(c->M + 1), hipMemcpyDeviceToHost, s));
+    } else {   // a window of the domain's grid: spread its cellStart over the domain's cells below
+      wcs.resize((size_t)(c->Mw + 1));
+      HIPCHK(c, hipMemcpyAsync(wcs.data(), c->cell_start, sizeof(uint32_t) * wcs.size(), hipMemcpyDeviceToHost, s));
+    }
+  }
   if (flags) {
     if (c->ad_on)
       HIPCHK(c, hipMemcpyAsync(flags, c->flags, (size_t)c->n_total, hipMemcpyDeviceToHost, s));
@@ -1845,6 +1898,28 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
   }
   HIPCHK(c, hipStreamSynchronize(s));
   if (sorted_ids) std::memcpy(sorted_ids, sid.data(), sizeof(int32_t) * (size_t)np);
+  if (!wcs.empty()) {
+    // cellStart of a domain cell = particles in window cells before it, in the
+    // common (z, y, x) order
+    const Grid& w = c->wgrid;
+    const int64_t X = c->grid.gdim[0], Y = c->grid.gdim[1], Z = c->grid.gdim[2];
+    uint32_t running = 0;
+    int64_t g = 0;
+    for (int64_t z = 0; z < Z; ++z)
+      for (int64_t y = 0; y < Y; ++y) {
+        const bool in_zy = z >= w.org[2] && z < w.org[2] + w.dims[2] && y >= w.org[1] && y < w.org[1] + w.dims[1];
+        for (int64_t x = 0; x < X; ++x, ++g) {
+          if (in_zy && x >= w.org[0] && x < w.org[0] + w.dims[0]) {
+            const int64_t wk = ((z - w.org[2]) * w.dims[1] + (y - w.org[1])) * w.dims[0] + (x - w.org[0]);
+            cell_start[g] = wcs[(size_t)wk];
+            running = wcs[(size_t)wk + 1];
+          } else {
+            cell_start[g] = running;
+          }
+        }
+      }
+    cell_start[c->M] = (uint32_t)np;
+  }
   if (want_lists) {
     const int64_t tot = (int64_t)(of.back() + om.back());
     if (nbr && tot > cap) return fail(c, CRM_E_INVALID, "cap too small for the neighbour entries");

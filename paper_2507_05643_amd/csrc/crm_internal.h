@@ -64,7 +64,9 @@ struct Grid {
   double R2;      // (2h)^2
   double ext;     // 2h, grow of the active boxes
   double S;       // cell size 2h
-  int32_t dims[3];
+  int32_t dims[3];  // cells per axis of the grid the rebuild sorts into (a window of the domain's grid)
+  int32_t org[3];   // the window's first cell in the domain's grid
+  int32_t gdim[3];  // cells per axis of the domain's grid
   int32_t cell;   // positions stored as cell index + FP32 offset
   // FP32 pre-test of the list radius: an FP32 squared distance below R2lo
   // (above R2hi) is one whose FP64 value is below (above) R2; R2 (1 -+ 2^-14),

@@ -388,6 +388,11 @@ __global__ void k_body_ranges(const int32_t* __restrict__ ids, int64_t n_proc, i
 // rank of each particle in its cell comes from an atomic counter (counting sort).
 __device__ inline int32_t clamp_cell(int32_t c, int32_t dim) { return c < 0 ? 0 : (c > dim - 1 ? dim - 1 : c); }
 
+// A cell of the domain's grid in the rebuild's window (clamped to it; every
+// processed particle's cell lies inside, at least one cell from its edges
+// unless the edge is the domain's).
+__device__ inline int32_t win_cell(int32_t c, const Grid& g, int k) { return clamp_cell(c - g.org[k], g.dims[k]); }
+
 __global__ __launch_bounds__(kBlock) void k_hash_count(const int32_t* __restrict__ ids, int64_t n,
                                                        const float4* __restrict__ m_a,
                                                        const float4* __restrict__ m_d, Grid g,
@@ -400,14 +405,14 @@ __global__ __launch_bounds__(kBlock) void k_hash_count(const int32_t* __restrict
   if (g.cell) {   // the stored cell, clamped to the grid
     const float4 d = m_d[id];
     const uint32_t w = __float_as_uint(d.w);
-    cx = clamp_cell((int32_t)__float_as_uint(d.z), g.dims[0]);
-    cy = clamp_cell(unpack_y(w), g.dims[1]);
-    cz = clamp_cell(unpack_z(w), g.dims[2]);
+    cx = win_cell(clamp_cell((int32_t)__float_as_uint(d.z), g.gdim[0]), g, 0);
+    cy = win_cell(clamp_cell(unpack_y(w), g.gdim[1]), g, 1);
+    cz = win_cell(clamp_cell(unpack_z(w), g.gdim[2]), g, 2);
   } else {
     const float4 p = m_a[id];
-    cx = cell_coord((double)p.x, g.lo[0], g.inv, g.dims[0]);
-    cy = cell_coord((double)p.y, g.lo[1], g.inv, g.dims[1]);
-    cz = cell_coord((double)p.z, g.lo[2], g.inv, g.dims[2]);
+    cx = win_cell(cell_coord((double)p.x, g.lo[0], g.inv, g.gdim[0]), g, 0);
+    cy = win_cell(cell_coord((double)p.y, g.lo[1], g.inv, g.gdim[1]), g, 1);
+    cz = win_cell(cell_coord((double)p.z, g.lo[2], g.inv, g.gdim[2]), g, 2);
   }
   uint32_t c = ((uint32_t)cz * (uint32_t)g.dims[1] + (uint32_t)cy) * (uint32_t)g.dims[0] + (uint32_t)cx;
   key[k] = c;
