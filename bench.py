@@ -45,19 +45,19 @@ PEAK_FP32_TFLOPS = 157.3
 TILE_NAMES = ("none", "small", "large")
 PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes of the activity pass per particle (all N particles, every
-# list rebuild with active domains): the stored position (12 B of FP32
-# coordinates, or 12 B of offsets + 8 B of cell indices) read, one flag byte
-# written.
-ACTIVITY_BYTES = {0: 12 + 1, 1: 20 + 1}
+# list rebuild with active domains): what decides the flag read (the 12 B of
+# FP32 coordinates; in cell-offset form the 8 B of cell indices, which reject
+# every particle but the few near a box), one flag byte written.
+ACTIVITY_BYTES = {0: 12 + 1, 1: 8 + 1}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a
 # plain copy of known size: fetch x2, write x1), with the digest of the kernel
 # sources they were taken on; reported only while the sources are unchanged
 # (summaries and commands in profiles/).
 MEASURED_TRAFFIC = {
-    "k_fluid_stage2 wheel bin": dict(bytes=None, source=None),
-    "k_activity strip pos_mode 0": dict(bytes=None, source=None),
-    "k_activity strip pos_mode 1": dict(bytes=None, source=None),
+    "k_fluid_stage2 wheel bin": dict(bytes=466.16e6, source="a839711d2a7301f0"),
+    "k_activity strip pos_mode 0": dict(bytes=2511.43e6, source="a839711d2a7301f0"),
+    "k_activity strip pos_mode 1": dict(bytes=2513.54e6, source="a839711d2a7301f0"),
 }
 KERNEL_SOURCES = ("crm_kernels.hip", "crm_device.h", "crm_internal.h")
 
@@ -211,9 +211,17 @@ def run_wheel(args, crm, scenes):
         one_step()
     tile = sim.autotune() if args.autotune else sim.autotune(TILE_NAMES.index(args.tile))
     torch.cuda.synchronize()
-    # events around the dominant kernel only, on the context's stream
-    sim.profiling(True, classes=["soil_stage2"])
-    wall = timed_steps(one_step, 0, args.steps)
+    if args.wheel_graph:
+        # the per-step kernels as one graph (the profiling events below would
+        # bypass it: the timed region then runs without them)
+        sim.graph(True)
+        wall = timed_steps(one_step, 0, args.steps)
+        sim.profiling(True, classes=["soil_stage2"])
+        timed_steps(one_step, 0, min(args.steps, 100))
+    else:
+        # events around the dominant kernel only, on the context's stream
+        sim.profiling(True, classes=["soil_stage2"])
+        wall = timed_steps(one_step, 0, args.steps)
     prof = sim.profile()
     # per-class breakdown (every kernel class timed) over a short untimed run
     sim.profiling(True)
@@ -448,6 +456,8 @@ def main():
                     help="further forms measured after the wheel bin, comma-separated from strip0 (10 km "
                          "strip, plain FP32 positions), strip1 (cell index + FP32 offset), batch (64 bins); "
                          "'none' for the wheel bin alone")
+    ap.add_argument("--wheel-graph", action="store_true",
+                    help="replay the wheel bin's per-step kernels as a hipGraph in the timed region")
     ap.add_argument("--trace-steps", type=int, default=20000,
                     help="after the forms, run the wheel bin this many steps from rest and report the drawbar "
                          "pull, vertical force and torque (20000: the 0.5 s single-wheel test)")

@@ -645,15 +645,18 @@ crm_status rebuild(crm_ctx* c) {
                                c->grid.cell != 0, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kSoilActive, c->frows, c->d_counts + 1, c->ctmp, s));
   HIPCHK(c, crm::compact_kind(c->pos4, n_proc, crm::kMarker, c->mrows, c->d_counts + 2, c->ctmp, s));
-  HIPCHK(c, crm::tile_tables(c->frows, n_proc, c->d_counts + 1, c->skey, c->cell_start, pw, c->tabs, s));
-  HIPCHK(c, crm::nbr_count_soil(c->frows, n_proc, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, g,
+  // the row lists hold at most this many rows (their counts are on the device):
+  // the soil and marker passes and scans run over these bounds, not n_proc
+  const int64_t rf = std::min(n_proc, c->n_soil), rm = std::min(n_proc, c->n_mark);
+  HIPCHK(c, crm::tile_tables(c->frows, rf, c->d_counts + 1, c->skey, c->cell_start, pw, c->tabs, s));
+  HIPCHK(c, crm::nbr_count_soil(c->frows, rf, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, g,
                                 c->tabs, c->cnt_f, c->stash_f, s));
-  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_f, c->off_f, n_proc, c->wtmp, s));
-  HIPCHK(c, crm::nbr_count(c->mrows, n_proc, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, g,
+  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_f, c->off_f, rf, c->wtmp, s));
+  HIPCHK(c, crm::nbr_count(c->mrows, rm, c->d_counts + 2, c->pos4, c->cpos, c->skey, c->cell_start, g,
                            true, c->cnt_m, c->stash_m, s));
-  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_m, c->off_m, n_proc, c->wtmp, s));
-  HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->off_f + n_proc, c->off_m + n_proc, s));
-  HIPCHK(c, crm::compact_nonzero(c->cnt_m, n_proc, c->near, c->d_counts + 5, c->ctmp, s));
+  HIPCHK(c, crm::scan_u32_to_u64(c->cnt_m, c->off_m, rm, c->wtmp, s));
+  HIPCHK(c, crm::copy2_u64(c->d_counts + 3, c->off_f + rf, c->off_m + rm, s));
+  HIPCHK(c, crm::compact_nonzero(c->cnt_m, rm, c->near, c->d_counts + 5, c->ctmp, s));
   crm_status st = read_counts(c);
   if (st != CRM_OK) return st;
   c->n_frows = (int64_t)c->h_counts[1];
