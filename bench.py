@@ -290,6 +290,61 @@ def run_wheel_trace(args, crm, scenes):
                                               Ty=T[::every, 1].round(5).tolist()))
 
 
+def strip_at(sc, x0):
+    """The strip scene with the vehicle moved so that its centre is at x = x0
+    (the soil and the floor are shared, not copied)."""
+    import dataclasses
+    cx = 0.5 * (sc.bodies[1].pos[0] + sc.bodies[-1].pos[0])
+    bodies = [sc.bodies[0]] + [dataclasses.replace(b, pos=(b.pos[0] + (x0 - cx), b.pos[1], b.pos[2]))
+                               for b in sc.bodies[1:]]
+    return dataclasses.replace(sc, bodies=bodies)
+
+
+def strip_subpatch(sc, xc, half=0.5):
+    """A 2 half x 4 m sub-patch of the strip around x = xc: its soil particles
+    (stored FP32 coordinates, as the strip holds them) and the floor markers
+    below them, in a domain of their own; no wheel. Settles under gravity."""
+    import dataclasses
+    from paper_2507_05643_amd import scenes
+    p = np.asarray(sc.pos, dtype=np.float64)
+    keep = (p[:, 0] >= xc - half) & (p[:, 0] < xc + half)
+    fl = sc.bodies[0]
+    m = np.asarray(fl.markers, dtype=np.float64)
+    mk = (m[:, 0] >= xc - half - 0.2) & (m[:, 0] < xc + half + 0.2)
+    dx = sc.params["dx"]
+    lo = (xc - half - 0.2 - 4 * dx, sc.params["domain_lo"][1], sc.params["domain_lo"][2])
+    hi = (xc + half + 0.2 + 4 * dx, sc.params["domain_hi"][1], sc.params["domain_hi"][2])
+    params = dict(sc.params, domain_lo=lo, domain_hi=hi, active_domains=0, ps_freq=10)
+    floor = scenes.Body(markers=np.ascontiguousarray(m[mk].astype(np.float32)), name="floor")
+    return dataclasses.replace(sc, pos=np.ascontiguousarray(p[keep].astype(np.float32)), vel=None, sigma=None,
+                               rho=None, bodies=[floor], params=params, name="strip_subpatch")
+
+
+def subpatch_drift(sc, crm, steps=100):
+    """Positions after `steps` steps of the strip's sub-patch at x ~ 9,999 m,
+    GPU (plain FP32 and cell-offset positions) against the FP64 oracle: the
+    displacement error max |x_gpu - x_oracle| over the largest displacement."""
+    from oracle.oracle import Oracle
+    orc = Oracle(sc, nbr_mode="cells")
+    t0 = time.perf_counter()
+    orc.step(steps)
+    t_orc = time.perf_counter() - t0
+    n = sc.n_soil
+    x0 = np.asarray(sc.pos, dtype=np.float64)
+    xr = orc.state()["pos"][:n]
+    dmax = float(np.abs(xr - x0).max())
+    out = dict(x_centre=round(float(x0[:, 0].mean()), 3), n_soil=n, n_particles=sc.n_total, steps=steps,
+               oracle_max_displacement_m=dmax,
+               oracle_particle_steps_per_s=sc.n_total * steps / t_orc)
+    for mode in (0, 1):
+        sim = crm.Simulation(sc, params=dict(sc.params, pos_mode=mode), device=0)
+        sim.step(steps)
+        xg = sim.state()["pos"][:n]
+        sim.close()
+        out[f"displacement_error_pos_mode_{mode}"] = float(np.abs(xg - xr).max() / dmax)
+    return out
+
+
 def run_strip(args, crm, scenes, pos_mode, sc=None):
     """Long strip with four wheels carrying active boxes, positions plain FP32
     (pos_mode 0) or cell index + FP32 offset (pos_mode 1); the vehicle sits at
@@ -431,16 +486,49 @@ def adjoint_cost(sim, one_step, k, ps_freq, n_soil, nb):
                 note="wall time of each call, host seeds and outputs included; *_again: second call")
 
 
-def cpu_baseline(scene, steps):
+def _oracle_rate(scene, steps):
     from oracle.oracle import Oracle
     orc = Oracle(scene, nbr_mode="cells")
     t0 = time.perf_counter()
     orc.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=scene.n_total * steps / dt, unit="particle-steps/s", cores=Oracle.threads(),
-                kind="oracle",
-                sample=f"{steps} steps of the same wheel-bin workload ({scene.n_total} particles, all "
-                       f"processed), FP64 C oracle with cell-list search, {dt:.1f} s")
+    return scene.n_total * steps / (time.perf_counter() - t0)
+
+
+def _oracle_rate_one_thread(workload, steps):
+    """The oracle on one host thread, in a child process (OpenMP reads the
+    thread count when the library starts)."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "from paper_2507_05643_amd import scenes\n"
+            "from oracle.oracle import Oracle\n"
+            "sc = scenes.%s\n"
+            "o = Oracle(sc, nbr_mode='cells'); t = time.perf_counter(); o.step(%d)\n"
+            "print(sc.n_total * %d / (time.perf_counter() - t))\n") % (ROOT, workload, steps, steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    return float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+
+
+def cpu_baseline(scenes, ps_freq, steps, runs, subpatch_rate=None):
+    """The FP64 oracle (cell-list neighbour search, OpenMP over the host's
+    threads) on the wheel bin: the median of `runs` runs of `steps` steps; then
+    one thread on one step of the same workload, and the other workloads."""
+    from oracle.oracle import Oracle
+    sc = scenes.wheel_bin(seed=0, ps_freq=ps_freq)
+    t0 = time.perf_counter()
+    rates = [_oracle_rate(sc, steps) for _ in range(runs)]
+    t_w = time.perf_counter() - t0
+    one = _oracle_rate_one_thread(f"wheel_bin(seed=0, ps_freq={ps_freq})", 1)
+    other = dict(column_16cubed_100_steps=_oracle_rate(scenes.column(seed=0, n=16, ps_freq=ps_freq), 100),
+                 plate_32x32x16_200_steps=_oracle_rate(scenes.plate_patch(seed=0, ps_freq=ps_freq), 200))
+    if subpatch_rate is not None:
+        other["strip_subpatch_at_9999m_100_steps"] = subpatch_rate
+    return dict(value=float(np.median(rates)), unit="particle-steps/s", cores=Oracle.threads(), kind="oracle",
+                sample=f"median of {runs} runs of {steps} steps of the same wheel-bin workload ({sc.n_total} "
+                       f"particles, all processed), FP64 C oracle with cell-list search, {t_w:.1f} s; one thread: "
+                       f"1 step; other workloads: one run each",
+                runs=[round(r) for r in rates], single_thread=one,
+                other_workloads={k: round(v) for k, v in other.items()})
 
 
 def main():
@@ -449,8 +537,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--ps-freq", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=30,
-                    help="oracle steps of the CPU baseline (about 10-20 s on 16 cores)")
+    ap.add_argument("--cpu-steps", type=int, default=10,
+                    help="oracle steps per run of the CPU baseline (about 3 s on 16 cores)")
+    ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="strip0,strip1,batch",
                     help="further forms measured after the wheel bin, comma-separated from strip0 (10 km "
@@ -499,14 +588,28 @@ def main():
     forms = {}
     wanted = [f for f in args.forms.split(",") if f and f != "none"]
     strip_scene = None
+    drift = None
     for f in wanted:
         t0 = time.perf_counter()
         if f in ("strip0", "strip1"):
             if strip_scene is None:
                 strip_scene = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x,
                                            ps_freq=args.ps_freq, t_delay=-1.0)
-            r = run_strip(args, crm, scenes, int(f[-1]), strip_scene)
+            mode = int(f[-1])
+            r = run_strip(args, crm, scenes, mode, strip_scene)
             name = "strip_fp32" if f == "strip0" else "strip_cell_offset"
+            # the same form with the vehicle near either end of the strip
+            steps = args.strip_steps
+            args.strip_steps = max(steps // 2, 1)
+            r["along_the_strip"] = {}
+            for xv in (10.0, args.strip_length - 10.0):
+                q = run_strip(args, crm, scenes, mode, strip_at(strip_scene, xv))
+                r["along_the_strip"][f"x={xv:g}"] = dict(value=q["value"], ms_per_step=q["ms_per_step"],
+                                                         n_processed=q["config"]["n_processed"],
+                                                         activity_launch_ms=(q["roofline"] or {}).get("launch_ms"))
+            args.strip_steps = steps
+            if drift is None and args.strip_length >= 9999.5:
+                drift = subpatch_drift(strip_subpatch(strip_scene, 9999.0), crm)
         elif f == "batch":
             strip_scene = None
             r = run_batch(args, crm, scenes)
@@ -525,7 +628,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scenes.wheel_bin(seed=0, ps_freq=args.ps_freq), args.cpu_steps)
+        cpu = cpu_baseline(scenes, args.ps_freq, args.cpu_steps, args.cpu_runs,
+                           drift["oracle_particle_steps_per_s"] if drift else None)
 
     out = {
         "metric": "particle-steps/s",
@@ -546,6 +650,7 @@ def main():
         "soil_particle_steps_per_s": w["soil_rate"],
         "adjoint": w["adjoint"],
         "forms": forms,
+        "strip_subpatch_drift": drift,
         "wheel_trace": trace,
         "total_seconds": round(time.perf_counter() - t_start, 1),
     }
