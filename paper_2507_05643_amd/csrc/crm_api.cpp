@@ -113,6 +113,8 @@ struct crm_ctx {
   bool plan_all = false;         // body_plan covers all markers (every particle processed)
   int64_t kbase = 0;             // rank of the first processed marker in the processed list
   std::vector<Body> placed;      // body poses of the markers' last placement in the master store
+  std::vector<Body> wplaced;     // body states of the markers' last placement in the working set
+  bool wplaced_ok = false;       // wplaced holds them (else every body counts as moved)
   bool place_all = true;         // place every body's markers at the next placement
   // Verlet lists (skin > 0): steps of the last rebuild, largest squared
   // displacement since (device word, pinned mirror, event of its copy)
@@ -679,6 +681,10 @@ crm_status rebuild(crm_ctx* c) {
                                c->stash_f, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, g, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
+  // every marker row of the new working set placed once (rows that lost or
+  // gained soil neighbours, values gathered from the master store)
+  HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->cnt_m, c->slot_id, c->n_soil, c->local, c->d_bodies,
+                                       c->grid, c->phys, c->A, c->B, true, s));
   // per-body ranges of the processed markers for the force sums
   c->kbase = c->n_proc - c->n_mrows;
   st = update_body_plan(c, ids);
@@ -743,7 +749,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   const Phys& P = c->phys;
   hipEvent_t e = prof ? prof_begin(c, 1) : nullptr;
   HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->cnt_m, c->slot_id, c->n_soil, c->local,
-                                       c->d_bodies, c->grid, P, c->A, c->B, s));
+                                       c->d_bodies, c->grid, P, c->A, c->B, false, s));
   if (prof) prof_end(c, 1, e);
   // stage 1 at y_n
   if (prof) e = prof_begin(c, 2);
@@ -842,6 +848,13 @@ crm_status track_displacement(crm_ctx* c) {
   return CRM_OK;
 }
 
+// The body states the step just placed its markers with (sized at crm_init:
+// no allocation here).
+void note_placement(crm_ctx* c) {
+  std::copy(c->h_bodies.begin(), c->h_bodies.begin() + c->nb, c->wplaced.begin());
+  c->wplaced_ok = true;
+}
+
 crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
   if (rebuild_due(c)) {
     hipEvent_t e = prof_begin(c, 0);
@@ -852,6 +865,7 @@ crm_status one_step(crm_ctx* c, const StepRecord* rec = nullptr) {
   crm_status st = rec ? launch_step(c, c->stream, false, rec)
                       : (c->use_graph && !c->prof) ? step_graph(c) : launch_step(c, c->stream, c->prof);
   if (st != CRM_OK) return st;
+  note_placement(c);
   st = track_displacement(c);
   if (st != CRM_OK) return st;
   c->step += 1;
@@ -1034,6 +1048,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     }
   }
   c->placed.assign((size_t)n_bodies, Body{});
+  c->wplaced.assign((size_t)n_bodies, Body{});
 
   // physical constants (Sec. 2.1, 2.2)
   const crm_params& P = *params;
@@ -1131,6 +1146,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
     B.R[0] = B.R[4] = B.R[8] = 1.0;
     for (int a = 0; a < 3; ++a) B.half[a] = bodies[b].active_half[a];
     B.has_box = (B.half[0] > 0.0 || B.half[1] > 0.0 || B.half[2] > 0.0) ? 1 : 0;
+    B.place = 1;
     set_box_bounds(B, g);
   }
 
@@ -1266,6 +1282,9 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
     quat_to_R(q, B.R);
     B.has_acc = (linacc || angacc) ? 1 : 0;
     set_box_bounds(B, c->grid);
+    const Body& W = c->wplaced[b];
+    B.place = (!c->wplaced_ok || std::memcmp(B.X, W.X, sizeof(B.X)) != 0 || std::memcmp(B.R, W.R, sizeof(B.R)) != 0 ||
+               std::memcmp(B.V, W.V, sizeof(B.V)) != 0 || std::memcmp(B.W, W.W, sizeof(B.W)) != 0) ? 1 : 0;
   }
   // the staging buffer is reused once its last upload has been read
   hipError_t e = c->bpin_pending ? hipEventSynchronize(c->bpin_ev) : hipSuccess;
@@ -1353,6 +1372,7 @@ crm_status crm_step_noalloc(crm_ctx* c, int32_t n_steps) {
       }
       st = launch_step(c, c->stream, false);
       if (st != CRM_OK) break;
+      note_placement(c);
       st = track_displacement(c);
       if (st != CRM_OK) break;
       c->step += 1;
@@ -1835,6 +1855,7 @@ crm_status crm_load_checkpoint(crm_ctx* c, const void* buf, size_t bytes) {
   c->working_valid = false;
   c->force_rebuild = true;
   c->place_all = true;
+  c->wplaced_ok = false;
   c->rec_valid = false;
   c->stepped = false;
   c->disp_pending = false;

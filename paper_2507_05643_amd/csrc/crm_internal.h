@@ -55,6 +55,8 @@ struct Body {
   int32_t chi[3]; // carry (offsets stay within one cell of [0, S))
   int32_t has_acc;
   int32_t has_box;
+  int32_t place;  // pose or velocity differ from the last placement of its markers in the working set
+  int32_t pad_;
 };
 
 // Cell grid of the linked list (cell size 2h) and the FP64 neighbour radius.
@@ -212,9 +214,11 @@ hipError_t max_disp(CPlanes A, const float4* pos4, const int4* cpos, int64_t n, 
 // Per step: marker positions of the processed markers into A and B.
 // cnt: the marker rows' soil-neighbour counts; rows with none also get their
 // (empty-sum) BCE values here, for both states.
+// all: every marker row; else only the rows of bodies whose `place` is set
+// (the others keep the values of their last placement).
 hipError_t place_markers_working(const int32_t* mrows, int64_t n_mrows, const uint32_t* cnt, const int32_t* slot_id,
                                  int64_t n_soil, const float4* local, const Body* bodies, Grid g, Phys P,
-                                 Planes A, Planes B, hipStream_t s);
+                                 Planes A, Planes B, bool all, hipStream_t s);
 
 // BCE extrapolation at state S (Sec. 2.5.1); with contrib != nullptr also the
 // marker accelerations and each processed marker's force and torque on its

@@ -741,12 +741,16 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_working(const int32_t*
                                                                   const int32_t* __restrict__ slot_id, int64_t n_soil,
                                                                   const float4* __restrict__ local,
                                                                   const Body* __restrict__ bodies, Grid g, Phys P,
-                                                                  Planes A, Planes B) {
+                                                                  Planes A, Planes B, int all) {
   int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
   int32_t s = mrows[r];
   float4 l = local[slot_id[s] - n_soil];
   const Body& Bd = bodies[__float_as_uint(l.w)];
+  // a body whose pose and velocity are those of the last placement keeps its
+  // markers' values (positions, and the body velocity of rows without soil
+  // neighbours); after a list rebuild every row is placed once
+  if (!all && !Bd.place) return;
   double x[3];
   body_point(Bd, l.x, l.y, l.z, x);
   float4 a = A.a[s], d = A.d[s];
@@ -2073,13 +2077,14 @@ hipError_t nbr_fill(const int32_t* rows, int64_t n_rows, const float4* pos4, con
 
 hipError_t place_markers_working(const int32_t* mrows, int64_t n, const uint32_t* cnt, const int32_t* slot_id,
                                  int64_t n_soil, const float4* local, const Body* bodies, Grid g, Phys P, Planes A,
-                                 Planes B, hipStream_t s) {
+                                 Planes B, bool all, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (g.cell)
-    k_place_markers_working<true><<<nblk(n), kBlock, 0, s>>>(mrows, n, cnt, slot_id, n_soil, local, bodies, g, P, A, B);
+    k_place_markers_working<true><<<nblk(n), kBlock, 0, s>>>(mrows, n, cnt, slot_id, n_soil, local, bodies, g, P, A, B,
+                                                             all ? 1 : 0);
   else
     k_place_markers_working<false><<<nblk(n), kBlock, 0, s>>>(mrows, n, cnt, slot_id, n_soil, local, bodies, g, P, A,
-                                                              B);
+                                                              B, all ? 1 : 0);
   return hipGetLastError();
 }
 
