@@ -103,34 +103,39 @@ __device__ inline void store_pos(const double x[3], const Grid& g, float4& a, fl
 
 
 // --------------------------------------------------------- lane groups ---
-// A row (a soil particle or a marker) is served by a group of kGroup
-// consecutive lanes: the group walks the row's candidates or neighbours kGroup
-// at a time, so that the lanes of a group touch consecutive slots of the
-// cell-sorted planes, and then sums its partial results across the group.
+// A row (a soil particle or a marker) is served by a group of G consecutive
+// lanes: the group walks the row's candidates or neighbours G at a time, so
+// that the lanes of a group touch consecutive slots of the cell-sorted planes,
+// and then sums its partial results across the group. The list passes, the
+// marker rows and the reverse sweep use groups of kGroup lanes; the soil
+// stages use narrower groups (more rows per wave share the per-row work).
 constexpr int kGroup = 8;
 static_assert(kWave % kGroup == 0, "group must divide the wave");
 
-__device__ inline int group_lane() { return threadIdx.x & (kGroup - 1); }
+template <int G = kGroup>
+__device__ inline int group_lane() { return threadIdx.x & (G - 1); }
 
-// Sum over the kGroup lanes of a group; every lane gets the total. DPP lane
+// Sum over the G lanes of a group; every lane gets the total. DPP lane
 // permutations: swap neighbours, swap pairs, mirror the two quads of 8 lanes,
 // mirror the two halves of 16 lanes.
 template <int Ctrl>
 __device__ inline float dpp_perm(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
 }
+template <int G = kGroup>
 __device__ inline float group_sum(float v) {
-  static_assert(kGroup == 2 || kGroup == 4 || kGroup == 8 || kGroup == 16, "group of 2, 4, 8 or 16 lanes");
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "group of 2, 4, 8 or 16 lanes");
   v += dpp_perm<0xB1>(v);                          // quad [1,0,3,2]
-  if (kGroup >= 4) v += dpp_perm<0x4E>(v);         // quad [2,3,0,1]
-  if (kGroup >= 8) v += dpp_perm<0x141>(v);        // half-row mirror
-  if (kGroup >= 16) v += dpp_perm<0x140>(v);       // row mirror
+  if (G >= 4) v += dpp_perm<0x4E>(v);              // quad [2,3,0,1]
+  if (G >= 8) v += dpp_perm<0x141>(v);             // half-row mirror
+  if (G >= 16) v += dpp_perm<0x140>(v);            // row mirror
   return v;
 }
 
 // Bits of this lane's group in a wave ballot.
+template <int G = kGroup>
 __device__ inline uint32_t group_bits(uint64_t ballot) {
-  return (uint32_t)(ballot >> (lane_id() & ~(kGroup - 1))) & ((1u << kGroup) - 1u);
+  return (uint32_t)(ballot >> (lane_id() & ~(G - 1))) & ((1u << G) - 1u);
 }
 
 
@@ -211,17 +216,17 @@ struct GlobalLoad {
   __device__ Nbr operator()(uint32_t j) const { return load_nbr(S, j); }
 };
 
-// Walks entries k0 + lane, k0 + lane + kGroup, ... < k1 of a CSR row and calls
+// Walks entries k0 + lane, k0 + lane + G, ... < k1 of a CSR row and calls
 // f(record, slot) for each, in that order, with the record from `load`. Two
 // entries per lane and step: both slots, then both records, are in flight
 // together (the second pair of loads repeats the first past the row's end).
-template <class Load, class Fn>
+template <int G = kGroup, class Load, class Fn>
 __device__ inline void walk_row_with(const Load& load, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
                                      Fn&& f) {
-  for (uint64_t k = k0 + group_lane(); k < k1; k += 2 * kGroup) {
-    const bool has1 = k + kGroup < k1;
+  for (uint64_t k = k0 + group_lane<G>(); k < k1; k += 2 * G) {
+    const bool has1 = k + G < k1;
     const uint32_t j0 = nbr[k];
-    const uint32_t j1 = nbr[has1 ? k + kGroup : k];
+    const uint32_t j1 = nbr[has1 ? k + G : k];
     const Nbr a = load(j0);
     const Nbr b = load(j1);
     f(a, j0);

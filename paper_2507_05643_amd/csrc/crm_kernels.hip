@@ -969,7 +969,7 @@ struct Rates {
 // a = (1/rho_i) sum_j V_j (s_i + s_j) . gradW + g + Pi_a (F3, artificial viscosity
 // with the sign that repels approaching pairs); ds/dt = Om s - s Om + 2G D +
 // (bulk K - 2G/3) tr D I with D, Om the symmetric and skew parts of L.
-// The group's lanes take the row's neighbours k = lane, lane + kGroup, ...;
+// The group's G lanes take the row's neighbours k = lane, lane + G, ...;
 // walk(pair) calls pair(record) for each of the lane's neighbours, with the
 // neighbour's volume V_j = m / rho_j in place of its density (a.w). One
 // reciprocal square root gives q and 1 / q. The own stress's share of F3 is
@@ -980,7 +980,7 @@ struct Rates {
 // density of the pair is (rho_i V_j + m) / (2 V_j)). Every product-sum is an
 // explicit FMA and nothing else is contracted, so each way of walking the
 // neighbours (tile or L1) gives the same bits by construction.
-template <bool CELL, class Walk>
+template <bool CELL, int G, class Walk>
 __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Walk&& walk, const Phys& P) {
 #pragma clang fp contract(off)
   const Own me = own_pos<CELL>(ma, md);
@@ -1026,11 +1026,11 @@ __device__ inline Rates fluid_rhs(float4 ma, float4 mb, float4 mc, float4 md, Wa
     a2 = fmaf(o.d.x, wx, a2); a2 = fmaf(o.d.y, wy, a2); a2 = fmaf(o.c.z + pi, wz, a2);
   };
   walk(pair);
-  L00 = group_sum(L00); L01 = group_sum(L01); L02 = group_sum(L02);
-  L10 = group_sum(L10); L11 = group_sum(L11); L12 = group_sum(L12);
-  L20 = group_sum(L20); L21 = group_sum(L21); L22 = group_sum(L22);
-  a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
-  g0 = group_sum(g0); g1 = group_sum(g1); g2 = group_sum(g2);
+  L00 = group_sum<G>(L00); L01 = group_sum<G>(L01); L02 = group_sum<G>(L02);
+  L10 = group_sum<G>(L10); L11 = group_sum<G>(L11); L12 = group_sum<G>(L12);
+  L20 = group_sum<G>(L20); L21 = group_sum<G>(L21); L22 = group_sum<G>(L22);
+  a0 = group_sum<G>(a0); a1 = group_sum<G>(a1); a2 = group_sum<G>(a2);
+  g0 = group_sum<G>(g0); g1 = group_sum<G>(g1); g2 = group_sum<G>(g2);
   a0 = fmaf(s4, g2, fmaf(s3, g1, fmaf(s0, g0, a0)));
   a1 = fmaf(s5, g2, fmaf(s1, g1, fmaf(s3, g0, a1)));
   a2 = fmaf(s2, g2, fmaf(s5, g1, fmaf(s4, g0, a2)));
@@ -1106,14 +1106,28 @@ __device__ inline void return_map(float st[6], const float sn[6], const Phys& P,
 // loads, and the pair loop reads neighbours from LDS instead of making an L1
 // line lookup per plane per pair. Blocks whose rows span two cell rows, or
 // whose ranges exceed the tile, read from global memory as before.
-constexpr int kRows = kBlock / kGroup;
+//
+// The soil list passes (k_nbr_count_soil, k_nbr_fill_soil) give each row
+// kGroup lanes, the stage kernels kSG. Eight lanes per row in the stages: four
+// lanes on 64-row blocks share the once-per-row work (staging, group sums,
+// update, return mapping) among 16 rows per wave and issue ~22 % fewer VALU
+// instructions, but a 64-row tile leaves three workgroups per CU (80 % of the
+// blocks fit 1024 records) instead of four, and the stages then run 9 %
+// slower; on 32-row blocks (two waves per workgroup) 22 % slower.
+constexpr int kRows = 32;
+constexpr int kSG = 8;
+constexpr int kListBlock = kRows * kGroup;
+constexpr int kStageBlock = kRows * kSG;
+static_assert(kListBlock <= 1024 && kStageBlock % kWave == 0, "whole waves per block");
+static_assert(kSG >= 4, "lanes 0-3 of a group store the four planes of a row");
 
 // FP32 positions: 52-byte records (sigma_xz in b.w, where the aux word sits in
 // HBM; sigma_yz apart); cell-offset positions: 64-byte records (plane d
 // carries the cells). Tile configurations (chosen per context, see
 // crm_autotune): 0 no tile, 1 small (768 or 640 records, 40 KB: four blocks
 // per CU), 2 large (1024 or 832 records, 53 KB: three blocks per CU). On the
-// wheel bin 84 % of the 32-row blocks fit 768 records and 99.8 % fit 1024.
+// wheel bin the 32-row blocks' cut ranges hold 526 records on average; 97 % of
+// the blocks fit 787 and 98 % fit 1024 (2 % span two cell rows).
 template <bool CELL, uint32_t CAP>
 struct StageTile;
 template <uint32_t CAP>
@@ -1242,9 +1256,9 @@ constexpr uint32_t kTileMax = 1024;
 // that also writes each entry's tile position: 16 i for slot j at tile index
 // i (the record's byte offset in each 16-byte tile plane), for the blocks whose
 // rows lie in one row of cells and whose ranges fit kTileMax records (other
-// blocks' positions are not written). Workgroup b serves the 32 rows of tile
-// table b, so the table is uniform.
-__global__ __launch_bounds__(kBlock) void k_nbr_fill_soil(const int32_t* __restrict__ rows, int64_t n_rows,
+// blocks' positions are not written). Workgroup b serves the kRows rows of
+// tile table b, so the table is uniform.
+__global__ __launch_bounds__(kListBlock) void k_nbr_fill_soil(const int32_t* __restrict__ rows, int64_t n_rows,
                                                           const float4* __restrict__ pos4,
                                                           const int4* __restrict__ cpos,
                                                           const uint32_t* __restrict__ skey,
@@ -1255,7 +1269,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill_soil(const int32_t* __restr
                                                           const uint32_t* __restrict__ tabs,
                                                           uint16_t* __restrict__ tix) {
   const int64_t blk = xcd_block();
-  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
+  const int64_t r = (blk * kListBlock + threadIdx.x) / kGroup;
   const bool live = r < n_rows;
   const uint32_t* tb = tabs + blk * kTabWords;
   const bool tiled = tb[19] != 0 && tb[18] <= kTileMax;
@@ -1300,21 +1314,24 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill_soil(const int32_t* __restr
 // ranges staged in LDS (positions, and cells with cell-offset positions): a
 // row's run of candidates in cells x - 1 .. x + 1 of one (y, z) row lies
 // inside the block's range of that (y, z) row, at tile index slot - o_k. Blocks
-// whose rows span two cell rows, or whose ranges exceed kScanCap records,
-// read the candidates from the planes.
-constexpr uint32_t kScanCap = 1024;
+// whose rows span two cell rows, or whose ranges exceed scan_cap records,
+// read the candidates from the planes. On the wheel bin the whole-cell ranges
+// of a 32-row block hold 633 records on average; 99.8 % of the blocks fit 1024.
+template <bool CELL>
+constexpr uint32_t scan_cap() { return 1024u; }
 
 template <bool CELL>
 struct ScanTile;
 template <>
 struct ScanTile<false> {
-  float4 p[kScanCap];
+  float4 p[scan_cap<false>()];
 };
 template <>
 struct ScanTile<true> {
-  float4 p[kScanCap];
-  int4 c[kScanCap];
+  float4 p[scan_cap<true>()];
+  int4 c[scan_cap<true>()];
 };
+static_assert(sizeof(ScanTile<true>) <= 49152 && sizeof(ScanTile<false>) <= 32768, "three count blocks per CU");
 
 // Candidates from the block's LDS tile: run k reads slot j at tile index
 // j - o_k and is cut to the block's range k [lo_k, hi_k), which holds every
@@ -1415,7 +1432,7 @@ struct ScanRowLoad {
 
 // Count pass of the soil rows. A block whose rows lie in one row of cells
 // and whose ranges (whole cells x_first - 1 .. x_last + 1 of the nine (y, z)
-// rows) fit kScanCap records stages their positions in LDS and cuts each
+// rows) fit scan_cap records stages their positions in LDS and cuts each
 // range to the slots whose x lies within [x_min - R', x_max + R']: x_min,
 // x_max are the extremes of the block's rows and R' is the list radius
 // widened by 2^-20, far above the FP64 rounding of the separations; every
@@ -1426,7 +1443,7 @@ struct ScanRowLoad {
 // ranges back into its table, so that the fill pass and the stage kernels
 // copy only those records into their tiles.
 template <bool CELL>
-__global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __restrict__ rows, int64_t rows_cap,
+__global__ __launch_bounds__(kListBlock) void k_nbr_count_soil(const int32_t* __restrict__ rows, int64_t rows_cap,
                                                            const uint64_t* __restrict__ n_rows_dev,
                                                            const float4* __restrict__ pos4,
                                                            const int4* __restrict__ cpos,
@@ -1439,9 +1456,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
   __shared__ uint32_t ct[36];     // per range: first slot, o_k, leading cut, trailing cut
   __shared__ unsigned long long xext[2];   // order keys of the rows' x extremes
   const int64_t nr = (int64_t)*n_rows_dev;
-  const int64_t nb_live = (nr * kGroup + kBlock - 1) / kBlock;
+  const int64_t nb_live = (nr + kRows - 1) / kRows;
   const int64_t blk = xcd_block_n(nb_live);
-  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
+  const int64_t r = (blk * kListBlock + threadIdx.x) / kGroup;
   const bool live = r < nr;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   int4 ci = make_int4(0, 0, 0, 0);
@@ -1458,15 +1475,16 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
   if (blk < nb_live) {                      // uniform over the block
     uint32_t* tb = tabs + blk * kTabWords;
     const uint32_t total = tb[18];
-    staged = tb[19] != 0 && total <= kScanCap;
+    staged = tb[19] != 0 && total <= scan_cap<CELL>();
     if (staged) {
       const TileLoad ld = tile_loader(tb);
-      constexpr int kPer = (int)(kScanCap / kBlock);
+      constexpr int kPer = (int)(scan_cap<CELL>() / kListBlock);
+      static_assert(scan_cap<CELL>() % kListBlock == 0, "whole records per thread");
       float4 p[kPer];
       int4 q[kPer];
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        const uint32_t t = threadIdx.x + (uint32_t)(u * kBlock);
+        const uint32_t t = threadIdx.x + (uint32_t)(u * kListBlock);
         if (t < total) {
           const uint32_t j = ld.slot(t);
           p[u] = pos4[j];
@@ -1494,7 +1512,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count_soil(const int32_t* __rest
       }
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        const uint32_t t = threadIdx.x + (uint32_t)(u * kBlock);
+        const uint32_t t = threadIdx.x + (uint32_t)(u * kListBlock);
         if (t < total) {
           tile.p[t] = p[u];
           if constexpr (CELL) tile.c[t] = q[u];
@@ -1603,11 +1621,11 @@ __device__ inline Nbr tile_rec(const StageTile<CELL, CAP>& T, uint32_t o) {
 // taken in entry order. pos(k) is the tile position of entry k (relative to
 // the block's first entry); e0..e1 are the row's entries; past the row's end
 // the walk reads its last entry again (a valid position).
-template <bool CELL, uint32_t CAP, class Pos, class Fn>
+template <int GW, bool CELL, uint32_t CAP, class Pos, class Fn>
 __device__ inline void walk_tile_pos(const StageTile<CELL, CAP>& T, const Pos& pos_of, uint32_t e0, uint32_t e1,
                                      Fn&& f) {
-  constexpr uint32_t G = kGroup;
-  const uint32_t ef = e0 + group_lane();
+  constexpr uint32_t G = (uint32_t)GW;
+  const uint32_t ef = e0 + (uint32_t)group_lane<GW>();
   if (ef >= e1) return;
   const uint32_t el = e1 - 1;
   auto pos = [&](uint32_t e) { return pos_of(e < el ? e : el); };
@@ -1645,10 +1663,10 @@ __device__ inline void walk_tile_pos(const StageTile<CELL, CAP>& T, const Pos& p
 // load from there is the walk's longest wait. Positions are below 16 total
 // (k_nbr_fill_soil, for blocks that stage); LDS reads past the block's
 // allocation would return zero, never fault.
-template <bool CELL, uint32_t CAP, class Fn>
+template <int GW, bool CELL, uint32_t CAP, class Fn>
 __device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* __restrict__ tix, uint32_t e0,
                                  uint32_t e1, Fn&& f) {
-  walk_tile_pos(T, [&](uint32_t k) {
+  walk_tile_pos<GW>(T, [&](uint32_t k) {
     return (uint32_t)*reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(tix) + 2u * k);
   }, e0, e1, f);
 }
@@ -1701,19 +1719,19 @@ __device__ inline void rec_store(StageTile<CELL, CAP>& T, const Rec& r, uint32_t
 template <bool CELL, uint32_t CAP>
 __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint32_t* __restrict__ tb,
                                   const TileLoad& ld, float m) {
-  static_assert(CAP <= 4 * kBlock, "four records per thread");
+  static_assert(CAP <= 4 * kStageBlock, "four records per thread");
   const uint32_t total = tb[18];
   const bool ok = tb[19] != 0 && total <= CAP;
   if (ok) {
     const uint32_t t0 = threadIdx.x;
     const Rec r0 = rec_load<CELL>(S, ld, t0, total);
-    const Rec r1 = rec_load<CELL>(S, ld, t0 + kBlock, total);
-    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kBlock, total);
-    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kBlock, total);
+    const Rec r1 = rec_load<CELL>(S, ld, t0 + kStageBlock, total);
+    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kStageBlock, total);
+    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kStageBlock, total);
     rec_store(T, r0, t0, total, m);
-    rec_store(T, r1, t0 + kBlock, total, m);
-    rec_store(T, r2, t0 + 2 * kBlock, total, m);
-    rec_store(T, r3, t0 + 3 * kBlock, total, m);
+    rec_store(T, r1, t0 + kStageBlock, total, m);
+    rec_store(T, r2, t0 + 2 * kStageBlock, total, m);
+    rec_store(T, r3, t0 + 3 * kStageBlock, total, m);
   }
   __syncthreads();
   return ok;
@@ -1722,7 +1740,7 @@ __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint
 // Tape of a stage for the reverse sweep: L in planes l0..l2 and, in stage 2,
 // the trial stress in planes t0..t1; plane k is written by lane k (mod group).
 __device__ inline void tape_write(const StageTape& T, int32_t s, const float L[9], const float* st, int np) {
-  for (int k = group_lane(); k < np; k += kGroup) {
+  for (int k = group_lane<kSG>(); k < np; k += kSG) {
     float4 v;
     float4* dst;
     if (k == 0) { v = make_float4(L[0], L[1], L[2], L[3]); dst = T.l0; }
@@ -1781,7 +1799,7 @@ __device__ inline void finish_stage2(Planes A, int32_t s, int gl, float4 ya, flo
 // Lanes 0-3 of the group write the four planes of the row's record. With TAPE
 // the velocity gradient L is also kept.
 template <bool CELL, bool TAPE, int CFG>
-__global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(kStageBlock) void k_fluid_stage1(CPlanes A, Planes B, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
                                                          const uint32_t* __restrict__ tabs,
@@ -1789,8 +1807,8 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
-  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
-  const int gl = group_lane();
+  const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
+  const int gl = group_lane<kSG>();
   const bool live = r < n;
   int32_t s = 0;
   uint64_t k0 = 0, k1 = 0;
@@ -1808,10 +1826,10 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
   if (staged) {
     const uint64_t kb = off[blk * kRows];
     const uint32_t e0 = live ? uint32_t(k0 - kb) : 0u, e1 = live ? uint32_t(k1 - kb) : 0u;
-    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
+    R = fluid_rhs<CELL, kSG>(ma, mb, mc, md, [&](auto&& f) { walk_tile<kSG>(tile, tix + kb, e0, e1, f); }, P);
   } else {
-    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
-      walk_row_with(GlobalLoad{A}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+    R = fluid_rhs<CELL, kSG>(ma, mb, mc, md, [&](auto&& f) {
+      walk_row_with<kSG>(GlobalLoad{A}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
         Nbr v = o;
         v.a.w = volume(P.m, o.a.w);
         f(v);
@@ -1825,7 +1843,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage1(CPlanes A, Planes B, co
 // Stage 2: A = A + dt f(B), then the return mapping on the stress. With TAPE
 // the velocity gradient and the trial stress are also kept.
 template <bool CELL, bool TAPE, int CFG>
-__global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(kStageBlock) void k_fluid_stage2(CPlanes B, Planes A, const int32_t* __restrict__ rows,
                                                          int64_t n, const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ nbr, Phys P, StageTape T,
                                                          const uint32_t* __restrict__ tabs,
@@ -1833,8 +1851,8 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
   const int64_t blk = xcd_block();
-  const int64_t r = (blk * kBlock + threadIdx.x) / kGroup;
-  const int gl = group_lane();
+  const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
+  const int gl = group_lane<kSG>();
   const bool live = r < n;
   int32_t s = 0;
   uint64_t k0 = 0, k1 = 0;
@@ -1854,10 +1872,10 @@ __global__ __launch_bounds__(kBlock) void k_fluid_stage2(CPlanes B, Planes A, co
   if (staged) {
     const uint64_t kb = off[blk * kRows];
     const uint32_t e0 = live ? uint32_t(k0 - kb) : 0u, e1 = live ? uint32_t(k1 - kb) : 0u;
-    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) { walk_tile(tile, tix + kb, e0, e1, f); }, P);
+    R = fluid_rhs<CELL, kSG>(ma, mb, mc, md, [&](auto&& f) { walk_tile<kSG>(tile, tix + kb, e0, e1, f); }, P);
   } else {
-    R = fluid_rhs<CELL>(ma, mb, mc, md, [&](auto&& f) {
-      walk_row_with(GlobalLoad{B}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+    R = fluid_rhs<CELL, kSG>(ma, mb, mc, md, [&](auto&& f) {
+      walk_row_with<kSG>(GlobalLoad{B}, k0, k1, nbr, [&](const Nbr& o, uint32_t) {
         Nbr v = o;
         v.a.w = volume(P.m, o.a.w);
         f(v);
@@ -1909,6 +1927,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_markers(CPlanes src, const i
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned nblk_groups(int64_t rows) { return nblk(rows * kGroup); }
+// Workgroups of the soil passes: one per kRows rows (one per tile table).
+inline unsigned soil_blocks(int64_t rows) { return (unsigned)((rows + kRows - 1) / kRows); }
 
 }  // namespace
 
@@ -2058,10 +2078,10 @@ hipError_t nbr_count_soil(const int32_t* rows, int64_t rows_cap, const uint64_t*
                           uint32_t* cnt, uint32_t* stash, hipStream_t s) {
   if (rows_cap <= 0) return hipSuccess;
   if (g.cell)
-    k_nbr_count_soil<true><<<nblk_groups(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs, g,
+    k_nbr_count_soil<true><<<soil_blocks(rows_cap), kListBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs, g,
                                                                     tabs, cnt, stash);
   else
-    k_nbr_count_soil<false><<<nblk_groups(rows_cap), kBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs,
+    k_nbr_count_soil<false><<<soil_blocks(rows_cap), kListBlock, 0, s>>>(rows, rows_cap, n_rows_dev, pos4, cpos, skey, cs,
                                                                      g, tabs, cnt, stash);
   return hipGetLastError();
 }
@@ -2137,7 +2157,7 @@ hipError_t nbr_fill_soil(const int32_t* rows, int64_t n_rows, const float4* pos4
                          const uint32_t* stash, const uint64_t* off, uint32_t* nbr, const uint32_t* tabs,
                          uint16_t* tix, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  k_nbr_fill_soil<<<nblk_groups(n_rows), kBlock, 0, s>>>(rows, n_rows, pos4, cpos, skey, cs, g, cnt, stash, off, nbr,
+  k_nbr_fill_soil<<<soil_blocks(n_rows), kListBlock, 0, s>>>(rows, n_rows, pos4, cpos, skey, cs, g, cnt, stash, off, nbr,
                                                          tabs, tix);
   return hipGetLastError();
 }
@@ -2148,13 +2168,13 @@ template <int CFG>
 void launch_stage1(CPlanes A, Planes B, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
                    const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, const uint16_t* tix,
                    hipStream_t s) {
-  const unsigned g = nblk_groups(n);
+  const unsigned g = soil_blocks(n);
   if (P.cell) {
-    if (tape) k_fluid_stage1<true, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
-    else k_fluid_stage1<true, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    if (tape) k_fluid_stage1<true, true, CFG><<<g, kStageBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage1<true, false, CFG><<<g, kStageBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
   } else {
-    if (tape) k_fluid_stage1<false, true, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
-    else k_fluid_stage1<false, false, CFG><<<g, kBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    if (tape) k_fluid_stage1<false, true, CFG><<<g, kStageBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage1<false, false, CFG><<<g, kStageBlock, 0, s>>>(A, B, rows, n, off, nbr, P, T, tabs, tix);
   }
 }
 
@@ -2162,13 +2182,13 @@ template <int CFG>
 void launch_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, const uint64_t* off, const uint32_t* nbr,
                    const Phys& P, const StageTape& T, bool tape, const uint32_t* tabs, const uint16_t* tix,
                    hipStream_t s) {
-  const unsigned g = nblk_groups(n);
+  const unsigned g = soil_blocks(n);
   if (P.cell) {
-    if (tape) k_fluid_stage2<true, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
-    else k_fluid_stage2<true, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    if (tape) k_fluid_stage2<true, true, CFG><<<g, kStageBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage2<true, false, CFG><<<g, kStageBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
   } else {
-    if (tape) k_fluid_stage2<false, true, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
-    else k_fluid_stage2<false, false, CFG><<<g, kBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    if (tape) k_fluid_stage2<false, true, CFG><<<g, kStageBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
+    else k_fluid_stage2<false, false, CFG><<<g, kStageBlock, 0, s>>>(B, A, rows, n, off, nbr, P, T, tabs, tix);
   }
 }
 
