@@ -102,6 +102,10 @@ struct crm_ctx {
   int64_t nbr_f_cap = 0;
   uint16_t* tix_f = nullptr;     // tile positions of the soil entries (nbr_f_cap)
   int64_t tix_f_cap = 0;
+  // nbr_f lacks the slots of the staged blocks with at most this many tile
+  // records (the stages read those blocks from their tiles; 0: nbr_f complete)
+  uint32_t nbr_skip = 0;
+  bool full_lists = false;        // rebuilds write every slot (reverse sweep)
   uint32_t* nbr_m = nullptr;
   int64_t nbr_m_cap = 0;
 
@@ -677,8 +681,12 @@ crm_status rebuild(crm_ctx* c) {
   if (st != CRM_OK) return st;
   c->ent_f = ef;
   c->ent_m = em;
+  // the slots of the blocks the stages read from their tiles are left out
+  // (written on demand by complete_lists)
+  const uint32_t skip = c->full_lists ? 0u : crm::tile_records(c->tile_cfg, c->grid.cell != 0);
   HIPCHK(c, crm::nbr_fill_soil(c->frows, c->n_frows, c->pos4, c->cpos, c->skey, c->cell_start, g, c->cnt_f,
-                               c->stash_f, c->off_f, c->nbr_f, c->tabs, c->tix_f, s));
+                               c->stash_f, c->off_f, c->nbr_f, c->tabs, c->tix_f, skip, s));
+  c->nbr_skip = skip;
   HIPCHK(c, crm::nbr_fill(c->mrows, c->n_mrows, c->pos4, c->cpos, c->skey, c->cell_start, g, true,
                           c->cnt_m, c->stash_m, c->off_m, c->nbr_m, s));
   // every marker row of the new working set placed once (rows that lost or
@@ -697,6 +705,15 @@ crm_status rebuild(crm_ctx* c) {
     HIPCHK(c, crm::fill_u32(c->d_disp, 0u, 1, s));
     c->disp_pending = false;
   }
+  return CRM_OK;
+}
+
+// Writes the slots the last rebuild left out of nbr_f (for the reverse sweep,
+// the exported lists and a change of tile configuration).
+crm_status complete_lists(crm_ctx* c) {
+  if (!c->working_valid || c->nbr_skip == 0) return CRM_OK;
+  HIPCHK(c, crm::nbr_slots(c->n_frows, c->off_f, c->tabs, c->tix_f, c->nbr_f, c->nbr_skip, c->stream));
+  c->nbr_skip = 0;
   return CRM_OK;
 }
 
@@ -1537,6 +1554,13 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
     c->step = c->rec_step0 + c->rec_seg[g];
     return CRM_OK;
   };
+  // the gathers below walk every soil row's slots: the replays' rebuilds write
+  // them all (until this call returns, on every path)
+  struct FullLists {
+    crm_ctx* c;
+    ~FullLists() { c->full_lists = false; }
+  } full_lists_scope{c};
+  c->full_lists = true;
   st = set_bodies_dev(c->rec_bodies);
   if (st != CRM_OK) return done(st);
   const Phys& P = c->phys;
@@ -1884,6 +1908,8 @@ crm_status crm_debug_export(crm_ctx* c, int32_t* sorted_ids, uint32_t* cell_star
   if (st != CRM_OK) return st;
   if (c->rebuilds == 0 || !c->working_valid) return fail(c, CRM_E_STATE, "no valid rebuild to export");
   hipStream_t s = c->stream;
+  st = complete_lists(c);
+  if (st != CRM_OK) return st;
   const int64_t np = c->n_proc;
   std::vector<int32_t> sid((size_t)np);
   HIPCHK(c, hipMemcpyAsync(sid.data(), c->slot_id, sizeof(int32_t) * (size_t)np, hipMemcpyDeviceToHost, s));
@@ -1969,6 +1995,11 @@ crm_status crm_autotune(crm_ctx* c, int32_t config, int32_t* chosen) {
   if (st != CRM_OK) return st;
   if (config > CRM_TILE_LARGE) return fail(c, CRM_E_INVALID, "unknown tile configuration");
   if (config >= 0) {
+    // blocks the new tile cannot hold read their slots through L1
+    if (crm::tile_records(config, c->grid.cell != 0) < c->nbr_skip) {
+      st = complete_lists(c);
+      if (st != CRM_OK) return st;
+    }
     c->tile_cfg = config;
     if (chosen) *chosen = config;
     return CRM_OK;
@@ -1978,7 +2009,10 @@ crm_status crm_autotune(crm_ctx* c, int32_t config, int32_t* chosen) {
     return c->working_valid ? CRM_OK : fail(c, CRM_E_STATE, "autotuning needs a list rebuild (take a step first)");
   }
   // stage 1 writes only y_mid, which the next step recomputes: time it on the
-  // current state with each configuration
+  // current state with each configuration (every slot in nbr_f for the blocks
+  // a configuration reads through L1)
+  st = complete_lists(c);
+  if (st != CRM_OK) return st;
   hipStream_t s = c->stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(c, hipEventCreate(&e0));

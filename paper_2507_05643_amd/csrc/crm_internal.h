@@ -281,12 +281,18 @@ int64_t tile_table_words(int64_t rows_cap);
 hipError_t tile_tables(const int32_t* frows, int64_t rows_cap, const uint64_t* n_frows_dev, const uint32_t* skey,
                        const uint32_t* cell_start, Phys P, uint32_t* tabs, hipStream_t s);
 // The fill pass of the soil rows, which also writes the tile position
-// (16-bit) of each entry of the blocks that can stage their neighbours (one
-// per nbr entry; the other blocks' entries untouched); tabs from tile_tables.
+// (16-bit) of each entry of the blocks the count pass staged (one per nbr
+// entry; the other blocks' entries untouched); tabs from tile_tables. The
+// slots of a staged block whose total is at most skip_cap are left out of
+// nbr (0: every slot written); nbr_slots writes them from the positions.
 hipError_t nbr_fill_soil(const int32_t* frows, int64_t n_frows, const float4* pos4, const int4* cpos,
                          const uint32_t* skey, const uint32_t* cell_start, Grid g, const uint32_t* cnt,
                          const uint32_t* stash, const uint64_t* off, uint32_t* nbr, const uint32_t* tabs,
-                         uint16_t* tix, hipStream_t s);
+                         uint16_t* tix, uint32_t skip_cap, hipStream_t s);
+hipError_t nbr_slots(int64_t n_frows, const uint64_t* off, const uint32_t* tabs, const uint16_t* tix, uint32_t* nbr,
+                     uint32_t skip_cap, hipStream_t s);
+// Records of tile configuration cfg (0 for none).
+uint32_t tile_records(int cfg, bool cell);
 
 // Reverse mode (one stage at a time, see crm_adjoint.hip). Adjoint records use
 // the state's plane layout: a = (x, y, z, rho), b = (u, -), c, d = stress.

@@ -547,6 +547,95 @@ struct ScanLoad {
   __device__ ScanLoad run(int, uint32_t&, uint32_t&) const { return *this; }
 };
 
+// Half-width of the x window of run (dy, dz) for a row at y, z (FP64, from
+// the grid's low corner) in global cell row cy, cz. Every candidate of cell
+// row cy + dy lies beyond the boundary between the two rows: at least
+// e_y = (cy + 1) S - y (dy = 1) or y - cy S (dy = -1) from the row in y, and
+// likewise in z, also where cells are clamped to the grid (a clamped row's
+// gap only grows). A neighbour within R therefore has
+// (x_i - x_j)^2 < R^2 - e_y^2 - e_z^2; the bound is taken with R widened to
+// R' = R (1 + 2^-20) and the gaps shrunk by S 2^-20, far above the FP64
+// rounding of the cell assignment and of the membership test. A run no
+// neighbour can reach gets a negative half-width.
+__device__ inline double run_half_width(int dy, int dz, double y, double z, int32_t cy, int32_t cz, double S) {
+#pragma clang fp contract(off)
+  const double m = S * 0x1p-20;
+  const double Rm = S * (1.0 + 0x1p-20);
+  double ey = dy > 0 ? (double)(cy + 1) * S - y : dy < 0 ? y - (double)cy * S : 0.0;
+  double ez = dz > 0 ? (double)(cz + 1) * S - z : dz < 0 ? z - (double)cz * S : 0.0;
+  ey = ey - m > 0.0 ? ey - m : 0.0;
+  ez = ez - m > 0.0 ? ez - m : 0.0;
+  const double w2 = (Rm * Rm - ey * ey) - ez * ez;
+  return w2 > 0.0 ? sqrt(w2) : -1.0;
+}
+
+// x of slot j in FP64: absolute, or cell index times cell size plus offset.
+template <bool CELL>
+__device__ inline double slot_x(const float4* __restrict__ pos4, const int4* __restrict__ cpos, uint32_t j,
+                                double S) {
+  if constexpr (CELL) return (double)cpos[j].x * S + (double)pos4[j].x;
+  else return (double)pos4[j].x;
+}
+
+// Candidates straight from the planes, each run cut to the row's x window
+// [x_i - W_k, x_i + W_k] (W_k = run_half_width): a run's slots ascend in x
+// (cells in x order, each cell's slots in x order), so two binary searches
+// over its positions give the part that can hold neighbours. Lane l of the
+// row's group narrows runs l and (lane 0) 8 before the scan; run(k) hands the
+// group run k's bounds from the lane that narrowed it.
+template <bool CELL>
+struct ScanNarrowLoad {
+  ScanLoad<CELL> ld;
+  uint32_t b0, e0, b1, e1;         // this lane's runs (gl and gl + 8)
+  __device__ void prepare(bool live, float4 pi, int4 ci, uint32_t c, const uint32_t* __restrict__ cs,
+                          const Grid& g) {
+    const uint32_t X = (uint32_t)g.dims[0], Y = (uint32_t)g.dims[1], Z = (uint32_t)g.dims[2];
+    const int gl = group_lane();
+    b0 = e0 = b1 = e1 = 0;
+    if (!live) return;
+    const int cx = (int)(c % X), cy = (int)((c / X) % Y), cz = (int)(c / (X * Y));
+    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < (int)X - 1 ? cx + 1 : (int)X - 1;
+    const double xi = CELL ? (double)ci.x * g.S + (double)pi.x : (double)pi.x;
+    const double yi = CELL ? (double)ci.y * g.S + (double)pi.y : (double)pi.y - g.lo[1];
+    const double zi = CELL ? (double)ci.z * g.S + (double)pi.z : (double)pi.z - g.lo[2];
+    for (int u = 0; u < 2; ++u) {
+      const int k = gl + kGroup * u;
+      if (k > 8) break;
+      const int z = cz + k / 3 - 1, y = cy + k % 3 - 1;
+      uint32_t b = 0, e = 0;
+      const double w = run_half_width(k % 3 - 1, k / 3 - 1, yi, zi, cy + g.org[1], cz + g.org[2], g.S);
+      if (z >= 0 && z < (int)Z && y >= 0 && y < (int)Y && w >= 0.0) {
+        const double wlo = xi - w, whi = xi + w;
+        const uint32_t row = ((uint32_t)z * Y + (uint32_t)y) * X;
+        b = cs[row + x0];
+        e = cs[row + x1 + 1];
+        uint32_t a = b, z1 = e;     // first slot at or above wlo
+        while (a < z1) {
+          const uint32_t m = a + (z1 - a) / 2;
+          if (slot_x<CELL>(ld.pos4, ld.cpos, m, g.S) < wlo) a = m + 1;
+          else z1 = m;
+        }
+        b = a;
+        uint32_t a2 = b, z2 = e;    // first slot above whi
+        while (a2 < z2) {
+          const uint32_t m = a2 + (z2 - a2) / 2;
+          if (slot_x<CELL>(ld.pos4, ld.cpos, m, g.S) <= whi) a2 = m + 1;
+          else z2 = m;
+        }
+        e = a2;
+      }
+      if (u == 0) { b0 = b; e0 = e; }
+      else { b1 = b; e1 = e; }
+    }
+  }
+  __device__ ScanLoad<CELL> run(int k, uint32_t& b, uint32_t& e) const {
+    const int src = (lane_id() & ~(kGroup - 1)) + (k & (kGroup - 1));
+    b = (uint32_t)__shfl((int)(k < kGroup ? b0 : b1), src);
+    e = (uint32_t)__shfl((int)(k < kGroup ? e0 : e1), src);
+    return ld;
+  }
+};
+
 template <bool FILL, bool CELL, bool SOIL_ONLY, class Load, class Emit>
 __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c, const Load& load,
                                       const uint32_t* __restrict__ cs, const Grid& g, const Emit& emit,
@@ -598,7 +687,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         const uint32_t m = group_bits(__ballot(hit));
         if (FILL && hit) {
           const uint32_t at_ = count + __popc(m & ((1u << gl) - 1u));
-          if (at_ < limit) emit(at_, j);
+          if (at_ < limit) emit(at_, j, k);
         }
         count += __popc(m);
       }
@@ -623,10 +712,36 @@ __device__ inline uint32_t group_scan_any(bool live, float4 pi, int4 ci, uint32_
                    : group_scan<FILL, false, false>(live, pi, ci, c, ld, cs, g, emit, limit);
 }
 
-// Writes entry `at` of a row's list.
+// The same with every run cut to the row's x window (ScanNarrowLoad).
+template <class Emit>
+__device__ inline uint32_t group_scan_narrow(bool live, float4 pi, int4 ci, uint32_t c,
+                                             const float4* __restrict__ pos4, const int4* __restrict__ cpos,
+                                             const uint32_t* __restrict__ cs, const Grid& g, bool soil_only,
+                                             const Emit& emit, uint32_t limit) {
+  if (g.cell) {
+    ScanNarrowLoad<true> ld{{pos4, cpos}, 0, 0, 0, 0};
+    ld.prepare(live, pi, ci, c, cs, g);
+    return soil_only ? group_scan<true, true, true>(live, pi, ci, c, ld, cs, g, emit, limit)
+                     : group_scan<true, true, false>(live, pi, ci, c, ld, cs, g, emit, limit);
+  }
+  ScanNarrowLoad<false> ld{{pos4, cpos}, 0, 0, 0, 0};
+  ld.prepare(live, pi, ci, c, cs, g);
+  return soil_only ? group_scan<true, false, true>(live, pi, ci, c, ld, cs, g, emit, limit)
+                   : group_scan<true, false, false>(live, pi, ci, c, ld, cs, g, emit, limit);
+}
+
+// Writes entry `at` of a row's list (slot j, found in run k).
 struct EmitTo {
   uint32_t* out;
-  __device__ void operator()(uint32_t at, uint32_t j) const { out[at] = j; }
+  __device__ void operator()(uint32_t at, uint32_t j, int) const { out[at] = j; }
+};
+
+// Writes entry `at` as the tile position 16 (j - o_k) of a staged block's cut
+// layout (o: the nine o_k, in LDS).
+struct EmitTilePos {
+  uint16_t* out;
+  const uint32_t* o;
+  __device__ void operator()(uint32_t at, uint32_t j, int k) const { out[at] = (uint16_t)((j - o[k]) << 4); }
 };
 
 // Count pass: counts every row's neighbours and keeps the first kStash of them
@@ -658,7 +773,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(const int32_t* __restrict_
     c = skey[s];
     out = stash + (uint64_t)r * kStash;
   }
-  const uint32_t count = group_scan_any<true>(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, EmitTo{out}, kStash);
+  const uint32_t count = group_scan_narrow(live, pi, ci, c, pos4, cpos, cs, g, soil_only != 0, EmitTo{out}, kStash);
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
 
@@ -1157,10 +1272,13 @@ static_assert(sizeof(StageTile<true, tile_cap<true, 2>()>) <= 54272, "three larg
 // Per block of kRows rows, computed once per list rebuild (k_tile_tables):
 // words 0-8 first slot of each of the nine ranges (~0: outside the grid),
 // 9-17 offset o_k (slot j of range k sits at tile index j - o_k), 18 total
-// records, 19 whether the block's rows lie in one row of cells. A block uses
-// its tile when they do and the total fits the tile. The ranges start as
-// whole cells x_first - 1 .. x_last + 1; the count pass then cuts them to
-// the x interval the block's rows reach (k_nbr_count_soil).
+// records, 19: 0 when the block's rows span two rows of cells, 1 when they lie
+// in one, 2 once the count pass has staged the block, cut its ranges to the x
+// interval its rows reach and kept its entries as tile positions
+// (k_nbr_count_soil). Only blocks marked 2 have tile positions, and a stage
+// uses its tile for such a block when the total fits the tile. The ranges
+// start as whole cells x_first - 1 .. x_last + 1.
+constexpr uint32_t kTabStaged = 2;
 constexpr int kTabWords = 20;
 
 __global__ __launch_bounds__(kBlock) void k_tile_tables(const int32_t* __restrict__ rows,
@@ -1249,15 +1367,14 @@ __device__ inline TileLoad tile_loader(const uint32_t* __restrict__ tb) {
   return l;
 }
 
-// Largest tile (records): blocks whose ranges exceed it never stage.
-constexpr uint32_t kTileMax = 1024;
-
-// The fill pass of the soil rows (the copy of k_nbr_fill, rescans included)
-// that also writes each entry's tile position: 16 i for slot j at tile index
-// i (the record's byte offset in each 16-byte tile plane), for the blocks whose
-// rows lie in one row of cells and whose ranges fit kTileMax records (other
-// blocks' positions are not written). Workgroup b serves the kRows rows of
-// tile table b, so the table is uniform.
+// The fill pass of the soil rows (the copy of k_nbr_fill, rescans included).
+// The count pass keeps a staged block's entries as tile positions, 16 i for
+// slot j at tile index i (the record's byte offset in each 16-byte tile
+// plane), in 16-bit words: they are copied to `tix`, and the slots are written
+// to `nbr` only where a stage may read the block through L1, i.e. when its
+// total exceeds skip_cap (the tile of the context's configuration; 0 writes
+// every slot). Other blocks' entries are slots, copied to `nbr`. Workgroup b
+// serves the kRows rows of tile table b, so the table is uniform.
 __global__ __launch_bounds__(kListBlock) void k_nbr_fill_soil(const int32_t* __restrict__ rows, int64_t n_rows,
                                                           const float4* __restrict__ pos4,
                                                           const int4* __restrict__ cpos,
@@ -1267,32 +1384,50 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_fill_soil(const int32_t* __r
                                                           const uint32_t* __restrict__ stash,
                                                           const uint64_t* __restrict__ off, uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ tabs,
-                                                          uint16_t* __restrict__ tix) {
+                                                          uint16_t* __restrict__ tix, uint32_t skip_cap) {
   const int64_t blk = xcd_block();
   const int64_t r = (blk * kListBlock + threadIdx.x) / kGroup;
   const bool live = r < n_rows;
   const uint32_t* tb = tabs + blk * kTabWords;
-  const bool tiled = tb[19] != 0 && tb[18] <= kTileMax;
+  const bool tiled = tb[19] == kTabStaged;
+  const bool slots = !tiled || tb[18] > skip_cap;
   const TileLoad ld = tile_loader(tb);
   const uint32_t count = live ? cnt[r] : 0u;
+  const bool rescan = count > kStash;                 // uniform within the group
   // all of the lane's stash words are loaded at once, without waiting for the
   // count (the words past it are read but never stored)
   constexpr int kPer = (int)(kStash / kGroup);
-  uint32_t v[kPer];
-  if (live) {
-    const uint32_t* src = stash + (uint64_t)r * kStash;
+  if (tiled) {
+    uint32_t v[kPer];
+    if (live) {
+      const uint16_t* src = reinterpret_cast<const uint16_t*>(stash + (uint64_t)r * kStash);
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) v[q] = src[(uint32_t)group_lane() + (uint32_t)(q * kGroup)];
-  }
-  const bool rescan = count > kStash;                 // uniform within the group
-  if (live && !rescan) {
-    const uint64_t base = off[r];
+      for (int q = 0; q < kPer; ++q) v[q] = src[(uint32_t)group_lane() + (uint32_t)(q * kGroup)];
+    }
+    if (live && !rescan) {
+      const uint64_t base = off[r];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
-      if (k < count) {
-        nbr[base + k] = v[q];
-        if (tiled) tix[base + k] = (uint16_t)(ld.index(v[q]) << 4);
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+        if (k < count) {
+          tix[base + k] = (uint16_t)v[q];
+          if (slots) nbr[base + k] = ld.slot(v[q] >> 4);
+        }
+      }
+    }
+  } else {
+    uint32_t v[kPer];
+    if (live) {
+      const uint32_t* src = stash + (uint64_t)r * kStash;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) v[q] = src[(uint32_t)group_lane() + (uint32_t)(q * kGroup)];
+    }
+    if (live && !rescan) {
+      const uint64_t base = off[r];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t k = (uint32_t)group_lane() + (uint32_t)(q * kGroup);
+        if (k < count) nbr[base + k] = v[q];
       }
     }
   }
@@ -1301,12 +1436,29 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_fill_soil(const int32_t* __r
     const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
     uint32_t* nb = nbr + off[r];
     uint16_t* tx = tix + off[r];
-    auto emit = [&](uint32_t at, uint32_t j) {
+    auto emit = [&](uint32_t at, uint32_t j, int) {
       nb[at] = j;
       if (tiled) tx[at] = (uint16_t)(ld.index(j) << 4);
     };
     group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, false, emit, 0xffffffffu);
   }
+}
+
+// The slots of the entries k_nbr_fill_soil left out (staged blocks whose total
+// is at most skip_cap), from their tile positions: for the reverse sweep, the
+// exported lists, and stages with a smaller tile or none.
+__global__ __launch_bounds__(kListBlock) void k_nbr_slots(int64_t n_rows, const uint64_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ tabs,
+                                                      const uint16_t* __restrict__ tix, uint32_t* __restrict__ nbr,
+                                                      uint32_t skip_cap) {
+  const int64_t blk = xcd_block();
+  const uint32_t* tb = tabs + blk * kTabWords;
+  if (tb[19] != kTabStaged || tb[18] > skip_cap) return;    // uniform over the block
+  const int64_t r = (blk * kListBlock + threadIdx.x) / kGroup;
+  if (r >= n_rows) return;
+  const TileLoad ld = tile_loader(tb);
+  const uint64_t k1 = off[r + 1];
+  for (uint64_t k = off[r] + (uint64_t)group_lane(); k < k1; k += kGroup) nbr[k] = ld.slot((uint32_t)tix[k] >> 4);
 }
 
 // ------------------------------------------- LDS-staged neighbour count ---
@@ -1370,7 +1522,10 @@ __device__ inline double tile_x(const ScanTile<CELL>& T, uint32_t t, double S) {
 // cell of a run can hold slots below it and only the last cell slots above
 // it, each in x order, so two binary searches in LDS give the run's part.
 // Lane l of the row's group narrows runs l and (lane 0) 8 before the scan;
-// run(k) hands the group run k's bounds from the lane that narrowed it.
+// run(k) hands the group run k's bounds from the lane that narrowed it. (The
+// per-run windows of ScanNarrowLoad do not pay here: the eight rows of a wave
+// lie anywhere in y and z within their cell, so the wave still steps through
+// each run as long as its longest row needs, and the searches get longer.)
 template <bool CELL>
 struct ScanRowLoad {
   const ScanTile<CELL>* T;
@@ -1454,6 +1609,7 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_count_soil(const int32_t* __
   __shared__ ScanTile<CELL> tile;
   __shared__ uint32_t rt[27];     // run table: o_k of the staged layout, cut bounds lo_k, hi_k
   __shared__ uint32_t ct[36];     // per range: first slot, o_k, leading cut, trailing cut
+  __shared__ uint32_t os[9];      // o_k of the cut layout (the stage kernels' tiles)
   __shared__ unsigned long long xext[2];   // order keys of the rows' x extremes
   const int64_t nr = (int64_t)*n_rows_dev;
   const int64_t nb_live = (nr + kRows - 1) / kRows;
@@ -1576,12 +1732,15 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_count_soil(const int32_t* __
           rt[m] = ct[9 + m];
           rt[9 + m] = nlo[m];
           rt[18 + m] = nhi[m];
+          os[m] = 0;
           if (ct[m] == 0xffffffffu) continue;
           tb[m] = nlo[m];
           tb[9 + m] = nlo[m] - acc;
+          os[m] = nlo[m] - acc;
           acc += nhi[m] - nlo[m];
         }
         tb[18] = acc;
+        tb[19] = kTabStaged;
       }
     }
     __syncthreads();
@@ -1590,9 +1749,13 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_count_soil(const int32_t* __
   if (staged) {
     ScanRowLoad<CELL> tl{&tile, rt, 0, 0, 0, 0};
     tl.prepare(live, pi, ci, c, cs, g);
-    count = group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g, EmitTo{out}, kStash);
+    // the row's entries as 16-bit tile positions of the cut layout
+    count = group_scan<true, CELL, false>(live, pi, ci, c, tl, cs, g,
+                                          EmitTilePos{reinterpret_cast<uint16_t*>(out), os}, kStash);
   } else {
-    count = group_scan<true, CELL, false>(live, pi, ci, c, ScanLoad<CELL>{pos4, cpos}, cs, g, EmitTo{out}, kStash);
+    ScanNarrowLoad<CELL> nl{{pos4, cpos}, 0, 0, 0, 0};
+    nl.prepare(live, pi, ci, c, cs, g);
+    count = group_scan<true, CELL, false>(live, pi, ci, c, nl, cs, g, EmitTo{out}, kStash);
   }
   if (r < rows_cap && group_lane() == 0) cnt[r] = live ? count : 0u;
 }
@@ -1720,8 +1883,9 @@ template <bool CELL, uint32_t CAP>
 __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint32_t* __restrict__ tb,
                                   const TileLoad& ld, float m) {
   static_assert(CAP <= 4 * kStageBlock, "four records per thread");
+  static_assert(CAP <= scan_cap<CELL>(), "a tile holds at most the count pass's staged records");
   const uint32_t total = tb[18];
-  const bool ok = tb[19] != 0 && total <= CAP;
+  const bool ok = tb[19] == kTabStaged && total <= CAP;
   if (ok) {
     const uint32_t t0 = threadIdx.x;
     const Rec r0 = rec_load<CELL>(S, ld, t0, total);
@@ -2155,11 +2319,24 @@ hipError_t tile_tables(const int32_t* rows, int64_t rows_cap, const uint64_t* n_
 hipError_t nbr_fill_soil(const int32_t* rows, int64_t n_rows, const float4* pos4, const int4* cpos,
                          const uint32_t* skey, const uint32_t* cs, Grid g, const uint32_t* cnt,
                          const uint32_t* stash, const uint64_t* off, uint32_t* nbr, const uint32_t* tabs,
-                         uint16_t* tix, hipStream_t s) {
+                         uint16_t* tix, uint32_t skip_cap, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   k_nbr_fill_soil<<<soil_blocks(n_rows), kListBlock, 0, s>>>(rows, n_rows, pos4, cpos, skey, cs, g, cnt, stash, off, nbr,
-                                                         tabs, tix);
+                                                             tabs, tix, skip_cap);
   return hipGetLastError();
+}
+
+hipError_t nbr_slots(int64_t n_rows, const uint64_t* off, const uint32_t* tabs, const uint16_t* tix, uint32_t* nbr,
+                     uint32_t skip_cap, hipStream_t s) {
+  if (n_rows <= 0 || skip_cap == 0) return hipSuccess;
+  k_nbr_slots<<<soil_blocks(n_rows), kListBlock, 0, s>>>(n_rows, off, tabs, tix, nbr, skip_cap);
+  return hipGetLastError();
+}
+
+uint32_t tile_records(int cfg, bool cell) {
+  if (cfg == 1) return cell ? tile_cap<true, 1>() : tile_cap<false, 1>();
+  if (cfg == 2) return cell ? tile_cap<true, 2>() : tile_cap<false, 2>();
+  return 0;
 }
 
 int64_t tile_table_words(int64_t rows_cap) { return ((rows_cap + kRows - 1) / kRows + 1) * kTabWords; }
