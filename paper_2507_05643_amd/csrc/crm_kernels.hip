@@ -664,6 +664,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         e = cs[row + x1 + 1];
       }
       const auto run = load.run(k, b, e);
+      const auto put = emit.run(k);
       for (uint32_t j0 = b; j0 < e; j0 += kGroup) {
         const uint32_t j = j0 + gl;
         bool hit = false;
@@ -687,7 +688,7 @@ __device__ inline uint32_t group_scan(bool live, float4 pi, int4 ci, uint32_t c,
         const uint32_t m = group_bits(__ballot(hit));
         if (FILL && hit) {
           const uint32_t at_ = count + __popc(m & ((1u << gl) - 1u));
-          if (at_ < limit) emit(at_, j, k);
+          if (at_ < limit) put(at_, j);
         }
         count += __popc(m);
       }
@@ -730,18 +731,25 @@ __device__ inline uint32_t group_scan_narrow(bool live, float4 pi, int4 ci, uint
                    : group_scan<true, false, false>(live, pi, ci, c, ld, cs, g, emit, limit);
 }
 
-// Writes entry `at` of a row's list (slot j, found in run k).
+// Writes entry `at` of a row's list (slot j). run(k) gives the writer of the
+// entries found in run k.
 struct EmitTo {
   uint32_t* out;
-  __device__ void operator()(uint32_t at, uint32_t j, int) const { out[at] = j; }
+  __device__ void operator()(uint32_t at, uint32_t j) const { out[at] = j; }
+  __device__ EmitTo run(int) const { return *this; }
 };
 
 // Writes entry `at` as the tile position 16 (j - o_k) of a staged block's cut
-// layout (o: the nine o_k, in LDS).
+// layout (o: the nine o_k, in LDS, read once per run).
 struct EmitTilePos {
   uint16_t* out;
   const uint32_t* o;
-  __device__ void operator()(uint32_t at, uint32_t j, int k) const { out[at] = (uint16_t)((j - o[k]) << 4); }
+  struct Run {
+    uint16_t* out;
+    uint32_t ok;
+    __device__ void operator()(uint32_t at, uint32_t j) const { out[at] = (uint16_t)((j - ok) << 4); }
+  };
+  __device__ Run run(int k) const { return Run{out, o[k]}; }
 };
 
 // Count pass: counts every row's neighbours and keeps the first kStash of them
@@ -1436,11 +1444,19 @@ __global__ __launch_bounds__(kListBlock) void k_nbr_fill_soil(const int32_t* __r
     const int4 ci = g.cell ? cpos[s] : make_int4(0, 0, 0, 0);
     uint32_t* nb = nbr + off[r];
     uint16_t* tx = tix + off[r];
-    auto emit = [&](uint32_t at, uint32_t j, int) {
-      nb[at] = j;
-      if (tiled) tx[at] = (uint16_t)(ld.index(j) << 4);
+    struct EmitBoth {
+      uint32_t* nb;
+      uint16_t* tx;
+      const TileLoad* ld;
+      bool tiled;
+      __device__ void operator()(uint32_t at, uint32_t j) const {
+        nb[at] = j;
+        if (tiled) tx[at] = (uint16_t)(ld->index(j) << 4);
+      }
+      __device__ EmitBoth run(int) const { return *this; }
     };
-    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, false, emit, 0xffffffffu);
+    group_scan_any<true>(true, pos4[s], ci, skey[s], pos4, cpos, cs, g, false, EmitBoth{nb, tx, &ld, tiled},
+                         0xffffffffu);
   }
 }
 
