@@ -416,7 +416,25 @@ __global__ __launch_bounds__(kBlock) void k_hash_count(const int32_t* __restrict
   }
   uint32_t c = ((uint32_t)cz * (uint32_t)g.dims[1] + (uint32_t)cy) * (uint32_t)g.dims[0] + (uint32_t)cx;
   key[k] = c;
-  rank[k] = atomicAdd(&cnt[c], 1u);
+  // the lanes of the wave that share a cell take one atomic between them: the
+  // lowest lane of each set adds the set's size, and each lane's rank is the
+  // returned base plus its place in the set (the order inside a cell is the
+  // gather's x order, whatever the ranks)
+  uint64_t todo = __ballot(1);
+  uint64_t mine = 0;
+  while (todo) {                                        // once per distinct cell
+    const int lead = __builtin_ctzll(todo);
+    const uint32_t lc = (uint32_t)__shfl((int)c, lead);
+    const uint64_t set = __ballot(c == lc) & todo;
+    if (c == lc) mine = set;
+    todo &= ~set;
+  }
+  const int lane = (int)lane_id();
+  const int first = __builtin_ctzll(mine);
+  uint32_t base = 0;
+  if (lane == first) base = atomicAdd(&cnt[c], (uint32_t)__popcll(mine));
+  base = (uint32_t)__shfl((int)base, first);
+  rank[k] = base + (uint32_t)__popcll(mine & lanemask_lt());
 }
 
 // Order-preserving maps of FP32 / FP64 values onto unsigned integers (total
@@ -501,7 +519,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(
   uint32_t kind = (id < n_soil) ? ((flags == nullptr || flags[id] == 2) ? kSoilActive : kSoilExtended) : kMarker;
   b.w = __uint_as_float(aux | kind);
   A.a[f] = a; A.b[f] = b; A.c[f] = cc; A.d[f] = d;
-  B.a[f] = a; B.b[f] = b; B.c[f] = cc; B.d[f] = d;
+  // stage 1 writes an active soil row's midpoint record before anything reads
+  // it; extended soil rows and markers keep y_n there
+  if (kind != kSoilActive) {
+    B.a[f] = a; B.b[f] = b; B.c[f] = cc; B.d[f] = d;
+  }
   pos4[f] = make_float4(a.x, a.y, a.z, b.w);
   if (cell) {
     const uint32_t w = __float_as_uint(d.w);
