@@ -1877,22 +1877,20 @@ struct Rec {
   float4 a, b, c, d;
 };
 
+// Record t of the block's ranges (a thread past the total reads record 0
+// again, which it does not store: no default values to set up).
 template <bool CELL>
 __device__ inline Rec rec_load(CPlanes S, const TileLoad& ld, uint32_t t, uint32_t total) {
   Rec r;
-  if (t < total) {
-    const uint32_t j = ld.slot(t);
-    r.a = S.a[j];
-    r.b = S.b[j];
-    r.c = S.c[j];
-    if constexpr (CELL) {
-      r.d = S.d[j];
-    } else {                       // sigma_xz, sigma_yz: the tile keeps no more of plane d
-      const float2 d2 = *reinterpret_cast<const float2*>(&S.d[j]);
-      r.d = make_float4(d2.x, d2.y, 0.f, 0.f);
-    }
-  } else {
-    r.a = r.b = r.c = r.d = make_float4(0.f, 0.f, 0.f, 0.f);
+  const uint32_t j = ld.slot(t < total ? t : 0u);
+  r.a = S.a[j];
+  r.b = S.b[j];
+  r.c = S.c[j];
+  if constexpr (CELL) {
+    r.d = S.d[j];
+  } else {                         // sigma_xz, sigma_yz: the tile keeps no more of plane d
+    const float2 d2 = *reinterpret_cast<const float2*>(&S.d[j]);
+    r.d = make_float4(d2.x, d2.y, 0.f, 0.f);
   }
   return r;
 }
@@ -1925,15 +1923,18 @@ __device__ inline bool stage_tile(StageTile<CELL, CAP>& T, CPlanes S, const uint
   const uint32_t total = tb[18];
   const bool ok = tb[19] == kTabStaged && total <= CAP;
   if (ok) {
+    // the third and fourth rounds only where the total reaches them (uniform)
     const uint32_t t0 = threadIdx.x;
+    const bool has2 = total > 2 * kStageBlock, has3 = total > 3 * kStageBlock;
     const Rec r0 = rec_load<CELL>(S, ld, t0, total);
     const Rec r1 = rec_load<CELL>(S, ld, t0 + kStageBlock, total);
-    const Rec r2 = rec_load<CELL>(S, ld, t0 + 2 * kStageBlock, total);
-    const Rec r3 = rec_load<CELL>(S, ld, t0 + 3 * kStageBlock, total);
+    Rec r2, r3;
+    if (has2) r2 = rec_load<CELL>(S, ld, t0 + 2 * kStageBlock, total);
+    if (has3) r3 = rec_load<CELL>(S, ld, t0 + 3 * kStageBlock, total);
     rec_store(T, r0, t0, total, m);
     rec_store(T, r1, t0 + kStageBlock, total, m);
-    rec_store(T, r2, t0 + 2 * kStageBlock, total, m);
-    rec_store(T, r3, t0 + 3 * kStageBlock, total, m);
+    if (has2) rec_store(T, r2, t0 + 2 * kStageBlock, total, m);
+    if (has3) rec_store(T, r3, t0 + 3 * kStageBlock, total, m);
   }
   __syncthreads();
   return ok;
@@ -2012,15 +2013,13 @@ __global__ __launch_bounds__(kStageBlock) void k_fluid_stage1(CPlanes A, Planes 
   const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
   const int gl = group_lane<kSG>();
   const bool live = r < n;
-  int32_t s = 0;
-  uint64_t k0 = 0, k1 = 0;
-  float4 ma = make_float4(0.f, 0.f, 0.f, 1.f), mb = make_float4(0.f, 0.f, 0.f, 0.f), mc = mb, md = mb;
-  if (live) {
-    s = rows[r];
-    ma = A.a[s]; mb = A.b[s]; mc = A.c[s]; md = A.d[s];
-    k0 = off[r];
-    k1 = off[r + 1];
-  }
+  // a group past the last row reads the last row (no default values to set
+  // up), walks no entries and stores nothing
+  const int64_t rr = live ? r : n - 1;
+  const int32_t s = rows[rr];
+  const float4 ma = A.a[s], mb = A.b[s], mc = A.c[s], md = A.d[s];
+  const uint64_t k0 = off[rr];
+  const uint64_t k1 = live ? off[rr + 1] : k0;
   const uint32_t* tb = tabs + blk * kTabWords;
   const TileLoad tl = tile_loader(tb);
   const bool staged = CFG != 0 && stage_tile(tile, A, tb, tl, P.m);
@@ -2056,17 +2055,14 @@ __global__ __launch_bounds__(kStageBlock) void k_fluid_stage2(CPlanes B, Planes 
   const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
   const int gl = group_lane<kSG>();
   const bool live = r < n;
-  int32_t s = 0;
-  uint64_t k0 = 0, k1 = 0;
-  float4 ma = make_float4(0.f, 0.f, 0.f, 1.f), mb = make_float4(0.f, 0.f, 0.f, 0.f), mc = mb, md = mb;
-  float4 ya = mb, yb = mb, yc = mb, yd = mb;
-  if (live) {
-    s = rows[r];
-    ma = B.a[s]; mb = B.b[s]; mc = B.c[s]; md = B.d[s];
-    ya = A.a[s]; yb = A.b[s]; yc = A.c[s]; yd = A.d[s];
-    k0 = off[r];
-    k1 = off[r + 1];
-  }
+  // a group past the last row reads the last row (no default values to set
+  // up), walks no entries and stores nothing
+  const int64_t rr = live ? r : n - 1;
+  const int32_t s = rows[rr];
+  const float4 ma = B.a[s], mb = B.b[s], mc = B.c[s], md = B.d[s];
+  const float4 ya = A.a[s], yb = A.b[s], yc = A.c[s], yd = A.d[s];
+  const uint64_t k0 = off[rr];
+  const uint64_t k1 = live ? off[rr + 1] : k0;
   const uint32_t* tb = tabs + blk * kTabWords;
   const TileLoad tl = tile_loader(tb);
   const bool staged = CFG != 0 && stage_tile(tile, B, tb, tl, P.m);
