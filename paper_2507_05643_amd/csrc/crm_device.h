@@ -234,10 +234,10 @@ __device__ inline void walk_row_with(const Load& load, uint64_t k0, uint64_t k1,
   }
 }
 
-template <class Fn>
+template <int G = kGroup, class Fn>
 __device__ inline void walk_row(const CPlanes& S, uint64_t k0, uint64_t k1, const uint32_t* __restrict__ nbr,
                                 Fn&& f) {
-  walk_row_with(GlobalLoad{S}, k0, k1, nbr, f);
+  walk_row_with<G>(GlobalLoad{S}, k0, k1, nbr, f);
 }
 
 // Own position of a row for pair separations: coordinates (FP32 absolute) or

@@ -938,14 +938,19 @@ __global__ __launch_bounds__(kBlock) void k_near_rows(const int32_t* __restrict_
 // With `contrib`, the marker acceleration from the momentum equation over the
 // soil neighbours (no body force) and the marker's force and torque on its
 // body, at entry cidx[s] - cbase (the marker's rank among the processed
-// markers in id order).
+// markers in id order). A marker row (~30 soil neighbours) takes a group of
+// kBG lanes; sixteen lanes, one two-entry step per row instead of two, made
+// both passes ~25 % slower (the per-row FP64 tail then costs twice as many
+// waves).
+constexpr int kBG = kGroup;
+
 template <bool FORCE, bool CELL>
 __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restrict__ rows, int64_t n,
                                                 const uint32_t* __restrict__ nbr,
                                                 const Body* __restrict__ bodies, const int32_t* __restrict__ cidx,
                                                 int64_t cbase, Phys P, double* __restrict__ contrib) {
-  const int64_t i = (xcd_block() * kBlock + threadIdx.x) / kGroup;
-  const int gl = group_lane();
+  const int64_t i = (xcd_block() * kBlock + threadIdx.x) / kBG;
+  const int gl = group_lane<kBG>();
   const bool live = i < n;
   int body = -1;
   int32_t s = 0;
@@ -965,7 +970,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
   float sw = 0.f, su0 = 0.f, su1 = 0.f, su2 = 0.f;
   float ss0 = 0.f, ss1 = 0.f, ss2 = 0.f, ss3 = 0.f, ss4 = 0.f, ss5 = 0.f;
   float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f;
-  walk_row(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+  walk_row<kBG>(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
     float dx, dy, dz;
     pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
     const float q = fsqrt(dx * dx + dy * dy + dz * dz) * P.inv_h;
@@ -977,11 +982,11 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
     const float rw = o.a.w * w;
     sr0 += rw * dx; sr1 += rw * dy; sr2 += rw * dz;
   });
-  sw = group_sum(sw);
-  su0 = group_sum(su0); su1 = group_sum(su1); su2 = group_sum(su2);
-  ss0 = group_sum(ss0); ss1 = group_sum(ss1); ss2 = group_sum(ss2);
-  ss3 = group_sum(ss3); ss4 = group_sum(ss4); ss5 = group_sum(ss5);
-  sr0 = group_sum(sr0); sr1 = group_sum(sr1); sr2 = group_sum(sr2);
+  sw = group_sum<kBG>(sw);
+  su0 = group_sum<kBG>(su0); su1 = group_sum<kBG>(su1); su2 = group_sum<kBG>(su2);
+  ss0 = group_sum<kBG>(ss0); ss1 = group_sum<kBG>(ss1); ss2 = group_sum<kBG>(ss2);
+  ss3 = group_sum<kBG>(ss3); ss4 = group_sum<kBG>(ss4); ss5 = group_sum<kBG>(ss5);
+  sr0 = group_sum<kBG>(sr0); sr1 = group_sum<kBG>(sr1); sr2 = group_sum<kBG>(sr2);
   double rv[3] = {0.0, 0.0, 0.0};
   float us[3] = {0.f, 0.f, 0.f}, sg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (live) {
@@ -1015,7 +1020,7 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
     // neighbours only: a_s = (1/rho_s) sum V_f (s_s + s_f) gradW + Pi.
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
     const float rhos = live ? ma.w : 1.0f;
-    walk_row(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
+    walk_row<kBG>(CPlanes(S), k0, k1, nbr, [&](const Nbr& o, uint32_t) {
       float dx, dy, dz;
       pair_sep<CELL>(me, o, P.Sf, dx, dy, dz);
       const float r2 = dx * dx + dy * dy + dz * dz;
@@ -1033,8 +1038,8 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
       const float cf = av ? P.av_coef * vr * F * __builtin_amdgcn_rcpf(0.5f * (rhos + o.a.w) * (r2 + P.xi2)) : 0.f;
       v0 += cf * dx; v1 += cf * dy; v2 += cf * dz;
     });
-    a0 = group_sum(a0); a1 = group_sum(a1); a2 = group_sum(a2);
-    v0 = group_sum(v0); v1 = group_sum(v1); v2 = group_sum(v2);
+    a0 = group_sum<kBG>(a0); a1 = group_sum<kBG>(a1); a2 = group_sum<kBG>(a2);
+    v0 = group_sum<kBG>(v0); v1 = group_sum<kBG>(v1); v2 = group_sum<kBG>(v2);
     if (live && gl == 0) {
       // force and torque of this marker on its body, by marker id
       const float ir = 1.0f / rhos;
@@ -2316,7 +2321,7 @@ hipError_t near_rows(const int32_t* mrows, const int32_t* near, int64_t n, const
 hipError_t bce(Planes S, const NearRow* rows, int64_t n, const uint32_t* nbr, const Body* bodies,
                const int32_t* cidx, int64_t cbase, Phys P, double* contrib, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const unsigned gsz = nblk_groups(n);
+  const unsigned gsz = nblk(n * kBG);
   if (P.cell) {
     if (contrib)
       k_bce<true, true><<<gsz, kBlock, 0, s>>>(S, rows, n, nbr, bodies, cidx, cbase, P, contrib);
