@@ -952,21 +952,24 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
   const int64_t i = (xcd_block() * kBlock + threadIdx.x) / kBG;
   const int gl = group_lane<kBG>();
   const bool live = i < n;
-  int body = -1;
-  int32_t s = 0;
-  float4 ma = make_float4(0.f, 0.f, 0.f, 0.f), mb = ma, md = ma;
-  uint64_t k0 = 0, k1 = 0;
-  if (live) {
-    const NearRow nr = rows[i];
-    s = nr.s;
-    ma = S.a[s];
-    mb = S.b[s];
-    if (CELL) md = S.d[s];
-    body = (int)(__float_as_uint(mb.w) >> 2);
-    k0 = nr.k0;
-    k1 = nr.k0 + nr.n;
-  }
+  // a group past the last row reads the last row, walks no entries and
+  // stores nothing
+  const NearRow nr = rows[live ? i : n - 1];
+  const int32_t s = nr.s;
+  const float4 ma = S.a[s], mb = S.b[s];
+  const float4 md = CELL ? S.d[s] : ma;     // the cells (cell-offset positions only)
+  const int body = (int)(__float_as_uint(mb.w) >> 2);
+  const uint64_t k0 = nr.k0, k1 = live ? nr.k0 + nr.n : nr.k0;
   const Own me = own_pos<CELL>(ma, md);
+  // body velocity and acceleration at the marker (FP64 lever arm), before the
+  // walk, so that the body record's loads and the FP64 work overlap it
+  double rv[3];
+  float ub[3], as[3];
+  {
+    const Body& Bd = bodies[body];
+    marker_arm<CELL>(me, Bd, P, rv);
+    body_motion(Bd, rv, ub, as);
+  }
   float sw = 0.f, su0 = 0.f, su1 = 0.f, su2 = 0.f;
   float ss0 = 0.f, ss1 = 0.f, ss2 = 0.f, ss3 = 0.f, ss4 = 0.f, ss5 = 0.f;
   float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f;
@@ -987,14 +990,8 @@ __global__ __launch_bounds__(kBlock) void k_bce(Planes S, const NearRow* __restr
   ss0 = group_sum<kBG>(ss0); ss1 = group_sum<kBG>(ss1); ss2 = group_sum<kBG>(ss2);
   ss3 = group_sum<kBG>(ss3); ss4 = group_sum<kBG>(ss4); ss5 = group_sum<kBG>(ss5);
   sr0 = group_sum<kBG>(sr0); sr1 = group_sum<kBG>(sr1); sr2 = group_sum<kBG>(sr2);
-  double rv[3] = {0.0, 0.0, 0.0};
   float us[3] = {0.f, 0.f, 0.f}, sg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (live) {
-    const Body& Bd = bodies[body];
-    // body velocity and acceleration at the marker (FP64 lever arm)
-    marker_arm<CELL>(me, Bd, P, rv);
-    float ub[3], as[3];
-    body_motion(Bd, rv, ub, as);
     if (sw > 0.f) {
       const float iw = 1.0f / sw;
       const float gd = ((P.gx - as[0]) * sr0 + (P.gy - as[1]) * sr1) + (P.gz - as[2]) * sr2;
