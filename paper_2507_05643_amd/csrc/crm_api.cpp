@@ -56,6 +56,7 @@ struct crm_ctx {
   float4 *m_a = nullptr, *m_b = nullptr, *m_c = nullptr, *m_d = nullptr;
   float4* local = nullptr;     // markers: (lx, ly, lz, body bits)
   uint8_t* flags = nullptr;
+  uint32_t* m_key = nullptr;      // the activity pre-test's compact positions (active domains only)
   int32_t* proc_ids = nullptr;
   Body* d_bodies = nullptr;
   float4* d_mat = nullptr;     // material table
@@ -509,6 +510,7 @@ crm_status place_master_markers(crm_ctx* c) {
     const bool moved = c->place_all || std::memcmp(B.X, Q.X, sizeof(B.X)) != 0 || std::memcmp(B.R, Q.R, sizeof(B.R)) != 0;
     if (!moved) continue;
     HIPCHK(c, crm::place_markers_master(c->local, bs[b], bs[b + 1], c->n_soil, c->d_bodies, c->grid, c->m_a, c->m_d,
+                                        c->m_key,
                                         c->stream));
     c->placed[b] = B;
   }
@@ -578,7 +580,8 @@ Grid rebuild_grid(const crm_ctx* c, int64_t& cells) {
 // read in between.
 crm_status scatter_back(crm_ctx* c) {
   hipStream_t s = c->stream;
-  HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, s));
+  HIPCHK(c, crm::scatter_rows(c->A, c->frows, c->n_frows, c->slot_id, c->m_a, c->m_b, c->m_c, c->m_d, c->m_key,
+                              c->grid.cell != 0, s));
   HIPCHK(c, crm::scatter_marker_rows(c->B, c->mrows, c->n_mrows, c->slot_id, c->m_b, c->m_c, c->m_d, s));
   return CRM_OK;
 }
@@ -616,7 +619,24 @@ crm_status rebuild(crm_ctx* c) {
   int64_t n_proc = c->n_total;
   if (c->ad_on) {
     hipEvent_t ea = prof_begin(c, 7);
-    HIPCHK(c, crm::activity_count(c->m_a, c->m_d, c->n_total, c->d_bodies, c->nb, c->grid, c->flags, c->ctmp, s));
+    crm::ActUnion un;
+    for (int k = 0; k < 3; ++k) {
+      un.flo[k] = INFINITY;
+      un.fhi[k] = -INFINITY;
+      un.clo[k] = INT32_MAX;
+      un.chi[k] = INT32_MIN;
+    }
+    for (const Body& B : c->h_bodies) {
+      if (!B.has_box) continue;
+      for (int k = 0; k < 3; ++k) {
+        un.flo[k] = std::min(un.flo[k], B.flo[k]);
+        un.fhi[k] = std::max(un.fhi[k], B.fhi[k]);
+        un.clo[k] = std::min(un.clo[k], B.clo[k]);
+        un.chi[k] = std::max(un.chi[k], B.chi[k]);
+      }
+    }
+    HIPCHK(c, crm::activity_count(c->m_a, c->m_d, c->m_key, c->n_total, c->d_bodies, c->nb, un, c->grid, c->flags,
+                                  c->ctmp, s));
     prof_end(c, 7, ea);
     HIPCHK(c, crm::compact_counted(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
     crm_status st = read_counts(c);
@@ -1176,6 +1196,8 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
             alloc_n(c, c->cell_tmp, (int64_t)crm::scan_tmp_elems(M)) && alloc_n(c, c->d_counts, 8) &&
             alloc_n(c, c->d_mat, crm::kMaxMaterials) && alloc_n(c, c->contrib, 6 * nm) &&
             alloc_n(c, c->d_bstart, n_bodies + 1);
+  if (ok && params->active_domains)
+    ok = alloc_n(c, c->m_key, n_total * crm::key_words(c->grid.cell != 0));
   if (!ok) {
     release(c);
     return fail(nullptr, CRM_E_NOMEM, "device allocation failed");
@@ -1218,6 +1240,7 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   if (e == hipSuccess) e = hipMemcpyAsync(c->m_b, hb.data(), f4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->m_c, hc.data(), f4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->m_d, hd.data(), f4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = crm::key_fill(c->m_a, c->m_d, n_total, c->grid.cell != 0, c->m_key, s);
   if (e == hipSuccess && nm > 0)
     e = hipMemcpyAsync(c->local, hl.data(), sizeof(float4) * (size_t)nm, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -1548,6 +1571,7 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
     float4* dst[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
     for (int q = 0; q < 4; ++q)
       HIPCHK(c, hipMemcpyAsync(dst[q], src + q * n, sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, crm::key_fill(c->m_a, c->m_d, (int64_t)n, c->grid.cell != 0, c->m_key, s));
     c->working_valid = false;
     c->force_rebuild = true;
     c->place_all = true;
@@ -1754,6 +1778,7 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
     HIPCHK(c, hipMemcpyAsync(c->m_b, hb.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->m_c, hc.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->m_d, hd.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, crm::key_fill(c->m_a, c->m_d, n, c->grid.cell != 0, c->m_key, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
   c->working_valid = false;
@@ -1858,6 +1883,7 @@ crm_status crm_load_checkpoint(crm_ctx* c, const void* buf, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(s));
   float4* planes[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
   for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(planes[q], o + q * pl, pl, hipMemcpyHostToDevice, s));
+  HIPCHK(c, crm::key_fill(c->m_a, c->m_d, c->n_total, c->grid.cell != 0, c->m_key, s));
   std::vector<Body> hb((size_t)(c->nb > 0 ? c->nb : 1));
   if (c->nb > 0) std::memcpy(hb.data(), bodies, sizeof(Body) * (size_t)c->nb);
   std::vector<float4> tab((size_t)h.n_mat);

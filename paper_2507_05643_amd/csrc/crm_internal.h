@@ -138,7 +138,7 @@ hipError_t copy_f64(double* dst, const double* src, int64_t n, hipStream_t s);
 // World positions x = X + R l (FP64, stored FP32 or cell + offset) of the
 // markers with local indices [k0, k1) into the master planes.
 hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int64_t n_soil, const Body* bodies,
-                                Grid g, float4* m_a, float4* m_d, hipStream_t s);
+                                Grid g, float4* m_a, float4* m_d, uint32_t* key, hipStream_t s);
 // out[b], b = 0..nb: first processed-marker rank of body b (markers processed
 // in id order; ids = the processed ids, NULL when all particles are processed).
 hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const int64_t* bstart, int32_t nb,
@@ -146,8 +146,19 @@ hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const
 
 // Activity flags of all particles (Sec. 4.2 item 2) and the count of flagged
 // particles per tile of compact_counted (its first pass), into tmp.
-hipError_t activity_count(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
-                          uint8_t* flags, uint32_t* tmp, hipStream_t s);
+// key: the activity pre-test's compact copy of the positions (key_words per
+// particle: x, y, z FP32 bits, or the cells d.zw), kept by scatter_rows and
+// place_markers_master and refilled by key_fill after whole uploads.
+constexpr int key_words(bool cell) { return cell ? 2 : 3; }
+hipError_t key_fill(const float4* m_a, const float4* m_d, int64_t n, bool cell, uint32_t* key, hipStream_t s);
+// The union of the bodies' pre-test bounds (FP32 and cell ranges): a
+// particle outside it is no candidate of any body.
+struct ActUnion {
+  float flo[3], fhi[3];
+  int32_t clo[3], chi[3];
+};
+hipError_t activity_count(const float4* m_a, const float4* m_d, const uint32_t* key, int64_t n, const Body* bodies,
+                          int32_t nb, const ActUnion& un, Grid g, uint8_t* flags, uint32_t* tmp, hipStream_t s);
 // Order-preserving compaction of the ids with flags != 0 from those counts
 // (scan, write; tiles without a flagged particle read no flag); count to
 // *count_dst (device). The flag array holds flags_padded(n) bytes, zero
@@ -320,7 +331,7 @@ hipError_t adj_unpack(int64_t n, CPlanes in, double* pos, float* vel, float* sig
 
 // Scatter working records back to the master planes.
 hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,
-                        float4* m_a, float4* m_b, float4* m_c, float4* m_d, hipStream_t s);
+                        float4* m_a, float4* m_b, float4* m_c, float4* m_d, uint32_t* key, bool cell, hipStream_t s);
 // Marker rows back to the master planes: velocity and stress (b, c, d.xy);
 // the master positions stay those of the last marker placement.
 hipError_t scatter_marker_rows(CPlanes src, const int32_t* rows, int64_t n_rows, const int32_t* slot_id,

@@ -227,10 +227,31 @@ hipError_t compact_impl(Pred pr, int64_t n, int32_t* out, uint64_t* count_dst, u
 }
 
 // ---------------------------------------------------- markers and flags ---
+// The activity pass's pre-test reads its own compact copy of each particle's
+// coordinates (FP32 x, y, z: 12 bytes) or cells (cell-offset positions: the
+// 8 bytes of d.zw) instead of a 16-byte plane. The copy is written wherever the
+// master store's positions change (the list rebuild's scatter, the markers'
+// placement) and refilled after whole uploads (key_fill).
+__device__ inline void put_key(uint32_t* __restrict__ key, int64_t i, float4 a, float4 d, bool cell) {
+  if (cell)
+    *reinterpret_cast<uint2*>(key + 2 * i) = make_uint2(__float_as_uint(d.z), __float_as_uint(d.w));
+  else
+    *reinterpret_cast<uint3*>(key + 3 * i) = make_uint3(__float_as_uint(a.x), __float_as_uint(a.y),
+                                                        __float_as_uint(a.z));
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_fill(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
+                                                     int64_t n, int cell, uint32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  put_key(key, i, m_a[i], cell ? m_d[i] : make_float4(0.f, 0.f, 0.f, 0.f), cell != 0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_place_markers_master(const float4* __restrict__ local, int64_t nm,
                                                                  int64_t n_soil, const Body* __restrict__ bodies,
                                                                  Grid g, float4* __restrict__ m_a,
-                                                                 float4* __restrict__ m_d) {
+                                                                 float4* __restrict__ m_d,
+                                                                 uint32_t* __restrict__ key) {
   int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= nm) return;
   float4 l = local[k];
@@ -241,6 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_place_markers_master(const float4* _
   store_pos(x, g, a, d);
   m_a[n_soil + k] = a;
   if (g.cell) m_d[n_soil + k] = d;
+  if (key) put_key(key, n_soil + k, a, d, g.cell != 0);
 }
 
 // Sec. 4.2 item 2: Active inside an oriented box (|R^T (x - X)| <= half per
@@ -282,18 +304,30 @@ __device__ inline uint8_t flag_of(const double xw[3], const Body* __restrict__ b
 // the others take the exact FP64 test of flag_of, so every flag is flag_of's.
 template <bool CELL>
 __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restrict__ m_a,
-                                                           const float4* __restrict__ m_d, int64_t n,
-                                                           const Body* __restrict__ bodies, int32_t nb, Grid g,
-                                                           uint8_t* __restrict__ flags, uint32_t* __restrict__ bcnt) {
+                                                           const float4* __restrict__ m_d,
+                                                           const uint32_t* __restrict__ key, int64_t n,
+                                                           const Body* __restrict__ bodies, int32_t nb, ActUnion un,
+                                                           Grid g, uint8_t* __restrict__ flags,
+                                                           uint32_t* __restrict__ bcnt) {
   const int64_t base = (int64_t)blockIdx.x * kFlagsTile + threadIdx.x;
   uint32_t cnt = 0;
 #pragma unroll 1
   for (int k0 = 0; k0 < kFlagsPer; k0 += 4) {
-    float4 p[4];   // a (FP32 coordinates) or d (cells in d.zw)
+    float4 p[4];   // the compact copy: x, y, z (FP32 coordinates) or the cells in p.zw
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t i = base + (int64_t)(k0 + q) * kBlock;
-      p[q] = i < n ? (CELL ? m_d[i] : m_a[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+      p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i < n) {
+        if (CELL) {
+          const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
+          p[q].z = __uint_as_float(kv.x);
+          p[q].w = __uint_as_float(kv.y);
+        } else {
+          const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
+          p[q] = make_float4(__uint_as_float(kv.x), __uint_as_float(kv.y), __uint_as_float(kv.z), 0.f);
+        }
+      }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -306,8 +340,15 @@ __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restr
           c[1] = unpack_y(w);
           c[2] = unpack_z(w);
         }
+        // first against the union of the bodies' bounds (almost every particle
+        // of a long terrain is outside it), then body by body
         bool cand = false;
-        for (int b = 0; b < nb; ++b) {
+        const bool near =
+            CELL ? (c[0] >= un.clo[0] && c[0] <= un.chi[0] && c[1] >= un.clo[1] && c[1] <= un.chi[1] &&
+                    c[2] >= un.clo[2] && c[2] <= un.chi[2])
+                 : (p[q].x >= un.flo[0] && p[q].x <= un.fhi[0] && p[q].y >= un.flo[1] && p[q].y <= un.fhi[1] &&
+                    p[q].z >= un.flo[2] && p[q].z <= un.fhi[2]);
+        for (int b = 0; b < (near ? nb : 0); ++b) {
           const Body& B = bodies[b];
           if (!B.has_box) continue;
           if (CELL)
@@ -319,9 +360,10 @@ __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restr
         }
         uint8_t f = 0;
         if (cand) {
-          const float4 a = CELL ? m_a[i] : p[q];
+          const float4 a = m_a[i];
+          const float4 d = CELL ? m_d[i] : a;
           double xw[3];
-          abs_pos(a, p[q], g, xw);
+          abs_pos(a, d, g, xw);
           f = flag_of(xw, bodies, nb, g.ext);
         }
         flags[i] = f;
@@ -2094,15 +2136,18 @@ __global__ __launch_bounds__(kStageBlock) void k_fluid_stage2(CPlanes B, Planes 
 __global__ __launch_bounds__(kBlock) void k_scatter(CPlanes src, const int32_t* __restrict__ rows, int64_t n,
                                                     const int32_t* __restrict__ slot_id,
                                                     float4* __restrict__ m_a, float4* __restrict__ m_b,
-                                                    float4* __restrict__ m_c, float4* __restrict__ m_d) {
+                                                    float4* __restrict__ m_c, float4* __restrict__ m_d,
+                                                    uint32_t* __restrict__ key, int cell) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
   const int32_t s = rows[r];
   const int32_t id = slot_id[s];
-  m_a[id] = src.a[s];
+  const float4 a = src.a[s], d = src.d[s];
+  m_a[id] = a;
   m_b[id] = src.b[s];
   m_c[id] = src.c[s];
-  m_d[id] = src.d[s];
+  m_d[id] = d;
+  if (key) put_key(key, id, a, d, cell != 0);
 }
 
 // Marker rows: the extrapolated velocity and stress only. A marker's position
@@ -2163,9 +2208,10 @@ hipError_t copy_f64(double* dst, const double* src, int64_t n, hipStream_t s) {
 }
 
 hipError_t place_markers_master(const float4* local, int64_t k0, int64_t k1, int64_t n_soil, const Body* bodies,
-                                Grid g, float4* m_a, float4* m_d, hipStream_t s) {
+                                Grid g, float4* m_a, float4* m_d, uint32_t* key, hipStream_t s) {
   if (k1 <= k0) return hipSuccess;
-  k_place_markers_master<<<nblk(k1 - k0), kBlock, 0, s>>>(local + k0, k1 - k0, n_soil + k0, bodies, g, m_a, m_d);
+  k_place_markers_master<<<nblk(k1 - k0), kBlock, 0, s>>>(local + k0, k1 - k0, n_soil + k0, bodies, g, m_a, m_d,
+                                                          key);
   return hipGetLastError();
 }
 
@@ -2188,12 +2234,12 @@ size_t compact_tmp_elems(int64_t n) {
   return (size_t)(2 * nb + 1) + scan_tmp_elems(nb);
 }
 
-hipError_t activity_count(const float4* m_a, const float4* m_d, int64_t n, const Body* bodies, int32_t nb, Grid g,
-                          uint8_t* flags, uint32_t* tmp, hipStream_t s) {
+hipError_t activity_count(const float4* m_a, const float4* m_d, const uint32_t* key, int64_t n, const Body* bodies,
+                          int32_t nb, const ActUnion& un, Grid g, uint8_t* flags, uint32_t* tmp, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nt = (n + kFlagsTile - 1) / kFlagsTile;
-  if (g.cell) k_activity_count<true><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags, tmp);
-  else k_activity_count<false><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, n, bodies, nb, g, flags, tmp);
+  if (g.cell) k_activity_count<true><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, key, n, bodies, nb, un, g, flags, tmp);
+  else k_activity_count<false><<<(unsigned)nt, kBlock, 0, s>>>(m_a, m_d, key, n, bodies, nb, un, g, flags, tmp);
   return hipGetLastError();
 }
 
@@ -2428,9 +2474,15 @@ hipError_t fluid_stage2(CPlanes B, Planes A, const int32_t* rows, int64_t n, con
 }
 
 hipError_t scatter_rows(CPlanes src, const int32_t* rows, int64_t n, const int32_t* slot_id, float4* m_a,
-                        float4* m_b, float4* m_c, float4* m_d, hipStream_t s) {
+                        float4* m_b, float4* m_c, float4* m_d, uint32_t* key, bool cell, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_scatter<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_a, m_b, m_c, m_d);
+  k_scatter<<<nblk(n), kBlock, 0, s>>>(src, rows, n, slot_id, m_a, m_b, m_c, m_d, key, cell ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t key_fill(const float4* m_a, const float4* m_d, int64_t n, bool cell, uint32_t* key, hipStream_t s) {
+  if (n <= 0 || !key) return hipSuccess;
+  k_key_fill<<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, cell ? 1 : 0, key);
   return hipGetLastError();
 }
 
