@@ -345,13 +345,15 @@ def subpatch_drift(sc, crm, steps=100):
     return out
 
 
-def run_strip(args, crm, scenes, pos_mode, sc=None):
+def run_strip(args, crm, scenes, pos_mode, sc=None, scan=0):
     """Long strip with four wheels carrying active boxes, positions plain FP32
     (pos_mode 0) or cell index + FP32 offset (pos_mode 1); the vehicle sits at
-    x = args.strip_x and moves with the wheels' speed."""
+    x = args.strip_x and moves with the wheels' speed. Active-domain flags from
+    the coarse-cell index (scan 0, the library's default) or from the test of
+    all N particles (scan 1, the paper's pass; its k_activity roofline)."""
     if sc is None:
         sc = scenes.strip(seed=0, length=args.strip_length, x0=args.strip_x, ps_freq=args.ps_freq, t_delay=-1.0)
-    params = dict(sc.params, pos_mode=pos_mode)
+    params = dict(sc.params, pos_mode=pos_mode, activity_scan=scan)
     dt = params["dt"]
     t0 = time.perf_counter()
     sim = crm.Simulation(sc, params=params, device=0)
@@ -378,10 +380,12 @@ def run_strip(args, crm, scenes, pos_mode, sc=None):
     sim.profiling(False)
     cnt = sim.counts()
     sim.close()
-    roof = activity_roofline(prof, cnt, pos_mode)
+    roof = activity_roofline(prof, cnt, pos_mode) if scan else None
+    bd = per_launch(prof)
     return dict(value=cnt["n_proc"] * steps / wall, ms_per_step=wall / steps * 1e3, steps=steps,
                 warmup=args.form_warmup, soil_rate=cnt["soil_rows"] * steps / wall, roofline=roof,
-                breakdown=per_launch(prof), init_s=round(t_init, 1),
+                activity_flags="test of all N" if scan else "coarse-cell index",
+                activity_launch_ms=bd.get("activity"), breakdown=bd, init_s=round(t_init, 1),
                 config={"workload": f"strip {args.strip_length:g} m x 4 m x 0.3 m at dx 0.05 m (seeded jitter), "
                                     f"3-layer floor, 4 wheels at 5 m/s at x = {args.strip_x:g} m with 2 m active "
                                     f"boxes, {'cell index + FP32 offset' if pos_mode else 'plain FP32'} positions",
@@ -598,6 +602,13 @@ def main():
             mode = int(f[-1])
             r = run_strip(args, crm, scenes, mode, strip_scene)
             name = "strip_fp32" if f == "strip0" else "strip_cell_offset"
+            # the same form with the paper's activity pass (all N particles
+            # tested at every rebuild): the k_activity roofline
+            q = run_strip(args, crm, scenes, mode, strip_scene, scan=1)
+            r["roofline"] = q["roofline"]
+            r["with_activity_scan"] = dict(value=q["value"], ms_per_step=q["ms_per_step"],
+                                           activity_launch_ms=q["activity_launch_ms"],
+                                           rebuild_ms=q["breakdown"].get("rebuild"))
             # the same form with the vehicle near either end of the strip
             steps = args.strip_steps
             args.strip_steps = max(steps // 2, 1)
@@ -606,7 +617,7 @@ def main():
                 q = run_strip(args, crm, scenes, mode, strip_at(strip_scene, xv))
                 r["along_the_strip"][f"x={xv:g}"] = dict(value=q["value"], ms_per_step=q["ms_per_step"],
                                                          n_processed=q["config"]["n_processed"],
-                                                         activity_launch_ms=(q["roofline"] or {}).get("launch_ms"))
+                                                         activity_launch_ms=q["activity_launch_ms"])
             args.strip_steps = steps
             if drift is None and args.strip_length >= 9999.5:
                 drift = subpatch_drift(strip_subpatch(strip_scene, 9999.0), crm)

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CRM_ABI_VERSION 3u
+#define CRM_ABI_VERSION 4u
 
 typedef enum {
   CRM_OK = 0,
@@ -89,7 +89,15 @@ typedef void (*crm_free_fn)(void* ptr, void* user, void* hip_stream);
  * (cells of that size; active boxes grown by 2h + skin), rebuilt when a
  * processed particle has moved more than skin / 2 since the last rebuild, or
  * after ps_freq steps. Since the kernel vanishes beyond 2h, the sums then equal
- * those over the exact 2h neighbours of every step (up to summation order). */
+ * those over the exact 2h neighbours of every step (up to summation order).
+ * activity_scan: the active-domain flags (Sec. 4.2 item 2) are those of a test
+ * of every particle against the active boxes; with 0 only the particles that
+ * an index of the master store by coarse cell places near a box, and those
+ * on the moved list (integrated, or markers of a body that moved, since the
+ * index was built), are tested (same flags); with 1 all N are (the paper's
+ * pass). moved_cap: entries of the moved list (0: max(16384, N / 32)); the
+ * index is rebuilt when the list would overflow, and a rebuild tests all N
+ * instead when the last rebuild integrated more than moved_cap / 2 rows. */
 typedef struct {
   uint32_t abi_version;  /* must be CRM_ABI_VERSION */
   uint32_t av_mode;
@@ -106,8 +114,9 @@ typedef struct {
   uint32_t pos_mode;     /* CRM_POS_FP32 or CRM_POS_CELL_OFFSET */
   double bulk_coeff;
   uint32_t kernel;       /* CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND */
-  uint32_t reserved;     /* must be 0 */
+  uint32_t activity_scan; /* 0: active-domain flags from an index by coarse cell (default); 1: a scan of all N */
   double skin;           /* Verlet-list skin (m, >= 0), see below */
+  int64_t moved_cap;     /* moved-list entries for activity_scan 0 (>= 0; 0: default), see below */
 } crm_params;
 
 /* A rigid body: BCE markers fixed in its frame (Sec. 2.5.1: layers at spacing

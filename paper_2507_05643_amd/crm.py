@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # CRM_LIB_PATH selects another build of the same library (e.g. for A/B timing).
 LIB_PATH = os.environ.get("CRM_LIB_PATH") or os.path.join(HERE, "libcrm.so")
 
-CRM_ABI_VERSION = 3
+CRM_ABI_VERSION = 4
 STATUS = {0: "CRM_OK", -1: "CRM_E_INVALID", -2: "CRM_E_NOMEM", -3: "CRM_E_DEVICE",
           -4: "CRM_E_STATE", -5: "CRM_E_NONFINITE", -6: "CRM_E_UNSUPPORTED"}
 
@@ -44,7 +44,8 @@ class crm_params(C.Structure):
         ("grow_G", C.c_double), ("shrink_S", C.c_double),
         ("shrink_interval", C.c_uint32), ("pos_mode", C.c_uint32),
         ("bulk_coeff", C.c_double),
-        ("kernel", C.c_uint32), ("reserved", C.c_uint32), ("skin", C.c_double),
+        ("kernel", C.c_uint32), ("activity_scan", C.c_uint32), ("skin", C.c_double),
+        ("moved_cap", C.c_int64),
     ]
 
 
@@ -160,6 +161,8 @@ def make_params(p: dict) -> crm_params:
     o.pos_mode = int(p.get("pos_mode", 0))
     o.kernel = int(p.get("kernel", 0))
     o.skin = float(p.get("skin", 0.0))
+    o.activity_scan = int(p.get("activity_scan", 0))
+    o.moved_cap = int(p.get("moved_cap", 0))
     return o
 
 

@@ -57,6 +57,25 @@ struct crm_ctx {
   float4* local = nullptr;     // markers: (lx, ly, lz, body bits)
   uint8_t* flags = nullptr;
   uint32_t* m_key = nullptr;      // the activity pre-test's compact positions (active domains only)
+  // active-domain flags from an index by coarse cell (active domains, activity_scan 0)
+  bool ix_on = false;             // index allocated
+  bool ix_valid = false;          // every particle not on the moved list is where the index lists it
+  bool flags_valid = false;       // flags hold exactly the last compaction's ids (proc_ids, d_counts[0])
+  bool ix_used = false;           // this rebuild's flags came from the index
+  int32_t ix_cd[3] = {0, 0, 0};
+  int64_t ix_M = 0;
+  uint32_t* ix_start = nullptr;   // ix_M + 1
+  uint32_t* ix_fill = nullptr;    // ix_M
+  uint32_t* ix_scan = nullptr;
+  int32_t* ix_ids = nullptr;      // n_total
+  uint32_t* ix_visit = nullptr;   // ix_M
+  uint32_t* h_visit_pin = nullptr;  // ix_M (pinned host: the visit list's upload)
+  uint8_t* moved = nullptr;       // flags_padded(n_total)
+  int32_t* mlist = nullptr;       // mcap; its count in d_counts[6]
+  int64_t mcap = 0;
+  std::vector<uint32_t> h_visit;
+  std::vector<Body> ix_bodies;    // body poses when the index was built
+  std::vector<uint8_t> ix_moving; // bodies whose markers are on the moved list
   int32_t* proc_ids = nullptr;
   Body* d_bodies = nullptr;
   float4* d_mat = nullptr;     // material table
@@ -226,7 +245,8 @@ std::string check_params(const crm_params* p) {
   if (p->abi_version != CRM_ABI_VERSION) return "abi_version mismatch";
   if (p->pos_mode > 1) return "pos_mode must be CRM_POS_FP32 or CRM_POS_CELL_OFFSET";
   if (p->kernel > 1) return "kernel must be CRM_KERNEL_CUBIC or CRM_KERNEL_WENDLAND";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->activity_scan > 1) return "activity_scan must be 0 or 1";
+  if (p->moved_cap < 0) return "moved_cap must be >= 0";
   if (!(std::isfinite(p->skin) && p->skin >= 0.0)) return "skin must be >= 0";
   auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
   if (!pos(p->dx)) return "dx must be > 0";
@@ -588,6 +608,91 @@ crm_status scatter_back(crm_ctx* c) {
 
 // Alg. 3 lines for a rebuild step: activity (t > t_delay), count, capacity,
 // then PreprocessNeighborList + Algorithm 1 on the processed set.
+// The active-domain flags and their per-tile counts from the coarse-cell
+// index (same flags as the scan of all N): the index is (re)built when stale
+// or when the moved list overflowed; the markers of bodies that moved since
+// then join the moved list; the last flags are cleared; the particles listed
+// under the coarse cells that the bodies' pre-test cell ranges touch, and
+// those on the moved list, are tested.
+crm_status activity_by_index(crm_ctx* c, hipStream_t s) {
+  const int64_t N = c->n_total;
+  const int64_t nw = crm::flags_padded(N) / 4;            // the byte arrays as words
+  // markers that would join the moved list now (bodies moved since the index)
+  auto pending = [&]() {
+    int64_t k = 0;
+    for (int b = 0; b < c->nb; ++b) {
+      const Body& B = c->h_bodies[b];
+      const Body& Q = c->ix_bodies[b];
+      if (!c->ix_moving[b] && (std::memcmp(B.X, Q.X, sizeof(B.X)) != 0 || std::memcmp(B.R, Q.R, sizeof(B.R)) != 0))
+        k += c->h_bstart[b + 1] - c->h_bstart[b];
+    }
+    return k;
+  };
+  // h_counts[6]: the moved list's length after the last rebuild's additions
+  if (!c->ix_valid || (int64_t)c->h_counts[6] + pending() > c->mcap) {
+    HIPCHK(c, crm::ix_build(c->m_a, c->m_d, N, c->grid, c->ix_start, c->ix_fill, c->ix_scan, c->ix_ids, s));
+    HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->moved), 0u, nw, s));
+    HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->d_counts + 6), 0u, 2, s));
+    c->h_counts[6] = 0;
+    c->ix_bodies = c->h_bodies;
+    c->ix_moving.assign((size_t)c->nb, 0);
+    c->ix_valid = true;
+    c->flags_valid = false;
+  }
+  for (int b = 0; b < c->nb; ++b) {
+    const Body& B = c->h_bodies[b];
+    const Body& Q = c->ix_bodies[b];
+    if (c->ix_moving[b] || (std::memcmp(B.X, Q.X, sizeof(B.X)) == 0 && std::memcmp(B.R, Q.R, sizeof(B.R)) == 0))
+      continue;
+    const int64_t k0 = c->h_bstart[b], k1 = c->h_bstart[b + 1];
+    HIPCHK(c, crm::moved_add(nullptr, nullptr, k1 - k0, nullptr, c->n_soil + k0, c->moved, c->mlist, c->d_counts + 6,
+                             c->mcap, s));
+    c->ix_moving[b] = 1;
+  }
+  if (c->flags_valid)
+    HIPCHK(c, crm::flags_clear(c->proc_ids, c->d_counts, N, c->flags, s));
+  else
+    HIPCHK(c, crm::fill_u32(reinterpret_cast<uint32_t*>(c->flags), 0u, nw, s));
+  HIPCHK(c, crm::fill_u32(c->ctmp, 0u, crm::flag_tiles(N), s));
+  // the coarse cells that the bodies' pre-test cell ranges touch
+  c->h_visit.clear();
+  const int32_t kc = crm::coarse_size();
+  for (const Body& B : c->h_bodies) {
+    if (!B.has_box) continue;
+    int32_t lo[3], hi[3];
+    bool empty = false;
+    for (int k = 0; k < 3; ++k) {
+      const int32_t a = std::max(B.clo[k], 0), z = std::min(B.chi[k], c->grid.gdim[k] - 1);
+      if (a > z) empty = true;
+      lo[k] = a / kc;
+      hi[k] = z / kc;
+    }
+    if (empty) {   // a range beyond the grid: its edge cells hold the particles outside
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(std::max(B.clo[k], 0), c->grid.gdim[k] - 1) / kc;
+        hi[k] = std::min(std::max(B.chi[k], 0), c->grid.gdim[k] - 1) / kc;
+      }
+    }
+    for (int32_t z = lo[2]; z <= hi[2]; ++z)
+      for (int32_t y = lo[1]; y <= hi[1]; ++y)
+        for (int32_t x = lo[0]; x <= hi[0]; ++x)
+          c->h_visit.push_back(((uint32_t)z * (uint32_t)c->ix_cd[1] + (uint32_t)y) * (uint32_t)c->ix_cd[0] +
+                               (uint32_t)x);
+  }
+  std::sort(c->h_visit.begin(), c->h_visit.end());
+  c->h_visit.erase(std::unique(c->h_visit.begin(), c->h_visit.end()), c->h_visit.end());
+  const int64_t nv = (int64_t)c->h_visit.size();
+  if (nv > 0) {
+    // the last upload from the pinned list has completed: every rebuild reads
+    // its counts back (a stream synchronisation) after this copy
+    std::memcpy(c->h_visit_pin, c->h_visit.data(), sizeof(uint32_t) * (size_t)nv);
+    HIPCHK(c, hipMemcpyAsync(c->ix_visit, c->h_visit_pin, sizeof(uint32_t) * (size_t)nv, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(c, crm::ix_flags(c->ix_visit, nv, c->ix_start, c->ix_ids, c->moved, c->mlist, c->d_counts + 6, c->mcap,
+                          c->m_key, c->m_a, c->m_d, c->d_bodies, c->nb, c->grid, c->flags, c->ctmp, s));
+  return CRM_OK;
+}
+
 crm_status rebuild(crm_ctx* c) {
   hipStream_t s = c->stream;
   const crm_params& P = c->prm;
@@ -617,7 +722,20 @@ crm_status rebuild(crm_ctx* c) {
   const double t = (double)c->step * P.dt;
   c->ad_on = P.active_domains && t > P.t_delay;
   int64_t n_proc = c->n_total;
-  if (c->ad_on) {
+  // the index while the integrated rows fill at most half the moved list
+  // (more: the test of all N costs less than the index's upkeep)
+  c->ix_used = c->ad_on && c->ix_on && 2 * c->n_frows <= c->mcap;
+  if (c->ix_used) {
+    hipEvent_t ea = prof_begin(c, 7);
+    crm_status st = activity_by_index(c, s);
+    if (st != CRM_OK) return st;
+    prof_end(c, 7, ea);
+    HIPCHK(c, crm::compact_counted(c->flags, c->n_total, c->proc_ids, c->d_counts, c->ctmp, s));
+    st = read_counts(c);
+    if (st != CRM_OK) return st;
+    n_proc = (int64_t)c->h_counts[0];
+    c->flags_valid = true;
+  } else if (c->ad_on) {
     hipEvent_t ea = prof_begin(c, 7);
     crm::ActUnion un;
     for (int k = 0; k < 3; ++k) {
@@ -642,6 +760,12 @@ crm_status rebuild(crm_ctx* c) {
     crm_status st = read_counts(c);
     if (st != CRM_OK) return st;
     n_proc = (int64_t)c->h_counts[0];
+    c->ix_valid = false;      // the rows integrated from here on are not tracked
+    c->flags_valid = false;
+  } else {
+    // every particle processed (and the soil integrated): the index is stale
+    c->ix_valid = false;
+    c->flags_valid = false;
   }
   // capacity policy (Sec. 4.2 item 3)
   int64_t ncap = crm_capacity_next(c->cap, n_proc, c->step, P.grow_G, P.shrink_S, P.shrink_interval);
@@ -674,6 +798,10 @@ crm_status rebuild(crm_ctx* c) {
   // the row lists hold at most this many rows (their counts are on the device):
   // the soil and marker passes and scans run over these bounds, not n_proc
   const int64_t rf = std::min(n_proc, c->n_soil), rm = std::min(n_proc, c->n_mark);
+  // the rows integrated until the next rebuild leave their place in the index
+  if (c->ix_used)
+    HIPCHK(c, crm::moved_add(c->frows, c->d_counts + 1, rf, c->slot_id, 0, c->moved, c->mlist, c->d_counts + 6,
+                             c->mcap, s));
   HIPCHK(c, crm::tile_tables(c->frows, rf, c->d_counts + 1, c->skey, c->cell_start, pw, c->tabs, s));
   HIPCHK(c, crm::nbr_count_soil(c->frows, rf, c->d_counts + 1, c->pos4, c->cpos, c->skey, c->cell_start, g,
                                 c->tabs, c->cnt_f, c->stash_f, s));
@@ -919,6 +1047,7 @@ void release(crm_ctx* c) {
   if (c->h_disp) (void)hipHostFree(c->h_disp);
   if (c->h_bpin) (void)hipHostFree(c->h_bpin);
   if (c->h_fpin) (void)hipHostFree(c->h_fpin);
+  if (c->h_visit_pin) (void)hipHostFree(c->h_visit_pin);
   if (c->bpin_ev) (void)hipEventDestroy(c->bpin_ev);
   if (c->fpin_ev) (void)hipEventDestroy(c->fpin_ev);
   if (c->disp_ev) (void)hipEventDestroy(c->disp_ev);
@@ -1198,6 +1327,17 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
             alloc_n(c, c->d_bstart, n_bodies + 1);
   if (ok && params->active_domains)
     ok = alloc_n(c, c->m_key, n_total * crm::key_words(c->grid.cell != 0));
+  if (ok && params->active_domains && !params->activity_scan) {
+    c->ix_M = crm::coarse_cells(c->grid, c->ix_cd);
+    c->mcap = params->moved_cap > 0 ? params->moved_cap : std::max<int64_t>(int64_t(1) << 14, n_total / 32);
+    ok = alloc_n(c, c->ix_start, c->ix_M + 1) && alloc_n(c, c->ix_fill, c->ix_M) &&
+         alloc_n(c, c->ix_scan, (int64_t)crm::scan_tmp_elems(c->ix_M)) && alloc_n(c, c->ix_ids, n_total) &&
+         alloc_n(c, c->ix_visit, c->ix_M) && alloc_n(c, c->moved, crm::flags_padded(n_total)) &&
+         alloc_n(c, c->mlist, c->mcap) &&
+         hipHostMalloc((void**)&c->h_visit_pin, sizeof(uint32_t) * (size_t)c->ix_M, hipHostMallocDefault) == hipSuccess;
+    c->ix_on = ok;
+    c->h_visit.reserve((size_t)std::min<int64_t>(c->ix_M, 1 << 16));
+  }
   if (!ok) {
     release(c);
     return fail(nullptr, CRM_E_NOMEM, "device allocation failed");
@@ -1572,6 +1712,7 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
     for (int q = 0; q < 4; ++q)
       HIPCHK(c, hipMemcpyAsync(dst[q], src + q * n, sizeof(float4) * n, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, crm::key_fill(c->m_a, c->m_d, (int64_t)n, c->grid.cell != 0, c->m_key, s));
+    c->ix_valid = false;
     c->working_valid = false;
     c->force_rebuild = true;
     c->place_all = true;
@@ -1784,6 +1925,7 @@ crm_status crm_set_state(crm_ctx* c, const double* pos, const float* vel, const 
   c->working_valid = false;
   c->force_rebuild = true;
   c->rec_valid = false;
+  c->ix_valid = false;
   return CRM_OK;
 }
 
@@ -1884,6 +2026,7 @@ crm_status crm_load_checkpoint(crm_ctx* c, const void* buf, size_t bytes) {
   float4* planes[4] = {c->m_a, c->m_b, c->m_c, c->m_d};
   for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(planes[q], o + q * pl, pl, hipMemcpyHostToDevice, s));
   HIPCHK(c, crm::key_fill(c->m_a, c->m_d, c->n_total, c->grid.cell != 0, c->m_key, s));
+  c->ix_valid = false;
   std::vector<Body> hb((size_t)(c->nb > 0 ? c->nb : 1));
   if (c->nb > 0) std::memcpy(hb.data(), bodies, sizeof(Body) * (size_t)c->nb);
   std::vector<float4> tab((size_t)h.n_mat);

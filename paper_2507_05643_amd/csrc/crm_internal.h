@@ -159,6 +159,28 @@ struct ActUnion {
 };
 hipError_t activity_count(const float4* m_a, const float4* m_d, const uint32_t* key, int64_t n, const Body* bodies,
                           int32_t nb, const ActUnion& un, Grid g, uint8_t* flags, uint32_t* tmp, hipStream_t s);
+// The same flags from an index of the master store by coarse cell (coarse_size
+// list cells per axis; coarse_cells cells, their counts per axis in cd):
+// ix_build lists every particle under its coarse cell (start: cells + 1
+// words, fill: cells words of scratch, scan_tmp: scan_tmp_elems(cells), ids: n);
+// ix_flags tests the particles listed under the coarse cells visit[0..n_visit)
+// that are not marked in moved, and the first min(*n_moved, mcap) ids of
+// mlist, writing their nonzero flags and counting them per compaction tile in
+// bcnt (zeroed beforehand); flags_clear zeroes the flags of a list's ids;
+// moved_add marks and lists (once) the ids of the rows (through slot_id) or
+// the ids id0 .. id0 + n_cap - 1 (rows null).
+int64_t coarse_cells(const Grid& g, int32_t cd[3]);
+int32_t coarse_size();
+int64_t flag_tiles(int64_t n);   // compaction tiles over n particles (bcnt words)
+hipError_t ix_build(const float4* m_a, const float4* m_d, int64_t n, Grid g, uint32_t* start, uint32_t* fill,
+                    uint32_t* scan_tmp, int32_t* ids, hipStream_t s);
+hipError_t ix_flags(const uint32_t* visit, int64_t n_visit, const uint32_t* start, const int32_t* ids,
+                    const uint8_t* moved, const int32_t* mlist, const uint64_t* n_moved, int64_t mcap,
+                    const uint32_t* key, const float4* m_a, const float4* m_d, const Body* bodies, int32_t nb, Grid g,
+                    uint8_t* flags, uint32_t* bcnt, hipStream_t s);
+hipError_t flags_clear(const int32_t* ids, const uint64_t* n_dev, int64_t cap, uint8_t* flags, hipStream_t s);
+hipError_t moved_add(const int32_t* rows, const uint64_t* n_dev, int64_t n_cap, const int32_t* slot_id, int64_t id0,
+                     uint8_t* moved, int32_t* list, uint64_t* n_moved, int64_t cap, hipStream_t s);
 // Order-preserving compaction of the ids with flags != 0 from those counts
 // (scan, write; tiles without a flagged particle read no flag); count to
 // *count_dst (device). The flag array holds flags_padded(n) bytes, zero

@@ -4,6 +4,7 @@
 // Nothing here is a dense contraction, so no MFMA: the neighbour interaction
 // is FP32 VALU work over cell-sorted records, the binning/compaction steps are
 // HBM streams built from wave64 ballots and block scans.
+#include <algorithm>
 #include <mutex>
 
 #include "crm_device.h"
@@ -227,6 +228,10 @@ hipError_t compact_impl(Pred pr, int64_t n, int32_t* out, uint64_t* count_dst, u
 }
 
 // ---------------------------------------------------- markers and flags ---
+// A cell index clamped to a grid of dim cells (particles outside are binned
+// into the edge cells).
+__device__ inline int32_t clamp_cell(int32_t c, int32_t dim) { return c < 0 ? 0 : (c > dim - 1 ? dim - 1 : c); }
+
 // The activity pass's pre-test reads its own compact copy of each particle's
 // coordinates (FP32 x, y, z: 12 bytes) or cells (cell-offset positions: the
 // 8 bytes of d.zw) instead of a 16-byte plane. The copy is written wherever the
@@ -376,6 +381,210 @@ __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restr
   if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
 }
 
+// ---------------------------------------------- activity by coarse cells ---
+// The same flags without reading all N particles: an index of the master
+// store by coarse cell (kCoarse list cells per axis) lists each particle under
+// the cell it was in when the index was built. Only integrated particles and
+// the markers of moving bodies change position, and each of those is put on a
+// moved list (and marked) the first time; every other particle is still where
+// the index says. A rebuild then tests the particles listed under the coarse
+// cells that the bodies' pre-test cell ranges touch (skipping marked ones) and
+// every particle of the moved list, with the same pre-test and flag_of as
+// k_activity_count, and counts the flagged particles per compaction tile.
+// Particles it does not test lie outside every body's pre-test range, where
+// k_activity_count's flag is 0 too; the previous rebuild's flags are cleared
+// first, so the flags, and the compaction of them, are the same.
+constexpr int kCoarse = 8;
+
+// Coarse cell of master particle i (its list cell clamped to the domain's grid).
+template <bool CELL>
+__device__ inline uint32_t coarse_of(const float4* __restrict__ m_a, const float4* __restrict__ m_d, int64_t i,
+                                     const Grid& g, int32_t cx, int32_t cy) {
+  int32_t c[3];
+  if (CELL) {
+    const float4 d = m_d[i];
+    const uint32_t w = __float_as_uint(d.w);
+    c[0] = clamp_cell((int32_t)__float_as_uint(d.z), g.gdim[0]);
+    c[1] = clamp_cell(unpack_y(w), g.gdim[1]);
+    c[2] = clamp_cell(unpack_z(w), g.gdim[2]);
+  } else {
+    const float4 a = m_a[i];
+    c[0] = cell_coord((double)a.x, g.lo[0], g.inv, g.gdim[0]);
+    c[1] = cell_coord((double)a.y, g.lo[1], g.inv, g.gdim[1]);
+    c[2] = cell_coord((double)a.z, g.lo[2], g.inv, g.gdim[2]);
+  }
+  return ((uint32_t)(c[2] / kCoarse) * (uint32_t)cy + (uint32_t)(c[1] / kCoarse)) * (uint32_t)cx +
+         (uint32_t)(c[0] / kCoarse);
+}
+
+// One atomic add per distinct address among the wave's active lanes; returns
+// each lane's old value plus its place among the lanes sharing its address.
+__device__ inline uint32_t wave_atomic_slot(uint32_t* __restrict__ base, uint32_t c) {
+  uint64_t todo = __ballot(1);
+  uint64_t mine = 0;
+  while (todo) {
+    const int lead = __builtin_ctzll(todo);
+    const uint32_t lc = (uint32_t)__shfl((int)c, lead);
+    const uint64_t set = __ballot(c == lc) & todo;
+    if (c == lc) mine = set;
+    todo &= ~set;
+  }
+  const int first = __builtin_ctzll(mine);
+  uint32_t b = 0;
+  if ((int)lane_id() == first) b = atomicAdd(&base[c], (uint32_t)__popcll(mine));
+  b = (uint32_t)__shfl((int)b, first);
+  return b + (uint32_t)__popcll(mine & lanemask_lt());
+}
+
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_ix_count(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
+                                                     int64_t n, Grid g, int32_t cx, int32_t cy,
+                                                     uint32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  (void)wave_atomic_slot(cnt, coarse_of<CELL>(m_a, m_d, i, g, cx, cy));
+}
+
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_ix_place(const float4* __restrict__ m_a, const float4* __restrict__ m_d,
+                                                     int64_t n, Grid g, int32_t cx, int32_t cy,
+                                                     const uint32_t* __restrict__ start, uint32_t* __restrict__ fill,
+                                                     int32_t* __restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = coarse_of<CELL>(m_a, m_d, i, g, cx, cy);
+  ids[start[c] + wave_atomic_slot(fill, c)] = (int32_t)i;
+}
+
+// k_activity_count's test of one particle (without the union pre-test).
+template <bool CELL>
+__device__ inline uint8_t act_flag(const uint32_t* __restrict__ key, const float4* __restrict__ m_a,
+                                   const float4* __restrict__ m_d, int64_t i, const Body* __restrict__ bodies,
+                                   int32_t nb, const Grid& g) {
+  bool cand = false;
+  if (CELL) {
+    const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
+    const int32_t c0 = (int32_t)kv.x, c1 = unpack_y(kv.y), c2 = unpack_z(kv.y);
+    for (int b = 0; b < nb; ++b) {
+      const Body& B = bodies[b];
+      if (!B.has_box) continue;
+      cand |= c0 >= B.clo[0] && c0 <= B.chi[0] && c1 >= B.clo[1] && c1 <= B.chi[1] && c2 >= B.clo[2] &&
+              c2 <= B.chi[2];
+    }
+  } else {
+    const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
+    const float x = __uint_as_float(kv.x), y = __uint_as_float(kv.y), z = __uint_as_float(kv.z);
+    for (int b = 0; b < nb; ++b) {
+      const Body& B = bodies[b];
+      if (!B.has_box) continue;
+      cand |= x >= B.flo[0] && x <= B.fhi[0] && y >= B.flo[1] && y <= B.fhi[1] && z >= B.flo[2] && z <= B.fhi[2];
+    }
+  }
+  if (!cand) return 0;
+  const float4 a = m_a[i];
+  const float4 d = CELL ? m_d[i] : a;
+  double xw[3];
+  abs_pos(a, d, g, xw);
+  return flag_of(xw, bodies, nb, g.ext);
+}
+
+// Writes a nonzero flag f of particle i and counts it in its compaction tile
+// (one atomic add per tile among the wave's lanes; every lane of the wave
+// calls this, with f = 0 for none).
+__device__ inline void put_flag(uint8_t f, int64_t i, uint8_t* __restrict__ flags, uint32_t* __restrict__ bcnt) {
+  if (f) flags[i] = f;
+  const uint32_t t = f ? (uint32_t)(i / kFlagsTile) : 0u;
+  uint64_t todo = __ballot(f != 0);
+  while (todo) {
+    const int lead = __builtin_ctzll(todo);
+    const uint32_t lt = (uint32_t)__shfl((int)t, lead);
+    const uint64_t set = __ballot(f != 0 && t == lt) & todo;
+    if ((int)lane_id() == lead) atomicAdd(&bcnt[lt], (uint32_t)__popcll(set));
+    todo &= ~set;
+  }
+}
+
+// Workgroups kQuerySplit * w .. kQuerySplit * w + kQuerySplit - 1 test the
+// particles listed under coarse cell visit[w] (those not marked as moved),
+// each a strided share: a coarse cell holds thousands of particles, and the
+// tests of one particle are a chain of dependent loads, so the cell's share
+// per lane is kept to a few.
+constexpr int kQuerySplit = 16;
+
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_ix_query(const uint32_t* __restrict__ visit,
+                                                     const uint32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ ids,
+                                                     const uint8_t* __restrict__ moved,
+                                                     const uint32_t* __restrict__ key, const float4* __restrict__ m_a,
+                                                     const float4* __restrict__ m_d, const Body* __restrict__ bodies,
+                                                     int32_t nb, Grid g, uint8_t* __restrict__ flags,
+                                                     uint32_t* __restrict__ bcnt) {
+  const uint32_t c = visit[blockIdx.x / kQuerySplit];
+  const uint32_t b = start[c] + (blockIdx.x % kQuerySplit) * kBlock, e = start[c + 1];
+  for (uint32_t k0 = b; k0 < e; k0 += kQuerySplit * kBlock) {   // the same trip count for every lane
+    const uint32_t k = k0 + threadIdx.x;
+    int32_t i = 0;
+    uint8_t f = 0;
+    if (k < e) {
+      i = ids[k];
+      const uint8_t mv = moved[i];                     // loaded beside the key
+      f = act_flag<CELL>(key, m_a, m_d, i, bodies, nb, g);
+      if (mv) f = 0;
+    }
+    put_flag(f, i, flags, bcnt);
+  }
+}
+
+// The same for the first min(*n_dev, cap) particles of an id list.
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_ix_list(const int32_t* __restrict__ list,
+                                                    const uint64_t* __restrict__ n_dev, int64_t cap,
+                                                    const uint32_t* __restrict__ key, const float4* __restrict__ m_a,
+                                                    const float4* __restrict__ m_d, const Body* __restrict__ bodies,
+                                                    int32_t nb, Grid g, uint8_t* __restrict__ flags,
+                                                    uint32_t* __restrict__ bcnt) {
+  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k0 = (int64_t)blockIdx.x * kBlock; k0 < n; k0 += stride) {   // uniform per block
+    const int64_t k = k0 + threadIdx.x;
+    int32_t i = 0;
+    uint8_t f = 0;
+    if (k < n) {
+      i = list[k];
+      f = act_flag<CELL>(key, m_a, m_d, i, bodies, nb, g);
+    }
+    put_flag(f, i, flags, bcnt);
+  }
+}
+
+// Clears the flags of the first *n_dev ids of a list (the previous rebuild's
+// processed particles).
+__global__ __launch_bounds__(kBlock) void k_flags_clear(const int32_t* __restrict__ ids,
+                                                        const uint64_t* __restrict__ n_dev, int64_t cap,
+                                                        uint8_t* __restrict__ flags) {
+  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+    flags[ids[k]] = 0;
+}
+
+// Puts particles on the moved list the first time: the ids of the active soil
+// rows (rows, through slot_id), or the ids id0 .. id0 + n - 1 (rows null).
+__global__ __launch_bounds__(kBlock) void k_moved_add(const int32_t* __restrict__ rows,
+                                                      const uint64_t* __restrict__ n_dev, int64_t n_cap,
+                                                      const int32_t* __restrict__ slot_id, int64_t id0,
+                                                      uint8_t* __restrict__ moved, int32_t* __restrict__ list,
+                                                      uint64_t* __restrict__ n_moved, int64_t cap) {
+  const int64_t n = n_dev ? ((int64_t)*n_dev < n_cap ? (int64_t)*n_dev : n_cap) : n_cap;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock) {
+    const int32_t id = rows ? slot_id[rows[k]] : (int32_t)(id0 + k);
+    if (moved[id]) continue;
+    moved[id] = 1;
+    const uint64_t p = atomicAdd((unsigned long long*)n_moved, 1ull);
+    if ((int64_t)p < cap) list[p] = id;
+  }
+}
+
 // Largest squared displacement of a processed particle since the last list
 // rebuild (A against the rebuild positions in pos4 / cpos), as the bits of a
 // non-negative float folded in with an integer atomic max (exact and
@@ -428,7 +637,6 @@ __global__ void k_body_ranges(const int32_t* __restrict__ ids, int64_t n_proc, i
 // ------------------------------------------------------ hashing and sort ---
 // Sec. 4.1 step 1: c = z * (Y * X) + y * X + x with cell size 2h. The arrival
 // rank of each particle in its cell comes from an atomic counter (counting sort).
-__device__ inline int32_t clamp_cell(int32_t c, int32_t dim) { return c < 0 ? 0 : (c > dim - 1 ? dim - 1 : c); }
 
 // A cell of the domain's grid in the rebuild's window (clamped to it; every
 // processed particle's cell lies inside, at least one cell from its edges
@@ -2232,6 +2440,64 @@ hipError_t body_ranges(const int32_t* ids, int64_t n_proc, int64_t n_soil, const
 size_t compact_tmp_elems(int64_t n) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
   return (size_t)(2 * nb + 1) + scan_tmp_elems(nb);
+}
+
+int64_t coarse_cells(const Grid& g, int32_t cd[3]) {
+  for (int k = 0; k < 3; ++k) cd[k] = (g.gdim[k] + kCoarse - 1) / kCoarse;
+  return (int64_t)cd[0] * cd[1] * cd[2];
+}
+
+int32_t coarse_size() { return kCoarse; }
+
+int64_t flag_tiles(int64_t n) { return (n + kFlagsTile - 1) / kFlagsTile; }
+
+hipError_t ix_build(const float4* m_a, const float4* m_d, int64_t n, Grid g, uint32_t* start, uint32_t* fill,
+                    uint32_t* scan_tmp, int32_t* ids, hipStream_t s) {
+  int32_t cd[3];
+  const int64_t M = coarse_cells(g, cd);
+  hipError_t e = fill_u32(fill, 0u, M, s);
+  if (e != hipSuccess) return e;
+  if (n > 0 && g.cell) k_ix_count<true><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, g, cd[0], cd[1], fill);
+  else if (n > 0) k_ix_count<false><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, g, cd[0], cd[1], fill);
+  e = scan_u32_to_u32(fill, start, M, scan_tmp, s);   // every cell's range, empty ones too
+  if (e == hipSuccess) e = fill_u32(fill, 0u, M, s);
+  if (e != hipSuccess || n <= 0) return e;
+  if (g.cell) k_ix_place<true><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, g, cd[0], cd[1], start, fill, ids);
+  else k_ix_place<false><<<nblk(n), kBlock, 0, s>>>(m_a, m_d, n, g, cd[0], cd[1], start, fill, ids);
+  return hipGetLastError();
+}
+
+hipError_t ix_flags(const uint32_t* visit, int64_t n_visit, const uint32_t* start, const int32_t* ids,
+                    const uint8_t* moved, const int32_t* mlist, const uint64_t* n_moved, int64_t mcap,
+                    const uint32_t* key, const float4* m_a, const float4* m_d, const Body* bodies, int32_t nb, Grid g,
+                    uint8_t* flags, uint32_t* bcnt, hipStream_t s) {
+  if (n_visit > 0) {
+    if (g.cell)
+      k_ix_query<true><<<(unsigned)(n_visit * kQuerySplit), kBlock, 0, s>>>(visit, start, ids, moved, key, m_a, m_d, bodies, nb, g,
+                                                            flags, bcnt);
+    else
+      k_ix_query<false><<<(unsigned)(n_visit * kQuerySplit), kBlock, 0, s>>>(visit, start, ids, moved, key, m_a, m_d, bodies, nb, g,
+                                                             flags, bcnt);
+  }
+  const unsigned gl = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk(mcap), 1024));
+  if (g.cell) k_ix_list<true><<<gl, kBlock, 0, s>>>(mlist, n_moved, mcap, key, m_a, m_d, bodies, nb, g, flags, bcnt);
+  else k_ix_list<false><<<gl, kBlock, 0, s>>>(mlist, n_moved, mcap, key, m_a, m_d, bodies, nb, g, flags, bcnt);
+  return hipGetLastError();
+}
+
+hipError_t flags_clear(const int32_t* ids, const uint64_t* n_dev, int64_t cap, uint8_t* flags, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  const unsigned gl = (unsigned)std::min<int64_t>(nblk(cap), 1024);
+  k_flags_clear<<<gl, kBlock, 0, s>>>(ids, n_dev, cap, flags);
+  return hipGetLastError();
+}
+
+hipError_t moved_add(const int32_t* rows, const uint64_t* n_dev, int64_t n_cap, const int32_t* slot_id, int64_t id0,
+                     uint8_t* moved, int32_t* list, uint64_t* n_moved, int64_t cap, hipStream_t s) {
+  if (n_cap <= 0) return hipSuccess;
+  const unsigned gl = (unsigned)std::min<int64_t>(nblk(n_cap), 1024);
+  k_moved_add<<<gl, kBlock, 0, s>>>(rows, n_dev, n_cap, slot_id, id0, moved, list, n_moved, cap);
+  return hipGetLastError();
 }
 
 hipError_t activity_count(const float4* m_a, const float4* m_d, const uint32_t* key, int64_t n, const Body* bodies,

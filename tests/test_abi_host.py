@@ -33,8 +33,9 @@ def test_every_declared_symbol_is_exported(crm):
 
 
 def test_params_layout(crm):
-    # two uint32, 3 + 3 doubles, 8 + 2 doubles, 6 doubles, 2 uint32, 3 doubles, 2 uint32, 1 double
-    assert C.sizeof(crm.crm_params) == 8 + 8 * 6 + 8 * 10 + 8 * 6 + 8 + 8 * 3 + 8 + 8 + 8 + 8
+    # two uint32, 3 + 3 doubles, 8 + 2 doubles, 6 doubles, 2 uint32, 3 doubles, 2 uint32, 1 double, 1 int64
+    assert C.sizeof(crm.crm_params) == 8 + 8 * 6 + 8 * 10 + 8 * 6 + 8 + 8 * 3 + 8 + 8 + 8 + 8 + 8
+    assert crm.crm_params.moved_cap.offset == C.sizeof(crm.crm_params) - 8
     assert crm.crm_params.ps_freq.offset == 8 + 8 * 6 + 8 * 10 + 8 * 6
     assert C.sizeof(crm.crm_body_desc) == 40
 
