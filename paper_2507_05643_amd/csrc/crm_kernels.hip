@@ -298,15 +298,64 @@ __device__ inline uint8_t flag_of(const double xw[3], const Body* __restrict__ b
   return best;
 }
 
+// The body-by-body pre-test and the exact test of one particle (the flag of
+// k_activity_count and of the index's queries).
+template <bool CELL>
+__device__ inline uint8_t act_flag(const uint32_t* __restrict__ key, const float4* __restrict__ m_a,
+                                   const float4* __restrict__ m_d, int64_t i, const Body* __restrict__ bodies,
+                                   int32_t nb, const Grid& g) {
+  bool cand = false;
+  if (CELL) {
+    const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
+    const int32_t c0 = (int32_t)kv.x, c1 = unpack_y(kv.y), c2 = unpack_z(kv.y);
+    for (int b = 0; b < nb; ++b) {
+      const Body& B = bodies[b];
+      if (!B.has_box) continue;
+      cand |= c0 >= B.clo[0] && c0 <= B.chi[0] && c1 >= B.clo[1] && c1 <= B.chi[1] && c2 >= B.clo[2] &&
+              c2 <= B.chi[2];
+    }
+  } else {
+    const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
+    const float x = __uint_as_float(kv.x), y = __uint_as_float(kv.y), z = __uint_as_float(kv.z);
+    for (int b = 0; b < nb; ++b) {
+      const Body& B = bodies[b];
+      if (!B.has_box) continue;
+      cand |= x >= B.flo[0] && x <= B.fhi[0] && y >= B.flo[1] && y <= B.fhi[1] && z >= B.flo[2] && z <= B.fhi[2];
+    }
+  }
+  if (!cand) return 0;
+  const float4 a = m_a[i];
+  const float4 d = CELL ? m_d[i] : a;
+  double xw[3];
+  abs_pos(a, d, g, xw);
+  return flag_of(xw, bodies, nb, g.ext);
+}
+
 // Sec. 4.2 item 2 over all N particles, fused with the first pass of the
 // order-preserving compaction: block b covers the tile of kFlagsTile particles
 // from b kFlagsTile (the tile of k_flags_write), thread t takes the particles
 // b kFlagsTile + k kBlock + t, k = 0..15 (each load of a wave reads 64
-// consecutive records; four in flight per thread), and the block's count of
-// flagged particles goes to bcnt[b]. A pre-test without FP64 (the world box's
-// FP32 bounds rounded outwards for FP32 coordinates, its range of cell indices
-// for cell-offset positions) rejects almost every particle of a long terrain;
-// the others take the exact FP64 test of flag_of, so every flag is flag_of's.
+// consecutive records), and the block's count of flagged particles goes to
+// bcnt[b]. A pre-test without FP64 (the world box's FP32 bounds rounded
+// outwards for FP32 coordinates, its range of cell indices for cell-offset
+// positions) rejects almost every particle of a long terrain; the others take
+// the exact FP64 test of flag_of, so every flag is flag_of's. All sixteen
+// loads are issued before the first test, the test against the union of the
+// bodies' bounds runs on the loaded values, and the few particles inside that
+// union take the rest in a loop that reloads them, so that no wait for a
+// store or a later load sits between the loads of a thread.
+template <bool CELL>
+__device__ inline bool in_union(float4 p, const ActUnion& un) {
+  if (CELL) {
+    const uint32_t w = __float_as_uint(p.w);
+    const int32_t c0 = (int32_t)__float_as_uint(p.z), c1 = unpack_y(w), c2 = unpack_z(w);
+    return c0 >= un.clo[0] && c0 <= un.chi[0] && c1 >= un.clo[1] && c1 <= un.chi[1] && c2 >= un.clo[2] &&
+           c2 <= un.chi[2];
+  }
+  return p.x >= un.flo[0] && p.x <= un.fhi[0] && p.y >= un.flo[1] && p.y <= un.fhi[1] && p.z >= un.flo[2] &&
+         p.z <= un.fhi[2];
+}
+
 template <bool CELL>
 __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restrict__ m_a,
                                                            const float4* __restrict__ m_d,
@@ -315,66 +364,44 @@ __global__ __launch_bounds__(kBlock) void k_activity_count(const float4* __restr
                                                            Grid g, uint8_t* __restrict__ flags,
                                                            uint32_t* __restrict__ bcnt) {
   const int64_t base = (int64_t)blockIdx.x * kFlagsTile + threadIdx.x;
+  float4 p[kFlagsPer];   // the compact copy: x, y, z (FP32 coordinates) or the cells in p.zw
+#pragma unroll
+  for (int q = 0; q < kFlagsPer; ++q) {
+    const int64_t i = base + (int64_t)q * kBlock;
+    p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n) {
+      if (CELL) {
+        const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
+        p[q].z = __uint_as_float(kv.x);
+        p[q].w = __uint_as_float(kv.y);
+      } else {
+        const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
+        p[q] = make_float4(__uint_as_float(kv.x), __uint_as_float(kv.y), __uint_as_float(kv.z), 0.f);
+      }
+    }
+  }
+  // almost every particle of a long terrain is outside the union: flag 0.
+  // All tests come before the first store (a byte store may alias the
+  // kernel's arguments for the compiler, which would then reload them and
+  // wait for the store first).
+  uint32_t near = 0;
+#pragma unroll
+  for (int q = 0; q < kFlagsPer; ++q)
+    if (base + (int64_t)q * kBlock < n && in_union<CELL>(p[q], un)) near |= 1u << q;
+#pragma unroll
+  for (int q = 0; q < kFlagsPer; ++q) {
+    const int64_t i = base + (int64_t)q * kBlock;
+    if (i < n && !((near >> q) & 1u)) flags[i] = 0;
+  }
   uint32_t cnt = 0;
 #pragma unroll 1
-  for (int k0 = 0; k0 < kFlagsPer; k0 += 4) {
-    float4 p[4];   // the compact copy: x, y, z (FP32 coordinates) or the cells in p.zw
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t i = base + (int64_t)(k0 + q) * kBlock;
-      p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (i < n) {
-        if (CELL) {
-          const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
-          p[q].z = __uint_as_float(kv.x);
-          p[q].w = __uint_as_float(kv.y);
-        } else {
-          const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
-          p[q] = make_float4(__uint_as_float(kv.x), __uint_as_float(kv.y), __uint_as_float(kv.z), 0.f);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t i = base + (int64_t)(k0 + q) * kBlock;
-      if (i < n) {
-        int32_t c[3] = {0, 0, 0};
-        if (CELL) {
-          const uint32_t w = __float_as_uint(p[q].w);
-          c[0] = (int32_t)__float_as_uint(p[q].z);
-          c[1] = unpack_y(w);
-          c[2] = unpack_z(w);
-        }
-        // first against the union of the bodies' bounds (almost every particle
-        // of a long terrain is outside it), then body by body
-        bool cand = false;
-        const bool near =
-            CELL ? (c[0] >= un.clo[0] && c[0] <= un.chi[0] && c[1] >= un.clo[1] && c[1] <= un.chi[1] &&
-                    c[2] >= un.clo[2] && c[2] <= un.chi[2])
-                 : (p[q].x >= un.flo[0] && p[q].x <= un.fhi[0] && p[q].y >= un.flo[1] && p[q].y <= un.fhi[1] &&
-                    p[q].z >= un.flo[2] && p[q].z <= un.fhi[2]);
-        for (int b = 0; b < (near ? nb : 0); ++b) {
-          const Body& B = bodies[b];
-          if (!B.has_box) continue;
-          if (CELL)
-            cand |= c[0] >= B.clo[0] && c[0] <= B.chi[0] && c[1] >= B.clo[1] && c[1] <= B.chi[1] &&
-                    c[2] >= B.clo[2] && c[2] <= B.chi[2];
-          else
-            cand |= p[q].x >= B.flo[0] && p[q].x <= B.fhi[0] && p[q].y >= B.flo[1] && p[q].y <= B.fhi[1] &&
-                    p[q].z >= B.flo[2] && p[q].z <= B.fhi[2];
-        }
-        uint8_t f = 0;
-        if (cand) {
-          const float4 a = m_a[i];
-          const float4 d = CELL ? m_d[i] : a;
-          double xw[3];
-          abs_pos(a, d, g, xw);
-          f = flag_of(xw, bodies, nb, g.ext);
-        }
-        flags[i] = f;
-        cnt += f != 0 ? 1u : 0u;
-      }
-    }
+  while (near) {
+    const int q = __builtin_ctz(near);
+    near &= near - 1u;
+    const int64_t i = base + (int64_t)q * kBlock;
+    const uint8_t f = act_flag<CELL>(key, m_a, m_d, i, bodies, nb, g);
+    flags[i] = f;
+    cnt += f != 0 ? 1u : 0u;
   }
   uint32_t tot;
   block_excl_scan(cnt, tot);
@@ -454,38 +481,6 @@ __global__ __launch_bounds__(kBlock) void k_ix_place(const float4* __restrict__ 
   if (i >= n) return;
   const uint32_t c = coarse_of<CELL>(m_a, m_d, i, g, cx, cy);
   ids[start[c] + wave_atomic_slot(fill, c)] = (int32_t)i;
-}
-
-// k_activity_count's test of one particle (without the union pre-test).
-template <bool CELL>
-__device__ inline uint8_t act_flag(const uint32_t* __restrict__ key, const float4* __restrict__ m_a,
-                                   const float4* __restrict__ m_d, int64_t i, const Body* __restrict__ bodies,
-                                   int32_t nb, const Grid& g) {
-  bool cand = false;
-  if (CELL) {
-    const uint2 kv = *reinterpret_cast<const uint2*>(key + 2 * i);
-    const int32_t c0 = (int32_t)kv.x, c1 = unpack_y(kv.y), c2 = unpack_z(kv.y);
-    for (int b = 0; b < nb; ++b) {
-      const Body& B = bodies[b];
-      if (!B.has_box) continue;
-      cand |= c0 >= B.clo[0] && c0 <= B.chi[0] && c1 >= B.clo[1] && c1 <= B.chi[1] && c2 >= B.clo[2] &&
-              c2 <= B.chi[2];
-    }
-  } else {
-    const uint3 kv = *reinterpret_cast<const uint3*>(key + 3 * i);
-    const float x = __uint_as_float(kv.x), y = __uint_as_float(kv.y), z = __uint_as_float(kv.z);
-    for (int b = 0; b < nb; ++b) {
-      const Body& B = bodies[b];
-      if (!B.has_box) continue;
-      cand |= x >= B.flo[0] && x <= B.fhi[0] && y >= B.flo[1] && y <= B.fhi[1] && z >= B.flo[2] && z <= B.fhi[2];
-    }
-  }
-  if (!cand) return 0;
-  const float4 a = m_a[i];
-  const float4 d = CELL ? m_d[i] : a;
-  double xw[3];
-  abs_pos(a, d, g, xw);
-  return flag_of(xw, bodies, nb, g.ext);
 }
 
 // Writes a nonzero flag f of particle i and counts it in its compaction tile
