@@ -556,7 +556,7 @@ def main():
                          "pull, vertical force and torque (20000: the 0.5 s single-wheel test)")
     ap.add_argument("--strip-length", type=float, default=10000.0)
     ap.add_argument("--strip-x", type=float, default=5000.0)
-    ap.add_argument("--strip-steps", type=int, default=400)
+    ap.add_argument("--strip-steps", type=int, default=2000)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--form-warmup", type=int, default=20)
     ap.add_argument("--tile", choices=TILE_NAMES, default="small",
@@ -610,15 +610,12 @@ def main():
                                            activity_launch_ms=q["activity_launch_ms"],
                                            rebuild_ms=q["breakdown"].get("rebuild"))
             # the same form with the vehicle near either end of the strip
-            steps = args.strip_steps
-            args.strip_steps = max(steps // 2, 1)
             r["along_the_strip"] = {}
             for xv in (10.0, args.strip_length - 10.0):
                 q = run_strip(args, crm, scenes, mode, strip_at(strip_scene, xv))
                 r["along_the_strip"][f"x={xv:g}"] = dict(value=q["value"], ms_per_step=q["ms_per_step"],
                                                          n_processed=q["config"]["n_processed"],
                                                          activity_launch_ms=q["activity_launch_ms"])
-            args.strip_steps = steps
             if drift is None and args.strip_length >= 9999.5:
                 drift = subpatch_drift(strip_subpatch(strip_scene, 9999.0), crm)
         elif f == "batch":
