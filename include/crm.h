@@ -97,7 +97,9 @@ typedef void (*crm_free_fn)(void* ptr, void* user, void* hip_stream);
  * index was built), are tested (same flags); with 1 all N are (the paper's
  * pass). moved_cap: entries of the moved list (0: max(16384, N / 32)); the
  * index is rebuilt when the list would overflow, and a rebuild tests all N
- * instead when the last rebuild integrated more than moved_cap / 2 rows. */
+ * instead when the last rebuild integrated more than moved_cap / 2 rows. The
+ * index takes 4 B per particle and 16 B per coarse cell (8 list cells per
+ * axis); with more coarse cells than max(N, 2^20) all N are tested. */
 typedef struct {
   uint32_t abi_version;  /* must be CRM_ABI_VERSION */
   uint32_t av_mode;

@@ -1327,7 +1327,12 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
             alloc_n(c, c->d_bstart, n_bodies + 1);
   if (ok && params->active_domains)
     ok = alloc_n(c, c->m_key, n_total * crm::key_words(c->grid.cell != 0));
-  if (ok && params->active_domains && !params->activity_scan) {
+  // the index's arrays scale with the domain's coarse cells: a domain far
+  // larger than the particles it holds tests all N instead
+  int32_t cd[3];
+  const int64_t coarse = crm::coarse_cells(c->grid, cd);
+  if (ok && params->active_domains && !params->activity_scan &&
+      coarse <= std::max<int64_t>(n_total, int64_t(1) << 20)) {
     c->ix_M = crm::coarse_cells(c->grid, c->ix_cd);
     c->mcap = params->moved_cap > 0 ? params->moved_cap : std::max<int64_t>(int64_t(1) << 14, n_total / 32);
     ok = alloc_n(c, c->ix_start, c->ix_M + 1) && alloc_n(c, c->ix_fill, c->ix_M) &&
