@@ -2,8 +2,9 @@
 
 A bin inside the batch is bit-identical (state and body forces) to the same bin
 run alone with the same grid, since its neighbour lists, their order and its
-bodies' marker ranges are the same; a small batch with per-bin friction
-matches the FP64 oracle with per-particle materials.
+bodies' marker ranges are the same (on an 8-bin batch, and on the full 64-bin
+batch under graph replay); a small batch with per-bin friction matches the
+FP64 oracle with per-particle materials.
 """
 import numpy as np
 import pytest
@@ -58,6 +59,39 @@ def test_bin_in_batch_equals_bin_alone(crm):
         F1, T1 = s1.forces()
         (ss, ms), = _bin_slices(alone)
         fs, fm = sl_full[b]
+        for k in ("pos", "vel", "sigma", "rho"):
+            assert np.array_equal(g1[k][ss], gf[k][fs]), (b, k)
+            assert np.array_equal(g1[k][ms], gf[k][fm]), (b, k, "markers")
+        assert np.array_equal(F1, Ff[2 * b:2 * b + 2]) and np.array_equal(T1, Tf[2 * b:2 * b + 2])
+        s1.close()
+
+
+def test_full_batch_bins_equal_bins_alone(crm):
+    """The 64-bin batch at full size (seed 0: 6,923,164 particles, the bench's
+    workload), stepped as a graph replay over two list rebuilds: its smallest
+    and largest bins are bit-identical to the same bins alone."""
+    kw = dict(seed=0, ps_freq=10)
+    full = scenes.batch_bins(**kw)
+    assert full.n_total == 6923164
+    sizes = [b["n"] for b in full.meta["bins"]]
+    pick = (int(np.argmin(sizes)), int(np.argmax(sizes)))
+    sim = _sim(crm, full)
+    sim.graph(True)
+    sim.step(25)
+    gf = sim.state()
+    Ff, Tf = sim.forces()
+    sl_full = _bin_slices(full)
+    sim.close()
+    for b in pick:
+        alone = scenes.batch_bins(only=[b], **kw)
+        s1 = _sim(crm, alone)
+        s1.graph(True)
+        s1.step(25)
+        g1 = s1.state()
+        F1, T1 = s1.forces()
+        (ss, ms), = _bin_slices(alone)
+        fs, fm = sl_full[b]
+        print("bin", b, "soil", sizes[b], flush=True)
         for k in ("pos", "vel", "sigma", "rho"):
             assert np.array_equal(g1[k][ss], gf[k][fs]), (b, k)
             assert np.array_equal(g1[k][ms], gf[k][fm]), (b, k, "markers")
