@@ -25,8 +25,8 @@
  *     CRM_E_NOMEM and CRM_E_STATE leave the context unchanged. CRM_E_DEVICE and
  *     CRM_E_NONFINITE poison the context: later calls return CRM_E_STATE.
  *   - Kernels run asynchronously; a device error surfaces at the next call that
- *     synchronises (crm_get_forces, crm_get_state, the debug exports, or a
- *     rebuild step).
+ *     synchronises (crm_get_forces, up to the last step's body sums;
+ *     crm_get_state, the debug exports, or a rebuild step).
  *   - Particle ids: the n_soil soil particles of crm_init are ids 0..n_soil-1;
  *     the markers of body b follow in body order (ids n_soil + ...).
  */
@@ -201,7 +201,10 @@ crm_status crm_step_noalloc(crm_ctx* ctx, int32_t n_steps);
 /* Force (N, world frame) and torque (N m, about the body origin) the soil
  * exerts on each body, from the stage-2 evaluation of the last step
  * (Sec. 2.5.1: sum of marker mass times marker acceleration). force, torque:
- * 3*nb doubles. Waits for the stream (by polling). Errors: CRM_E_INVALID,
+ * 3*nb doubles. Waits (by polling) until the stream has written those sums:
+ * a step reduces them before its stage 2, which the sums do not depend on, so
+ * after a step the call returns while stage 2 still runs, and the caller's
+ * next crm_set_bodies and step queue behind it. Errors: CRM_E_INVALID,
  * CRM_E_STATE (no step taken yet), CRM_E_NONFINITE, CRM_E_DEVICE. */
 crm_status crm_get_forces(crm_ctx* ctx, int32_t nb, double* force, double* torque);
 

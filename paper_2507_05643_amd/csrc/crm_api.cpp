@@ -151,6 +151,7 @@ struct crm_ctx {
   Body* h_bpin = nullptr;
   double* h_fpin = nullptr;
   hipEvent_t bpin_ev = nullptr, fpin_ev = nullptr;
+  int64_t fpin_step = -1;         // fpin_ev marks the body sums of the step that leaves c->step at this value
   bool bpin_pending = false;
   hipEvent_t disp_ev = nullptr;
   bool disp_pending = false;
@@ -167,8 +168,8 @@ struct crm_ctx {
   // replay of the per-step kernels as one hipGraph
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr, graph2 = nullptr;   // a step's kernels up to the body sums, then stage 2
+  hipGraphExec_t gexec = nullptr, gexec2 = nullptr;
   std::vector<const void*> graph_key;
 
   // profiling: event pairs per kernel class
@@ -907,10 +908,14 @@ crm_status copy_planes(crm_ctx* c, CPlanes src, Planes dst, int64_t n, hipStream
   return CRM_OK;
 }
 
-// The kernels of one step after the (optional) rebuild, on stream s.
-crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* rec = nullptr) {
+// The kernels of one step after the (optional) rebuild, on stream s, in two
+// parts: up to the body sums (marker placement, BCE, stage 1, BCE with the
+// forces, their reduction into the mapped host buffer), then stage 2, which
+// the sums do not depend on. Between the two, a direct launch records fpin_ev,
+// so that crm_get_forces returns while stage 2 still runs and the caller's
+// next body state is computed and enqueued meanwhile.
+crm_status launch_head(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* rec) {
   const crm::StageTape* tape1 = rec ? &rec->t1 : nullptr;
-  const crm::StageTape* tape2 = rec ? &rec->t2 : nullptr;
   const Phys& P = c->phys;
   hipEvent_t e = prof ? prof_begin(c, 1) : nullptr;
   HIPCHK(c, crm::place_markers_working(c->mrows, c->n_mrows, c->cnt_m, c->slot_id, c->n_soil, c->local,
@@ -928,7 +933,7 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   HIPCHK(c, crm::fluid_stage1(c->A, c->B, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape1, c->tabs, c->tix_f,
                               c->tile_cfg, s));
   if (prof) prof_end(c, 3, e);
-  // stage 2 at y_mid, body forces from this evaluation
+  // the markers at y_mid and the body forces from this evaluation
   if (prof) e = prof_begin(c, 4);
   HIPCHK(c, crm::bce(c->B, c->nrow, c->n_near, c->nbr_m, c->d_bodies, c->slot_k, c->kbase, P, c->contrib, s));
   if (prof) prof_end(c, 4, e);
@@ -936,22 +941,61 @@ crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     crm_status st = copy_planes(c, c->B, rec->ym, c->n_proc, s);
     if (st != CRM_OK) return st;
   }
-  if (prof) e = prof_begin(c, 5);
-  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, P, tape2, c->tabs, c->tix_f,
-                              c->tile_cfg, s));
-  if (prof) prof_end(c, 5, e);
   if (prof) e = prof_begin(c, 6);
   HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_fmap, s));
   if (prof) prof_end(c, 6, e);
   return CRM_OK;
 }
 
+// Stage 2 at y_mid.
+crm_status launch_tail(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* rec) {
+  const crm::StageTape* tape2 = rec ? &rec->t2 : nullptr;
+  hipEvent_t e = prof ? prof_begin(c, 5) : nullptr;
+  HIPCHK(c, crm::fluid_stage2(c->B, c->A, c->frows, c->n_frows, c->off_f, c->nbr_f, c->phys, tape2, c->tabs,
+                              c->tix_f, c->tile_cfg, s));
+  if (prof) prof_end(c, 5, e);
+  return CRM_OK;
+}
+
+// Marks the body sums just enqueued on the context's stream as those of the
+// step in progress (c->step before its increment).
+crm_status mark_forces(crm_ctx* c) {
+  HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
+  c->fpin_step = c->step + 1;
+  return CRM_OK;
+}
+
+crm_status launch_step(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* rec = nullptr) {
+  crm_status st = launch_head(c, s, prof, rec);
+  if (st == CRM_OK && s == c->stream && c->nb > 0) st = mark_forces(c);
+  if (st == CRM_OK) st = launch_tail(c, s, prof, rec);
+  return st;
+}
+
 void drop_graph(crm_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
+  if (c->gexec2) (void)hipGraphExecDestroy(c->gexec2);
+  if (c->graph2) (void)hipGraphDestroy(c->graph2);
+  c->gexec = c->gexec2 = nullptr;
+  c->graph = c->graph2 = nullptr;
   c->graph_key.clear();
+}
+
+// One part of a step captured on the capture stream and instantiated.
+crm_status capture_part(crm_ctx* c, bool head, hipGraph_t* g, hipGraphExec_t* x) {
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  crm_status st = head ? launch_head(c, c->cap_stream, false, nullptr) : launch_tail(c, c->cap_stream, false, nullptr);
+  hipGraph_t gg = nullptr;
+  hipError_t ee = hipStreamEndCapture(c->cap_stream, &gg);
+  if (st != CRM_OK) {
+    if (gg) (void)hipGraphDestroy(gg);
+    return st;
+  }
+  if (ee != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+  *g = gg;
+  HIPCHK(c, hipGraphInstantiate(x, gg, nullptr, nullptr, 0));
+  return CRM_OK;
 }
 
 // Everything the captured kernels bake in: buffers and row counts.
@@ -965,23 +1009,23 @@ std::vector<const void*> graph_key(const crm_ctx* c) {
 
 crm_status step_graph(crm_ctx* c) {
   std::vector<const void*> key = graph_key(c);
-  if (!c->gexec || key != c->graph_key) {
+  if (!c->gexec || !c->gexec2 || key != c->graph_key) {
     drop_graph(c);
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    crm_status st = launch_step(c, c->cap_stream, false);
-    hipGraph_t g = nullptr;
-    hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+    crm_status st = capture_part(c, true, &c->graph, &c->gexec);
+    if (st == CRM_OK) st = capture_part(c, false, &c->graph2, &c->gexec2);
     if (st != CRM_OK) {
-      if (g) (void)hipGraphDestroy(g);
+      drop_graph(c);
       return st;
     }
-    if (ee != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
-    c->graph = g;
-    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
     c->graph_key = key;
   }
   HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  if (c->nb > 0) {
+    crm_status st = mark_forces(c);
+    if (st != CRM_OK) return st;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec2, c->stream));
   return CRM_OK;
 }
 
@@ -1722,6 +1766,7 @@ crm_status crm_adjoint(crm_ctx* c, const double* lam_pos, const float* lam_vel, 
     c->force_rebuild = true;
     c->place_all = true;
     c->step = c->rec_step0 + c->rec_seg[g];
+    c->fpin_step = -1;
     return CRM_OK;
   };
   // the gathers below walk every soil row's slots: the replays' rebuilds write
@@ -1833,8 +1878,12 @@ crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque)
   if ((!force || !torque) && nb > 0) return fail(c, CRM_E_INVALID, "force and torque are required");
   if (!c->stepped) return fail(c, CRM_E_STATE, "no step taken yet");
   if (nb == 0) return CRM_OK;
-  // the last step's reduction wrote the sums into h_fpin (mapped host memory)
-  HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
+  // the last step's reduction wrote the sums into h_fpin (mapped host memory);
+  // fpin_ev marks them unless something was enqueued since without a mark
+  if (c->fpin_step != c->step) {
+    HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
+    c->fpin_step = c->step;
+  }
   HIPCHK(c, poll_event(c->fpin_ev));
   std::atomic_thread_fence(std::memory_order_acquire);
   const double* h = c->h_fpin;
@@ -2049,6 +2098,7 @@ crm_status crm_load_checkpoint(crm_ctx* c, const void* buf, size_t bytes) {
     c->h_mat.clear();
   }
   c->step = h.step;
+  c->fpin_step = -1;
   c->tile_cfg = h.tile_cfg;
   c->working_valid = false;
   c->force_rebuild = true;
