@@ -151,7 +151,10 @@ struct crm_ctx {
   Body* h_bpin = nullptr;
   double* h_fpin = nullptr;
   hipEvent_t bpin_ev = nullptr, fpin_ev = nullptr;
-  int64_t fpin_step = -1;         // fpin_ev marks the body sums of the step that leaves c->step at this value
+  int64_t fpin_step = -1;         // the counters mark the body sums of the step that leaves c->step at this value
+  volatile uint64_t* h_fseq = nullptr;   // per body: reductions written (host view, after the sums in h_fpin)
+  uint64_t* d_fseq = nullptr;            // device alias of h_fseq
+  uint64_t fseq = 0;                     // reductions enqueued
   bool bpin_pending = false;
   hipEvent_t disp_ev = nullptr;
   bool disp_pending = false;
@@ -942,7 +945,7 @@ crm_status launch_head(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
     if (st != CRM_OK) return st;
   }
   if (prof) e = prof_begin(c, 6);
-  HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_fmap, s));
+  HIPCHK(c, crm::segment_reduce(c->contrib, c->body_plan, c->d_fmap, s, c->d_fseq));
   if (prof) prof_end(c, 6, e);
   return CRM_OK;
 }
@@ -957,10 +960,13 @@ crm_status launch_tail(crm_ctx* c, hipStream_t s, bool prof, const StepRecord* r
   return CRM_OK;
 }
 
-// Marks the body sums just enqueued on the context's stream as those of the
-// step in progress (c->step before its increment).
+// Notes that the body sums just enqueued on the context's stream (their
+// reduction moves every body's counter by one) are those of the step in
+// progress (c->step before its increment). Every executed reduction of the
+// step kernels is enqueued through here, so the counters equal fseq once the
+// last one has written its sums.
 crm_status mark_forces(crm_ctx* c) {
-  HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
+  c->fseq += 1;
   c->fpin_step = c->step + 1;
   return CRM_OK;
 }
@@ -1399,14 +1405,17 @@ crm_status crm_init(const crm_params* params, int64_t n_soil, const double* pos,
   {
     const size_t nbp = (size_t)(n_bodies > 0 ? n_bodies : 1);
     if (hipHostMalloc((void**)&c->h_bpin, sizeof(Body) * nbp, hipHostMallocDefault) != hipSuccess) c->h_bpin = nullptr;
-    // the force sums go straight to host memory: pinned, mapped, coherent
-    if (hipHostMalloc((void**)&c->h_fpin, sizeof(double) * 6 * nbp, hipHostMallocMapped | hipHostMallocCoherent) !=
+    // the force sums go straight to host memory: pinned, mapped, coherent;
+    // after them one counter per body (moved by each reduction)
+    if (hipHostMalloc((void**)&c->h_fpin, sizeof(double) * 7 * nbp, hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostGetDevicePointer((void**)&c->d_fmap, c->h_fpin, 0) != hipSuccess) {
       if (c->h_fpin) (void)hipHostFree(c->h_fpin);
       c->h_fpin = nullptr;
     } else {
-      std::memset(c->h_fpin, 0, sizeof(double) * 6 * nbp);
+      std::memset(c->h_fpin, 0, sizeof(double) * 7 * nbp);
+      c->h_fseq = reinterpret_cast<volatile uint64_t*>(c->h_fpin + 6 * nbp);
+      c->d_fseq = reinterpret_cast<uint64_t*>(c->d_fmap + 6 * nbp);
     }
     if (!c->h_bpin || !c->h_fpin || hipEventCreateWithFlags(&c->bpin_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->fpin_ev, hipEventDisableTiming) != hipSuccess) {
@@ -1515,15 +1524,21 @@ crm_status crm_set_bodies(crm_ctx* c, int32_t nb, const double* pos, const doubl
     B.place = (!c->wplaced_ok || std::memcmp(B.X, W.X, sizeof(B.X)) != 0 || std::memcmp(B.R, W.R, sizeof(B.R)) != 0 ||
                std::memcmp(B.V, W.V, sizeof(B.V)) != 0 || std::memcmp(B.W, W.W, sizeof(B.W)) != 0) ? 1 : 0;
   }
-  // the staging buffer is reused once its last upload has been read
-  hipError_t e = c->bpin_pending ? hipEventSynchronize(c->bpin_ev) : hipSuccess;
-  if (e == hipSuccess) {
-    std::memcpy(c->h_bpin, hb.data(), sizeof(Body) * (size_t)nb);
-    e = hipMemcpyAsync(c->d_bodies, c->h_bpin, sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipSuccess;
+  if (nb <= crm::kBodyPack) {
+    // a few bodies travel in a kernel's arguments
+    e = crm::put_bodies(hb.data(), nb, c->d_bodies, c->stream);
+  } else {
+    // the staging buffer is reused once its last upload has been read
+    e = c->bpin_pending ? hipEventSynchronize(c->bpin_ev) : hipSuccess;
+    if (e == hipSuccess) {
+      std::memcpy(c->h_bpin, hb.data(), sizeof(Body) * (size_t)nb);
+      e = hipMemcpyAsync(c->d_bodies, c->h_bpin, sizeof(Body) * (size_t)nb, hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->bpin_ev, c->stream);
+    if (e == hipSuccess) c->bpin_pending = true;
   }
-  if (e == hipSuccess) e = hipEventRecord(c->bpin_ev, c->stream);
   if (e != hipSuccess) return fail(c, CRM_E_DEVICE, std::string("body upload: ") + hipGetErrorString(e));
-  c->bpin_pending = true;
   c->h_bodies.swap(hb);
   return CRM_OK;
 }
@@ -1878,13 +1893,28 @@ crm_status crm_get_forces(crm_ctx* c, int32_t nb, double* force, double* torque)
   if ((!force || !torque) && nb > 0) return fail(c, CRM_E_INVALID, "force and torque are required");
   if (!c->stepped) return fail(c, CRM_E_STATE, "no step taken yet");
   if (nb == 0) return CRM_OK;
-  // the last step's reduction wrote the sums into h_fpin (mapped host memory);
-  // fpin_ev marks them unless something was enqueued since without a mark
-  if (c->fpin_step != c->step) {
+  // the last step's reduction wrote the sums into h_fpin (mapped host memory)
+  if (c->fpin_step == c->step) {
+    // its counters, polled; the stream's state is looked at now and then, so
+    // that a device error ends the wait
+    for (uint32_t it = 1;; ++it) {
+      bool done = true;
+      for (int b = 0; b < nb && done; ++b) done = c->h_fseq[b] == c->fseq;
+      if (done) break;
+      if ((it & 1023u) == 0) {
+        const hipError_t e = hipStreamQuery(c->stream);
+        if (e == hipSuccess) {
+          for (int b = 0; b < nb; ++b)
+            if (c->h_fseq[b] != c->fseq) return fail(c, CRM_E_DEVICE, "body sums not written by the finished stream");
+          break;
+        }
+        if (e != hipErrorNotReady) return fail(c, CRM_E_DEVICE, std::string("force read: ") + hipGetErrorString(e));
+      }
+    }
+  } else {
     HIPCHK(c, hipEventRecord(c->fpin_ev, c->stream));
-    c->fpin_step = c->step;
+    HIPCHK(c, poll_event(c->fpin_ev));
   }
-  HIPCHK(c, poll_event(c->fpin_ev));
   std::atomic_thread_fence(std::memory_order_acquire);
   const double* h = c->h_fpin;
   for (int b = 0; b < nb; ++b)

@@ -285,7 +285,17 @@ struct SegPlan {
   double* partial = nullptr;
 };
 int64_t reduce_chunk();
-hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s);
+// seq (optional, nseg counters): each segment's counter moves by one once its
+// sums are written (system scope).
+hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s,
+                          uint64_t* seq = nullptr);
+// The first nb <= kBodyPack bodies uploaded to dst through a kernel's arguments.
+constexpr int kBodyPack = 8;
+struct BodyPack {
+  Body b[kBodyPack];
+};
+static_assert(sizeof(BodyPack) <= 3072, "the body table fits the kernel arguments");
+hipError_t put_bodies(const Body* bodies, int32_t nb, Body* dst, hipStream_t s);
 
 // Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
 // mapping (Sec. 2.4). With a tape, the velocity gradient of each row (and in

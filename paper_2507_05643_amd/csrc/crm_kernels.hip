@@ -5,6 +5,7 @@
 // is FP32 VALU work over cell-sorted records, the binning/compaction steps are
 // HBM streams built from wave64 ballots and block scans.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 
 #include "crm_device.h"
@@ -1329,9 +1330,12 @@ __global__ __launch_bounds__(kBlock) void k_chunk_reduce(const double* __restric
 
 // One block per segment: thread t sums chunks first + t, first + t + kBlock,
 // ... in order, then a tree over the threads.
+// With seq, the block then adds one to seq[g] behind a system-scope fence, so
+// that a host polling seq (host memory mapped for the device, like out) finds
+// the segment's sums written once the count moves.
 __global__ __launch_bounds__(kBlock) void k_segment_sum(const double* __restrict__ partial,
                                                         const int32_t* __restrict__ first,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, uint64_t* seq) {
   __shared__ double red[6][kBlock];
   const int32_t g = blockIdx.x;
   const int t = threadIdx.x;
@@ -1346,6 +1350,15 @@ __global__ __launch_bounds__(kBlock) void k_segment_sum(const double* __restrict
     __syncthreads();
   }
   if (t < 6) out[(int64_t)g * 6 + t] = red[t][0];
+  if (seq) {
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) {
+      volatile uint64_t* q = seq + g;
+      *q = *q + 1u;
+      __threadfence_system();
+    }
+  }
 }
 
 // ------------------------------------------------------------- fluid ---
@@ -2643,11 +2656,30 @@ hipError_t bce(Planes S, const NearRow* rows, int64_t n, const uint32_t* nbr, co
 int64_t reduce_chunk() { return kRedChunk; }
 
 
-hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s) {
+hipError_t segment_reduce(const double* in, const SegPlan& plan, double* out, hipStream_t s, uint64_t* seq) {
   if (plan.nseg <= 0) return hipSuccess;
   if (plan.nchunk > 0)
     k_chunk_reduce<<<(unsigned)plan.nchunk, kBlock, 0, s>>>(in, plan.lo, plan.hi, plan.partial);
-  k_segment_sum<<<(unsigned)plan.nseg, kBlock, 0, s>>>(plan.partial, plan.first, out);
+  k_segment_sum<<<(unsigned)plan.nseg, kBlock, 0, s>>>(plan.partial, plan.first, out, seq);
+  return hipGetLastError();
+}
+
+// The body table from the kernel's arguments (up to kBodyPack bodies): the
+// upload of a co-simulation step without a copy engine transfer or a staging
+// buffer to guard.
+__global__ void k_put_bodies(BodyPack p, int32_t nb, Body* __restrict__ dst) {
+  const int nw = nb * (int)(sizeof(Body) / sizeof(uint32_t));
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&p.b[0]);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int k = threadIdx.x; k < nw; k += blockDim.x) d[k] = src[k];
+}
+
+hipError_t put_bodies(const Body* bodies, int32_t nb, Body* dst, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (nb > kBodyPack) return hipErrorInvalidValue;
+  BodyPack p;
+  std::memcpy(&p.b[0], bodies, sizeof(Body) * (size_t)nb);
+  k_put_bodies<<<1, 256, 0, s>>>(p, nb, dst);
   return hipGetLastError();
 }
 
