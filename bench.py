@@ -58,6 +58,7 @@ MEASURED_TRAFFIC = {
     "k_fluid_stage2 wheel bin": dict(bytes=466.16e6, source="b834257696421030"),
     "k_activity strip pos_mode 0": dict(bytes=1923.1e6, source="b834257696421030"),
     "k_activity strip pos_mode 1": dict(bytes=1334.5e6, source="b834257696421030"),
+    "k_fluid_stage2 batch small": dict(bytes=4122.6e6, source="b834257696421030"),
 }
 KERNEL_SOURCES = ("crm_kernels.hip", "crm_device.h", "crm_internal.h")
 
@@ -420,7 +421,7 @@ def run_batch(args, crm, scenes):
     sim.profiling(False)
     cnt = sim.counts()
     sim.close()
-    roof = stage2_roofline(prof, cnt, None)
+    roof = stage2_roofline(prof, cnt, f"k_fluid_stage2 batch {TILE_NAMES[tile]}" if args.ps_freq == 10 else None)
     value = cnt["n_proc"] * steps / wall
 
     # one context per bin
