@@ -112,6 +112,7 @@ struct Phys {
   double lo[3];   // grid origin
   int32_t gdim[3];  // cells per axis
   const float4* mat;  // per material: (mu_s, mu_2, cohesion, -cohesion / mu_s)
+  const int32_t* bperm;  // launch order of the stage kernels' soil blocks (block_order), or null: cell order
 };
 
 // ---- static scratch of the step that allocates nothing --------------------
@@ -296,6 +297,16 @@ struct BodyPack {
 };
 static_assert(sizeof(BodyPack) <= 3072, "the body table fits the kernel arguments");
 hipError_t put_bodies(const Body* bodies, int32_t nb, Body* dst, hipStream_t s);
+// Launch order of the n_rows soil rows' blocks (kRows rows each) for the stage
+// kernels, from the rows' cells in grid g: perm[p] = the block logical block p
+// runs, ordered by (chunk of order_width() cells along x of the block's first
+// row, its row of cells, x). cnt, first: block_order_size(g) words; base:
+// that + 1; scan_tmp: scan_tmp_elems(block_order_size(g)).
+int32_t order_width();
+int64_t soil_block_count(int64_t rows);   // blocks of the soil rows' tile tables and stage kernels
+int64_t block_order_size(const Grid& g);
+hipError_t block_order(const int32_t* rows, const uint32_t* skey, int64_t n_rows, Grid g, uint32_t* cnt,
+                       uint32_t* first, uint32_t* base, uint32_t* scan_tmp, int32_t* perm, hipStream_t s);
 
 // Soil RHS + RK2 stage update (Sec. 2.2, 2.3) and, in stage 2, the return
 // mapping (Sec. 2.4). With a tape, the velocity gradient of each row (and in

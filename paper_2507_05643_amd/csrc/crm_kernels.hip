@@ -2132,6 +2132,17 @@ __device__ inline void walk_tile(const StageTile<CELL, CAP>& T, const uint16_t* 
   }, e0, e1, f);
 }
 
+// The soil block a stage kernel's workgroup serves: logical block xcd_block()
+// through the launch order when there is one (a value past the last block,
+// which a launch order of rows in cell order never holds, is clamped).
+__device__ inline int64_t stage_block(const int32_t* __restrict__ bperm, int64_t n) {
+  const int64_t b = xcd_block();
+  if (!bperm) return b;
+  const int64_t last = (n + kRows - 1) / kRows - 1;
+  const int64_t p = bperm[b];
+  return p >= 0 && p <= last ? p : last;
+}
+
 // One record on its way into the tile.
 struct Rec {
   float4 a, b, c, d;
@@ -2269,7 +2280,7 @@ __global__ __launch_bounds__(kStageBlock) void k_fluid_stage1(CPlanes A, Planes 
                                                          const uint16_t* __restrict__ tix) {
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
-  const int64_t blk = xcd_block();
+  const int64_t blk = stage_block(P.bperm, n);
   const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
   const int gl = group_lane<kSG>();
   const bool live = r < n;
@@ -2311,7 +2322,7 @@ __global__ __launch_bounds__(kStageBlock) void k_fluid_stage2(CPlanes B, Planes 
                                                          const uint16_t* __restrict__ tix) {
   constexpr uint32_t CAP = tile_cap<CELL, CFG>();
   __shared__ StageTile<CELL, CAP> tile;
-  const int64_t blk = xcd_block();
+  const int64_t blk = stage_block(P.bperm, n);
   const int64_t r = (blk * kStageBlock + threadIdx.x) / kSG;
   const int gl = group_lane<kSG>();
   const bool live = r < n;
@@ -2672,6 +2683,67 @@ __global__ void k_put_bodies(BodyPack p, int32_t nb, Body* __restrict__ dst) {
   const uint32_t* src = reinterpret_cast<const uint32_t*>(&p.b[0]);
   uint32_t* d = reinterpret_cast<uint32_t*>(dst);
   for (int k = threadIdx.x; k < nw; k += blockDim.x) d[k] = src[k];
+}
+
+// ------------------------------------ launch order of the soil blocks ---
+// In cell order the blocks that read one record (those of the nine rows of
+// cells around it) lie up to a plane of rows apart, farther than an XCD's L2
+// holds on wide grids, and the record is fetched from HBM up to three times.
+// Ordered by chunks of kOrderW cells along x (then row of cells, then x), the
+// plane within a chunk is kOrderW cells wide. Blocks are in cell order, so
+// the blocks of one (chunk, row) group are consecutive.
+constexpr int kOrderW = 16;
+
+__device__ inline uint32_t block_group(const int32_t* __restrict__ rows, const uint32_t* __restrict__ skey,
+                                       int64_t b, uint32_t X, uint32_t R) {
+  const uint32_t c = skey[rows[b * kRows]];
+  return (c % X) / (uint32_t)kOrderW * R + c / X;
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_groups(const int32_t* __restrict__ rows,
+                                                         const uint32_t* __restrict__ skey, int64_t nb, uint32_t X,
+                                                         uint32_t R, uint32_t* __restrict__ cnt,
+                                                         uint32_t* __restrict__ first) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nb) return;
+  const uint32_t e = block_group(rows, skey, b, X, R);
+  atomicAdd(&cnt[e], 1u);
+  if (b == 0 || block_group(rows, skey, b - 1, X, R) != e) first[e] = (uint32_t)b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_perm(const int32_t* __restrict__ rows,
+                                                       const uint32_t* __restrict__ skey, int64_t nb, uint32_t X,
+                                                       uint32_t R, const uint32_t* __restrict__ base,
+                                                       const uint32_t* __restrict__ first,
+                                                       const uint32_t* __restrict__ cnt, int32_t* __restrict__ perm) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nb) return;
+  const uint32_t e = block_group(rows, skey, b, X, R);
+  const uint32_t k = (uint32_t)b - first[e];
+  if (k < cnt[e]) perm[base[e] + k] = (int32_t)b;   // always, for rows in cell order
+}
+
+int32_t order_width() { return kOrderW; }
+
+int64_t soil_block_count(int64_t rows) { return (rows + kRows - 1) / kRows; }
+
+int64_t block_order_size(const Grid& g) {
+  return (int64_t)((g.dims[0] + kOrderW - 1) / kOrderW) * g.dims[1] * g.dims[2];
+}
+
+hipError_t block_order(const int32_t* rows, const uint32_t* skey, int64_t n_rows, Grid g, uint32_t* cnt,
+                       uint32_t* first, uint32_t* base, uint32_t* scan_tmp, int32_t* perm, hipStream_t s) {
+  const int64_t nb = (n_rows + kRows - 1) / kRows;
+  if (nb <= 0) return hipSuccess;
+  const int64_t M = block_order_size(g);
+  const uint32_t X = (uint32_t)g.dims[0], R = (uint32_t)g.dims[1] * (uint32_t)g.dims[2];
+  hipError_t e = fill_u32(cnt, 0u, M, s);
+  if (e != hipSuccess) return e;
+  k_block_groups<<<nblk(nb), kBlock, 0, s>>>(rows, skey, nb, X, R, cnt, first);
+  e = scan_u32_to_u32(cnt, base, M, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  k_block_perm<<<nblk(nb), kBlock, 0, s>>>(rows, skey, nb, X, R, base, first, cnt, perm);
+  return hipGetLastError();
 }
 
 hipError_t put_bodies(const Body* bodies, int32_t nb, Body* dst, hipStream_t s) {
