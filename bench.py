@@ -55,10 +55,10 @@ ACTIVITY_BYTES = {0: 12 + 1, 1: 8 + 1}
 # sources they were taken on; reported only while the sources are unchanged
 # (summaries and commands in profiles/).
 MEASURED_TRAFFIC = {
-    "k_fluid_stage2 wheel bin": dict(bytes=466.16e6, source="b834257696421030"),
-    "k_activity strip pos_mode 0": dict(bytes=1923.1e6, source="b834257696421030"),
-    "k_activity strip pos_mode 1": dict(bytes=1334.5e6, source="b834257696421030"),
-    "k_fluid_stage2 batch small": dict(bytes=4122.6e6, source="b834257696421030"),
+    "k_fluid_stage2 wheel bin": dict(bytes=466.16e6, source="e9246f134bbde8ee"),
+    "k_activity strip pos_mode 0": dict(bytes=1923.2e6, source="e9246f134bbde8ee"),
+    "k_activity strip pos_mode 1": dict(bytes=1334.5e6, source="e9246f134bbde8ee"),
+    "k_fluid_stage2 batch small": dict(bytes=1914.5e6, source="e9246f134bbde8ee"),
 }
 KERNEL_SOURCES = ("crm_kernels.hip", "crm_device.h", "crm_internal.h")
 
