@@ -573,7 +573,7 @@ def main():
                          "kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the step runs on one GPU",
               file=sys.stderr)
         sys.exit(2)
 
